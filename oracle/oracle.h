@@ -1,0 +1,145 @@
+/*
+ * CPU oracle for matching-based AMG preconditioned CG on IgA stiffness systems.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code is the slow, plain, obviously-correct
+ * FP64 statement of what the method computes.  Only the test-suite, the smoke
+ * check and the CPU-baseline leg of the benchmark may load it.  It shares no
+ * code, header, table or helper with the HIP library; the two meet only through
+ * the seeded input generator (random draws, no arithmetic of the method).
+ *
+ * Paper: D'Ambra, Durastante, Filippone, "Parallel matching-based AMG
+ * preconditioners for elliptic equations discretized by IgA" (arXiv 2511.21268).
+ * Each function cites the passage it follows.  Where the paper is silent the
+ * reading taken is stated beside the code.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp (no FMA contraction anywhere, so the
+ * aggregates and coarse matrices are fixed to the bit by the evaluation orders
+ * written below).
+ *
+ * Parity pins (tests/test_oracle_*.py): every function below is checked against
+ * closed forms, invariants, library routines or brute force.  None is unpinned
+ * except the iteration counts of the configurations, which the paper does not
+ * print for this preconditioner (see the header of krylov.c).
+ */
+#ifndef AMG_ORACLE_H
+#define AMG_ORACLE_H
+#include <stdint.h>
+
+/* ---------------- iga.c : B-spline discretization (Sec. 2) ---------------- */
+
+/* Gauss-Legendre nodes/weights on [-1,1], q points (Newton on P_q). */
+int  or_gauss_legendre(int q, double *x, double *w);
+/* Open uniform knot vector with n elements, degree p: length n+2p+1. */
+void or_knots(int p, int n, double *t);
+/* Value and derivative of B-spline N_{i,p} at x by the Cox-de Boor recursion. */
+double or_bspline(const double *t, int i, int p, double x);
+double or_bspline_deriv(const double *t, int i, int p, double x);
+/* 1D mass M1 and stiffness K1 (dense m x m, m=n+p, row-major), and the integrals
+ * of each basis function (the 1D load vector for f = 1), by (p+1)-point Gauss
+ * quadrature per element. */
+void or_matrices_1d(int p, int n, double *M, double *K, double *Fint);
+/* Size of the Dirichlet-reduced tensor system: N = (n+p-2)^d and its nnz. */
+void or_poisson_size(int d, int p, int n, int64_t *N, int64_t *nnz);
+/* Size with Dirichlet only on the faces flagged in dir[2k] (low) and
+ * dir[2k+1] (high) of direction k (x = 0, y = 1, z = 2); dir NULL = all faces. */
+void or_tensor_size(int d, int p, int n, const int *dir, int64_t *N, int64_t *nnz);
+/* As or_poisson_kron with the face flags of or_tensor_size (all zero: the
+ * singular Neumann matrix of the full basis). */
+int  or_poisson_kron_bc(int d, int p, int n, const int *dir, int64_t *rp, int32_t *ci,
+                        double *v, double *F);
+/* Constant-coefficient Poisson, homogeneous Dirichlet on every face:
+ * K = sum of Kronecker products of K1 and M1 (lexicographic, x fastest),
+ * the first and last basis function of every direction removed.  CSR out,
+ * arrays sized by or_poisson_size.  Also F for f = 1 when F != NULL. */
+int  or_poisson_kron(int d, int p, int n, int64_t *rp, int32_t *ci, double *v, double *F);
+/* 3D stiffness with coefficient kappa by (p+1)^3-point Gauss quadrature, by the
+ * plain element loop (every quadrature point, every local pair).  kappa is given
+ * by its parameters: kappa(x) = exp(0.5 * sum_k a[k] cos(2 pi m_k . x)), nk terms
+ * (nk = 0 gives kappa = 1).  Output in the same CSR pattern as or_poisson_kron,
+ * plus F for f = 1.  Intended for small n only. */
+int  or_diffusion_quad3d(int p, int n, int nk, const double *a, const int32_t *mk,
+                         int64_t *rp, int32_t *ci, double *v, double *F);
+
+/* ---------------- amg.c : hierarchy (Sec. 3, 3.1) ---------------- */
+
+typedef struct {
+    int sweeps_per_level;   /* m pairwise sweeps per level (aggregates <= 2^m) */
+    int max_coarse;         /* coarsest size for the dense Cholesky            */
+    int max_levels;
+    int nu_pre, nu_post;    /* l1-Jacobi sweeps                                 */
+    int match_positive_only;/* 1: only edges with c > 1 are eligible           */
+    int smoother;           /* 0: l1-Jacobi, 1: degree-4 polynomial            */
+} or_params;
+
+void or_params_default(or_params *p);
+
+typedef struct {
+    int64_t n, nnz;
+    int64_t *rp; int32_t *ci; double *v;
+    double *invd;           /* 1 / l1 diagonal                                */
+    double *w;              /* test vector on this level                      */
+    int32_t *agg;           /* aggregate (coarse index) of each row; ell < L  */
+    double *pc;             /* prolongator coefficient of each row; ell < L   */
+    double poly[4];         /* polynomial smoother coefficients (smoother 1)  */
+} or_level;
+
+typedef struct {
+    or_params prm;
+    int nlev;               /* levels 0..nlev-1; the last one is factored     */
+    or_level *lev;
+    double *chol;           /* dense lower Cholesky factor, nL x nL row-major */
+} or_hier;
+
+/* c_ij of eq. (cij) for the stored entry k_ij (i<j, from row i). */
+double or_cij(double kij, double kii, double kjj, double wi, double wj);
+/* Greedy matching on an explicit edge list (weights c, ends ei < ej): sort
+ * into the strict order below, then take each edge whose ends are both free. */
+int  or_greedy_edges(int64_t n, int64_t ne, const double *c, const int32_t *ei,
+                     const int32_t *ej, int positive_only, int32_t *mate);
+/* Greedy matching in the strict order (c desc, min index asc, max index asc),
+ * by a full sort of the eligible edges.  mate[i] = partner or -1. */
+int  or_match(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+              const double *w, int positive_only, int32_t *mate);
+/* Count the edges that violate the greedy characterisation of `mate`: an
+ * eligible edge not in the matching none of whose endpoints is matched through
+ * an edge that comes earlier in the order, or a matched pair that is not an
+ * eligible edge.  Zero iff mate is the greedy matching. */
+int64_t or_check_greedy(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+                        const double *w, int positive_only, const int32_t *mate);
+/* Number coarse nodes by scanning rows, and build the pairwise prolongator
+ * (eq. prolongation) and the restricted test vector.  Returns n_c. */
+int64_t or_pairwise_p(int64_t n, const int32_t *mate, const double *w,
+                      int32_t *agg, double *pc, double *wc);
+void or_l1_invdiag(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, double *invd);
+/* Dense Cholesky, in place lower factor.  Returns 0 or -2 (pivot <= 0). */
+int  or_cholesky(int n, double *a);
+void or_chol_solve(int n, const double *L, const double *b, double *x);
+
+/* Build the hierarchy.  K is copied.  w NULL means ones.
+ * Returns 0, -1 (bad argument), -2 (not SPD), -6 (coarsening stalled). */
+int  or_setup(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+              const double *w, const or_params *prm, or_hier **out);
+void or_free(or_hier *h);
+int  or_nlevels(const or_hier *h);
+void or_level_info(const or_hier *h, int l, int64_t *n, int64_t *nnz);
+void or_level_matrix(const or_hier *h, int l, int64_t *rp, int32_t *ci, double *v);
+void or_level_agg(const or_hier *h, int l, int32_t *agg, double *pc, double *invd, double *w);
+void or_coarse_factor(const or_hier *h, double *L);
+int  or_set_poly(or_hier *h, int l, const double *coef);
+
+/* ---------------- krylov.c : V-cycle and CG (Sec. 3, 4) ---------------- */
+
+void or_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+             const double *x, double *y);
+double or_dot(int64_t n, const double *x, const double *y);
+/* z = B r, one V-cycle from level l with zero initial guess. */
+void or_vcycle(const or_hier *h, int l, const double *r, double *z);
+/* Preconditioned CG (flexible = 0) or FCG(1) (flexible = 1) on level 0.
+ * u: in initial guess, out solution.  Returns 0 converged, 1 not converged,
+ * -5 breakdown.  hist (may be NULL) receives ||r_k||/||F|| for k = 0..iters. */
+int  or_pcg(const or_hier *h, const double *F, double *u, double tol, int itmax,
+            int flexible, int *iters, double *relres, double *hist);
+/* l1-Jacobi-preconditioned polynomial smoother error polynomial check. */
+int  or_poly_accept(const double *coef);
+
+#endif
