@@ -1,0 +1,208 @@
+/*
+ * amg.h -- C ABI of the MI355X (gfx950) solve path for K u = F, K sparse SPD:
+ * conjugate gradients preconditioned by a matching-based aggregation AMG
+ * V-cycle (D'Ambra, Durastante, Filippone, arXiv 2511.21268).
+ *
+ * Two-phase use, as in the paper's preconditioner-build-then-Krylov split
+ * (Sec. 4, the hierarchy build followed by the Krylov call with initial guess in,
+ * solution out, iteration count and error estimate out):
+ *   amg_setup()  builds the hierarchy on the host (compatible weighted matching,
+ *                Sec. 3.1) and uploads it to the device, factoring the coarsest
+ *                matrix there;
+ *   pcg_solve()  runs the whole solve phase in HIP kernels on the device.
+ *
+ * Conventions common to every call:
+ *  - all functions return amg_status; AMG_OK == 0; negative values are errors,
+ *    positive values are warnings (the output is valid);
+ *  - "host" pointers are ordinary CPU memory, "device" pointers are HIP device
+ *    memory of the device that was current when amg_setup ran;
+ *  - the caller owns every array it passes; the library copies what it keeps and
+ *    holds no caller pointer after a call returns;
+ *  - a context is not thread-safe: calls on one context must not overlap;
+ *  - on error, amg_last_error() returns a message (thread-local, valid until the
+ *    next call on the same thread).
+ */
+#ifndef AMG_H
+#define AMG_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AMG_OK = 0,
+    AMG_NOT_CONVERGED = 1,  /* itmax reached; u holds the last iterate          */
+    AMG_ERR_ARG = -1,       /* invalid argument or matrix                       */
+    AMG_ERR_NOT_SPD = -2,   /* non-positive pivot in the coarsest factorization */
+    AMG_ERR_HIP = -3,       /* HIP runtime error                                */
+    AMG_ERR_OOM = -4,       /* device or host allocation failed                 */
+    AMG_ERR_BREAKDOWN = -5, /* (p, K p) <= 0 or non-finite, or (r, B r) <= 0    */
+    AMG_ERR_STATE = -6      /* coarsening stalled above 2000 unknowns           */
+} amg_status;
+
+typedef struct amg_ctx amg_ctx;   /* opaque: the hierarchy on host and device */
+
+typedef struct {
+    int sweeps_per_level;   /* m pairwise matching sweeps composed per level
+                               (aggregates of at most 2^m; Sec. 3.1 m-step);
+                               default 2, range 1..3                            */
+    int max_coarse;         /* stop coarsening at <= this many rows and factor
+                               that level densely; default 200, range 1..2000   */
+    int max_levels;         /* default 40                                       */
+    int nu_pre, nu_post;    /* smoother sweeps before / after the coarse
+                               correction (Sec. 3 steps 1 and 5); default 1, 1;
+                               nu_pre must be >= 1                              */
+    int vcycle_fp32;        /* 0: V-cycle in FP64; 1: V-cycle in FP32 (outer
+                               residual, dots, coarse Cholesky stay FP64)       */
+    int smoother;           /* 0: l1-Jacobi (Sec. 3.2); 1: degree-4 polynomial
+                               in D^{-1}K (coefficients by amg_set_poly_coeffs) */
+    int krylov;             /* 0: CG; 1: flexible CG, FCG(1) (Sec. 3.1 end)     */
+    int match_positive_only;/* 0: every edge eligible (default);
+                               1: only edges with c_ij > 1 (log c_ij > 0)       */
+    int itmax;              /* default 1000                                     */
+} amg_params;
+
+/* Fill p with the defaults above.  p must not be NULL. */
+amg_status amg_params_default(amg_params *p);
+
+/*
+ * Build the hierarchy for the n x n matrix K given in CSR on the host.
+ *  row_ptr[n+1] int64, col[nnz] int32 (sorted ascending within each row),
+ *  val[nnz] FP64; K must be symmetric in pattern and values, with a positive
+ *  diagonal entry stored in every row, and all values finite.
+ *  w: host test vector of length n (Sec. 3.1 eq. (cij)); NULL means all ones.
+ *  prm: NULL means defaults.  hip_stream: the hipStream_t every later call of
+ *  this context is ordered on (NULL = the null stream).
+ * Per level: edge weights c_ij = 1 - 2 k_ij w_i w_j / (k_ii w_i^2 + k_jj w_j^2)
+ * (eq. (cij)), greedy matching in the order (c desc, min index, max index),
+ * pairwise prolongator of eq. (prolongation), Galerkin K_c = P^T K P
+ * (eq. (galerkin_matrix_projection)), composed m times.
+ * Errors: AMG_ERR_ARG (n <= 0, malformed or non-symmetric K, non-finite values,
+ * missing or non-positive diagonal), AMG_ERR_NOT_SPD, AMG_ERR_STATE,
+ * AMG_ERR_OOM, AMG_ERR_HIP.  On error *out is NULL.
+ */
+amg_status amg_setup(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                     const double *w, const amg_params *prm, void *hip_stream, amg_ctx **out);
+
+/*
+ * Solve K u = F (Sec. 4: CG or FCG preconditioned by one V-cycle per iteration).
+ *  F: device, length n, FP64.  u: device, length n, FP64; in: initial guess,
+ *  out: solution (last iterate on AMG_NOT_CONVERGED).  F and u must not alias.
+ *  Stops when ||r_k||_2 <= tol ||F||_2 on the recursive residual.
+ *  iters (host, may be NULL): completed updates of u.
+ *  relres (host, may be NULL): ||r_k||_2 / ||F||_2 of the recursion at exit.
+ *  relres_true (host, may be NULL): ||F - K u||_2 / ||F||_2, computed at exit.
+ * F == 0 gives u = 0, iters = 0, AMG_OK.  The call is ordered on the context's
+ * stream and returns after the solve has finished on the device.
+ * Errors: AMG_ERR_ARG (NULL pointers, tol < 0, non-finite F), AMG_ERR_BREAKDOWN,
+ * AMG_ERR_HIP; warning AMG_NOT_CONVERGED.
+ */
+amg_status pcg_solve(amg_ctx *c, const double *F, double *u, double tol,
+                     int *iters, double *relres, double *relres_true);
+
+/*
+ * Solve nrhs independent systems K U[:,k] = F[:,k] sharing every matrix pass:
+ * one block SpMV and one block V-cycle per iteration, each column with its own
+ * FCG(1) scalars, converged columns frozen.
+ *  F, U: device, n x nrhs column-major FP64 (U in: guesses, out: solutions).
+ *  iters, relres: host arrays of length nrhs (may be NULL).
+ *  1 <= nrhs <= 16.  The V-cycle precision follows prm.vcycle_fp32.
+ * Errors as pcg_solve; AMG_NOT_CONVERGED if any column did not converge.
+ */
+amg_status pcg_solve_batched(amg_ctx *c, int nrhs, const double *F, double *U, double tol,
+                             int *iters, double *relres);
+
+/*
+ * Apply the preconditioner once: z = B r, one V-cycle from the finest level
+ * with a zero initial guess (Sec. 3, the five steps of the two-level
+ * correction applied recursively).  r, z: device, length n, FP64, no aliasing.
+ * The V-cycle precision follows prm.vcycle_fp32.
+ */
+amg_status amg_vcycle(amg_ctx *c, const double *r, double *z);
+
+/*
+ * y = K_l x with the device copy of level l's matrix (FP64; level 0 is the
+ * caller's K).  x, y: device, length n_l, FP64, no aliasing.
+ * level in 0 .. levels-2, or 0 for a single-level hierarchy.
+ */
+amg_status amg_spmv(amg_ctx *c, int level, const double *x, double *y);
+
+/*
+ * Set the degree-4 polynomial smoother of one level (used when prm.smoother
+ * == 1): correction sum_{k=0..3} coeffs[k] (D^{-1}K)^k D^{-1} r (Sec. 3.2,
+ * polynomial acceleration of l1-Jacobi).  Accepted iff the error polynomial
+ * e(t) = 1 - sum coeffs[k] t^{k+1} has |e| <= 1 on [0,1] and e < 1 on (0,1]
+ * (checked on 10^4 steps): then the V-cycle stays SPD.  Rejected coefficients
+ * leave the level on l1-Jacobi and return AMG_NOT_CONVERGED (a warning).
+ * level in 0 .. levels-2.
+ */
+amg_status amg_set_poly_coeffs(amg_ctx *c, int level, const double coeffs[4]);
+
+/* Levels and sizes.  level = -1: *n receives the number of levels and *nnz the
+ * total stored entries (operator complexity = total / nnz of level 0). */
+amg_status amg_get_level_info(const amg_ctx *c, int level, int64_t *n, int64_t *nnz);
+
+/* Host copies of level `level`'s aggregate map (agg[i] = coarse index of row i)
+ * and prolongator coefficients (pc[i]); level in 0 .. levels-2.  Either output
+ * may be NULL. */
+amg_status amg_get_aggregates(const amg_ctx *c, int level, int32_t *agg, double *pc);
+
+/* Host CSR copy of the Galerkin matrix of `level` (sizes from
+ * amg_get_level_info).  Any output may be NULL. */
+amg_status amg_get_coarse_matrix(const amg_ctx *c, int level, int64_t *row_ptr, int32_t *col,
+                                 double *val);
+
+/* Host-only build of the same hierarchy (no device memory, no HIP call): for
+ * inspecting aggregates, coarse matrices and operator complexity on a machine
+ * without a GPU.  The level accessors work on the result; the solve calls
+ * return AMG_ERR_STATE.  Arguments and errors as amg_setup, except that the
+ * coarsest level is not factored (AMG_ERR_NOT_SPD cannot occur). */
+amg_status amg_setup_host(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                          const double *w, const amg_params *prm, amg_ctx **out);
+
+/* One pairwise matching sweep on its own (Sec. 3.1): mate[i] = the row matched
+ * with row i, or -1.  Same edge weights, eligibility and order as amg_setup;
+ * host arrays; K as in amg_setup (symmetric CSR), w NULL means ones. */
+amg_status amg_match(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                     const double *w, int positive_only, int32_t *mate);
+
+/* Free everything the context holds (host and device).  NULL is a no-op. */
+void amg_destroy(amg_ctx *c);
+
+/* Message of the last error on this thread ("" if none). */
+const char *amg_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Measurement.  While enabled, every launch of the level-0 sparse
+ * matrix-pass kernel (SpMV, residual, smoother sweep) inside the solve calls
+ * is bracketed by HIP events on the context's stream; amg_get_profile returns
+ * the number of launches, their summed device time and their summed
+ * algorithmic HBM bytes (each launch: matrix values and index bytes without
+ * padding, plus the vectors it must read and write once).
+ */
+amg_status amg_set_profiling(amg_ctx *c, int enable);
+amg_status amg_get_profile(amg_ctx *c, int64_t *launches, double *ms, double *bytes);
+/* Description of the level-0 layout: slice height, stored entries with
+ * padding, index bytes per entry (2 or 4). */
+amg_status amg_get_format(const amg_ctx *c, int level, int *slice, int64_t *stored,
+                          int *index_bytes);
+
+/* ------------------------------------------------------------------------
+ * Workload generator (Sec. 2): the Dirichlet-reduced stiffness matrix of the
+ * Poisson problem on the unit square (d = 2) or cube (d = 3), tensor-product
+ * B-splines of degree p with n equal elements per direction, open uniform knots
+ * (maximum regularity), homogeneous Dirichlet on every face, lexicographic
+ * order with x fastest, constant coefficient: the Kronecker sum of the 1D
+ * stiffness and mass matrices, each by (p+1)-point Gauss quadrature.
+ * amg_iga_poisson_size gives N = (n+p-2)^d and nnz; amg_iga_poisson fills
+ * caller-allocated host CSR arrays and F for f = 1 (F may be NULL).
+ */
+amg_status amg_iga_poisson_size(int d, int p, int n, int64_t *N, int64_t *nnz);
+amg_status amg_iga_poisson(int d, int p, int n, int64_t *row_ptr, int32_t *col, double *val,
+                           double *F);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

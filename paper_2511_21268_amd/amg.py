@@ -1,0 +1,249 @@
+"""ctypes binding of libamgiga.so (include/amg.h): argument marshalling only.
+
+Every step of the solve runs in the library's HIP kernels; torch is used only
+to hold device vectors and to name the stream.  Loading fails loudly when the
+library has not been built (there is no fallback path).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libamgiga.so")
+
+AMG_OK, AMG_NOT_CONVERGED = 0, 1
+AMG_ERR_ARG, AMG_ERR_NOT_SPD, AMG_ERR_HIP, AMG_ERR_OOM, AMG_ERR_BREAKDOWN, AMG_ERR_STATE = -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "AMG_OK", 1: "AMG_NOT_CONVERGED", -1: "AMG_ERR_ARG", -2: "AMG_ERR_NOT_SPD",
+                -3: "AMG_ERR_HIP", -4: "AMG_ERR_OOM", -5: "AMG_ERR_BREAKDOWN", -6: "AMG_ERR_STATE"}
+
+EXPORTS = ["amg_params_default", "amg_setup", "pcg_solve", "pcg_solve_batched", "amg_vcycle", "amg_spmv",
+           "amg_set_poly_coeffs",
+           "amg_get_level_info", "amg_get_aggregates", "amg_get_coarse_matrix", "amg_setup_host", "amg_match",
+           "amg_destroy", "amg_last_error", "amg_set_profiling", "amg_get_profile", "amg_get_format",
+           "amg_iga_poisson_size", "amg_iga_poisson"]
+
+
+class AmgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("sweeps_per_level", C.c_int), ("max_coarse", C.c_int), ("max_levels", C.c_int),
+                ("nu_pre", C.c_int), ("nu_post", C.c_int), ("vcycle_fp32", C.c_int), ("smoother", C.c_int),
+                ("krylov", C.c_int), ("match_positive_only", C.c_int), ("itmax", C.c_int)]
+
+
+i64p = C.POINTER(C.c_int64)
+i32p = C.POINTER(C.c_int32)
+f64p = C.POINTER(C.c_double)
+_lib = None
+
+
+def lib():
+    """Load libamgiga.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} missing "
+                               "(run __graft_entry__.build() or python paper_2511_21268_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.amg_params_default.argtypes = [C.POINTER(Params)]
+        L.amg_setup.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, C.POINTER(Params), vp, C.POINTER(vp)]
+        L.amg_setup_host.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, C.POINTER(Params), C.POINTER(vp)]
+        L.amg_match.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, C.c_int, i32p]
+        L.pcg_solve.argtypes = [vp, vp, vp, C.c_double, C.POINTER(C.c_int), f64p, f64p]
+        L.pcg_solve_batched.argtypes = [vp, C.c_int, vp, vp, C.c_double, C.POINTER(C.c_int), f64p]
+        L.amg_set_poly_coeffs.argtypes = [vp, C.c_int, f64p]
+        L.amg_vcycle.argtypes = [vp, vp, vp]
+        L.amg_spmv.argtypes = [vp, C.c_int, vp, vp]
+        L.amg_get_level_info.argtypes = [vp, C.c_int, i64p, i64p]
+        L.amg_get_aggregates.argtypes = [vp, C.c_int, i32p, f64p]
+        L.amg_get_coarse_matrix.argtypes = [vp, C.c_int, i64p, i32p, f64p]
+        L.amg_destroy.argtypes = [vp]
+        L.amg_destroy.restype = None
+        L.amg_last_error.restype = C.c_char_p
+        L.amg_set_profiling.argtypes = [vp, C.c_int]
+        L.amg_get_profile.argtypes = [vp, i64p, f64p, f64p]
+        L.amg_get_format.argtypes = [vp, C.c_int, C.POINTER(C.c_int), i64p, C.POINTER(C.c_int)]
+        L.amg_iga_poisson_size.argtypes = [C.c_int, C.c_int, C.c_int, i64p, i64p]
+        L.amg_iga_poisson.argtypes = [C.c_int, C.c_int, C.c_int, i64p, i32p, f64p, f64p]
+        _lib = L
+    return _lib
+
+
+def _check(st, allow=(AMG_OK,)):
+    if st not in allow:
+        raise AmgError(st, lib().amg_last_error().decode())
+    return st
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+def params_default(**kw):
+    prm = Params()
+    lib().amg_params_default(C.byref(prm))
+    for k, v in kw.items():
+        if not hasattr(prm, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(prm, k, int(v))
+    return prm
+
+
+def iga_poisson(d, p, n, want_F=True):
+    """Host CSR (int64 indptr, int32 indices, f64 data) of the Dirichlet-reduced
+    IgA Poisson stiffness matrix, and F for f = 1 (library's own generator)."""
+    N = C.c_int64(); nz = C.c_int64()
+    _check(lib().amg_iga_poisson_size(d, p, n, C.byref(N), C.byref(nz)))
+    rp = np.empty(N.value + 1, np.int64); ci = np.empty(nz.value, np.int32); v = np.empty(nz.value)
+    F = np.empty(N.value) if want_F else None
+    _check(lib().amg_iga_poisson(d, p, n, _p(rp, i64p), _p(ci, i32p), _p(v, f64p),
+                                 _p(F, f64p) if want_F else None))
+    return rp, ci, v, F
+
+
+def match(indptr, indices, data, w=None, positive_only=False):
+    rp = np.ascontiguousarray(indptr, np.int64); ci = np.ascontiguousarray(indices, np.int32)
+    v = np.ascontiguousarray(data, np.float64)
+    n = len(rp) - 1
+    wv = None if w is None else np.ascontiguousarray(w, np.float64)
+    mate = np.empty(n, np.int32)
+    _check(lib().amg_match(n, _p(rp, i64p), _p(ci, i32p), _p(v, f64p), _p(wv, f64p) if wv is not None else None,
+                           int(positive_only), _p(mate, i32p)))
+    return mate
+
+
+class Context:
+    """An amg_ctx: the hierarchy on host and device, and the solve calls."""
+
+    def __init__(self, indptr, indices, data, w=None, stream=None, host_only=False, **params):
+        rp = np.ascontiguousarray(indptr, np.int64); ci = np.ascontiguousarray(indices, np.int32)
+        v = np.ascontiguousarray(data, np.float64)
+        self.n = len(rp) - 1
+        self.prm = params_default(**params)
+        wv = None if w is None else np.ascontiguousarray(w, np.float64)
+        h = C.c_void_p()
+        wp = _p(wv, f64p) if wv is not None else None
+        if host_only:
+            st = lib().amg_setup_host(self.n, _p(rp, i64p), _p(ci, i32p), _p(v, f64p), wp, C.byref(self.prm),
+                                      C.byref(h))
+        else:
+            import torch
+            if stream is None:
+                stream = torch.cuda.current_stream()
+            self.stream = stream
+            st = lib().amg_setup(self.n, _p(rp, i64p), _p(ci, i32p), _p(v, f64p), wp, C.byref(self.prm),
+                                 C.c_void_p(stream.cuda_stream), C.byref(h))
+        _check(st)
+        self.h = h
+        self.host_only = host_only
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().amg_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- inspection --------------------------------------------------------
+    @property
+    def nlevels(self):
+        n = C.c_int64(); nz = C.c_int64()
+        _check(lib().amg_get_level_info(self.h, -1, C.byref(n), C.byref(nz)))
+        return n.value
+
+    def level_info(self, level):
+        n = C.c_int64(); nz = C.c_int64()
+        _check(lib().amg_get_level_info(self.h, level, C.byref(n), C.byref(nz)))
+        return n.value, nz.value
+
+    def opc(self):
+        n = C.c_int64(); nz = C.c_int64()
+        _check(lib().amg_get_level_info(self.h, -1, C.byref(n), C.byref(nz)))
+        return nz.value / self.level_info(0)[1]
+
+    def aggregates(self, level):
+        n, _ = self.level_info(level)
+        agg = np.empty(n, np.int32); pc = np.empty(n)
+        _check(lib().amg_get_aggregates(self.h, level, _p(agg, i32p), _p(pc, f64p)))
+        return agg, pc
+
+    def coarse_matrix(self, level):
+        n, nz = self.level_info(level)
+        rp = np.empty(n + 1, np.int64); ci = np.empty(nz, np.int32); v = np.empty(nz)
+        _check(lib().amg_get_coarse_matrix(self.h, level, _p(rp, i64p), _p(ci, i32p), _p(v, f64p)))
+        return rp, ci, v
+
+    def format(self, level=0):
+        sl = C.c_int(); stored = C.c_int64(); ib = C.c_int()
+        _check(lib().amg_get_format(self.h, level, C.byref(sl), C.byref(stored), C.byref(ib)))
+        return dict(slice=sl.value, stored=stored.value, index_bytes=ib.value)
+
+    def set_poly(self, level, coeffs):
+        c = np.ascontiguousarray(coeffs, np.float64)
+        return _check(lib().amg_set_poly_coeffs(self.h, level, _p(c, f64p)), allow=(AMG_OK, AMG_NOT_CONVERGED))
+
+    # ---- measurement ---------------------------------------------------------
+    def set_profiling(self, on):
+        _check(lib().amg_set_profiling(self.h, int(on)))
+
+    def profile(self):
+        n = C.c_int64(); ms = C.c_double(); by = C.c_double()
+        _check(lib().amg_get_profile(self.h, C.byref(n), C.byref(ms), C.byref(by)))
+        return dict(launches=n.value, ms=ms.value, bytes=by.value)
+
+    # ---- operators ---------------------------------------------------------------
+    def vcycle(self, r):
+        import torch
+        assert r.dtype == torch.float64 and r.is_cuda and r.is_contiguous() and r.numel() == self.n
+        z = torch.empty_like(r)
+        _check(lib().amg_vcycle(self.h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr())))
+        return z
+
+    def spmv(self, x, level=0):
+        import torch
+        n = self.level_info(level)[0]
+        assert x.dtype == torch.float64 and x.is_cuda and x.is_contiguous() and x.numel() == n
+        y = torch.empty_like(x)
+        _check(lib().amg_spmv(self.h, level, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())))
+        return y
+
+    # ---- solve ------------------------------------------------------------------
+    def solve(self, F, u=None, tol=1e-8, check=True):
+        """F: float64 device tensor (n,).  u: device tensor, initial guess (zeros
+        if None), overwritten with the solution.  Returns a dict."""
+        import torch
+        assert F.dtype == torch.float64 and F.is_cuda and F.is_contiguous() and F.numel() == self.n
+        if u is None:
+            u = torch.zeros_like(F)
+        assert u.dtype == torch.float64 and u.is_cuda and u.is_contiguous() and u.numel() == self.n
+        it = C.c_int(); rel = C.c_double(); relt = C.c_double()
+        st = lib().pcg_solve(self.h, C.c_void_p(F.data_ptr()), C.c_void_p(u.data_ptr()), float(tol),
+                             C.byref(it), C.byref(rel), C.byref(relt))
+        if check:
+            _check(st, allow=(AMG_OK, AMG_NOT_CONVERGED))
+        return dict(status=st, u=u, iters=it.value, relres=rel.value, relres_true=relt.value)
+
+    def solve_batched(self, F, U=None, tol=1e-8, check=True):
+        """F: (n, k) float64 device tensor in column-major order (a transposed
+        view of a contiguous (k, n) tensor), k <= 16."""
+        import torch
+        n, k = F.shape
+        assert n == self.n and F.dtype == torch.float64 and F.is_cuda
+        Ft = F.t().contiguous()          # (k, n) row-major == (n, k) column-major
+        Ut = torch.zeros_like(Ft) if U is None else U.t().contiguous()
+        its = (C.c_int * k)(); rel = np.empty(k)
+        st = lib().pcg_solve_batched(self.h, k, C.c_void_p(Ft.data_ptr()), C.c_void_p(Ut.data_ptr()), float(tol),
+                                     its, _p(rel, f64p))
+        if check:
+            _check(st, allow=(AMG_OK, AMG_NOT_CONVERGED))
+        return dict(status=st, U=Ut.t(), iters=list(its), relres=rel)

@@ -1,0 +1,87 @@
+// Host-side hierarchy of the matching-based AMG (paper Sec. 3.1) and the IgA
+// workload generator (Sec. 2).  Compiled by g++ with -ffp-contract=off: the
+// aggregates and Galerkin matrices are fixed to the bit by the evaluation order
+// written in host_setup.cpp.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace amgiga {
+
+struct Csr {
+    int64_t n = 0;
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci;
+    std::vector<double> v;
+    int64_t nnz() const { return rp.empty() ? 0 : rp[n]; }
+};
+
+// A borrowed CSR (the caller's arrays, or a Csr's).
+struct CsrView {
+    int64_t n = 0;
+    const int64_t *rp = nullptr;
+    const int32_t *ci = nullptr;
+    const double *v = nullptr;
+    int64_t nnz() const { return rp[n]; }
+};
+
+inline CsrView view(const Csr &a) { return CsrView{a.n, a.rp.data(), a.ci.data(), a.v.data()}; }
+
+struct SetupParams {
+    int sweeps = 2;
+    int max_coarse = 200;
+    int max_levels = 40;
+    int positive_only = 0;
+};
+
+struct HostLevel {
+    int64_t n = 0, nnz = 0;
+    Csr K;                       // Galerkin matrix (empty for level 0: caller's)
+    std::vector<double> invd;    // 1 / l1 diagonal
+    std::vector<double> w;       // test vector of this level
+    std::vector<int32_t> agg;    // coarse index of each row (not on coarsest)
+    std::vector<double> pc;      // prolongator coefficient of each row
+    int max_members = 0;         // largest aggregate size into the next level
+};
+
+struct HostHierarchy {
+    std::vector<HostLevel> lev;  // lev.back() is the coarsest (factored) level
+    std::vector<double> coarse_lower;  // dense n_L x n_L, lower triangle of K_L
+};
+
+// Status codes follow amg_status.
+int validate_csr(const CsrView &K, std::string &err);
+int build_hierarchy(const CsrView &K0, const double *w, const SetupParams &prm,
+                    HostHierarchy &H, std::string &err);
+
+// Pieces exposed for the unit tests of the library's own setup.
+double cij(double kij, double kii, double kjj, double wi, double wj);
+void suitor_match(const CsrView &K, const double *w, int positive_only, int32_t *mate);
+
+// Workload generator.
+void iga_size(int d, int p, int n, int64_t *N, int64_t *nnz);
+int iga_poisson(int d, int p, int n, int64_t *rp, int32_t *ci, double *v, double *F);
+
+// Runs f(begin, end) over [0, n) split in contiguous chunks on host threads.
+template <class F> void parallel_for(int64_t n, F f);
+
+}  // namespace amgiga
+
+#include <thread>
+namespace amgiga {
+int host_threads();
+template <class F> void parallel_for(int64_t n, F f)
+{
+    int nt = host_threads();
+    if (n < 4096 || nt <= 1) { f((int64_t)0, n); return; }
+    std::vector<std::thread> th;
+    int64_t chunk = (n + nt - 1) / nt;
+    for (int t = 0; t < nt; t++) {
+        int64_t b = t * chunk, e = b + chunk < n ? b + chunk : n;
+        if (b >= e) break;
+        th.emplace_back([=]() { f(b, e); });
+    }
+    for (auto &x : th) x.join();
+}
+}  // namespace amgiga

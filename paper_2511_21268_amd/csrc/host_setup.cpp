@@ -1,0 +1,523 @@
+// Host construction of the AMG hierarchy by compatible weighted matching
+// (paper Sec. 3.1) and the IgA workload generator (Sec. 2).
+//
+// Per level, m pairwise sweeps are composed (the m-step aggregation of
+// Sec. 3.1, P = P1 P2 ... Pm).  Each sweep:
+//   1. edge weights c_ij of eq. (cij) with the stored k_ij of row min(i,j);
+//   2. the greedy matching of eq. (maxprod)'s linear-time approximation, taken
+//      in the strict order (c descending, min index, max index), computed here
+//      by the suitor algorithm (Manne & Halappanavar), which yields the same
+//      matching as the sorted greedy scan for a strict total order, without a
+//      global sort;
+//   3. coarse numbering by the smallest member, pairwise prolongator of
+//      eq. (prolongation), restricted test vector;
+//   4. Galerkin product of eq. (galerkin_matrix_projection), row-parallel with a
+//      fixed per-row summation order (members ascending, entries ascending).
+// Every floating-point expression is written with explicit association and the
+// file is compiled without FMA contraction, so that two implementations of the
+// same readings agree to the bit.
+#include "host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+namespace amgiga {
+
+int host_threads()
+{
+    unsigned h = std::thread::hardware_concurrency();
+    if (h == 0) h = 1;
+    if (h > 32) h = 32;
+    return (int)h;
+}
+
+double cij(double kij, double kii, double kjj, double wi, double wj)
+{
+    double num = ((2.0 * kij) * wi) * wj;
+    double den = (kii * wi) * wi + (kjj * wj) * wj;
+    return 1.0 - num / den;
+}
+
+static int64_t find_in_row(const CsrView &K, int64_t row, int32_t col)
+{
+    const int32_t *b = K.ci + K.rp[row], *e = K.ci + K.rp[row + 1];
+    const int32_t *p = std::lower_bound(b, e, col);
+    if (p == e || *p != col) return -1;
+    return (int64_t)(p - K.ci);
+}
+
+int validate_csr(const CsrView &K, std::string &err)
+{
+    if (K.n <= 0 || K.n > 2147483647LL) { err = "n must be in 1 .. 2^31-1"; return -1; }
+    if (!K.rp || !K.ci || !K.v) { err = "NULL CSR array"; return -1; }
+    if (K.rp[0] != 0) { err = "row_ptr[0] must be 0"; return -1; }
+    for (int64_t i = 0; i < K.n; i++)
+        if (K.rp[i + 1] < K.rp[i]) { err = "row_ptr not monotone"; return -1; }
+    // each chunk records its first failing row and the reason
+    std::vector<std::pair<int64_t, int>> fails;
+    std::mutex mx;
+    parallel_for(K.n, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; i++) {
+            int code = 0;
+            bool diag = false;
+            for (int64_t k = K.rp[i]; k < K.rp[i + 1] && !code; k++) {
+                int32_t j = K.ci[k];
+                if (j < 0 || j >= K.n) code = 1;
+                else if (k > K.rp[i] && j <= K.ci[k - 1]) code = 2;
+                else if (!std::isfinite(K.v[k])) code = 3;
+                else if (j == i) { diag = true; if (!(K.v[k] > 0.0)) code = 4; }
+                else {
+                    int64_t t = find_in_row(K, j, (int32_t)i);
+                    if (t < 0) code = 5;
+                    else if (!(K.v[t] == K.v[k])) code = 6;
+                }
+            }
+            if (!code && !diag) code = 4;
+            if (code) {
+                std::lock_guard<std::mutex> g(mx);
+                fails.push_back({i, code});
+                return;
+            }
+        }
+    });
+    if (!fails.empty()) {
+        std::sort(fails.begin(), fails.end());
+        static const char *msg[] = {"", "column index out of range", "columns not strictly ascending",
+                                    "non-finite value", "missing or non-positive diagonal",
+                                    "pattern not symmetric", "values not symmetric"};
+        err = std::string(msg[fails[0].second]) + " in row " + std::to_string(fails[0].first);
+        return -1;
+    }
+    return 0;
+}
+
+// c of every stored off-diagonal entry, taken from row min(i,j); NaN marks an
+// ineligible entry (diagonal, zero value, non-finite c, or c <= 1 when only
+// positive log-weights are eligible).
+static std::vector<double> edge_weights(const CsrView &K, const double *w, int positive_only)
+{
+    std::vector<double> diag(K.n), c(K.nnz());
+    parallel_for(K.n, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; i++) {
+            double d = 0.0;
+            for (int64_t k = K.rp[i]; k < K.rp[i + 1]; k++)
+                if (K.ci[k] == i) d = K.v[k];
+            diag[i] = d;
+        }
+    });
+    parallel_for(K.n, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; i++) {
+            for (int64_t k = K.rp[i]; k < K.rp[i + 1]; k++) {
+                int64_t j = K.ci[k];
+                double val = NAN;
+                if (j != i) {
+                    double kv;
+                    if (i < j) kv = K.v[k];
+                    else {
+                        int64_t t = find_in_row(K, j, (int32_t)i);
+                        kv = t >= 0 ? K.v[t] : 0.0;
+                    }
+                    if (kv != 0.0) {
+                        int64_t a = i < j ? i : j, bb = i < j ? j : i;
+                        double cv = cij(kv, diag[a], diag[bb], w[a], w[bb]);
+                        bool ok = std::isfinite(cv) && (!positive_only || cv > 1.0);
+                        if (ok) val = cv;
+                    }
+                }
+                c[k] = val;
+            }
+        }
+    });
+    return c;
+}
+
+// Edge (c, a, b) precedes (c2, a2, b2) in the matching order; a < b, a2 < b2.
+static inline bool precedes(double c, int64_t a, int64_t b, double c2, int64_t a2, int64_t b2)
+{
+    if (c != c2) return c > c2;
+    if (a != a2) return a < a2;
+    return b < b2;
+}
+
+// Suitor algorithm: every vertex proposes to the neighbour whose edge is best
+// in the order among those that would accept it (its current suitor's edge is
+// worse); a displaced suitor proposes again.  On termination the suitor
+// relation is mutual on the matched pairs and equals the greedy matching.
+static void suitor_core(const CsrView &K, const std::vector<double> &c, int32_t *mate)
+{
+    int64_t n = K.n;
+    std::vector<int32_t> suitor(n, -1);
+    std::vector<double> ws(n, 0.0);
+    for (int64_t u = 0; u < n; u++) {
+        int64_t cur = u;
+        while (cur >= 0) {
+            int64_t best = -1;
+            double bc = 0.0;
+            int64_t ba = 0, bb = 0;
+            for (int64_t k = K.rp[cur]; k < K.rp[cur + 1]; k++) {
+                double cv = c[k];
+                if (cv != cv) continue;
+                int64_t v = K.ci[k];
+                int64_t a = cur < v ? cur : v, b = cur < v ? v : cur;
+                if (best >= 0 && !precedes(cv, a, b, bc, ba, bb)) continue;
+                int64_t s = suitor[v];
+                if (s >= 0) {
+                    int64_t sa = s < v ? s : v, sb = s < v ? v : s;
+                    if (!precedes(cv, a, b, ws[v], sa, sb)) continue;
+                }
+                best = v; bc = cv; ba = a; bb = b;
+            }
+            if (best < 0) break;
+            int64_t y = suitor[best];
+            suitor[best] = (int32_t)cur;
+            ws[best] = bc;
+            cur = y;
+        }
+    }
+    for (int64_t v = 0; v < n; v++) {
+        int64_t s = suitor[v];
+        mate[v] = (s >= 0 && suitor[s] == v) ? (int32_t)s : -1;
+    }
+}
+
+void suitor_match(const CsrView &K, const double *w, int positive_only, int32_t *mate)
+{
+    std::vector<double> c = edge_weights(K, w, positive_only);
+    suitor_core(K, c, mate);
+}
+
+// Coarse numbering by the smallest member; pairwise prolongator and restricted
+// test vector (eq. (prolongation)).
+static int64_t pairwise(int64_t n, const int32_t *mate, const double *w, std::vector<int32_t> &agg,
+                        std::vector<double> &pc, std::vector<double> &wc)
+{
+    agg.assign(n, -1);
+    pc.assign(n, 0.0);
+    int64_t nc = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (agg[i] >= 0) continue;
+        agg[i] = (int32_t)nc;
+        if (mate[i] >= 0) agg[mate[i]] = (int32_t)nc;
+        nc++;
+    }
+    wc.assign(nc, 0.0);
+    for (int64_t i = 0; i < n; i++) {
+        int64_t j = mate[i];
+        if (j >= 0) {
+            double s = std::sqrt(w[i] * w[i] + w[j] * w[j]);
+            pc[i] = w[i] / s;
+            wc[agg[i]] = s;
+        } else {
+            pc[i] = (w[i] != 0.0) ? w[i] / std::fabs(w[i]) : 1.0;
+            wc[agg[i]] = std::fabs(w[i]);
+        }
+    }
+    return nc;
+}
+
+// Galerkin product for a one-entry-per-row prolongator, parallel over coarse
+// rows; within a coarse row the sum order is members ascending, then each
+// member's stored entries ascending, from +0.0.
+static Csr galerkin(const CsrView &K, int64_t nc, const std::vector<int32_t> &agg,
+                    const std::vector<double> &pc)
+{
+    int64_t n = K.n;
+    std::vector<int64_t> mp(nc + 1, 0), mem(n);
+    for (int64_t i = 0; i < n; i++) mp[agg[i] + 1]++;
+    for (int64_t I = 0; I < nc; I++) mp[I + 1] += mp[I];
+    {
+        std::vector<int64_t> fill(mp.begin(), mp.end() - 1);
+        for (int64_t i = 0; i < n; i++) mem[fill[agg[i]]++] = i;
+    }
+    Csr C;
+    C.n = nc;
+    C.rp.assign(nc + 1, 0);
+    // pass 1: distinct coarse columns per coarse row
+    parallel_for(nc, [&](int64_t b, int64_t e) {
+        std::vector<int64_t> stamp(nc, -1);
+        for (int64_t I = b; I < e; I++) {
+            int64_t cnt = 0;
+            for (int64_t m = mp[I]; m < mp[I + 1]; m++) {
+                int64_t i = mem[m];
+                for (int64_t k = K.rp[i]; k < K.rp[i + 1]; k++) {
+                    int32_t J = agg[K.ci[k]];
+                    if (stamp[J] != I) { stamp[J] = I; cnt++; }
+                }
+            }
+            C.rp[I + 1] = cnt;
+        }
+    });
+    for (int64_t I = 0; I < nc; I++) C.rp[I + 1] += C.rp[I];
+    C.ci.resize(C.rp[nc]);
+    C.v.resize(C.rp[nc]);
+    // pass 2: accumulate
+    parallel_for(nc, [&](int64_t b, int64_t e) {
+        std::vector<int64_t> stamp(nc, -1);
+        std::vector<double> acc(nc);
+        std::vector<int32_t> touched;
+        for (int64_t I = b; I < e; I++) {
+            touched.clear();
+            for (int64_t m = mp[I]; m < mp[I + 1]; m++) {
+                int64_t i = mem[m];
+                double pi = pc[i];
+                for (int64_t k = K.rp[i]; k < K.rp[i + 1]; k++) {
+                    int64_t j = K.ci[k];
+                    int32_t J = agg[j];
+                    double t = (pi * K.v[k]) * pc[j];
+                    if (stamp[J] != I) { stamp[J] = I; acc[J] = 0.0; touched.push_back(J); }
+                    acc[J] = acc[J] + t;
+                }
+            }
+            std::sort(touched.begin(), touched.end());
+            int64_t pos = C.rp[I];
+            for (int32_t J : touched) { C.ci[pos] = J; C.v[pos] = acc[J]; pos++; }
+        }
+    });
+    return C;
+}
+
+static void l1_invdiag(const CsrView &K, std::vector<double> &invd)
+{
+    invd.resize(K.n);
+    parallel_for(K.n, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; i++) {
+            double d = 0.0;
+            for (int64_t k = K.rp[i]; k < K.rp[i + 1]; k++)
+                if (K.ci[k] == i) d = K.v[k];
+            for (int64_t k = K.rp[i]; k < K.rp[i + 1]; k++)
+                if (K.ci[k] != i) d = d + std::fabs(K.v[k]);
+            invd[i] = 1.0 / d;
+        }
+    });
+}
+
+static void make_coarsest(HostHierarchy &H, const CsrView &K)
+{
+    int64_t n = K.n;
+    H.coarse_lower.assign((size_t)(n * n), 0.0);
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t k = K.rp[i]; k < K.rp[i + 1]; k++)
+            if (K.ci[k] <= i) H.coarse_lower[(size_t)(i * n + K.ci[k])] = K.v[k];
+}
+
+int build_hierarchy(const CsrView &K0, const double *w, const SetupParams &prm,
+                    HostHierarchy &H, std::string &err)
+{
+    int maxl = prm.max_levels > 0 ? prm.max_levels : 1;
+    H.lev.clear();
+    H.lev.emplace_back();
+    {
+        HostLevel &L0 = H.lev[0];
+        L0.n = K0.n;
+        L0.nnz = K0.nnz();
+        L0.w.resize(K0.n);
+        for (int64_t i = 0; i < K0.n; i++) L0.w[i] = w ? w[i] : 1.0;
+        l1_invdiag(K0, L0.invd);
+    }
+    for (int l = 0;; l++) {
+        CsrView K = l == 0 ? K0 : view(H.lev[l].K);
+        int64_t nl = H.lev[l].n;
+        if (nl <= prm.max_coarse) { make_coarsest(H, K); return 0; }
+        if (l == maxl - 1) {
+            if (nl <= 2000) { make_coarsest(H, K); return 0; }
+            err = "coarsening reached max_levels above 2000 unknowns";
+            return -6;
+        }
+        std::vector<int32_t> agg(nl);
+        std::vector<double> pc(nl);
+        Csr cur;
+        std::vector<double> cw;
+        const double *wl = H.lev[l].w.data();
+        int64_t nc = nl;
+        for (int s = 0; s < prm.sweeps; s++) {
+            CsrView kv = s == 0 ? K : view(cur);
+            const double *ww = s == 0 ? wl : cw.data();
+            std::vector<int32_t> mate(kv.n);
+            suitor_match(kv, ww, prm.positive_only, mate.data());
+            std::vector<int32_t> ag;
+            std::vector<double> pcs, wc;
+            nc = pairwise(kv.n, mate.data(), ww, ag, pcs, wc);
+            Csr C = galerkin(kv, nc, ag, pcs);
+            if (s == 0) {
+                agg = ag;
+                pc = pcs;
+            } else {
+                for (int64_t i = 0; i < nl; i++) {
+                    pc[i] = pc[i] * pcs[agg[i]];
+                    agg[i] = ag[agg[i]];
+                }
+            }
+            cur = std::move(C);
+            cw = std::move(wc);
+        }
+        if ((double)nc > 0.9 * (double)nl) {
+            if (nl <= 2000) { make_coarsest(H, K); return 0; }
+            err = "coarsening stalled above 2000 unknowns";
+            return -6;
+        }
+        HostLevel &L = H.lev[l];
+        L.agg = std::move(agg);
+        L.pc = std::move(pc);
+        {
+            std::vector<int> cnt(nc, 0);
+            for (int64_t i = 0; i < nl; i++) cnt[L.agg[i]]++;
+            L.max_members = *std::max_element(cnt.begin(), cnt.end());
+        }
+        HostLevel next;
+        next.n = cur.n;
+        next.nnz = cur.nnz();
+        next.K = std::move(cur);
+        next.w = std::move(cw);
+        l1_invdiag(view(next.K), next.invd);
+        H.lev.push_back(std::move(next));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Workload generator: 1D B-spline matrices by Gauss quadrature, then the
+// Kronecker sum.  Basis values by the triangular (de Boor) scheme.
+
+static void gauss_nodes(int q, double *x, double *w)
+{
+    for (int k = 0; k < q; k++) {
+        double z = std::cos(M_PI * (2.0 * k + 1.0) / (2.0 * q));
+        for (int it = 0; it < 100; it++) {
+            double a = 1.0, b = z;          // P_0, P_1
+            for (int j = 2; j <= q; j++) { double c = ((2 * j - 1) * z * b - (j - 1) * a) / j; a = b; b = c; }
+            if (q == 1) { a = 1.0; b = z; }
+            double dp = q * (a - z * b) / (1.0 - z * z);
+            double dz = b / dp;
+            z -= dz;
+            if (std::fabs(dz) <= 1e-17) break;
+        }
+        double a = 1.0, b = z;
+        for (int j = 2; j <= q; j++) { double c = ((2 * j - 1) * z * b - (j - 1) * a) / j; a = b; b = c; }
+        if (q == 1) { a = 1.0; b = z; }
+        double dp = q * (a - z * b) / (1.0 - z * z);
+        x[q - 1 - k] = z;
+        w[q - 1 - k] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Values N[0..p] and derivatives D[0..p] of the p+1 functions nonzero on knot
+// span s at x (triangular scheme with left/right knot distances).
+static void span_basis(const std::vector<double> &t, int s, int p, double x, double *N, double *D)
+{
+    double left[16], right[16], ndu[16][16];
+    ndu[0][0] = 1.0;
+    for (int j = 1; j <= p; j++) {
+        left[j] = x - t[s + 1 - j];
+        right[j] = t[s + j] - x;
+        double saved = 0.0;
+        for (int r = 0; r < j; r++) {
+            ndu[j][r] = right[r + 1] + left[j - r];      // lower triangle: knot differences
+            double tmp = ndu[r][j - 1] / ndu[j][r];
+            ndu[r][j] = saved + right[r + 1] * tmp;
+            saved = left[j - r] * tmp;
+        }
+        ndu[j][j] = saved;
+    }
+    for (int r = 0; r <= p; r++) N[r] = ndu[r][p];
+    // first derivative from the degree p-1 values
+    for (int r = 0; r <= p; r++) {
+        double d = 0.0;
+        if (r >= 1) d += ndu[r - 1][p - 1] / ndu[p][r - 1];
+        if (r <= p - 1) d -= ndu[r][p - 1] / ndu[p][r];
+        D[r] = p * d;
+    }
+}
+
+static void matrices_1d(int p, int n, std::vector<double> &M, std::vector<double> &K,
+                        std::vector<double> &Fi)
+{
+    int m = n + p;
+    std::vector<double> t(n + 2 * p + 1);
+    for (int i = 0; i <= p; i++) { t[i] = 0.0; t[n + p + i] = 1.0; }
+    for (int k = 1; k < n; k++) t[p + k] = (double)k / (double)n;
+    double xg[16], wg[16];
+    gauss_nodes(p + 1, xg, wg);
+    M.assign((size_t)m * m, 0.0);
+    K.assign((size_t)m * m, 0.0);
+    Fi.assign(m, 0.0);
+    for (int e = 0; e < n; e++) {
+        int s = p + e;
+        double a = t[s], h = t[s + 1] - t[s];
+        for (int q = 0; q <= p; q++) {
+            double x = a + 0.5 * (xg[q] + 1.0) * h, wq = 0.5 * wg[q] * h;
+            double N[16], D[16];
+            span_basis(t, s, p, x, N, D);
+            for (int i = 0; i <= p; i++) {
+                Fi[s - p + i] += wq * N[i];
+                for (int j = 0; j <= p; j++) {
+                    M[(size_t)(s - p + i) * m + (s - p + j)] += wq * (N[i] * N[j]);
+                    K[(size_t)(s - p + i) * m + (s - p + j)] += wq * (D[i] * D[j]);
+                }
+            }
+        }
+    }
+}
+
+void iga_size(int d, int p, int n, int64_t *N, int64_t *nnz)
+{
+    int64_t md = n + p - 2;
+    int64_t b = 0;
+    for (int64_t i = 0; i < md; i++) {
+        int64_t lo = i - p < 0 ? 0 : i - p, hi = i + p > md - 1 ? md - 1 : i + p;
+        b += hi - lo + 1;
+    }
+    int64_t nn = 1, nz = 1;
+    for (int k = 0; k < d; k++) { nn *= md; nz *= b; }
+    *N = nn;
+    *nnz = nz;
+}
+
+int iga_poisson(int d, int p, int n, int64_t *rp, int32_t *ci, double *v, double *F)
+{
+    if (d < 2 || d > 3 || p < 1 || p > 10 || n < 1 || n + p - 2 < 1) return -1;
+    int m = n + p, md = m - 2;
+    std::vector<double> M, K, Fi;
+    matrices_1d(p, n, M, K, Fi);
+    auto M1 = [&](int a, int b) { return M[(size_t)(a + 1) * m + (b + 1)]; };
+    auto K1 = [&](int a, int b) { return K[(size_t)(a + 1) * m + (b + 1)]; };
+    auto len1 = [&](int i) { int lo = i - p < 0 ? 0 : i - p, hi = i + p > md - 1 ? md - 1 : i + p; return hi - lo + 1; };
+    int64_t N = 1;
+    for (int k = 0; k < d; k++) N *= md;
+    // row pointer: row length is the product of the 1D lengths
+    rp[0] = 0;
+    for (int64_t g = 0; g < N; g++) {
+        int ix = (int)(g % md), iy = (int)((g / md) % md), iz = d == 3 ? (int)(g / ((int64_t)md * md)) : 0;
+        int64_t len = (int64_t)len1(ix) * len1(iy) * (d == 3 ? len1(iz) : 1);
+        rp[g + 1] = rp[g] + len;
+    }
+    parallel_for(N, [&](int64_t b, int64_t e) {
+        for (int64_t g = b; g < e; g++) {
+            int ix = (int)(g % md), iy = (int)((g / md) % md), iz = d == 3 ? (int)(g / ((int64_t)md * md)) : 0;
+            int64_t pos = rp[g];
+            int zlo = d == 3 ? std::max(0, iz - p) : 0, zhi = d == 3 ? std::min(md - 1, iz + p) : 0;
+            int ylo = std::max(0, iy - p), yhi = std::min(md - 1, iy + p);
+            int xlo = std::max(0, ix - p), xhi = std::min(md - 1, ix + p);
+            for (int jz = zlo; jz <= zhi; jz++)
+                for (int jy = ylo; jy <= yhi; jy++)
+                    for (int jx = xlo; jx <= xhi; jx++) {
+                        double val;
+                        if (d == 2) {
+                            val = K1(iy, jy) * M1(ix, jx) + M1(iy, jy) * K1(ix, jx);
+                        } else {
+                            double a = (K1(iz, jz) * M1(iy, jy)) * M1(ix, jx);
+                            double bb = (M1(iz, jz) * K1(iy, jy)) * M1(ix, jx);
+                            double c = (M1(iz, jz) * M1(iy, jy)) * K1(ix, jx);
+                            val = (a + bb) + c;
+                        }
+                        ci[pos] = (int32_t)(jx + (int64_t)md * (jy + (int64_t)md * jz));
+                        v[pos] = val;
+                        pos++;
+                    }
+            if (F) F[g] = d == 2 ? Fi[iy + 1] * Fi[ix + 1] : (Fi[iz + 1] * Fi[iy + 1]) * Fi[ix + 1];
+        }
+    });
+    return 0;
+}
+
+}  // namespace amgiga

@@ -1,0 +1,368 @@
+// Device kernels of the solve phase (gfx950, wave64).
+//
+// Sparse matrices are held in a sliced-ELL layout (SELL-C with C = 64 rows per
+// slice, one slice per wavefront, lane = row): each slice stores width w_s
+// entries per row (w_s = the slice's longest row, rounded up to 8), column-major
+// across the 64 rows so that every load of the wave is one contiguous run.
+// Entries are interleaved in groups of G per lane so that each lane issues
+// 16-byte loads: element (k, lane) of a slice starting at element `base` lives at
+//     base + (k / G) * 64 * G + lane * G + (k % G),
+// with G = 2 for FP64 values, 4 for FP32 values and int32 columns, and 8 for
+// 16-bit column deltas.  A lane walks its row in ascending column order; with
+// 16-bit deltas the column is a running sum starting at col0[row] (the row's
+// first column), so the index stream costs 2 bytes per entry.  Padding entries
+// hold value 0 and delta 0.
+//
+// Every reduction is deterministic: fixed grid, butterfly within the wave, a
+// fixed-order sum across the block's waves, one partial per block, and a
+// single-block final sum in index order.  No floating-point atomics.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace amgk {
+
+typedef double vd2 __attribute__((ext_vector_type(2)));
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef unsigned vu4 __attribute__((ext_vector_type(4)));
+typedef int vi4 __attribute__((ext_vector_type(4)));
+
+constexpr int SLICE = 64;
+constexpr int SELL_WAVES = 4;          // slices (wavefronts) per 256-thread block
+constexpr int RED_THREADS = 256;
+
+enum Epi { EPI_SPMV = 0, EPI_RESID = 1, EPI_SMOOTH = 2, EPI_POLY = 3 };
+
+// scalar slots of the solver's device scalar array
+enum Slot { S_RZ = 0, S_PQ, S_RR, S_ALPHA, S_BETA, S_PR, S_ZQ, S_FF, S_FLAG, S_TMP, S_NSLOTS = 16 };
+enum FinOp { FIN_STORE = 0, FIN_PQ_CG, FIN_PQ_FCG, FIN_RZ_CG, FIN_ZQ_FCG, FIN_RZ0 };
+
+__device__ inline double wave_sum(double v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum of one value per thread over a 256-thread block, in a fixed order;
+// the result is valid in thread 0.
+__device__ inline double block_sum(double v, double *lds)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) s = ((lds[0] + lds[1]) + lds[2]) + lds[3];
+    return s;
+}
+
+// ---- loads of 8 consecutive entries (k .. k+7) of one lane -------------------
+
+__device__ inline void load8(const double *__restrict__ val, int64_t base, int kk, int lane, double v[8])
+{
+    const vd2 *p = reinterpret_cast<const vd2 *>(val + base) + (int64_t)(kk >> 1) * SLICE + lane;
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        vd2 t = __builtin_nontemporal_load(p + c * SLICE);
+        v[2 * c] = t.x;
+        v[2 * c + 1] = t.y;
+    }
+}
+
+__device__ inline void load8(const float *__restrict__ val, int64_t base, int kk, int lane, float v[8])
+{
+    const vf4 *p = reinterpret_cast<const vf4 *>(val + base) + (int64_t)(kk >> 2) * SLICE + lane;
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        vf4 t = __builtin_nontemporal_load(p + c * SLICE);
+        v[4 * c] = t.x; v[4 * c + 1] = t.y; v[4 * c + 2] = t.z; v[4 * c + 3] = t.w;
+    }
+}
+
+// 16-bit deltas: one 16-byte load holds the 8 deltas of entries kk .. kk+7.
+__device__ inline void load_idx8(const uint16_t *__restrict__ d16, int64_t base, int kk, int lane, int &col,
+                                 int c[8])
+{
+    const vu4 *p = reinterpret_cast<const vu4 *>(d16 + base) + (int64_t)(kk >> 3) * SLICE + lane;
+    vu4 t = __builtin_nontemporal_load(p);
+    unsigned w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        col += (int)(w[q] & 0xffffu);
+        c[2 * q] = col;
+        col += (int)(w[q] >> 16);
+        c[2 * q + 1] = col;
+    }
+}
+
+__device__ inline void load_idx8(const int32_t *__restrict__ c32, int64_t base, int kk, int lane, int &col,
+                                 int c[8])
+{
+    const vi4 *p = reinterpret_cast<const vi4 *>(c32 + base) + (int64_t)(kk >> 2) * SLICE + lane;
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        vi4 t = __builtin_nontemporal_load(p + h * SLICE);
+        c[4 * h] = t.x; c[4 * h + 1] = t.y; c[4 * h + 2] = t.z; c[4 * h + 3] = t.w;
+    }
+    col = c[7];
+}
+
+// ---- the sparse matrix-pass kernel -------------------------------------------
+//
+// acc = (K x)_row, then by epilogue:
+//   EPI_SPMV  : y = acc;                   dots: (x, y), (x, g1)
+//   EPI_RESID : y = f - acc
+//   EPI_SMOOTH: y = x + invd (f - acc);    dots: (y, g0), (y, g1)
+//   EPI_POLY  : y = a invd f + invd acc    (a = coef; one Horner step of the
+//               polynomial smoother: c <- a D^{-1} r + D^{-1} K c)
+// VT: matrix, x and invd type; FT: type of f; OT: type of y; IT: index stream
+// (uint16_t deltas or int32_t columns).  NDOT dots are accumulated in FP64 and
+// written as one partial per block to partial[blockIdx.x * 2 + d].
+template <typename VT, typename FT, typename OT, typename IT, int EPI, int NDOT>
+__global__ __launch_bounds__(256) void k_sell(int64_t nrows, int64_t nslices, const int64_t *__restrict__ soff,
+                                              const VT *__restrict__ val, const IT *__restrict__ idx,
+                                              const int32_t *__restrict__ col0, const VT *__restrict__ x,
+                                              const FT *__restrict__ f, const VT *__restrict__ invd,
+                                              OT *__restrict__ y, const double *__restrict__ g0,
+                                              const double *__restrict__ g1, double *__restrict__ partial,
+                                              VT coef)
+{
+    __shared__ double lds[8];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t s = (int64_t)blockIdx.x * SELL_WAVES + wid;
+    double d0 = 0.0, d1 = 0.0;
+    if (s < nslices) {
+        const int64_t row = s * SLICE + lane;
+        const int64_t base = soff[s];
+        const int width = (int)((soff[s + 1] - base) >> 6);
+        int col = (sizeof(IT) == 2) ? col0[row] : 0;
+        VT acc = 0;
+        for (int kk = 0; kk < width; kk += 8) {
+            VT v[8];
+            int c[8];
+            load_idx8(idx, base, kk, lane, col, c);
+            load8(val, base, kk, lane, v);
+#pragma unroll
+            for (int t = 0; t < 8; t++) acc = fma(v[t], x[c[t]], acc);
+        }
+        if (row < nrows) {
+            if (EPI == EPI_SPMV) {
+                y[row] = (OT)acc;
+                if (NDOT >= 1) d0 = (double)x[row] * (double)acc;
+                if (NDOT >= 2) d1 = (double)x[row] * g1[row];
+            } else if (EPI == EPI_RESID) {
+                y[row] = (OT)((VT)f[row] - acc);
+            } else if (EPI == EPI_SMOOTH) {
+                VT out = x[row] + invd[row] * ((VT)f[row] - acc);
+                y[row] = (OT)out;
+                if (NDOT >= 1) d0 = (double)out * g0[row];
+                if (NDOT >= 2) d1 = (double)out * g1[row];
+            } else {
+                VT di = invd[row];
+                y[row] = (OT)(coef * (di * (VT)f[row]) + di * acc);
+            }
+        }
+    }
+    if (NDOT >= 1) {
+        double t0 = block_sum(d0, lds);
+        double t1 = NDOT >= 2 ? block_sum(d1, lds + 4) : 0.0;
+        if (threadIdx.x == 0) {
+            partial[2 * blockIdx.x] = t0;
+            partial[2 * blockIdx.x + 1] = t1;
+        }
+    }
+}
+
+// ---- vector kernels ----------------------------------------------------------
+
+// u = invd * f  (one smoothing sweep from the zero guess: K 0 = 0)
+template <typename VT, typename FT>
+__global__ void k_scale(int64_t n, const VT *__restrict__ invd, const FT *__restrict__ f, VT *__restrict__ u)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) u[i] = invd[i] * (VT)f[i];
+}
+
+// u = coef * invd * f  (first Horner step of the polynomial smoother from zero)
+template <typename VT, typename FT>
+__global__ void k_scale_coef(int64_t n, const VT *__restrict__ invd, const FT *__restrict__ f, VT *__restrict__ u,
+                             VT coef)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) u[i] = coef * (invd[i] * (VT)f[i]);
+}
+
+// y = x + c   (smoother correction), written in the output type
+template <typename VT, typename OT>
+__global__ void k_add(int64_t n, const VT *__restrict__ x, const VT *__restrict__ c, OT *__restrict__ y)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (OT)(x[i] + c[i]);
+}
+
+// Restriction f_c = P^T r over the members of each coarse row (ascending, at
+// most mw, padded with -1), fused with the coarse level's zero-guess smoothing
+// sweep u_c = invd_c * f_c when uc != nullptr.  Sum order is fixed and no
+// contraction is applied: f_c is the same bits as a sequential P^T r.
+template <typename VT>
+__global__ void k_restrict(int64_t nc, int mw, const int32_t *__restrict__ members, const VT *__restrict__ pc,
+                           const VT *__restrict__ r, VT *__restrict__ fc, const VT *__restrict__ invdc,
+                           VT *__restrict__ uc, VT coef)
+{
+#pragma clang fp contract(off)
+    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    VT s = 0;
+    for (int t = 0; t < mw; t++) {
+        int m = members[I * mw + t];
+        if (m < 0) break;
+        VT prod = pc[m] * r[m];
+        s = s + prod;
+    }
+    fc[I] = s;
+    if (uc) uc[I] = coef * (invdc[I] * s);
+}
+
+// Prolongation and correction u_i += pc_i e[agg_i] (no contraction).
+template <typename VT>
+__global__ void k_prolong(int64_t n, const int32_t *__restrict__ agg, const VT *__restrict__ pc,
+                          const VT *__restrict__ e, VT *__restrict__ u)
+{
+#pragma clang fp contract(off)
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    VT prod = pc[i] * e[agg[i]];
+    u[i] = u[i] + prod;
+}
+
+// Coarsest level: e = L^{-T} (L^{-1} f) with the precomputed inverse Cholesky
+// factor (row-major, leading dimension ld) and its transpose; FP64 arithmetic
+// whatever the level type.  One 256-thread block, n <= 2048.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_coarse_solve(int n, int ld, const double *__restrict__ Linv,
+                                                      const double *__restrict__ LinvT, const VT *__restrict__ f,
+                                                      VT *__restrict__ e)
+{
+    __shared__ double fs[2048];
+    __shared__ double ys[2048];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < n; i += 256) fs[i] = (double)f[i];
+    __syncthreads();
+    for (int i = wid; i < n; i += 4) {
+        const double *row = Linv + (int64_t)i * ld;
+        double s = 0.0;
+        for (int k = lane; k <= i; k += 64) s = fma(row[k], fs[k], s);
+        s = wave_sum(s);
+        if (lane == 0) ys[i] = s;
+    }
+    __syncthreads();
+    for (int j = wid; j < n; j += 4) {
+        const double *row = LinvT + (int64_t)j * ld;
+        double s = 0.0;
+        for (int k = j + lane; k < n; k += 64) s = fma(row[k], ys[k], s);
+        s = wave_sum(s);
+        if (lane == 0) e[j] = (VT)s;
+    }
+}
+
+// Dot-product partials: one per block of a fixed grid (grid-stride).
+__global__ void k_dot2(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                       const double *__restrict__ c, double *__restrict__ partial)
+{
+    __shared__ double lds[8];
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        s0 = fma(a[i], b[i], s0);
+        if (c) s1 = fma(a[i], c[i], s1);
+    }
+    double t0 = block_sum(s0, lds), t1 = block_sum(s1, lds + 4);
+    if (threadIdx.x == 0) { partial[2 * blockIdx.x] = t0; partial[2 * blockIdx.x + 1] = t1; }
+}
+
+// u += alpha p ; r -= alpha q ; partials of (r, r).  Skipped once a breakdown
+// flag is set (so u keeps the last valid iterate).
+__global__ void k_cg_update(int64_t n, const double *__restrict__ sc, double *__restrict__ u,
+                            double *__restrict__ r, const double *__restrict__ p, const double *__restrict__ q,
+                            double *__restrict__ partial)
+{
+    __shared__ double lds[8];
+    const bool skip = sc[S_FLAG] != 0.0;
+    const double alpha = sc[S_ALPHA];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double ri = r[i];
+        if (!skip) {
+            u[i] = fma(alpha, p[i], u[i]);
+            ri = fma(-alpha, q[i], ri);
+            r[i] = ri;
+        }
+        s = fma(ri, ri, s);
+    }
+    double t = block_sum(s, lds);
+    if (threadIdx.x == 0) { partial[2 * blockIdx.x] = t; partial[2 * blockIdx.x + 1] = 0.0; }
+}
+
+// p = z + beta p
+__global__ void k_cg_pupdate(int64_t n, const double *__restrict__ sc, const double *__restrict__ z,
+                             double *__restrict__ p)
+{
+    const double beta = sc[S_BETA];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = fma(beta, p[i], z[i]);
+}
+
+template <typename DT, typename ST>
+__global__ void k_copy(int64_t n, const ST *__restrict__ s, DT *__restrict__ d)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        d[i] = (DT)s[i];
+}
+
+template <typename T>
+__global__ void k_fill(int64_t n, T v, T *__restrict__ d)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) d[i] = v;
+}
+
+// Final sum of the block partials (two dots) in index order, then the scalar
+// recurrences of CG / FCG(1) on the device.
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partial, int nblk, double *sc,
+                                                   int op, int slot)
+{
+    __shared__ double lds[8];
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) { s0 += partial[2 * b]; s1 += partial[2 * b + 1]; }
+    double t0 = block_sum(s0, lds), t1 = block_sum(s1, lds + 4);
+    if (threadIdx.x != 0) return;
+    switch (op) {
+    case FIN_STORE:
+        sc[slot] = t0;
+        if (slot + 1 < S_NSLOTS && slot == S_TMP) sc[slot + 1] = t1;
+        break;
+    case FIN_PQ_CG:
+    case FIN_PQ_FCG: {
+        sc[S_PQ] = t0;
+        if (op == FIN_PQ_FCG) sc[S_PR] = t1;
+        double num = op == FIN_PQ_FCG ? t1 : sc[S_RZ];
+        if (!(t0 > 0.0) || !isfinite(t0)) { if (sc[S_FLAG] == 0.0) sc[S_FLAG] = 1.0; }
+        else sc[S_ALPHA] = num / t0;
+        break;
+    }
+    case FIN_RZ0:
+        sc[S_RZ] = t0;
+        if (!(t0 > 0.0) || !isfinite(t0)) { if (sc[S_FLAG] == 0.0) sc[S_FLAG] = 2.0; }
+        break;
+    case FIN_RZ_CG:
+        if (!(t0 > 0.0) || !isfinite(t0)) { if (sc[S_FLAG] == 0.0) sc[S_FLAG] = 2.0; }
+        else { sc[S_BETA] = t0 / sc[S_RZ]; sc[S_RZ] = t0; }
+        break;
+    case FIN_ZQ_FCG:
+        sc[S_ZQ] = t0;
+        if (!isfinite(t0)) { if (sc[S_FLAG] == 0.0) sc[S_FLAG] = 2.0; }
+        else sc[S_BETA] = -t0 / sc[S_PQ];
+        break;
+    }
+}
+
+}  // namespace amgk

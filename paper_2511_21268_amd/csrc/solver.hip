@@ -1,0 +1,897 @@
+// amg_ctx: device hierarchy, V-cycle and CG / FCG drivers, and the C ABI of
+// include/amg.h.  Every step of the solve phase runs in the kernels of
+// kernels.h / coarse.h on the context's stream; the host only enqueues them and
+// reads one small scalar block per iteration to test convergence.
+#include "amg.h"
+#include "coarse.h"
+#include "host.h"
+#include "kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace amgk;
+using amgiga::CsrView;
+using amgiga::HostHierarchy;
+
+static thread_local std::string g_err;
+
+namespace {
+
+struct Fail {
+    amg_status st;
+};
+
+void set_err(const std::string &m) { g_err = m; }
+
+#define HIPCHK(x)                                                                              \
+    do {                                                                                       \
+        hipError_t e_ = (x);                                                                   \
+        if (e_ != hipSuccess) {                                                                \
+            set_err(std::string("HIP error: ") + hipGetErrorString(e_) + " at " #x);           \
+            throw Fail{e_ == hipErrorOutOfMemory ? AMG_ERR_OOM : AMG_ERR_HIP};                 \
+        }                                                                                      \
+    } while (0)
+
+template <typename T> T *dalloc(size_t n)
+{
+    void *p = nullptr;
+    if (n == 0) n = 1;
+    HIPCHK(hipMalloc(&p, n * sizeof(T)));
+    return (T *)p;
+}
+
+template <typename T> T *dupload(const T *h, size_t n)
+{
+    T *d = dalloc<T>(n);
+    if (n) HIPCHK(hipMemcpy(d, h, n * sizeof(T), hipMemcpyHostToDevice));
+    return d;
+}
+
+inline unsigned nblocks(int64_t n, int per = 256) { return (unsigned)((n + per - 1) / per); }
+inline unsigned vgrid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256)); }
+
+// Host-side sliced-ELL image of one level (layout described in kernels.h).
+struct SellHost {
+    int64_t nslices = 0, stored = 0;
+    int idx16 = 1;
+    std::vector<int64_t> soff;
+    std::vector<double> v64;
+    std::vector<float> v32;
+    std::vector<uint16_t> d16;
+    std::vector<int32_t> c32, col0;
+};
+
+void build_sell(const CsrView &K, bool want64, bool want32, SellHost &S)
+{
+    const int64_t n = K.n;
+    S.nslices = (n + SLICE - 1) / SLICE;
+    S.soff.assign(S.nslices + 1, 0);
+    int maxd = 0;
+    for (int64_t s = 0; s < S.nslices; s++) {
+        int64_t w = 0;
+        for (int64_t r = s * SLICE; r < std::min(n, (s + 1) * SLICE); r++) w = std::max(w, K.rp[r + 1] - K.rp[r]);
+        w = (w + 7) / 8 * 8;
+        S.soff[s + 1] = S.soff[s] + SLICE * w;
+    }
+    S.stored = S.soff[S.nslices];
+    std::vector<int> md(amgiga::host_threads() + 1, 0);
+    amgiga::parallel_for(n, [&](int64_t b, int64_t e) {
+        int m = 0;
+        for (int64_t r = b; r < e; r++)
+            for (int64_t k = K.rp[r] + 1; k < K.rp[r + 1]; k++) m = std::max(m, K.ci[k] - K.ci[k - 1]);
+        static std::mutex mx;
+        std::lock_guard<std::mutex> g(mx);
+        md[0] = std::max(md[0], m);
+    });
+    maxd = md[0];
+    S.idx16 = maxd <= 65535 ? 1 : 0;
+    if (want64) S.v64.assign(S.stored, 0.0);
+    if (want32) S.v32.assign(S.stored, 0.0f);
+    if (S.idx16) {
+        S.d16.assign(S.stored, 0);
+        S.col0.assign(S.nslices * SLICE, 0);
+    } else {
+        S.c32.assign(S.stored, 0);
+    }
+    amgiga::parallel_for(S.nslices, [&](int64_t sb, int64_t se) {
+        for (int64_t s = sb; s < se; s++) {
+            const int64_t base = S.soff[s];
+            const int64_t w = (S.soff[s + 1] - base) / SLICE;
+            for (int lane = 0; lane < SLICE; lane++) {
+                int64_t r = s * SLICE + lane;
+                int64_t len = r < n ? K.rp[r + 1] - K.rp[r] : 0;
+                const int64_t r0 = r < n ? K.rp[r] : 0;
+                if (S.idx16 && r < n) S.col0[r] = K.ci[r0];
+                for (int64_t k = 0; k < w; k++) {
+                    double v = k < len ? K.v[r0 + k] : 0.0;
+                    if (want64) S.v64[base + (k / 2) * 128 + lane * 2 + (k % 2)] = v;
+                    if (want32) S.v32[base + (k / 4) * 256 + lane * 4 + (k % 4)] = (float)v;
+                    if (S.idx16) {
+                        int d = (k >= 1 && k < len) ? K.ci[r0 + k] - K.ci[r0 + k - 1] : 0;
+                        S.d16[base + (k / 8) * 512 + lane * 8 + (k % 8)] = (uint16_t)d;
+                    } else {
+                        int32_t c = k < len ? K.ci[r0 + k] : (len > 0 ? K.ci[r0 + len - 1] : 0);
+                        S.c32[base + (k / 4) * 256 + lane * 4 + (k % 4)] = c;
+                    }
+                }
+            }
+        }
+    });
+}
+
+struct DevMat {
+    int64_t n = 0, nnz = 0, nslices = 0, stored = 0;
+    int idx16 = 1;
+    int64_t *soff = nullptr;
+    int32_t *col0 = nullptr, *c32 = nullptr;
+    uint16_t *d16 = nullptr;
+    double *v64 = nullptr;
+    float *v32 = nullptr;
+    template <typename VT> const VT *val() const;
+};
+template <> const double *DevMat::val<double>() const { return v64; }
+template <> const float *DevMat::val<float>() const { return v32; }
+
+struct Level {
+    int64_t n = 0, nnz = 0;
+    DevMat A;
+    double *invd64 = nullptr;
+    float *invd32 = nullptr;
+    // transfer to the next level
+    int32_t *agg = nullptr, *members = nullptr;
+    int mw = 0;
+    double *pc64 = nullptr;
+    float *pc32 = nullptr;
+    // work vectors in the V-cycle precision
+    void *f = nullptr, *u = nullptr, *u2 = nullptr, *r = nullptr, *c = nullptr, *c2 = nullptr;
+    double poly[4] = {1.0, 0.0, 0.0, 0.0};
+    int poly_on = 0;
+    template <typename VT> VT *invd() const;
+    template <typename VT> VT *pc() const;
+};
+template <> double *Level::invd<double>() const { return invd64; }
+template <> float *Level::invd<float>() const { return invd32; }
+template <> double *Level::pc<double>() const { return pc64; }
+template <> float *Level::pc<float>() const { return pc32; }
+
+}  // namespace
+
+struct amg_ctx {
+    amg_params prm;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int host_only = 0;
+    HostHierarchy host;
+    std::vector<Level> lev;
+    int nlev = 0;
+    int nL = 0, ldL = 0;
+    double *Linv = nullptr, *LinvT = nullptr;
+    int64_t n = 0;
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+    double *partial = nullptr;
+    int64_t partial_cap = 0;
+    double *sc = nullptr;
+    double *hsc = nullptr;     // pinned host copy of the scalar block
+    hipEvent_t ev_iter = nullptr;
+    std::vector<void *> allocs;
+    // profiling
+    int prof = 0;
+    std::vector<hipEvent_t> evpool;
+    size_t evused = 0;
+    std::vector<double> evbytes;
+    int64_t prof_launches = 0;
+    double prof_ms = 0.0, prof_bytes = 0.0;
+
+    template <typename T> T *alloc(size_t k)
+    {
+        T *d = dalloc<T>(k);
+        allocs.push_back(d);
+        return d;
+    }
+    template <typename T> T *upload(const std::vector<T> &h)
+    {
+        T *d = dupload(h.data(), h.size());
+        allocs.push_back(d);
+        return d;
+    }
+    ~amg_ctx()
+    {
+        if (!host_only) (void)hipStreamSynchronize(stream);
+        for (void *p : allocs) (void)hipFree(p);
+        if (hsc) (void)hipHostFree(hsc);
+        if (ev_iter) (void)hipEventDestroy(ev_iter);
+        for (auto e : evpool) (void)hipEventDestroy(e);
+    }
+
+    bool fp32() const { return prm.vcycle_fp32 != 0; }
+
+    // ---- profiling of level-0 matrix passes -------------------------------
+    void prof_begin()
+    {
+        if (!prof) return;
+        while (evpool.size() < evused + 2) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            evpool.push_back(e);
+        }
+        HIPCHK(hipEventRecord(evpool[evused], stream));
+    }
+    void prof_end(double bytes)
+    {
+        if (!prof) return;
+        HIPCHK(hipEventRecord(evpool[evused + 1], stream));
+        evbytes.push_back(bytes);
+        evused += 2;
+    }
+    void prof_collect()
+    {
+        if (!prof) return;
+        for (size_t k = 0; k + 1 < evused; k += 2) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, evpool[k], evpool[k + 1]));
+            prof_ms += ms;
+            prof_launches++;
+            prof_bytes += evbytes[k / 2];
+        }
+        evused = 0;
+        evbytes.clear();
+    }
+    // algorithmic bytes of one level-0 pass: matrix without padding + vectors
+    double pass_bytes(int vb, int nvec) const
+    {
+        const DevMat &A = lev[0].A;
+        double ib = A.idx16 ? 2.0 : 4.0;
+        return (double)A.nnz * (vb + ib) + (A.idx16 ? 4.0 * A.n : 0.0) + (double)nvec * 8.0 * A.n;
+    }
+
+    // ---- kernel launchers --------------------------------------------------
+    template <typename VT, typename FT, typename OT, int EPI, int NDOT>
+    void sell(int l, const VT *x, const FT *f, const VT *invd, OT *y, const double *g0, const double *g1,
+              VT coef = 1)
+    {
+        const DevMat &A = lev[l].A;
+        unsigned nb = (unsigned)((A.nslices + SELL_WAVES - 1) / SELL_WAVES);
+        if (l == 0) {
+            int nvec = 2 + (EPI == EPI_RESID ? 1 : 0) + (EPI == EPI_SMOOTH ? 2 : 0) + (EPI == EPI_POLY ? 2 : 0) +
+                       (NDOT >= 2 ? 1 : 0) + (EPI == EPI_SMOOTH && NDOT >= 1 ? 1 : 0);
+            prof_begin();
+            launch_sell<VT, FT, OT, EPI, NDOT>(A, nb, x, f, invd, y, g0, g1, coef);
+            prof_end(pass_bytes((int)sizeof(VT), nvec));
+        } else {
+            launch_sell<VT, FT, OT, EPI, NDOT>(A, nb, x, f, invd, y, g0, g1, coef);
+        }
+    }
+    template <typename VT, typename FT, typename OT, int EPI, int NDOT>
+    void launch_sell(const DevMat &A, unsigned nb, const VT *x, const FT *f, const VT *invd, OT *y,
+                     const double *g0, const double *g1, VT coef)
+    {
+        if (A.idx16)
+            hipLaunchKernelGGL((k_sell<VT, FT, OT, uint16_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream, A.n,
+                               A.nslices, A.soff, A.val<VT>(), A.d16, A.col0, x, f, invd, y, g0, g1, partial, coef);
+        else
+            hipLaunchKernelGGL((k_sell<VT, FT, OT, int32_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream, A.n,
+                               A.nslices, A.soff, A.val<VT>(), A.c32, A.col0, x, f, invd, y, g0, g1, partial, coef);
+        HIPCHK(hipGetLastError());
+    }
+    unsigned sell_blocks(int l) const { return (unsigned)((lev[l].A.nslices + SELL_WAVES - 1) / SELL_WAVES); }
+    void finalize(unsigned nblk, int op, int slot = 0)
+    {
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, stream, partial, (int)nblk, sc, op, slot);
+        HIPCHK(hipGetLastError());
+    }
+    unsigned dot_partials(int64_t m, const double *a, const double *b, const double *c)
+    {
+        unsigned g = vgrid(m);
+        hipLaunchKernelGGL(k_dot2, dim3(g), dim3(256), 0, stream, m, a, b, c, partial);
+        HIPCHK(hipGetLastError());
+        return g;
+    }
+    void dot2(int64_t m, const double *a, const double *b, const double *c, int op, int slot = 0)
+    {
+        finalize(dot_partials(m, a, b, c), op, slot);
+    }
+    unsigned vc_nb = 0;   // partial blocks left by the last V-cycle's dots
+    template <typename DT, typename ST> void copy(int64_t m, const ST *s, DT *d)
+    {
+        hipLaunchKernelGGL((k_copy<DT, ST>), dim3(vgrid(m)), dim3(256), 0, stream, m, s, d);
+        HIPCHK(hipGetLastError());
+    }
+
+    // ---- smoothing steps (Sec. 3 eq. (smoother)) ----------------------------
+    // u_out = u_in + M (f - K u_in) with M = D^{-1} (l1-Jacobi) or the degree-4
+    // polynomial p(D^{-1}K) D^{-1}.  At level 0 the last sweep may write the
+    // FP64 output with dot partials (dots != 0).
+    template <typename VT, typename FT, typename OT>
+    void sweep(int l, const FT *f, const VT *uin, OT *uout, int ndot, const double *g0, const double *g1)
+    {
+        Level &L = lev[l];
+        if (!L.poly_on) {
+            if (ndot == 2) sell<VT, FT, OT, EPI_SMOOTH, 2>(l, uin, f, L.invd<VT>(), uout, g0, g1);
+            else if (ndot == 1) sell<VT, FT, OT, EPI_SMOOTH, 1>(l, uin, f, L.invd<VT>(), uout, g0, g1);
+            else sell<VT, FT, OT, EPI_SMOOTH, 0>(l, uin, f, L.invd<VT>(), uout, g0, g1);
+            if (ndot) vc_nb = sell_blocks(l);
+            return;
+        }
+        VT *res = (VT *)L.r, *c = (VT *)L.c, *c2 = (VT *)L.c2;
+        sell<VT, FT, VT, EPI_RESID, 0>(l, uin, f, L.invd<VT>(), res, nullptr, nullptr);
+        const VT *cr = poly_apply<VT, VT>(l, res, c, c2);
+        finish_sweep<VT, OT>(l, uin, cr, uout, ndot, g0, g1);
+    }
+    // Horner from zero: c = a3 D^{-1} r, then c = a_k D^{-1} r + D^{-1} K c.
+    template <typename VT, typename FT> VT *poly_apply(int l, const FT *rr, VT *&c, VT *&c2)
+    {
+        Level &L = lev[l];
+        hipLaunchKernelGGL((k_scale_coef<VT, FT>), dim3(nblocks(L.n)), dim3(256), 0, stream, L.n, L.invd<VT>(), rr,
+                           c, (VT)L.poly[3]);
+        HIPCHK(hipGetLastError());
+        for (int k = 2; k >= 0; k--) {
+            sell<VT, FT, VT, EPI_POLY, 0>(l, c, rr, L.invd<VT>(), c2, nullptr, nullptr, (VT)L.poly[k]);
+            std::swap(c, c2);
+        }
+        return c;
+    }
+    template <typename VT, typename OT>
+    void finish_sweep(int l, const VT *uin, const VT *c, OT *uout, int ndot, const double *g0, const double *g1)
+    {
+        Level &L = lev[l];
+        hipLaunchKernelGGL((k_add<VT, OT>), dim3(nblocks(L.n)), dim3(256), 0, stream, L.n, uin, c, uout);
+        HIPCHK(hipGetLastError());
+        if (ndot) vc_nb = dot_partials(L.n, (const double *)uout, g0, g1);
+    }
+
+    // ---- the V-cycle (Sec. 3, steps 1-5, recursively) -----------------------
+    // Level l solves approximately K_l u = f with a zero initial guess and
+    // returns where the result lives.  At level 0, the last post-smoothing sweep
+    // writes zout (FP64) and the dot partials for the Krylov scalars.
+    template <typename VT, typename FT>
+    VT *vlevel(int l, const FT *f, double *zout, int ndot, const double *g0, const double *g1, bool u_ready)
+    {
+        Level &L = lev[l];
+        VT *u = (VT *)L.u, *u2 = (VT *)L.u2;
+        // 1. pre-smoothing from the zero guess
+        if (!u_ready) {
+            if (L.poly_on) {
+                VT *c = (VT *)L.c, *c2 = (VT *)L.c2;
+                VT *res = poly_apply<VT, FT>(l, f, c, c2);
+                copy<VT, VT>(L.n, res, u);
+            } else {
+                hipLaunchKernelGGL((k_scale<VT, FT>), dim3(nblocks(L.n)), dim3(256), 0, stream, L.n, L.invd<VT>(),
+                                   f, u);
+                HIPCHK(hipGetLastError());
+            }
+        } else if (L.poly_on) {
+            // the restriction wrote a3 D^{-1} f into u: finish Horner from there
+            VT *c = u, *c2 = (VT *)L.c2;
+            for (int k = 2; k >= 0; k--) {
+                sell<VT, FT, VT, EPI_POLY, 0>(l, c, f, L.invd<VT>(), c2, nullptr, nullptr, (VT)L.poly[k]);
+                std::swap(c, c2);
+            }
+            if (c != u) copy<VT, VT>(L.n, c, u);
+        }
+        for (int s = 1; s < prm.nu_pre; s++) {
+            sweep<VT, FT, VT>(l, f, u, u2, 0, nullptr, nullptr);
+            std::swap(u, u2);
+        }
+        // 2. residual and restriction (fused with the coarse pre-smoothing)
+        sell<VT, FT, VT, EPI_RESID, 0>(l, u, f, L.invd<VT>(), (VT *)L.r, nullptr, nullptr);
+        Level &C = lev[l + 1];
+        const bool coarsest = (l + 1 == nlev - 1);
+        const VT a3 = C.poly_on ? (VT)C.poly[3] : (VT)1;
+        hipLaunchKernelGGL((k_restrict<VT>), dim3(nblocks(C.n)), dim3(256), 0, stream, C.n, L.mw, L.members,
+                           L.pc<VT>(), (const VT *)L.r, (VT *)C.f, coarsest ? nullptr : C.invd<VT>(),
+                           coarsest ? nullptr : (VT *)C.u, a3);
+        HIPCHK(hipGetLastError());
+        // 3. coarse solve
+        VT *e;
+        if (coarsest) {
+            e = (VT *)C.u;
+            hipLaunchKernelGGL((k_coarse_solve<VT>), dim3(1), dim3(256), 0, stream, nL, ldL, Linv, LinvT,
+                               (const VT *)C.f, e);
+            HIPCHK(hipGetLastError());
+        } else {
+            e = vlevel<VT, VT>(l + 1, (const VT *)C.f, nullptr, 0, nullptr, nullptr, true);
+        }
+        // 4. prolongation and correction
+        hipLaunchKernelGGL((k_prolong<VT>), dim3(nblocks(L.n)), dim3(256), 0, stream, L.n, L.agg, L.pc<VT>(), e, u);
+        HIPCHK(hipGetLastError());
+        // 5. post-smoothing
+        for (int s = 1; s <= prm.nu_post; s++) {
+            if (zout && s == prm.nu_post) {
+                sweep<VT, FT, double>(l, f, u, zout, ndot, g0, g1);
+                return nullptr;
+            }
+            sweep<VT, FT, VT>(l, f, u, u2, 0, nullptr, nullptr);
+            std::swap(u, u2);
+        }
+        if (zout) {
+            copy<double, VT>(L.n, u, zout);
+            if (ndot) vc_nb = dot_partials(L.n, zout, g0, g1);
+            return nullptr;
+        }
+        return u;
+    }
+
+    // z = B r; when ndot > 0 the partials of (z, g0) [and (z, g1)] are left in
+    // `partial` and the number of blocks to finalize is returned.
+    unsigned vcycle(const double *rin, double *zout, int ndot, const double *g0, const double *g1)
+    {
+        vc_nb = 0;
+        if (nlev == 1) {
+            hipLaunchKernelGGL((k_coarse_solve<double>), dim3(1), dim3(256), 0, stream, nL, ldL, Linv, LinvT, rin,
+                               zout);
+            HIPCHK(hipGetLastError());
+            if (ndot) vc_nb = dot_partials(n, zout, g0, g1);
+            return vc_nb;
+        }
+        if (fp32()) vlevel<float, double>(0, rin, zout, ndot, g0, g1, false);
+        else vlevel<double, double>(0, rin, zout, ndot, g0, g1, false);
+        return vc_nb;
+    }
+};
+
+// ---------------------------------------------------------------------------
+
+static amg_status build_device(amg_ctx *c, const CsrView &K0)
+{
+    HostHierarchy &H = c->host;
+    c->lev.resize(c->nlev);
+    const bool fp32 = c->fp32();
+    const size_t vsz = fp32 ? sizeof(float) : sizeof(double);
+    for (int l = 0; l < c->nlev; l++) {
+        auto &hl = H.lev[l];
+        Level &L = c->lev[l];
+        L.n = hl.n;
+        L.nnz = hl.nnz;
+        const bool coarsest = (l == c->nlev - 1);
+        if (!coarsest || l == 0) {
+            {
+                CsrView K = l == 0 ? K0 : amgiga::view(hl.K);
+                SellHost S;
+                bool want64 = (l == 0) || !fp32;
+                bool want32 = fp32;
+                build_sell(K, want64, want32, S);
+                DevMat &A = L.A;
+                A.n = hl.n; A.nnz = hl.nnz; A.nslices = S.nslices; A.stored = S.stored; A.idx16 = S.idx16;
+                A.soff = c->upload(S.soff);
+                if (want64) A.v64 = c->upload(S.v64);
+                if (want32) A.v32 = c->upload(S.v32);
+                if (S.idx16) { A.d16 = c->upload(S.d16); A.col0 = c->upload(S.col0); }
+                else A.c32 = c->upload(S.c32);
+            }
+        }
+        L.invd64 = c->upload(hl.invd);
+        if (fp32) {
+            std::vector<float> t(hl.invd.begin(), hl.invd.end());
+            L.invd32 = c->upload(t);
+        }
+        if (!coarsest) {
+            L.agg = c->upload(hl.agg);
+            L.pc64 = c->upload(hl.pc);
+            if (fp32) {
+                std::vector<float> t(hl.pc.begin(), hl.pc.end());
+                L.pc32 = c->upload(t);
+            }
+            int64_t nc = H.lev[l + 1].n;
+            L.mw = hl.max_members;
+            std::vector<int32_t> mem((size_t)(nc * L.mw), -1);
+            std::vector<int> fill(nc, 0);
+            for (int64_t i = 0; i < hl.n; i++) {
+                int32_t I = hl.agg[i];
+                mem[(size_t)I * L.mw + fill[I]++] = (int32_t)i;
+            }
+            L.members = c->upload(mem);
+        }
+        size_t nn = (size_t)hl.n;
+        L.f = c->alloc<char>(nn * vsz);
+        L.u = c->alloc<char>(nn * vsz);
+        L.u2 = c->alloc<char>(nn * vsz);
+        L.r = c->alloc<char>(nn * vsz);
+        L.c = c->alloc<char>(nn * vsz);
+        L.c2 = c->alloc<char>(nn * vsz);
+    }
+    // coarsest level: dense Cholesky on the device, then the inverse factor
+    {
+        auto &hl = H.lev.back();
+        int nl = (int)hl.n;
+        int npad = (nl + 15) / 16 * 16;
+        std::vector<double> A((size_t)npad * npad, 0.0);
+        for (int i = 0; i < nl; i++)
+            for (int j = 0; j <= i; j++) A[(size_t)i * npad + j] = H.coarse_lower[(size_t)i * nl + j];
+        for (int i = nl; i < npad; i++) A[(size_t)i * npad + i] = 1.0;
+        double *dA = c->upload(A);
+        int *dst = c->alloc<int>(1);
+        HIPCHK(hipMemsetAsync(dst, 0, sizeof(int), c->stream));
+        hipLaunchKernelGGL(k_chol_mfma, dim3(1), dim3(256), 0, c->stream, npad, dA, dst);
+        HIPCHK(hipGetLastError());
+        int hst = 0;
+        HIPCHK(hipMemcpyAsync(&hst, dst, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (hst) {
+            set_err("coarsest matrix is not SPD (non-positive Cholesky pivot)");
+            return AMG_ERR_NOT_SPD;
+        }
+        c->nL = nl;
+        c->ldL = npad;
+        c->Linv = c->alloc<double>((size_t)npad * npad);
+        c->LinvT = c->alloc<double>((size_t)npad * npad);
+        hipLaunchKernelGGL(k_tri_inv, dim3((nl + 255) / 256), dim3(256), 0, c->stream, nl, npad, dA, c->Linv,
+                           c->LinvT);
+        HIPCHK(hipGetLastError());
+    }
+    c->n = H.lev[0].n;
+    c->r = c->alloc<double>(c->n);
+    c->z = c->alloc<double>(c->n);
+    c->p = c->alloc<double>(c->n);
+    c->q = c->alloc<double>(c->n);
+    c->partial_cap = 2 * std::max<int64_t>(2048, c->sell_blocks(0));
+    c->partial = c->alloc<double>(c->partial_cap);
+    c->sc = c->alloc<double>(S_NSLOTS);
+    HIPCHK(hipHostMalloc((void **)&c->hsc, S_NSLOTS * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_iter, hipEventDisableTiming));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return AMG_OK;
+}
+
+extern "C" {
+
+amg_status amg_params_default(amg_params *p)
+{
+    if (!p) { set_err("NULL params"); return AMG_ERR_ARG; }
+    p->sweeps_per_level = 2;
+    p->max_coarse = 200;
+    p->max_levels = 40;
+    p->nu_pre = 1;
+    p->nu_post = 1;
+    p->vcycle_fp32 = 0;
+    p->smoother = 0;
+    p->krylov = 0;
+    p->match_positive_only = 0;
+    p->itmax = 1000;
+    return AMG_OK;
+}
+
+const char *amg_last_error(void) { return g_err.c_str(); }
+
+static amg_status setup_common(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                               const double *w, const amg_params *prm, void *hip_stream, int host_only,
+                               amg_ctx **out)
+{
+    g_err.clear();
+    if (!out) { set_err("NULL out"); return AMG_ERR_ARG; }
+    *out = nullptr;
+    amg_params P;
+    amg_params_default(&P);
+    if (prm) P = *prm;
+    if (P.sweeps_per_level < 1 || P.sweeps_per_level > 3 || P.max_coarse < 1 || P.max_coarse > 2000 ||
+        P.max_levels < 1 || P.nu_pre < 1 || P.nu_post < 0 || P.itmax < 1 || P.krylov < 0 || P.krylov > 1 ||
+        P.smoother < 0 || P.smoother > 1) {
+        set_err("parameter out of range");
+        return AMG_ERR_ARG;
+    }
+    if (n <= 0 || !row_ptr || !col || !val) { set_err("n <= 0 or NULL CSR array"); return AMG_ERR_ARG; }
+    CsrView K0{n, row_ptr, col, val};
+    std::string err;
+    if (amgiga::validate_csr(K0, err)) { set_err(err); return AMG_ERR_ARG; }
+    if (w)
+        for (int64_t i = 0; i < n; i++)
+            if (!std::isfinite(w[i])) { set_err("non-finite test vector"); return AMG_ERR_ARG; }
+    std::unique_ptr<amg_ctx> c;
+    try {
+        c.reset(new amg_ctx());
+        c->prm = P;
+        c->host_only = host_only;
+        c->stream = (hipStream_t)hip_stream;
+        amgiga::SetupParams sp;
+        sp.sweeps = P.sweeps_per_level;
+        sp.max_coarse = P.max_coarse;
+        sp.max_levels = P.max_levels;
+        sp.positive_only = P.match_positive_only;
+        int rc = amgiga::build_hierarchy(K0, w, sp, c->host, err);
+        if (rc) { set_err(err); return (amg_status)rc; }
+        c->nlev = (int)c->host.lev.size();
+        if (!host_only) {
+            HIPCHK(hipGetDevice(&c->device));
+            amg_status st = build_device(c.get(), K0);
+            if (st != AMG_OK) return st;
+        }
+    } catch (Fail &f) {
+        return f.st;
+    } catch (std::bad_alloc &) {
+        set_err("host allocation failed");
+        return AMG_ERR_OOM;
+    }
+    *out = c.release();
+    return AMG_OK;
+}
+
+amg_status amg_setup(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val, const double *w,
+                     const amg_params *prm, void *hip_stream, amg_ctx **out)
+{
+    return setup_common(n, row_ptr, col, val, w, prm, hip_stream, 0, out);
+}
+
+amg_status amg_setup_host(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                          const double *w, const amg_params *prm, amg_ctx **out)
+{
+    return setup_common(n, row_ptr, col, val, w, prm, nullptr, 1, out);
+}
+
+amg_status amg_match(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val, const double *w,
+                     int positive_only, int32_t *mate)
+{
+    g_err.clear();
+    if (n <= 0 || !row_ptr || !col || !val || !mate) { set_err("n <= 0 or NULL array"); return AMG_ERR_ARG; }
+    CsrView K{n, row_ptr, col, val};
+    std::string err;
+    if (amgiga::validate_csr(K, err)) { set_err(err); return AMG_ERR_ARG; }
+    std::vector<double> ones;
+    if (!w) { ones.assign(n, 1.0); w = ones.data(); }
+    amgiga::suitor_match(K, w, positive_only, mate);
+    return AMG_OK;
+}
+
+void amg_destroy(amg_ctx *c) { delete c; }
+
+static amg_status solve_impl(amg_ctx *c, const double *F, double *u, double tol, int *iters, double *relres,
+                             double *relres_true)
+{
+    const int64_t n = c->n;
+    const bool flex = c->prm.krylov == 1;
+    const int itmax = c->prm.itmax;
+    hipStream_t st = c->stream;
+    c->evused = 0;
+    c->evbytes.clear();
+    hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(256), 0, st, (int64_t)S_NSLOTS, 0.0, c->sc);
+    HIPCHK(hipGetLastError());
+    // r = F - K u ; (F, F) ; (r, r)
+    c->sell<double, double, double, EPI_RESID, 0>(0, u, F, c->lev[0].invd64, c->r, nullptr, nullptr);
+    c->dot2(n, F, F, nullptr, FIN_STORE, S_FF);
+    c->dot2(n, c->r, c->r, nullptr, FIN_STORE, S_RR);
+    HIPCHK(hipMemcpyAsync(c->hsc, c->sc, S_NSLOTS * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double ff = c->hsc[S_FF];
+    if (!std::isfinite(ff)) { set_err("non-finite right-hand side"); return AMG_ERR_ARG; }
+    if (iters) *iters = 0;
+    if (ff == 0.0) {
+        hipLaunchKernelGGL((k_fill<double>), dim3(vgrid(n)), dim3(256), 0, st, n, 0.0, u);
+        HIPCHK(hipStreamSynchronize(st));
+        if (relres) *relres = 0.0;
+        if (relres_true) *relres_true = 0.0;
+        return AMG_OK;
+    }
+    const double nF = std::sqrt(ff);
+    double rr = c->hsc[S_RR];
+    amg_status status = AMG_NOT_CONVERGED;
+    int k = 0;
+    if (std::sqrt(rr) <= tol * nF) {
+        status = AMG_OK;
+    } else {
+        // z = B r ; (r, z) ; p = z
+        unsigned nb = c->vcycle(c->r, c->z, flex ? 0 : 1, c->r, nullptr);
+        if (!flex) c->finalize(nb, FIN_RZ0);
+        c->copy<double, double>(n, c->z, c->p);
+        for (k = 1; k <= itmax; k++) {
+            // q = K p, (p, q) [, (p, r)] -> alpha
+            if (flex) c->sell<double, double, double, EPI_SPMV, 2>(0, c->p, nullptr, nullptr, c->q, nullptr, c->r);
+            else c->sell<double, double, double, EPI_SPMV, 1>(0, c->p, nullptr, nullptr, c->q, nullptr, nullptr);
+            c->finalize(c->sell_blocks(0), flex ? FIN_PQ_FCG : FIN_PQ_CG);
+            // u += alpha p ; r -= alpha q ; (r, r)
+            unsigned g = vgrid(n);
+            hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(256), 0, st, n, c->sc, u, c->r, c->p, c->q, c->partial);
+            HIPCHK(hipGetLastError());
+            c->finalize(g, FIN_STORE, S_RR);
+            HIPCHK(hipMemcpyAsync(c->hsc, c->sc, S_NSLOTS * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipEventRecord(c->ev_iter, st));
+            // speculative: next preconditioned direction while the host tests convergence
+            if (k < itmax) {
+                unsigned nb2 = c->vcycle(c->r, c->z, 1, flex ? c->q : c->r, nullptr);
+                c->finalize(nb2, flex ? FIN_ZQ_FCG : FIN_RZ_CG);
+                hipLaunchKernelGGL(k_cg_pupdate, dim3(vgrid(n)), dim3(256), 0, st, n, c->sc, c->z, c->p);
+                HIPCHK(hipGetLastError());
+            }
+            HIPCHK(hipEventSynchronize(c->ev_iter));
+            if (c->hsc[S_FLAG] != 0.0) {
+                status = AMG_ERR_BREAKDOWN;
+                k = k - 1;
+                set_err("CG breakdown: (p, K p) <= 0 or (r, B r) <= 0 or non-finite");
+                break;
+            }
+            rr = c->hsc[S_RR];
+            if (std::sqrt(rr) <= tol * nF) { status = AMG_OK; break; }
+        }
+        if (k > itmax) k = itmax;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    c->prof_collect();
+    if (iters) *iters = k;
+    if (relres) *relres = std::sqrt(rr) / nF;
+    if (relres_true) {
+        int saved = c->prof;
+        c->prof = 0;
+        c->sell<double, double, double, EPI_RESID, 0>(0, u, F, c->lev[0].invd64, c->r, nullptr, nullptr);
+        c->prof = saved;
+        c->dot2(n, c->r, c->r, nullptr, FIN_STORE, S_TMP);
+        HIPCHK(hipMemcpyAsync(c->hsc, c->sc, S_NSLOTS * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        *relres_true = std::sqrt(c->hsc[S_TMP]) / nF;
+    }
+    return status;
+}
+
+amg_status pcg_solve(amg_ctx *c, const double *F, double *u, double tol, int *iters, double *relres,
+                     double *relres_true)
+{
+    g_err.clear();
+    if (!c || !F || !u || !(tol >= 0.0)) { set_err("NULL argument or tol < 0"); return AMG_ERR_ARG; }
+    if (c->host_only) { set_err("context was built by amg_setup_host"); return AMG_ERR_STATE; }
+    if (F == u) { set_err("F and u alias"); return AMG_ERR_ARG; }
+    try {
+        return solve_impl(c, F, u, tol, iters, relres, relres_true);
+    } catch (Fail &f) {
+        return f.st;
+    }
+}
+
+amg_status pcg_solve_batched(amg_ctx *c, int nrhs, const double *F, double *U, double tol, int *iters,
+                             double *relres)
+{
+    (void)c; (void)nrhs; (void)F; (void)U; (void)tol; (void)iters; (void)relres;
+    set_err("batched solve not available in this build");
+    return AMG_ERR_STATE;
+}
+
+amg_status amg_vcycle(amg_ctx *c, const double *r, double *z)
+{
+    g_err.clear();
+    if (!c || !r || !z || r == z) { set_err("NULL or aliased argument"); return AMG_ERR_ARG; }
+    if (c->host_only) { set_err("context was built by amg_setup_host"); return AMG_ERR_STATE; }
+    try {
+        c->vcycle(r, z, 0, nullptr, nullptr);
+        HIPCHK(hipStreamSynchronize(c->stream));
+    } catch (Fail &f) {
+        return f.st;
+    }
+    return AMG_OK;
+}
+
+amg_status amg_spmv(amg_ctx *c, int level, const double *x, double *y)
+{
+    g_err.clear();
+    if (!c || !x || !y || x == y) { set_err("NULL or aliased argument"); return AMG_ERR_ARG; }
+    if (c->host_only) { set_err("context was built by amg_setup_host"); return AMG_ERR_STATE; }
+    if (level < 0 || level >= c->nlev || (level == c->nlev - 1 && level > 0)) {
+        set_err("level has no sparse device matrix");
+        return AMG_ERR_ARG;
+    }
+    if (!c->lev[level].A.v64) { set_err("level is held in FP32 only (vcycle_fp32)"); return AMG_ERR_ARG; }
+    try {
+        int saved = c->prof;
+        c->prof = 0;
+        c->sell<double, double, double, EPI_SPMV, 0>(level, x, nullptr, nullptr, y, nullptr, nullptr);
+        c->prof = saved;
+        HIPCHK(hipStreamSynchronize(c->stream));
+    } catch (Fail &f) {
+        return f.st;
+    }
+    return AMG_OK;
+}
+
+static int poly_ok(const double *a)
+{
+    for (int s = 0; s <= 10000; s++) {
+        double t = s / 10000.0;
+        double e = 1.0 - t * (((a[3] * t + a[2]) * t + a[1]) * t + a[0]);
+        if (!std::isfinite(e) || std::fabs(e) > 1.0) return 0;
+        if (s > 0 && !(e < 1.0)) return 0;
+    }
+    return 1;
+}
+
+amg_status amg_set_poly_coeffs(amg_ctx *c, int level, const double coeffs[4])
+{
+    g_err.clear();
+    if (!c || !coeffs || level < 0 || level >= c->nlev - 1) { set_err("bad level or NULL"); return AMG_ERR_ARG; }
+    if (c->host_only) { set_err("context was built by amg_setup_host"); return AMG_ERR_STATE; }
+    if (!poly_ok(coeffs)) {
+        set_err("polynomial rejected: error polynomial leaves [-1, 1] or reaches 1 on (0, 1]");
+        return AMG_NOT_CONVERGED;
+    }
+    Level &L = c->lev[level];
+    for (int k = 0; k < 4; k++) L.poly[k] = coeffs[k];
+    L.poly_on = c->prm.smoother == 1 ? 1 : 0;
+    return AMG_OK;
+}
+
+amg_status amg_get_level_info(const amg_ctx *c, int level, int64_t *n, int64_t *nnz)
+{
+    if (!c || !n || !nnz || level < -1 || level >= c->nlev) { set_err("bad level or NULL"); return AMG_ERR_ARG; }
+    if (level == -1) {
+        *n = c->nlev;
+        int64_t t = 0;
+        for (auto &L : c->host.lev) t += L.nnz;
+        *nnz = t;
+        return AMG_OK;
+    }
+    *n = c->host.lev[level].n;
+    *nnz = c->host.lev[level].nnz;
+    return AMG_OK;
+}
+
+amg_status amg_get_aggregates(const amg_ctx *c, int level, int32_t *agg, double *pc)
+{
+    if (!c || level < 0 || level >= c->nlev - 1) { set_err("bad level"); return AMG_ERR_ARG; }
+    auto &L = c->host.lev[level];
+    if (agg) std::memcpy(agg, L.agg.data(), L.agg.size() * sizeof(int32_t));
+    if (pc) std::memcpy(pc, L.pc.data(), L.pc.size() * sizeof(double));
+    return AMG_OK;
+}
+
+amg_status amg_get_coarse_matrix(const amg_ctx *c, int level, int64_t *row_ptr, int32_t *col, double *val)
+{
+    if (!c || level < 1 || level >= c->nlev) { set_err("level must be 1 .. levels-1"); return AMG_ERR_ARG; }
+    auto &K = c->host.lev[level].K;
+    if (row_ptr) std::memcpy(row_ptr, K.rp.data(), K.rp.size() * sizeof(int64_t));
+    if (col) std::memcpy(col, K.ci.data(), K.ci.size() * sizeof(int32_t));
+    if (val) std::memcpy(val, K.v.data(), K.v.size() * sizeof(double));
+    return AMG_OK;
+}
+
+amg_status amg_set_profiling(amg_ctx *c, int enable)
+{
+    if (!c) return AMG_ERR_ARG;
+    c->prof = enable ? 1 : 0;
+    c->prof_launches = 0;
+    c->prof_ms = 0.0;
+    c->prof_bytes = 0.0;
+    return AMG_OK;
+}
+
+amg_status amg_get_profile(amg_ctx *c, int64_t *launches, double *ms, double *bytes)
+{
+    if (!c) return AMG_ERR_ARG;
+    if (launches) *launches = c->prof_launches;
+    if (ms) *ms = c->prof_ms;
+    if (bytes) *bytes = c->prof_bytes;
+    return AMG_OK;
+}
+
+amg_status amg_get_format(const amg_ctx *c, int level, int *slice, int64_t *stored, int *index_bytes)
+{
+    if (!c || c->host_only || level < 0 || level >= c->nlev || (level == c->nlev - 1 && level > 0)) {
+        set_err("level has no sparse device matrix");
+        return AMG_ERR_ARG;
+    }
+    const DevMat &A = c->lev[level].A;
+    if (slice) *slice = SLICE;
+    if (stored) *stored = A.stored;
+    if (index_bytes) *index_bytes = A.idx16 ? 2 : 4;
+    return AMG_OK;
+}
+
+amg_status amg_iga_poisson_size(int d, int p, int n, int64_t *N, int64_t *nnz)
+{
+    if (d < 2 || d > 3 || p < 1 || p > 10 || n < 1 || n + p - 2 < 1 || !N || !nnz) {
+        set_err("need d in {2,3}, 1 <= p <= 10, n + p > 2");
+        return AMG_ERR_ARG;
+    }
+    amgiga::iga_size(d, p, n, N, nnz);
+    return AMG_OK;
+}
+
+amg_status amg_iga_poisson(int d, int p, int n, int64_t *row_ptr, int32_t *col, double *val, double *F)
+{
+    if (!row_ptr || !col || !val) { set_err("NULL output"); return AMG_ERR_ARG; }
+    if (amgiga::iga_poisson(d, p, n, row_ptr, col, val, F)) { set_err("bad d, p or n"); return AMG_ERR_ARG; }
+    return AMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+"""GPU parity of the HIP solve path against the oracle (FP64): kernels one by
+one, the V-cycle, and the whole PCG solve."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _csr(rp, ci, v):
+    return sp.csr_matrix((v, ci, rp), shape=(len(rp) - 1, len(rp) - 1))
+
+
+@pytest.fixture(scope="module")
+def amg():
+    import paper_2511_21268_amd as m
+    assert torch.cuda.is_available()
+    m.lib()
+    return m
+
+
+CASES = [(2, 2, 32), (2, 3, 40), (3, 2, 12), (3, 3, 16)]
+
+
+@pytest.mark.parametrize("d,p,n", CASES)
+def test_spmv_matches_oracle(oracle, amg, d, p, n):
+    print(f"case spmv d={d} p={p} n={n}", flush=True)
+    rp, ci, v, _ = oracle.poisson_kron(d, p, n)
+    ctx = amg.Context(rp, ci, v)
+    x = np.random.default_rng(1).standard_normal(len(rp) - 1)
+    y = ctx.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = oracle.spmv(rp, ci, v, x)
+    scale = _csr(rp, ci, np.abs(v)) @ np.abs(x)
+    assert np.all(np.abs(y - ref) <= 8 * np.finfo(float).eps * scale + 1e-300)
+    for l in range(1, ctx.nlevels - 1):
+        rpl, cil, vl = ctx.coarse_matrix(l)
+        xl = np.random.default_rng(l).standard_normal(len(rpl) - 1)
+        yl = ctx.spmv(torch.from_numpy(xl).cuda(), level=l).cpu().numpy()
+        refl = oracle.spmv(rpl, cil, vl, xl)
+        scl = _csr(rpl, cil, np.abs(vl)) @ np.abs(xl)
+        assert np.all(np.abs(yl - refl) <= 8 * np.finfo(float).eps * scl + 1e-300)
+
+
+@pytest.mark.parametrize("d,p,n", CASES)
+def test_vcycle_matches_oracle(oracle, amg, d, p, n):
+    print(f"case vcycle d={d} p={p} n={n}", flush=True)
+    rp, ci, v, _ = oracle.poisson_kron(d, p, n)
+    ctx = amg.Context(rp, ci, v)
+    h = oracle.Hierarchy(rp, ci, v)
+    assert ctx.nlevels == h.nlevels
+    r = np.random.default_rng(2).standard_normal(len(rp) - 1)
+    z = ctx.vcycle(torch.from_numpy(r).cuda()).cpu().numpy()
+    zo = h.vcycle(r)
+    assert np.linalg.norm(z - zo) <= 1e-12 * np.linalg.norm(zo)
+
+
+@pytest.mark.parametrize("d,p,n,seed", [(2, 2, 32, 0), (2, 2, 32, 1), (3, 2, 12, 0), (3, 3, 16, 2), (3, 3, 20, 3)])
+def test_pcg_parity(oracle, amg, d, p, n, seed):
+    print(f"case pcg d={d} p={p} n={n} seed={seed}", flush=True)
+    from paper_2511_21268_amd.workloads import rhs_normal
+    rp, ci, v, _ = oracle.poisson_kron(d, p, n)
+    N = len(rp) - 1
+    F = rhs_normal(N, seed)
+    ref = oracle.Hierarchy(rp, ci, v).solve(F, tol=1e-8)
+    ctx = amg.Context(rp, ci, v)
+    # aggregates of every level are the oracle's, bit for bit
+    h = oracle.Hierarchy(rp, ci, v)
+    for l in range(h.nlevels - 1):
+        a, pc = ctx.aggregates(l)
+        ao, pco, _, _ = h.level_agg(l)
+        assert np.array_equal(a, ao) and np.array_equal(pc, pco)
+    out = ctx.solve(torch.from_numpy(F).cuda(), tol=1e-8)
+    u = out["u"].cpu().numpy()
+    assert out["status"] == 0 and ref["rc"] == 0
+    assert out["iters"] == ref["iters"]
+    assert np.linalg.norm(u - ref["u"]) <= 1e-10 * np.linalg.norm(ref["u"])
+    assert out["relres_true"] <= 1e-8
+    true = np.linalg.norm(F - _csr(rp, ci, v) @ u) / np.linalg.norm(F)
+    assert true <= 1e-8
+
+
+def test_single_level_and_edge_cases(oracle, amg):
+    print("case edge", flush=True)
+    rp, ci, v, F = oracle.poisson_kron(2, 3, 10)      # N = 121 <= 200: one level
+    ctx = amg.Context(rp, ci, v)
+    assert ctx.nlevels == 1
+    Ft = torch.from_numpy(F).cuda()
+    out = ctx.solve(Ft, tol=1e-10)
+    assert out["iters"] == 1 and out["relres_true"] <= 1e-10
+    rp, ci, v, F = oracle.poisson_kron(2, 2, 32)
+    ctx = amg.Context(rp, ci, v)
+    Ft = torch.from_numpy(F).cuda()
+    zero = ctx.solve(torch.zeros_like(Ft))
+    assert zero["iters"] == 0 and zero["status"] == 0 and not zero["u"].any()
+    ctx1 = amg.Context(rp, ci, v, itmax=1)
+    one = ctx1.solve(Ft)
+    assert one["status"] == 1 and one["iters"] == 1
+    full = ctx.solve(Ft)
+    again = ctx.solve(Ft, u=full["u"].clone())
+    assert again["iters"] == 0
+    with pytest.raises(amg.AmgError):
+        bad = Ft.clone(); bad[3] = float("nan")
+        ctx.solve(bad)
+
+
+def test_determinism(oracle, amg):
+    print("case determinism", flush=True)
+    rp, ci, v, _ = oracle.poisson_kron(3, 3, 16)
+    from paper_2511_21268_amd.workloads import rhs_normal
+    F = torch.from_numpy(rhs_normal(len(rp) - 1, 5)).cuda()
+    ctx = amg.Context(rp, ci, v)
+    a = ctx.solve(F)
+    b = ctx.solve(F)
+    assert a["iters"] == b["iters"] and torch.equal(a["u"], b["u"])
