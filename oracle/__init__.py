@@ -74,6 +74,7 @@ def lib():
         L.or_params_default.argtypes = [C.POINTER(Params)]
         L.or_setup.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, C.POINTER(Params), C.POINTER(C.c_void_p)]
         L.or_free.argtypes = [C.c_void_p]
+        L.or_set_verbose.argtypes = [C.c_int]
         L.or_nlevels.argtypes = [C.c_void_p]
         L.or_level_info.argtypes = [C.c_void_p, C.c_int, i64p, i64p]
         L.or_level_matrix.argtypes = [C.c_void_p, C.c_int, i64p, i32p, f64p]
@@ -257,6 +258,10 @@ def spmv(rp, ci, v, x):
 def dot(x, y):
     x = _f64(x); y = _f64(y)
     return lib().or_dot(len(x), _p(x, f64p), _p(y, f64p))
+
+
+def set_verbose(v):
+    lib().or_set_verbose(int(v))
 
 
 def poly_accept(coef):

@@ -30,8 +30,12 @@
  */
 #include "oracle.h"
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+
+static int verbose = 0;
+void or_set_verbose(int v) { verbose = v; }
 
 void or_params_default(or_params *p)
 {
@@ -418,6 +422,11 @@ int or_setup(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
         L->agg = agg;
         L->pc = pc;
         level_from(&h->lev[l + 1], cur, cw);
+        if (verbose) {
+            fprintf(stderr, "oracle setup: level %d done: n=%lld nnz=%lld\n", l + 1, (long long)cur.n,
+                    (long long)cur.nnz);
+            fflush(stderr);
+        }
     }
     *out = h;
     return rc;

@@ -1,0 +1,127 @@
+"""GPU: flexible CG (FCG(1)), the FP32 V-cycle inside FP64 FCG, the error
+paths of the C ABI, and the degree-4 polynomial smoother, each against the
+oracle."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _csr(rp, ci, v):
+    return sp.csr_matrix((v, ci, rp), shape=(len(rp) - 1, len(rp) - 1))
+
+
+@pytest.fixture(scope="module")
+def amg():
+    import paper_2511_21268_amd as m
+    assert torch.cuda.is_available()
+    m.lib()
+    return m
+
+
+@pytest.mark.parametrize("d,p,n", [(2, 2, 32), (3, 3, 16), (3, 4, 12)])
+def test_fcg_fp64_parity(oracle, amg, d, p, n):
+    """FCG(1) with the FP64 V-cycle: same iterations and iterates as the
+    oracle's flexible CG."""
+    print(f"case fcg64 d={d} p={p} n={n}", flush=True)
+    from paper_2511_21268_amd.workloads import rhs_normal
+    rp, ci, v, _ = oracle.poisson_kron(d, p, n)
+    F = rhs_normal(len(rp) - 1, 4)
+    ref = oracle.Hierarchy(rp, ci, v).solve(F, tol=1e-8, flexible=True)
+    ctx = amg.Context(rp, ci, v, krylov=1)
+    out = ctx.solve(torch.from_numpy(F).cuda(), tol=1e-8)
+    u = out["u"].cpu().numpy()
+    assert out["status"] == 0 and out["iters"] == ref["iters"]
+    assert np.linalg.norm(u - ref["u"]) <= 1e-10 * np.linalg.norm(ref["u"])
+
+
+@pytest.mark.parametrize("d,p,n", [(2, 2, 32), (3, 3, 16), (3, 4, 12), (3, 4, 20)])
+def test_fp32_vcycle_fcg(oracle, amg, d, p, n):
+    """V-cycle in FP32 inside FP64 FCG: the FP64 true residual reaches 1e-8;
+    the V-cycle itself agrees with the FP64 oracle V-cycle to FP32 accuracy;
+    the solution error against the FP64 oracle solve is reported."""
+    print(f"case fp32 d={d} p={p} n={n}", flush=True)
+    from paper_2511_21268_amd.workloads import rhs_normal
+    rp, ci, v, _ = oracle.poisson_kron(d, p, n)
+    N = len(rp) - 1
+    F = rhs_normal(N, 1)
+    h = oracle.Hierarchy(rp, ci, v)
+    ref = h.solve(F, tol=1e-8)
+    ctx = amg.Context(rp, ci, v, krylov=1, vcycle_fp32=1)
+    r = np.random.default_rng(9).standard_normal(N)
+    z = ctx.vcycle(torch.from_numpy(r).cuda()).cpu().numpy()
+    zo = h.vcycle(r)
+    assert np.linalg.norm(z - zo) <= 2e-5 * np.linalg.norm(zo)
+    out = ctx.solve(torch.from_numpy(F).cuda(), tol=1e-8)
+    u = out["u"].cpu().numpy()
+    true = np.linalg.norm(F - _csr(rp, ci, v) @ u) / np.linalg.norm(F)
+    err = np.linalg.norm(u - ref["u"]) / np.linalg.norm(ref["u"])
+    print(f"  iters fp32/fcg={out['iters']} fp64/pcg oracle={ref['iters']} true={true:.2e} err={err:.2e}")
+    assert out["status"] == 0 and true <= 1e-8 and out["relres_true"] <= 1e-8
+    assert abs(out["iters"] - ref["iters"]) <= max(3, ref["iters"] // 10)
+    assert err <= 1e-6
+
+
+def test_not_spd_coarsest(amg):
+    """An indefinite matrix with a positive diagonal and <= 200 rows is a single
+    level whose dense Cholesky meets a non-positive pivot."""
+    print("case not-spd", flush=True)
+    n = 50
+    K = sp.diags([-1.5, 1.0, -1.5], [-1, 0, 1], shape=(n, n)).tocsr()
+    K.sort_indices()
+    with pytest.raises(amg.AmgError) as e:
+        amg.Context(K.indptr, K.indices, K.data)
+    assert e.value.status == -2
+
+
+def test_breakdown_matches_oracle(oracle, amg):
+    """Shifted 2D Laplacian L - s I with lambda_min(L) < s: the fine matrix is
+    indefinite while the Galerkin coarse matrices stay SPD, so set-up succeeds
+    and CG breaks down; both codes stop at the same iteration."""
+    print("case breakdown", flush=True)
+    n = 40
+    L = sp.diags([-1, -1, 4, -1, -1], [-n, -1, 0, 1, n], shape=(n * n, n * n)).tolil()
+    for i in range(1, n):
+        L[i * n, i * n - 1] = 0
+        L[i * n - 1, i * n] = 0
+    L = L.tocsr()
+    L.eliminate_zeros()
+    lmin = np.linalg.eigvalsh(L.toarray())[0]
+    K = (L - 1.5 * lmin * sp.identity(n * n)).tocsr()
+    K.sort_indices()
+    F = np.random.default_rng(0).standard_normal(n * n)
+    ref = oracle.Hierarchy(K.indptr, K.indices, K.data).solve(F)
+    assert ref["rc"] == -5
+    ctx = amg.Context(K.indptr, K.indices, K.data)
+    out = ctx.solve(torch.from_numpy(F).cuda(), check=False)
+    assert out["status"] == -5 and out["iters"] == ref["iters"]
+    assert np.all(np.isfinite(out["u"].cpu().numpy()))
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_polynomial_smoother_vcycle(oracle, amg, fp32):
+    """Degree-4 polynomial smoother on every level: V-cycle against the oracle's
+    (FP64: 1e-12; FP32: FP32 accuracy) and a converging solve."""
+    print(f"case poly fp32={fp32}", flush=True)
+    rp, ci, v, F = oracle.poisson_kron(3, 3, 16)
+    coef = [[2.0, -1.0, 0.0, 0.0], [4.0, -6.0, 4.0, -1.0], [1.7, -0.2, -0.6, 0.1]]
+    h = oracle.Hierarchy(rp, ci, v, smoother=1)
+    ctx = amg.Context(rp, ci, v, smoother=1, vcycle_fp32=fp32, krylov=fp32)
+    for l in range(h.nlevels - 1):
+        c = coef[l % 3]
+        assert h.set_poly(l, c) == 0
+        assert ctx.set_poly(l, c) == 0
+    assert ctx.set_poly(0, [3.0, 0, 0, 0]) == 1          # rejected: keeps its coefficients
+    r = np.random.default_rng(3).standard_normal(len(F))
+    z = ctx.vcycle(torch.from_numpy(r).cuda()).cpu().numpy()
+    zo = h.vcycle(r)
+    tol = 2e-5 if fp32 else 1e-12
+    assert np.linalg.norm(z - zo) <= tol * np.linalg.norm(zo)
+    ref = h.solve(F, flexible=bool(fp32))
+    out = ctx.solve(torch.from_numpy(F).cuda())
+    assert out["status"] == 0 and out["relres_true"] <= 1e-8
+    if not fp32:
+        assert out["iters"] == ref["iters"]

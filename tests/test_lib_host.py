@@ -1,0 +1,151 @@
+"""Host side of the HIP library (no GPU): the C ABI loads and exports what
+include/amg.h declares, and the library's own set-up (suitor matching,
+pairwise prolongator, Galerkin product, level loop) reproduces the oracle's
+hierarchy bit for bit (paper Sec. 3.1)."""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def amg():
+    import paper_2511_21268_amd as m
+    m.lib()
+    return m
+
+
+def test_library_exports_every_declared_symbol(amg):
+    hdr = open(os.path.join(ROOT, "include", "amg.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    declared = set(re.findall(r"\b((?:amg|pcg)_[a-z0-9_]+)\s*\(", hdr))
+    assert len(declared) >= 15
+    lib = amg.lib()
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    from paper_2511_21268_amd.amg import EXPORTS
+    assert declared == set(EXPORTS)
+
+
+def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
+    import paper_2511_21268_amd.amg as A
+    monkeypatch.setattr(A, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(A, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        A.lib()
+    monkeypatch.undo()
+    assert A.lib() is not None
+
+
+def _random_sym(n, density, seed, ties):
+    rng = np.random.default_rng(seed)
+    A = sp.random(n, n, density=density, random_state=seed,
+                  data_rvs=(lambda k: -rng.integers(1, 4, k) / 4.0) if ties else (lambda k: rng.uniform(-1, 1, k)))
+    A = sp.triu(A, 1)
+    A = (A + A.T).tocsr()
+    d = np.abs(A).sum(axis=1).A1 + (1.0 if ties else rng.uniform(0.1, 1.0, n))
+    A = (A + sp.diags(d)).tocsr()
+    A.sort_indices()
+    return A
+
+
+@pytest.mark.parametrize("seed,ties,pos", [(0, True, False), (1, True, False), (2, False, False),
+                                           (3, True, True), (4, False, True)])
+def test_suitor_matching_equals_sorted_greedy(oracle, amg, seed, ties, pos):
+    A = _random_sym(400, 0.02, seed, ties)
+    w = None if ties else np.random.default_rng(seed).uniform(0.2, 1.5, 400)
+    m_lib = amg.match(A.indptr, A.indices, A.data, w, positive_only=pos)
+    m_or = oracle.match(A.indptr, A.indices, A.data, w, positive_only=pos)
+    assert np.array_equal(m_lib, m_or)
+    assert oracle.check_greedy(A.indptr, A.indices, A.data, m_lib, w, positive_only=pos) == 0
+
+
+def _compare_hierarchies(ctx, h):
+    assert ctx.nlevels == h.nlevels
+    for l in range(h.nlevels):
+        assert ctx.level_info(l) == h.level_info(l)
+    for l in range(h.nlevels - 1):
+        a, pc = ctx.aggregates(l)
+        ao, pco, _, _ = h.level_agg(l)
+        assert np.array_equal(a, ao), l
+        assert np.array_equal(pc.view(np.int64), pco.view(np.int64)), l
+    for l in range(1, h.nlevels):
+        for x, y in zip(ctx.coarse_matrix(l), h.level_matrix(l)):
+            assert np.array_equal(np.asarray(x).view(np.uint8), np.asarray(y).view(np.uint8)), l
+
+
+@pytest.mark.parametrize("d,p,n,kw", [
+    (2, 2, 32, {}),
+    (2, 3, 50, {}),
+    (3, 2, 14, {}),
+    (3, 3, 18, {}),
+    (3, 4, 10, {}),
+    (2, 2, 40, {"sweeps_per_level": 1}),
+    (2, 2, 40, {"sweeps_per_level": 3}),
+    (3, 3, 12, {"match_positive_only": 1}),
+    (2, 2, 40, {"max_coarse": 50}),
+])
+def test_host_hierarchy_bitwise_equals_oracle(oracle, amg, d, p, n, kw):
+    rp, ci, v, _ = oracle.poisson_kron(d, p, n)
+    ctx = amg.Context(rp, ci, v, host_only=True, **kw)
+    h = oracle.Hierarchy(rp, ci, v, **kw)
+    _compare_hierarchies(ctx, h)
+
+
+def test_host_hierarchy_with_test_vector_and_kappa(oracle, amg):
+    from paper_2511_21268_amd.workloads import kappa_params
+    a, mk = kappa_params(7)
+    rp, ci, v, _ = oracle.diffusion_quad3d(2, 6, a, mk)
+    # the quadrature matrix is symmetric only up to rounding: symmetrise exactly
+    K = sp.csr_matrix((v, ci, rp))
+    K = ((K + K.T) * 0.5).tocsr()
+    K.sort_indices()
+    w = np.random.default_rng(0).uniform(0.5, 1.5, K.shape[0])
+    ctx = amg.Context(K.indptr, K.indices, K.data, w=w, host_only=True)
+    h = oracle.Hierarchy(K.indptr, K.indices, K.data, w=w)
+    _compare_hierarchies(ctx, h)
+
+
+def test_generator_equals_oracle_assembly(oracle, amg):
+    for d, p, n in [(2, 2, 32), (3, 3, 12), (3, 4, 9), (3, 5, 8)]:
+        rp, ci, v, F = amg.iga_poisson(d, p, n)
+        ro, co, vo, Fo = oracle.poisson_kron(d, p, n)
+        assert np.array_equal(rp, ro) and np.array_equal(ci, co)
+        assert np.abs(v - vo).max() <= 2e-15 * np.abs(vo).max()
+        assert np.abs(F - Fo).max() <= 2e-15 * np.abs(Fo).max()
+        K = sp.csr_matrix((v, ci, rp))
+        assert (K != K.T).nnz == 0
+
+
+def test_setup_rejects_invalid_input(amg):
+    from paper_2511_21268_amd.amg import AMG_ERR_ARG
+    rp = np.array([0, 2, 4]); ci = np.array([0, 1, 0, 1])
+    cases = [
+        np.array([2.0, -1.0, -0.5, 2.0]),            # values not symmetric
+        np.array([2.0, -1.0, -1.0, -2.0]),           # non-positive diagonal
+        np.array([2.0, np.nan, np.nan, 2.0]),        # non-finite
+    ]
+    for v in cases:
+        with pytest.raises(amg.AmgError) as e:
+            amg.Context(rp, ci, v, host_only=True)
+        assert e.value.status == AMG_ERR_ARG
+    with pytest.raises(amg.AmgError):                # pattern not symmetric
+        amg.Context(np.array([0, 2, 3]), np.array([0, 1, 1]), np.array([2.0, -1.0, 2.0]), host_only=True)
+    with pytest.raises(amg.AmgError):                # unsorted columns
+        amg.Context(np.array([0, 2, 4]), np.array([1, 0, 0, 1]), np.array([-1.0, 2.0, -1.0, 2.0]), host_only=True)
+    with pytest.raises(amg.AmgError):                # missing diagonal
+        amg.Context(np.array([0, 1, 2]), np.array([1, 0]), np.array([-1.0, -1.0]), host_only=True)
+    with pytest.raises(amg.AmgError):                # bad parameter
+        amg.Context(rp, ci, np.array([2.0, -1.0, -1.0, 2.0]), host_only=True, sweeps_per_level=0)
+
+
+def test_operator_complexity_reported(amg, oracle):
+    rp, ci, v, _ = oracle.poisson_kron(3, 3, 16)
+    ctx = amg.Context(rp, ci, v, host_only=True)
+    h = oracle.Hierarchy(rp, ci, v)
+    assert ctx.opc() == pytest.approx(h.opc(), rel=1e-15)
+    assert 1.0 < ctx.opc() < 2.0
