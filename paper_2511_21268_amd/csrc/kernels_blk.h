@@ -1,0 +1,388 @@
+// Block (multi right-hand side) kernels of the batched solve: NB = 16 columns
+// held row-major (X[row * 16 + j], 64 B per row in FP32, 128 B in FP64) so that
+// one matrix entry, read once from HBM, multiplies 16 contiguous values.
+//
+// The matrix is the same SELL-64 image as the single-vector kernels (layout in
+// kernels.h).  A wavefront covers a 64-row slice; with LPR lanes per row it
+// walks the slice in LPR sub-slices of 64/LPR rows, each lane owning 16/LPR
+// columns.  Per column, every row sum, every dot partial and every vector
+// update uses the same operation order as the single-vector kernels, so a
+// column of the block solve carries the same bits as the single solve.
+#pragma once
+#include "kernels.h"
+
+namespace amgk {
+
+constexpr int NB = 16;
+
+// per-column scalar slots: sc[slot * NB + j]
+enum BSlot { B_RZ = 0, B_PQ, B_RR, B_ALPHA, B_BETA, B_PR, B_ZQ, B_FF, B_FLAG, B_DONE, B_ITERS, B_THR, B_NSLOTS };
+enum BFin { BF_FF = 0, BF_RR0, BF_RZ0, BF_PQ_CG, BF_PQ_FCG, BF_RR, BF_RZ_CG, BF_ZQ_FCG };
+
+__device__ inline bool bactive(const double *sc, int j) { return sc[B_DONE * NB + j] == 0.0 && sc[B_FLAG * NB + j] == 0.0; }
+
+// Sum over the 256-thread block of one value per thread and column, per column
+// in the order of block_sum; results valid in thread 0 (out[NB]).
+template <int NC>
+__device__ inline void block_sum_cols(double (&v)[NC], double *lds /* 4 * NC */)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NC; j++) v[j] = wave_sum(v[j]);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < NC; j++) lds[wid * NC + j] = v[j];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < NC; j++) v[j] = ((lds[j] + lds[NC + j]) + lds[2 * NC + j]) + lds[3 * NC + j];
+}
+
+template <typename T> struct BlkVec;
+template <> struct BlkVec<float> {
+    static __device__ inline void load(const float *p, float (&o)[NB])
+    {
+        const vf4 *q = reinterpret_cast<const vf4 *>(p);
+#pragma unroll
+        for (int h = 0; h < 4; h++) {
+            vf4 t = q[h];
+            o[4 * h] = t.x; o[4 * h + 1] = t.y; o[4 * h + 2] = t.z; o[4 * h + 3] = t.w;
+        }
+    }
+};
+template <> struct BlkVec<double> {
+    static __device__ inline void load(const double *p, double (&o)[NB])
+    {
+        const vd2 *q = reinterpret_cast<const vd2 *>(p);
+#pragma unroll
+        for (int h = 0; h < 8; h++) {
+            vd2 t = q[h];
+            o[2 * h] = t.x; o[2 * h + 1] = t.y;
+        }
+    }
+};
+
+// Block matrix pass, lane = row (all 16 columns per lane).  Epilogues as k_sell:
+//   EPI_SPMV : Y = K X;                 dots per column (X_j, Y_j), (X_j, G1_j)
+//   EPI_RESID: Y = F - K X
+//   EPI_SMOOTH: Y = X + D^{-1}(F - K X); dots per column (Y_j, G0_j), (Y_j, G1_j)
+//   EPI_POLY : Y = a D^{-1} F + D^{-1} K X
+// Partials: partial[(blockIdx.x * 2 + d) * NB + j].
+template <typename VT, typename FT, typename OT, typename IT, int EPI, int NDOT>
+__global__ __launch_bounds__(256) void k_sell_blk(int64_t nrows, int64_t nslices, const int64_t *__restrict__ soff,
+                                                  const VT *__restrict__ val, const IT *__restrict__ idx,
+                                                  const int32_t *__restrict__ col0, const VT *__restrict__ X,
+                                                  const FT *__restrict__ F, const VT *__restrict__ invd,
+                                                  OT *__restrict__ Y, const double *__restrict__ G0,
+                                                  const double *__restrict__ G1, double *__restrict__ partial,
+                                                  VT coef)
+{
+    __shared__ double lds[8 * NB];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t s = (int64_t)blockIdx.x * SELL_WAVES + wid;
+    double d0[NB], d1[NB];
+#pragma unroll
+    for (int j = 0; j < NB; j++) { d0[j] = 0.0; d1[j] = 0.0; }
+    if (s < nslices) {
+        const int64_t row = s * SLICE + lane;
+        const int64_t base = soff[s];
+        const int width = (int)((soff[s + 1] - base) >> 6);
+        int col = (sizeof(IT) == 2) ? col0[row] : 0;
+        VT acc[NB];
+#pragma unroll
+        for (int j = 0; j < NB; j++) acc[j] = 0;
+        for (int kk = 0; kk < width; kk += 8) {
+            VT v[8];
+            int c[8];
+            load_idx8(idx, base, kk, lane, col, c);
+            load8(val, base, kk, lane, v);
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                VT xv[NB];
+                BlkVec<VT>::load(X + (int64_t)c[t] * NB, xv);
+#pragma unroll
+                for (int j = 0; j < NB; j++) acc[j] = fma(v[t], xv[j], acc[j]);
+            }
+        }
+        if (row < nrows) {
+            const int64_t o = row * NB;
+            if (EPI == EPI_SPMV) {
+#pragma unroll
+                for (int j = 0; j < NB; j++) {
+                    Y[o + j] = (OT)acc[j];
+                    if (NDOT >= 1) d0[j] = (double)X[o + j] * (double)acc[j];
+                    if (NDOT >= 2) d1[j] = (double)X[o + j] * G1[o + j];
+                }
+            } else if (EPI == EPI_RESID) {
+#pragma unroll
+                for (int j = 0; j < NB; j++) Y[o + j] = (OT)((VT)F[o + j] - acc[j]);
+            } else if (EPI == EPI_SMOOTH) {
+                const VT di = invd[row];
+#pragma unroll
+                for (int j = 0; j < NB; j++) {
+                    VT out = X[o + j] + di * ((VT)F[o + j] - acc[j]);
+                    Y[o + j] = (OT)out;
+                    if (NDOT >= 1) d0[j] = (double)out * G0[o + j];
+                    if (NDOT >= 2) d1[j] = (double)out * G1[o + j];
+                }
+            } else {
+                const VT di = invd[row];
+#pragma unroll
+                for (int j = 0; j < NB; j++) Y[o + j] = (OT)(coef * (di * (VT)F[o + j]) + di * acc[j]);
+            }
+        }
+    }
+    if (NDOT >= 1) {
+        block_sum_cols<NB>(d0, lds);
+        if (NDOT >= 2) block_sum_cols<NB>(d1, lds + 4 * NB);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int j = 0; j < NB; j++) {
+                partial[(2 * blockIdx.x) * NB + j] = d0[j];
+                partial[(2 * blockIdx.x + 1) * NB + j] = NDOT >= 2 ? d1[j] : 0.0;
+            }
+    }
+}
+
+// ---- elementwise block kernels (one thread per row, 16 columns) ---------------
+
+template <typename VT, typename FT>
+__global__ void k_scale_blk(int64_t n, const VT *__restrict__ invd, const FT *__restrict__ f, VT *__restrict__ u,
+                            VT coef)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const VT di = invd[i];
+#pragma unroll
+    for (int j = 0; j < NB; j++) u[i * NB + j] = coef * (di * (VT)f[i * NB + j]);
+}
+
+// coef == 1 keeps the l1 sweep's bits: 1 * (d * f) == d * f exactly.
+template <typename VT>
+__global__ void k_restrict_blk(int64_t nc, int mw, const int32_t *__restrict__ members, const VT *__restrict__ pc,
+                               const VT *__restrict__ r, VT *__restrict__ fc, const VT *__restrict__ invdc,
+                               VT *__restrict__ uc, VT coef)
+{
+#pragma clang fp contract(off)
+    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    VT s[NB];
+#pragma unroll
+    for (int j = 0; j < NB; j++) s[j] = 0;
+    for (int t = 0; t < mw; t++) {
+        int m = members[I * mw + t];
+        if (m < 0) break;
+        const VT pm = pc[m];
+#pragma unroll
+        for (int j = 0; j < NB; j++) {
+            VT prod = pm * r[(int64_t)m * NB + j];
+            s[j] = s[j] + prod;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; j++) fc[I * NB + j] = s[j];
+    if (uc) {
+        const VT di = invdc[I];
+#pragma unroll
+        for (int j = 0; j < NB; j++) uc[I * NB + j] = coef * (di * s[j]);
+    }
+}
+
+template <typename VT>
+__global__ void k_prolong_blk(int64_t n, const int32_t *__restrict__ agg, const VT *__restrict__ pc,
+                              const VT *__restrict__ e, VT *__restrict__ u)
+{
+#pragma clang fp contract(off)
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const VT pi = pc[i];
+    const int64_t a = (int64_t)agg[i] * NB;
+#pragma unroll
+    for (int j = 0; j < NB; j++) {
+        VT prod = pi * e[a + j];
+        u[i * NB + j] = u[i * NB + j] + prod;
+    }
+}
+
+template <typename VT, typename OT>
+__global__ void k_add_blk(int64_t n, const VT *__restrict__ x, const VT *__restrict__ c, OT *__restrict__ y)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * NB) return;
+    y[i] = (OT)(x[i] + c[i]);
+}
+
+// Coarsest level, 16 columns: E = L^{-T} (L^{-1} F) in FP64, one block; Y is a
+// global scratch of n * NB doubles.  Per column the same sums as k_coarse_solve.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_coarse_solve_blk(int n, int ld, const double *__restrict__ Linv,
+                                                          const double *__restrict__ LinvT, const VT *__restrict__ f,
+                                                          double *__restrict__ Y, VT *__restrict__ e)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int i = wid; i < n; i += 4) {
+        const double *row = Linv + (int64_t)i * ld;
+        for (int j = 0; j < NB; j++) {
+            double s = 0.0;
+            for (int k = lane; k <= i; k += 64) s = fma(row[k], (double)f[(int64_t)k * NB + j], s);
+            s = wave_sum(s);
+            if (lane == 0) Y[(int64_t)i * NB + j] = s;
+        }
+    }
+    __syncthreads();
+    for (int jr = wid; jr < n; jr += 4) {
+        const double *row = LinvT + (int64_t)jr * ld;
+        for (int j = 0; j < NB; j++) {
+            double s = 0.0;
+            for (int k = jr + lane; k < n; k += 64) s = fma(row[k], Y[(int64_t)k * NB + j], s);
+            s = wave_sum(s);
+            if (lane == 0) e[(int64_t)jr * NB + j] = (VT)s;
+        }
+    }
+}
+
+// Column-major (n x k, leading dimension n) <-> row-major block (n x NB).
+__global__ void k_pack_blk(int64_t n, int k, const double *__restrict__ cm, double *__restrict__ rm)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+#pragma unroll
+    for (int j = 0; j < NB; j++) rm[i * NB + j] = j < k ? cm[(int64_t)j * n + i] : 0.0;
+}
+
+__global__ void k_unpack_blk(int64_t n, int k, const double *__restrict__ rm, double *__restrict__ cm)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int j = 0; j < k; j++) cm[(int64_t)j * n + i] = rm[i * NB + j];
+}
+
+// Dot partials per column, same grid-stride order as k_dot2.
+__global__ void k_dot2_blk(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                           const double *__restrict__ c, double *__restrict__ partial)
+{
+    __shared__ double lds[8 * NB];
+    double s0[NB], s1[NB];
+#pragma unroll
+    for (int j = 0; j < NB; j++) { s0[j] = 0.0; s1[j] = 0.0; }
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+#pragma unroll
+        for (int j = 0; j < NB; j++) {
+            s0[j] = fma(a[i * NB + j], b[i * NB + j], s0[j]);
+            if (c) s1[j] = fma(a[i * NB + j], c[i * NB + j], s1[j]);
+        }
+    }
+    block_sum_cols<NB>(s0, lds);
+    block_sum_cols<NB>(s1, lds + 4 * NB);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < NB; j++) {
+            partial[(2 * blockIdx.x) * NB + j] = s0[j];
+            partial[(2 * blockIdx.x + 1) * NB + j] = s1[j];
+        }
+}
+
+// u += alpha p ; r -= alpha q for the active columns; partials of (r, r).
+__global__ void k_bcg_update(int64_t n, const double *__restrict__ sc, double *__restrict__ u,
+                             double *__restrict__ r, const double *__restrict__ p, const double *__restrict__ q,
+                             double *__restrict__ partial)
+{
+    __shared__ double lds[4 * NB];
+    double al[NB], s[NB];
+    bool act[NB];
+#pragma unroll
+    for (int j = 0; j < NB; j++) { act[j] = bactive(sc, j); al[j] = sc[B_ALPHA * NB + j]; s[j] = 0.0; }
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+#pragma unroll
+        for (int j = 0; j < NB; j++) {
+            double ri = r[i * NB + j];
+            if (act[j]) {
+                u[i * NB + j] = fma(al[j], p[i * NB + j], u[i * NB + j]);
+                ri = fma(-al[j], q[i * NB + j], ri);
+                r[i * NB + j] = ri;
+            }
+            s[j] = fma(ri, ri, s[j]);
+        }
+    }
+    block_sum_cols<NB>(s, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < NB; j++) { partial[(2 * blockIdx.x) * NB + j] = s[j]; partial[(2 * blockIdx.x + 1) * NB + j] = 0.0; }
+}
+
+__global__ void k_bcg_pupdate(int64_t n, const double *__restrict__ sc, const double *__restrict__ z,
+                              double *__restrict__ p)
+{
+    double be[NB];
+    bool act[NB];
+#pragma unroll
+    for (int j = 0; j < NB; j++) { act[j] = bactive(sc, j); be[j] = sc[B_BETA * NB + j]; }
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+#pragma unroll
+        for (int j = 0; j < NB; j++)
+            if (act[j]) p[i * NB + j] = fma(be[j], p[i * NB + j], z[i * NB + j]);
+}
+
+// Final per-column sums of the partials (index order) and the scalar
+// recurrences, masks and iteration counters of the 16 independent solves.
+__global__ __launch_bounds__(256) void k_bfinalize(const double *__restrict__ partial, int nblk, double *sc,
+                                                   int op, int k, double tol)
+{
+    __shared__ double lds[8 * NB];
+    double s0[NB], s1[NB];
+#pragma unroll
+    for (int j = 0; j < NB; j++) { s0[j] = 0.0; s1[j] = 0.0; }
+    for (int b = threadIdx.x; b < nblk; b += 256)
+#pragma unroll
+        for (int j = 0; j < NB; j++) { s0[j] += partial[(2 * b) * NB + j]; s1[j] += partial[(2 * b + 1) * NB + j]; }
+    block_sum_cols<NB>(s0, lds);
+    block_sum_cols<NB>(s1, lds + 4 * NB);
+    if (threadIdx.x != 0) return;
+    for (int j = 0; j < NB; j++) {
+        const double a = s0[j], b = s1[j];
+        double *F = sc + B_FLAG * NB + j, *D = sc + B_DONE * NB + j;
+        switch (op) {
+        case BF_FF:
+            sc[B_FF * NB + j] = a;
+            sc[B_THR * NB + j] = tol * sqrt(a);
+            break;
+        case BF_RR0:   // initial residual: converged columns are done before any update
+            sc[B_RR * NB + j] = a;
+            if (sc[B_FF * NB + j] == 0.0 || sqrt(a) <= sc[B_THR * NB + j]) *D = 1.0;
+            break;
+        case BF_RZ0:
+            if (*D != 0.0) break;
+            sc[B_RZ * NB + j] = a;
+            if (!(a > 0.0) || !isfinite(a)) *F = 2.0;
+            break;
+        case BF_PQ_CG:
+        case BF_PQ_FCG:
+            if (*D != 0.0 || *F != 0.0) break;
+            sc[B_PQ * NB + j] = a;
+            if (op == BF_PQ_FCG) sc[B_PR * NB + j] = b;
+            if (!(a > 0.0) || !isfinite(a)) *F = 1.0;
+            else sc[B_ALPHA * NB + j] = (op == BF_PQ_FCG ? b : sc[B_RZ * NB + j]) / a;
+            break;
+        case BF_RR:
+            if (*D != 0.0 || *F != 0.0) break;
+            sc[B_RR * NB + j] = a;
+            sc[B_ITERS * NB + j] = (double)k;
+            if (sqrt(a) <= sc[B_THR * NB + j]) *D = 1.0;
+            break;
+        case BF_RZ_CG:
+            if (*D != 0.0 || *F != 0.0) break;
+            if (!(a > 0.0) || !isfinite(a)) *F = 2.0;
+            else { sc[B_BETA * NB + j] = a / sc[B_RZ * NB + j]; sc[B_RZ * NB + j] = a; }
+            break;
+        case BF_ZQ_FCG:
+            if (*D != 0.0 || *F != 0.0) break;
+            sc[B_ZQ * NB + j] = a;
+            if (!isfinite(a)) *F = 2.0;
+            else sc[B_BETA * NB + j] = -a / sc[B_PQ * NB + j];
+            break;
+        }
+    }
+}
+
+}  // namespace amgk

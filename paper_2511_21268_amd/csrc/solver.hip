@@ -6,6 +6,7 @@
 #include "coarse.h"
 #include "host.h"
 #include "kernels.h"
+#include "kernels_blk.h"
 
 #include <hip/hip_runtime.h>
 
@@ -151,8 +152,9 @@ struct Level {
     int mw = 0;
     double *pc64 = nullptr;
     float *pc32 = nullptr;
-    // work vectors in the V-cycle precision
+    // work vectors in the V-cycle precision (single vector, and 16-column blocks)
     void *f = nullptr, *u = nullptr, *u2 = nullptr, *r = nullptr, *c = nullptr, *c2 = nullptr;
+    void *bf = nullptr, *bu = nullptr, *bu2 = nullptr, *br = nullptr, *bc = nullptr, *bc2 = nullptr;
     double poly[4] = {1.0, 0.0, 0.0, 0.0};
     int poly_on = 0;
     template <typename VT> VT *invd() const;
@@ -179,6 +181,9 @@ struct amg_ctx {
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
     double *partial = nullptr;
     int64_t partial_cap = 0;
+    // batched solve (allocated on first use)
+    double *bR = nullptr, *bZ = nullptr, *bP = nullptr, *bQ = nullptr, *bU = nullptr, *bF = nullptr;
+    double *bY = nullptr, *bsc = nullptr, *hbsc = nullptr, *bpartial = nullptr;
     double *sc = nullptr;
     double *hsc = nullptr;     // pinned host copy of the scalar block
     hipEvent_t ev_iter = nullptr;
@@ -208,6 +213,7 @@ struct amg_ctx {
         if (!host_only) (void)hipStreamSynchronize(stream);
         for (void *p : allocs) (void)hipFree(p);
         if (hsc) (void)hipHostFree(hsc);
+        if (hbsc) (void)hipHostFree(hbsc);
         if (ev_iter) (void)hipEventDestroy(ev_iter);
         for (auto e : evpool) (void)hipEventDestroy(e);
     }
@@ -434,6 +440,171 @@ struct amg_ctx {
         }
         if (fp32()) vlevel<float, double>(0, rin, zout, ndot, g0, g1, false);
         else vlevel<double, double>(0, rin, zout, ndot, g0, g1, false);
+        return vc_nb;
+    }
+
+    // ---- batched (16 columns) ------------------------------------------------
+    void blk_alloc()
+    {
+        if (bR) return;
+        const size_t vsz = fp32() ? sizeof(float) : sizeof(double);
+        for (int l = 0; l < nlev; l++) {
+            Level &L = lev[l];
+            size_t nn = (size_t)L.n * NB * vsz;
+            L.bf = alloc<char>(nn); L.bu = alloc<char>(nn); L.bu2 = alloc<char>(nn);
+            L.br = alloc<char>(nn); L.bc = alloc<char>(nn); L.bc2 = alloc<char>(nn);
+        }
+        size_t nb = (size_t)n * NB;
+        bR = alloc<double>(nb); bZ = alloc<double>(nb); bP = alloc<double>(nb);
+        bQ = alloc<double>(nb); bU = alloc<double>(nb); bF = alloc<double>(nb);
+        bY = alloc<double>((size_t)std::max(nL, 1) * NB);
+        bsc = alloc<double>(B_NSLOTS * NB);
+        bpartial = alloc<double>((size_t)partial_cap * NB);
+        HIPCHK(hipHostMalloc((void **)&hbsc, B_NSLOTS * NB * sizeof(double), hipHostMallocDefault));
+    }
+    template <typename VT, typename FT, typename OT, int EPI, int NDOT>
+    void sell_blk(int l, const VT *x, const FT *f, const VT *invd, OT *y, const double *g0, const double *g1,
+                  VT coef = 1)
+    {
+        const DevMat &A = lev[l].A;
+        unsigned nb = sell_blocks(l);
+        if (l == 0) prof_begin();
+        if (A.idx16)
+            hipLaunchKernelGGL((k_sell_blk<VT, FT, OT, uint16_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream, A.n,
+                               A.nslices, A.soff, A.val<VT>(), A.d16, A.col0, x, f, invd, y, g0, g1, bpartial, coef);
+        else
+            hipLaunchKernelGGL((k_sell_blk<VT, FT, OT, int32_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream, A.n,
+                               A.nslices, A.soff, A.val<VT>(), A.c32, A.col0, x, f, invd, y, g0, g1, bpartial, coef);
+        HIPCHK(hipGetLastError());
+        if (l == 0) {
+            // 16 columns: matrix once, 16 vectors of each kind
+            const DevMat &M = lev[0].A;
+            double ib = M.idx16 ? 2.0 : 4.0;
+            int nvec = 2 + (EPI == EPI_RESID ? 1 : 0) + (EPI == EPI_SMOOTH ? 1 : 0) + (EPI == EPI_POLY ? 1 : 0) +
+                       (NDOT >= 2 ? 1 : 0) + (EPI == EPI_SMOOTH && NDOT >= 1 ? 1 : 0);
+            double bytes = (double)M.nnz * (sizeof(VT) + ib) + (M.idx16 ? 4.0 * M.n : 0.0) +
+                           (double)nvec * NB * sizeof(VT) * M.n +
+                           ((EPI == EPI_SMOOTH || EPI == EPI_POLY) ? (double)sizeof(VT) * M.n : 0.0);
+            prof_end(bytes);
+        }
+    }
+    void bfinalize(unsigned nblk, int op, int k = 0, double tol = 0.0)
+    {
+        hipLaunchKernelGGL(k_bfinalize, dim3(1), dim3(256), 0, stream, bpartial, (int)nblk, bsc, op, k, tol);
+        HIPCHK(hipGetLastError());
+    }
+    unsigned bdot_partials(int64_t m, const double *a, const double *b, const double *c)
+    {
+        unsigned g = vgrid(m);
+        hipLaunchKernelGGL(k_dot2_blk, dim3(g), dim3(256), 0, stream, m, a, b, c, bpartial);
+        HIPCHK(hipGetLastError());
+        return g;
+    }
+    template <typename VT, typename FT> VT *bpoly_apply(int l, const FT *rr, VT *&c, VT *&c2)
+    {
+        Level &L = lev[l];
+        hipLaunchKernelGGL((k_scale_blk<VT, FT>), dim3(nblocks(L.n)), dim3(256), 0, stream, L.n, L.invd<VT>(), rr,
+                           c, (VT)L.poly[3]);
+        HIPCHK(hipGetLastError());
+        for (int k = 2; k >= 0; k--) {
+            sell_blk<VT, FT, VT, EPI_POLY, 0>(l, c, rr, L.invd<VT>(), c2, nullptr, nullptr, (VT)L.poly[k]);
+            std::swap(c, c2);
+        }
+        return c;
+    }
+    template <typename VT, typename FT, typename OT>
+    void bsweep(int l, const FT *f, const VT *uin, OT *uout, int ndot, const double *g0, const double *g1)
+    {
+        Level &L = lev[l];
+        if (!L.poly_on) {
+            if (ndot == 2) sell_blk<VT, FT, OT, EPI_SMOOTH, 2>(l, uin, f, L.invd<VT>(), uout, g0, g1);
+            else if (ndot == 1) sell_blk<VT, FT, OT, EPI_SMOOTH, 1>(l, uin, f, L.invd<VT>(), uout, g0, g1);
+            else sell_blk<VT, FT, OT, EPI_SMOOTH, 0>(l, uin, f, L.invd<VT>(), uout, g0, g1);
+            if (ndot) vc_nb = sell_blocks(l);
+            return;
+        }
+        VT *res = (VT *)L.br, *c = (VT *)L.bc, *c2 = (VT *)L.bc2;
+        sell_blk<VT, FT, VT, EPI_RESID, 0>(l, uin, f, L.invd<VT>(), res, nullptr, nullptr);
+        const VT *cr = bpoly_apply<VT, VT>(l, res, c, c2);
+        hipLaunchKernelGGL((k_add_blk<VT, OT>), dim3(nblocks(L.n * NB)), dim3(256), 0, stream, L.n, uin, cr, uout);
+        HIPCHK(hipGetLastError());
+        if (ndot) vc_nb = bdot_partials(L.n, (const double *)uout, g0, g1);
+    }
+    template <typename VT, typename FT>
+    VT *vlevel_blk(int l, const FT *f, double *zout, int ndot, const double *g0, const double *g1, bool u_ready)
+    {
+        Level &L = lev[l];
+        VT *u = (VT *)L.bu, *u2 = (VT *)L.bu2;
+        if (!u_ready) {
+            if (L.poly_on) {
+                VT *c = (VT *)L.bc, *c2 = (VT *)L.bc2;
+                VT *res = bpoly_apply<VT, FT>(l, f, c, c2);
+                hipLaunchKernelGGL((k_copy<VT, VT>), dim3(vgrid(L.n * NB)), dim3(256), 0, stream, L.n * NB,
+                                   (const VT *)res, u);
+            } else {
+                hipLaunchKernelGGL((k_scale_blk<VT, FT>), dim3(nblocks(L.n)), dim3(256), 0, stream, L.n,
+                                   L.invd<VT>(), f, u, (VT)1);
+            }
+            HIPCHK(hipGetLastError());
+        } else if (L.poly_on) {
+            VT *c = u, *c2 = (VT *)L.bc2;
+            for (int k = 2; k >= 0; k--) {
+                sell_blk<VT, FT, VT, EPI_POLY, 0>(l, c, f, L.invd<VT>(), c2, nullptr, nullptr, (VT)L.poly[k]);
+                std::swap(c, c2);
+            }
+            if (c != u) copy<VT, VT>(L.n * NB, c, u);
+        }
+        for (int s = 1; s < prm.nu_pre; s++) {
+            bsweep<VT, FT, VT>(l, f, u, u2, 0, nullptr, nullptr);
+            std::swap(u, u2);
+        }
+        sell_blk<VT, FT, VT, EPI_RESID, 0>(l, u, f, L.invd<VT>(), (VT *)L.br, nullptr, nullptr);
+        Level &C = lev[l + 1];
+        const bool coarsest = (l + 1 == nlev - 1);
+        const VT a3 = C.poly_on ? (VT)C.poly[3] : (VT)1;
+        hipLaunchKernelGGL((k_restrict_blk<VT>), dim3(nblocks(C.n)), dim3(256), 0, stream, C.n, L.mw, L.members,
+                           L.pc<VT>(), (const VT *)L.br, (VT *)C.bf, coarsest ? nullptr : C.invd<VT>(),
+                           coarsest ? nullptr : (VT *)C.bu, a3);
+        HIPCHK(hipGetLastError());
+        VT *e;
+        if (coarsest) {
+            e = (VT *)C.bu;
+            hipLaunchKernelGGL((k_coarse_solve_blk<VT>), dim3(1), dim3(256), 0, stream, nL, ldL, Linv, LinvT,
+                               (const VT *)C.bf, bY, e);
+            HIPCHK(hipGetLastError());
+        } else {
+            e = vlevel_blk<VT, VT>(l + 1, (const VT *)C.bf, nullptr, 0, nullptr, nullptr, true);
+        }
+        hipLaunchKernelGGL((k_prolong_blk<VT>), dim3(nblocks(L.n)), dim3(256), 0, stream, L.n, L.agg, L.pc<VT>(), e,
+                           u);
+        HIPCHK(hipGetLastError());
+        for (int s = 1; s <= prm.nu_post; s++) {
+            if (zout && s == prm.nu_post) {
+                bsweep<VT, FT, double>(l, f, u, zout, ndot, g0, g1);
+                return nullptr;
+            }
+            bsweep<VT, FT, VT>(l, f, u, u2, 0, nullptr, nullptr);
+            std::swap(u, u2);
+        }
+        if (zout) {
+            copy<double, VT>(L.n * NB, u, zout);
+            if (ndot) vc_nb = bdot_partials(L.n, zout, g0, g1);
+            return nullptr;
+        }
+        return u;
+    }
+    unsigned vcycle_blk(const double *rin, double *zout, int ndot, const double *g0, const double *g1)
+    {
+        vc_nb = 0;
+        if (nlev == 1) {
+            hipLaunchKernelGGL((k_coarse_solve_blk<double>), dim3(1), dim3(256), 0, stream, nL, ldL, Linv, LinvT,
+                               rin, bY, zout);
+            HIPCHK(hipGetLastError());
+            if (ndot) vc_nb = bdot_partials(n, zout, g0, g1);
+            return vc_nb;
+        }
+        if (fp32()) vlevel_blk<float, double>(0, rin, zout, ndot, g0, g1, false);
+        else vlevel_blk<double, double>(0, rin, zout, ndot, g0, g1, false);
         return vc_nb;
     }
 };
@@ -741,12 +912,96 @@ amg_status pcg_solve(amg_ctx *c, const double *F, double *u, double tol, int *it
     }
 }
 
+static amg_status solve_batched_impl(amg_ctx *c, int nrhs, const double *F, double *U, double tol, int *iters,
+                                     double *relres)
+{
+    const int64_t n = c->n;
+    const bool flex = c->prm.krylov == 1;
+    const int itmax = c->prm.itmax;
+    hipStream_t st = c->stream;
+    c->blk_alloc();
+    c->evused = 0;
+    c->evbytes.clear();
+    hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(256), 0, st, (int64_t)(B_NSLOTS * NB), 0.0, c->bsc);
+    // columns beyond nrhs are done from the start
+    std::vector<double> done0(NB, 0.0);
+    for (int j = nrhs; j < NB; j++) done0[j] = 1.0;
+    HIPCHK(hipMemcpyAsync(c->bsc + B_DONE * NB, done0.data(), NB * sizeof(double), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_pack_blk, dim3(nblocks(n)), dim3(256), 0, st, n, nrhs, F, c->bF);
+    hipLaunchKernelGGL(k_pack_blk, dim3(nblocks(n)), dim3(256), 0, st, n, nrhs, (const double *)U, c->bU);
+    HIPCHK(hipGetLastError());
+    // R = F - K U ; (F_j, F_j) ; (R_j, R_j)
+    c->sell_blk<double, double, double, EPI_RESID, 0>(0, c->bU, c->bF, c->lev[0].invd64, c->bR, nullptr, nullptr);
+    c->bfinalize(c->bdot_partials(n, c->bF, c->bF, nullptr), BF_FF, 0, tol);
+    c->bfinalize(c->bdot_partials(n, c->bR, c->bR, nullptr), BF_RR0);
+    HIPCHK(hipMemcpyAsync(c->hbsc, c->bsc, B_NSLOTS * NB * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int j = 0; j < nrhs; j++)
+        if (!std::isfinite(c->hbsc[B_FF * NB + j])) { set_err("non-finite right-hand side"); return AMG_ERR_ARG; }
+    auto all_stopped = [&]() {
+        for (int j = 0; j < nrhs; j++)
+            if (c->hbsc[B_DONE * NB + j] == 0.0 && c->hbsc[B_FLAG * NB + j] == 0.0) return false;
+        return true;
+    };
+    if (!all_stopped()) {
+        unsigned nb = c->vcycle_blk(c->bR, c->bZ, flex ? 0 : 1, c->bR, nullptr);
+        if (!flex) c->bfinalize(nb, BF_RZ0);
+        c->copy<double, double>(n * NB, c->bZ, c->bP);
+        for (int k = 1; k <= itmax; k++) {
+            if (flex) c->sell_blk<double, double, double, EPI_SPMV, 2>(0, c->bP, nullptr, nullptr, c->bQ, nullptr, c->bR);
+            else c->sell_blk<double, double, double, EPI_SPMV, 1>(0, c->bP, nullptr, nullptr, c->bQ, nullptr, nullptr);
+            c->bfinalize(c->sell_blocks(0), flex ? BF_PQ_FCG : BF_PQ_CG);
+            unsigned g = vgrid(n);
+            hipLaunchKernelGGL(k_bcg_update, dim3(g), dim3(256), 0, st, n, c->bsc, c->bU, c->bR, c->bP, c->bQ,
+                               c->bpartial);
+            HIPCHK(hipGetLastError());
+            c->bfinalize(g, BF_RR, k);
+            HIPCHK(hipMemcpyAsync(c->hbsc, c->bsc, B_NSLOTS * NB * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipEventRecord(c->ev_iter, st));
+            if (k < itmax) {
+                unsigned nb2 = c->vcycle_blk(c->bR, c->bZ, 1, flex ? c->bQ : c->bR, nullptr);
+                c->bfinalize(nb2, flex ? BF_ZQ_FCG : BF_RZ_CG);
+                hipLaunchKernelGGL(k_bcg_pupdate, dim3(vgrid(n)), dim3(256), 0, st, n, c->bsc, c->bZ, c->bP);
+                HIPCHK(hipGetLastError());
+            }
+            HIPCHK(hipEventSynchronize(c->ev_iter));
+            if (all_stopped()) break;
+        }
+    }
+    hipLaunchKernelGGL(k_unpack_blk, dim3(nblocks(n)), dim3(256), 0, st, n, nrhs, (const double *)c->bU, U);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(c->hbsc, c->bsc, B_NSLOTS * NB * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    c->prof_collect();
+    amg_status status = AMG_OK;
+    for (int j = 0; j < nrhs; j++) {
+        const double ff = c->hbsc[B_FF * NB + j];
+        if (iters) iters[j] = (int)c->hbsc[B_ITERS * NB + j];
+        if (relres) relres[j] = ff > 0.0 ? std::sqrt(c->hbsc[B_RR * NB + j]) / std::sqrt(ff) : 0.0;
+        if (c->hbsc[B_FLAG * NB + j] != 0.0) {
+            status = AMG_ERR_BREAKDOWN;
+            set_err("CG breakdown in column " + std::to_string(j));
+        } else if (c->hbsc[B_DONE * NB + j] == 0.0 && status == AMG_OK) {
+            status = AMG_NOT_CONVERGED;
+        }
+    }
+    return status;
+}
+
 amg_status pcg_solve_batched(amg_ctx *c, int nrhs, const double *F, double *U, double tol, int *iters,
                              double *relres)
 {
-    (void)c; (void)nrhs; (void)F; (void)U; (void)tol; (void)iters; (void)relres;
-    set_err("batched solve not available in this build");
-    return AMG_ERR_STATE;
+    g_err.clear();
+    if (!c || !F || !U || F == U || !(tol >= 0.0) || nrhs < 1 || nrhs > NB) {
+        set_err("NULL / aliased argument, tol < 0, or nrhs outside 1..16");
+        return AMG_ERR_ARG;
+    }
+    if (c->host_only) { set_err("context was built by amg_setup_host"); return AMG_ERR_STATE; }
+    try {
+        return solve_batched_impl(c, nrhs, F, U, tol, iters, relres);
+    } catch (Fail &f) {
+        return f.st;
+    }
 }
 
 amg_status amg_vcycle(amg_ctx *c, const double *r, double *z)

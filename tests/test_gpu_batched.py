@@ -1,0 +1,87 @@
+"""GPU: the batched solve (up to 16 right-hand sides sharing every block
+SpMV and block V-cycle, each column with its own CG / FCG(1) scalars) against
+the single-vector solve and the oracle."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def amg():
+    import paper_2511_21268_amd as m
+    assert torch.cuda.is_available()
+    m.lib()
+    return m
+
+
+def _csr(rp, ci, v):
+    return sp.csr_matrix((v, ci, rp), shape=(len(rp) - 1, len(rp) - 1))
+
+
+@pytest.mark.parametrize("d,p,n,k", [(2, 2, 32, 16), (3, 3, 16, 16), (3, 2, 14, 5)])
+def test_batched_fp64_equals_single_and_oracle(oracle, amg, d, p, n, k):
+    print(f"case batched fp64 d={d} p={p} n={n} k={k}", flush=True)
+    from paper_2511_21268_amd.workloads import rhs_block
+    rp, ci, v, _ = oracle.poisson_kron(d, p, n)
+    N = len(rp) - 1
+    Fh = rhs_block(N, range(k))
+    Fh[:, 1] = 0.0                                   # a zero column: u = 0 after 0 iterations
+    ctx = amg.Context(rp, ci, v)
+    Ft = torch.from_numpy(Fh).cuda()
+    out = ctx.solve_batched(Ft, tol=1e-8)
+    U = out["U"].cpu().numpy()
+    h = oracle.Hierarchy(rp, ci, v)
+    assert out["status"] == 0
+    for j in range(k):
+        single = ctx.solve(Ft[:, j].contiguous(), tol=1e-8)
+        us = single["u"].cpu().numpy()
+        assert out["iters"][j] == single["iters"], j
+        assert np.array_equal(U[:, j], us), j       # same bits as the single-vector solve
+        if j == 1:
+            assert out["iters"][j] == 0 and not U[:, j].any()
+            continue
+        ref = h.solve(Fh[:, j], tol=1e-8)
+        assert out["iters"][j] == ref["iters"], j
+        assert np.linalg.norm(U[:, j] - ref["u"]) <= 1e-10 * np.linalg.norm(ref["u"])
+
+
+@pytest.mark.parametrize("d,p,n", [(3, 3, 16), (3, 4, 14)])
+def test_batched_fp32_vcycle_fcg(oracle, amg, d, p, n):
+    """16 columns, FP32 block V-cycle inside FP64 FCG: every column reaches the
+    FP64 true residual 1e-8 and matches the single-vector FP32 solve."""
+    print(f"case batched fp32 d={d} p={p} n={n}", flush=True)
+    from paper_2511_21268_amd.workloads import rhs_block
+    rp, ci, v, _ = oracle.poisson_kron(d, p, n)
+    N = len(rp) - 1
+    Fh = rhs_block(N, range(16))
+    ctx = amg.Context(rp, ci, v, vcycle_fp32=1, krylov=1)
+    Ft = torch.from_numpy(Fh).cuda()
+    out = ctx.solve_batched(Ft, tol=1e-8)
+    U = out["U"].cpu().numpy()
+    assert out["status"] == 0
+    K = _csr(rp, ci, v)
+    h = oracle.Hierarchy(rp, ci, v)
+    for j in range(16):
+        true = np.linalg.norm(Fh[:, j] - K @ U[:, j]) / np.linalg.norm(Fh[:, j])
+        assert true <= 1e-8, (j, true)
+        single = ctx.solve(Ft[:, j].contiguous(), tol=1e-8)
+        assert abs(out["iters"][j] - single["iters"]) <= 1
+        ref = h.solve(Fh[:, j], tol=1e-8)
+        err = np.linalg.norm(U[:, j] - ref["u"]) / np.linalg.norm(ref["u"])
+        assert err <= 1e-6, (j, err)
+
+
+def test_batched_itmax_and_args(oracle, amg):
+    print("case batched edge", flush=True)
+    from paper_2511_21268_amd.workloads import rhs_block
+    rp, ci, v, _ = oracle.poisson_kron(2, 2, 32)
+    N = len(rp) - 1
+    ctx = amg.Context(rp, ci, v, itmax=2)
+    out = ctx.solve_batched(torch.from_numpy(rhs_block(N, range(3))).cuda())
+    assert out["status"] == 1 and out["iters"] == [2, 2, 2]
+    with pytest.raises(amg.AmgError):
+        ctx.solve_batched(torch.zeros(N, 17, dtype=torch.float64, device="cuda"))
