@@ -61,6 +61,10 @@ typedef struct {
     int match_positive_only;/* 0: every edge eligible (default);
                                1: only edges with c_ij > 1 (log c_ij > 0)       */
     int itmax;              /* default 1000                                     */
+    int nrhs;               /* 1 (default): single-vector layout only; 2..16:
+                               also build the layout of the block kernels used by
+                               pcg_solve_batched and autotune it (lanes per row
+                               and block size, timed on the level-0 matrix)     */
 } amg_params;
 
 /* Fill p with the defaults above.  p must not be NULL. */
@@ -127,6 +131,17 @@ amg_status amg_vcycle(amg_ctx *c, const double *r, double *z);
  * level in 0 .. levels-2, or 0 for a single-level hierarchy.
  */
 amg_status amg_spmv(amg_ctx *c, int level, const double *x, double *y);
+
+/*
+ * Variant of the block kernels used by pcg_solve_batched: lpr lanes per matrix
+ * row (1: the single-vector SELL-64 image, one lane per row and 16 columns per
+ * lane; 4 or 16: the SELL-(64/lpr) block image, 16/lpr columns per lane) and
+ * threads per block (256 or 512).  amg_setup with prm.nrhs > 1 sets the fastest
+ * by timing; amg_set_batched_variant overrides it (lpr 4/16 only when that
+ * image was built, i.e. the autotuner's choice).
+ */
+amg_status amg_get_batched_variant(const amg_ctx *c, int *lpr, int *threads);
+amg_status amg_set_batched_variant(amg_ctx *c, int lpr, int threads);
 
 /*
  * Set the degree-4 polynomial smoother of one level (used when prm.smoother
@@ -201,6 +216,62 @@ amg_status amg_get_format(const amg_ctx *c, int level, int *slice, int64_t *stor
 amg_status amg_iga_poisson_size(int d, int p, int n, int64_t *N, int64_t *nnz);
 amg_status amg_iga_poisson(int d, int p, int n, int64_t *row_ptr, int32_t *col, double *val,
                            double *F);
+
+/* ------------------------------------------------------------------------
+ * Learned polynomial smoother: a small MLP (8 -> 64 -> 64 -> 4, tanh) maps the
+ * features of a level to the coefficients of its degree-4 polynomial smoother
+ * (Sec. 3.2 polynomial acceleration; coefficients as in amg_set_poly_coeffs).
+ * Parameters: a vector of AMG_MLP_NPARAM entries
+ *   W1[64][8] b1[64] W2[64][64] b2[64] W3[4][64] b3[4],
+ * held as BF16 bit patterns (uint16) for the kernels and as an FP32 master copy
+ * for training; accumulation is FP32.  All MLP arrays below are device arrays
+ * of the caller, ordered on hip_stream; B samples, row-major.
+ */
+#define AMG_MLP_NPARAM 4996
+#define AMG_MLP_NFEAT 8
+#define AMG_MLP_NACT 128     /* stored activations per sample (h1, h2)        */
+#define AMG_MLP_NDEL 132     /* stored deltas per sample (dy, dh2, dh1)        */
+
+/* Features of level `level` (host output, AMG_MLP_NFEAT floats):
+ * log10(n)/7, (nnz/n)/1000, mean and min over rows of k_ii/d_i (d = l1 diagonal),
+ * mean of sum_{j!=i} k_ij / d_i, fraction of positive off-diagonal entries,
+ * level / (levels-1), n_{level+1}/n_level (0 on the coarsest). */
+amg_status amg_level_features(const amg_ctx *c, int level, float *feat);
+
+/* Y[B][4] = MLP(X[B][8]) with BF16 weights w; act (may be NULL) receives the
+ * hidden activations, AMG_MLP_NACT floats per sample, for the backward pass. */
+amg_status amg_mlp_forward(const uint16_t *w, const float *X, int B, float *Y, float *act, void *hip_stream);
+
+/* Gradient of L = mean_{s,i} (Y - T)^2 with respect to the parameters (grad,
+ * AMG_MLP_NPARAM floats) and the loss (1 float), from a forward pass's Y and
+ * act; del is a workspace of B * AMG_MLP_NDEL floats. */
+amg_status amg_mlp_backward(const uint16_t *w, const float *X, const float *act, const float *Y, const float *T,
+                            int B, float *del, float *grad, float *loss, void *hip_stream);
+
+/* One Adam step (b1 = 0.9, b2 = 0.999, eps = 1e-8) on the FP32 master weights
+ * with bias correction for step >= 1, then w = BF16(master) (round to nearest
+ * even).  step = 0 only rounds master into w. */
+amg_status amg_mlp_adam(float *master, uint16_t *w, const float *grad, float *m, float *v, int step, float lr,
+                        void *hip_stream);
+
+/* Predict every level's smoother with the MLP (weights: host BF16 array) on the
+ * device, scale the outputs by scale[4] into coefficients, and set each level
+ * through the acceptance test of amg_set_poly_coeffs; a rejected level keeps
+ * l1-Jacobi.  accepted (host, may be NULL): levels-1 flags; coeffs (host, may be
+ * NULL): (levels-1) x 4 predicted coefficients.  Needs prm.smoother == 1. */
+amg_status amg_set_learned_poly(amg_ctx *c, const uint16_t *w_host, const double scale[4], int *accepted,
+                                double *coeffs);
+
+/*
+ * Variable-coefficient workload: -div(kappa grad u) = 1 on the unit cube with
+ * kappa(x) = exp(0.5 sum_{k<nk} a[k] cos(2 pi m_k . x)), m_k = mk[3k..3k+2],
+ * the same space, boundary conditions, pattern and order as amg_iga_poisson
+ * (d = 3), assembled by (p+1)^3-point Gauss quadrature with sum factorization
+ * (Sec. 2.2).  Sizes from amg_iga_poisson_size(3, p, n, ...); F (may be NULL)
+ * receives the load vector of f = 1.  1 <= p <= 7.
+ */
+amg_status amg_iga_diffusion(int p, int n, int nk, const double *a, const int32_t *mk, int64_t *row_ptr,
+                             int32_t *col, double *val, double *F);
 
 #ifdef __cplusplus
 }

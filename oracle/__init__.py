@@ -15,7 +15,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "liboracle.so")
-_SRC = ["iga.c", "amg.c", "krylov.c"]
+_SRC = ["iga.c", "amg.c", "krylov.c", "mlp.c"]
 
 
 def build(force=True):
@@ -61,6 +61,7 @@ def lib():
         L.or_poisson_kron_bc.argtypes = [C.c_int, C.c_int, C.c_int, i32p, i64p, i32p, f64p, f64p]
         L.or_greedy_edges.argtypes = [C.c_int64, C.c_int64, f64p, i32p, i32p, C.c_int, i32p]
         L.or_diffusion_quad3d.argtypes = [C.c_int, C.c_int, C.c_int, f64p, i32p, i64p, i32p, f64p, f64p]
+        L.or_diffusion_sf3d.argtypes = [C.c_int, C.c_int, C.c_int, f64p, i32p, i64p, i32p, f64p, f64p]
         L.or_cij.argtypes = [C.c_double] * 5
         L.or_cij.restype = C.c_double
         L.or_match.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, C.c_int, i32p]
@@ -88,6 +89,12 @@ def lib():
         L.or_pcg.argtypes = [C.c_void_p, f64p, f64p, C.c_double, C.c_int, C.c_int,
                              C.POINTER(C.c_int), f64p, f64p]
         L.or_poly_accept.argtypes = [f64p]
+        u16p = C.POINTER(C.c_uint16)
+        L.or_mlp_forward.argtypes = [u16p, f64p, C.c_int, f64p]
+        L.or_mlp_loss_grad.argtypes = [u16p, f64p, f64p, C.c_int, f64p]
+        L.or_mlp_loss_grad.restype = C.c_double
+        L.or_mlp_loss_grad_w.argtypes = [f64p, f64p, f64p, C.c_int, f64p]
+        L.or_mlp_loss_grad_w.restype = C.c_double
         _lib = L
     return _lib
 
@@ -173,16 +180,17 @@ def poisson_kron_bc(d, p, n, dirichlet):
     return rp, ci, v, F
 
 
-def diffusion_quad3d(p, n, a=None, mk=None):
-    """3D stiffness with kappa(x) = exp(0.5 sum a_k cos(2 pi m_k.x)) by the plain
-    element loop with (p+1)^3 Gauss points; a = None gives kappa = 1."""
+def diffusion_quad3d(p, n, a=None, mk=None, factorized=False):
+    """3D stiffness with kappa(x) = exp(0.5 sum a_k cos(2 pi m_k.x)) by (p+1)^3
+    Gauss points per element: the plain element loop, or (factorized=True)
+    sum factorization; a = None gives kappa = 1."""
     N, nz = poisson_size(3, p, n)
     rp = np.zeros(N + 1, np.int64); ci = np.zeros(nz, np.int32); v = np.zeros(nz); F = np.zeros(N)
     nk = 0 if a is None else len(a)
     a_ = _f64(a if a is not None else np.zeros(1))
     m_ = _i32(mk if mk is not None else np.zeros((1, 3), np.int32)).reshape(-1)
-    rc = lib().or_diffusion_quad3d(p, n, nk, _p(a_, f64p), _p(m_, i32p), _p(rp, i64p), _p(ci, i32p),
-                                   _p(v, f64p), _p(F, f64p))
+    fn = lib().or_diffusion_sf3d if factorized else lib().or_diffusion_quad3d
+    rc = fn(p, n, nk, _p(a_, f64p), _p(m_, i32p), _p(rp, i64p), _p(ci, i32p), _p(v, f64p), _p(F, f64p))
     if rc:
         raise ValueError("or_diffusion_quad3d failed")
     return rp, ci, v, F
@@ -267,6 +275,36 @@ def set_verbose(v):
 def poly_accept(coef):
     c = _f64(coef)
     return bool(lib().or_poly_accept(_p(c, f64p)))
+
+
+# ---------------------------------------------------------------- MLP
+MLP_NPARAM = 4996
+
+
+def _u16(a):
+    return np.ascontiguousarray(a, dtype=np.uint16)
+
+
+def mlp_forward(w_bf16, X):
+    w = _u16(w_bf16); X = _f64(X)
+    B = X.shape[0]
+    Y = np.zeros((B, 4))
+    lib().or_mlp_forward(w.ctypes.data_as(C.POINTER(C.c_uint16)), _p(X, f64p), B, _p(Y, f64p))
+    return Y
+
+
+def mlp_loss_grad(w_bf16, X, T):
+    w = _u16(w_bf16); X = _f64(X); T = _f64(T)
+    g = np.zeros(MLP_NPARAM)
+    loss = lib().or_mlp_loss_grad(w.ctypes.data_as(C.POINTER(C.c_uint16)), _p(X, f64p), _p(T, f64p), X.shape[0],
+                                  _p(g, f64p))
+    return loss, g
+
+
+def mlp_loss_w(w, X, T):
+    """Loss at real-valued parameters w (for finite differences)."""
+    w = _f64(w); X = _f64(X); T = _f64(T)
+    return lib().or_mlp_loss_grad_w(_p(w, f64p), _p(X, f64p), _p(T, f64p), X.shape[0], None)
 
 
 class Hierarchy:

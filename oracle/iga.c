@@ -333,3 +333,126 @@ int or_diffusion_quad3d(int p, int n, int nk, const double *a, const int32_t *mk
     free(t);
     return 0;
 }
+
+/* The same integral as or_diffusion_quad3d, with the quadrature sums of each
+ * element factorized direction by direction (sum factorization, Sec. 2.2's
+ * fast-assembly remark): for each of the three gradient terms,
+ *   T1[qx][qy][az][bz] = sum_qz kw(q) Z_az(qz) Z_bz(qz),
+ *   T2[qx][ay][by][az][bz] = sum_qy T1 Y_ay(qy) Y_by(qy),
+ *   k_local += sum_qx T2 X_ax(qx) X_bx(qx),
+ * with X/Y/Z the value or the derivative table of the direction carrying the
+ * derivative.  Same CSR pattern and F as the plain loop. */
+int or_diffusion_sf3d(int p, int n, int nk, const double *a, const int32_t *mk,
+                      int64_t *rp, int32_t *ci, double *v, double *F)
+{
+    int m = n + p, md = m - 2, q1 = p + 1;
+    if (p < 1 || p > 7 || n < 1 || md < 1) return -1;
+    double *t = malloc(sizeof(double) * (n + 2 * p + 1));
+    double xg[16], wg[16];
+    or_knots(p, n, t);
+    or_gauss_legendre(q1, xg, wg);
+    int mdv[3] = {md, md, md};
+    tensor_pattern(mdv, p, rp, ci);
+    int64_t N = (int64_t)md * md * md;
+    memset(v, 0, sizeof(double) * rp[N]);
+    if (F) memset(F, 0, sizeof(double) * N);
+    /* 1D tables per element index and direction are the same for every
+     * direction (same knots): B[e][l][q], D[e][l][q], X[e][q], W[e][q] */
+    double *B = malloc(sizeof(double) * n * q1 * q1), *D = malloc(sizeof(double) * n * q1 * q1);
+    double *X = malloc(sizeof(double) * n * q1), *W = malloc(sizeof(double) * n * q1);
+    for (int e = 0; e < n; e++) {
+        int s = p + e;
+        double lo = t[s], h = t[s + 1] - t[s];
+        for (int q = 0; q < q1; q++) {
+            double xq = lo + (xg[q] + 1.0) * 0.5 * h;
+            X[e * q1 + q] = xq;
+            W[e * q1 + q] = wg[q] * 0.5 * h;
+            for (int l = 0; l < q1; l++) {
+                B[(e * q1 + l) * q1 + q] = or_bspline(t, s - p + l, p, xq);
+                D[(e * q1 + l) * q1 + q] = or_bspline_deriv(t, s - p + l, p, xq);
+            }
+        }
+    }
+    int nq = q1 * q1 * q1, nl = q1 * q1 * q1;
+    double *kw = malloc(sizeof(double) * nq), *Kl = malloc(sizeof(double) * nl * nl);
+    double *T1 = malloc(sizeof(double) * q1 * q1 * q1 * q1);
+    double *T2 = malloc(sizeof(double) * q1 * q1 * q1 * q1 * q1);
+    for (int ez = 0; ez < n; ez++)
+    for (int ey = 0; ey < n; ey++)
+    for (int ex = 0; ex < n; ex++) {
+        const double *Bx = B + ex * q1 * q1, *By = B + ey * q1 * q1, *Bz = B + ez * q1 * q1;
+        const double *Dx = D + ex * q1 * q1, *Dy = D + ey * q1 * q1, *Dz = D + ez * q1 * q1;
+        for (int qz = 0; qz < q1; qz++)
+            for (int qy = 0; qy < q1; qy++)
+                for (int qx = 0; qx < q1; qx++) {
+                    double Wt = (W[ex * q1 + qx] * W[ey * q1 + qy]) * W[ez * q1 + qz];
+                    kw[(qx * q1 + qy) * q1 + qz] = kappa_eval(nk, a, mk, X[ex * q1 + qx], X[ey * q1 + qy],
+                                                              X[ez * q1 + qz]) * Wt;
+                    if (F) {
+                        for (int az = 0; az < q1; az++)
+                        for (int ay = 0; ay < q1; ay++)
+                        for (int ax = 0; ax < q1; ax++) {
+                            int fx = ex + ax, fy = ey + ay, fz = ez + az;
+                            if (fx == 0 || fx == m - 1 || fy == 0 || fy == m - 1 || fz == 0 || fz == m - 1) continue;
+                            int64_t g = (fx - 1) + (int64_t)md * ((fy - 1) + (int64_t)md * (fz - 1));
+                            F[g] += Wt * ((Bx[ax * q1 + qx] * By[ay * q1 + qy]) * Bz[az * q1 + qz]);
+                        }
+                    }
+                }
+        memset(Kl, 0, sizeof(double) * nl * nl);
+        for (int term = 0; term < 3; term++) {
+            const double *Tx = term == 0 ? Dx : Bx, *Ty = term == 1 ? Dy : By, *Tz = term == 2 ? Dz : Bz;
+            /* contract qz */
+            for (int qx = 0; qx < q1; qx++)
+            for (int qy = 0; qy < q1; qy++)
+            for (int az = 0; az < q1; az++)
+            for (int bz = 0; bz < q1; bz++) {
+                double s = 0.0;
+                for (int qz = 0; qz < q1; qz++)
+                    s += kw[(qx * q1 + qy) * q1 + qz] * (Tz[az * q1 + qz] * Tz[bz * q1 + qz]);
+                T1[((qx * q1 + qy) * q1 + az) * q1 + bz] = s;
+            }
+            /* contract qy */
+            for (int qx = 0; qx < q1; qx++)
+            for (int ay = 0; ay < q1; ay++)
+            for (int by = 0; by < q1; by++)
+            for (int az = 0; az < q1; az++)
+            for (int bz = 0; bz < q1; bz++) {
+                double s = 0.0;
+                for (int qy = 0; qy < q1; qy++)
+                    s += T1[((qx * q1 + qy) * q1 + az) * q1 + bz] * (Ty[ay * q1 + qy] * Ty[by * q1 + qy]);
+                T2[(((qx * q1 + ay) * q1 + by) * q1 + az) * q1 + bz] = s;
+            }
+            /* contract qx into the local matrix; local index (az, ay, ax) with x fastest */
+            for (int az = 0; az < q1; az++)
+            for (int ay = 0; ay < q1; ay++)
+            for (int ax = 0; ax < q1; ax++)
+            for (int bz = 0; bz < q1; bz++)
+            for (int by = 0; by < q1; by++)
+            for (int bx = 0; bx < q1; bx++) {
+                double s = 0.0;
+                for (int qx = 0; qx < q1; qx++)
+                    s += T2[(((qx * q1 + ay) * q1 + by) * q1 + az) * q1 + bz] * (Tx[ax * q1 + qx] * Tx[bx * q1 + qx]);
+                Kl[((az * q1 + ay) * q1 + ax) * nl + ((bz * q1 + by) * q1 + bx)] += s;
+            }
+        }
+        /* scatter into the global matrix */
+        for (int az = 0; az < q1; az++)
+        for (int ay = 0; ay < q1; ay++)
+        for (int ax = 0; ax < q1; ax++) {
+            int fx = ex + ax, fy = ey + ay, fz = ez + az;
+            if (fx == 0 || fx == m - 1 || fy == 0 || fy == m - 1 || fz == 0 || fz == m - 1) continue;
+            int64_t g = (fx - 1) + (int64_t)md * ((fy - 1) + (int64_t)md * (fz - 1));
+            for (int bz = 0; bz < q1; bz++)
+            for (int by = 0; by < q1; by++)
+            for (int bx = 0; bx < q1; bx++) {
+                int hx = ex + bx, hy = ey + by, hz = ez + bz;
+                if (hx == 0 || hx == m - 1 || hy == 0 || hy == m - 1 || hz == 0 || hz == m - 1) continue;
+                int64_t hh = (hx - 1) + (int64_t)md * ((hy - 1) + (int64_t)md * (hz - 1));
+                v[find_pos(rp, ci, g, hh)] += Kl[((az * q1 + ay) * q1 + ax) * nl + ((bz * q1 + by) * q1 + bx)];
+            }
+        }
+    }
+    free(B); free(D); free(X); free(W); free(kw); free(Kl); free(T1); free(T2); free(t);
+    return 0;
+}

@@ -60,6 +60,11 @@ int  or_poisson_kron(int d, int p, int n, int64_t *rp, int32_t *ci, double *v, d
 int  or_diffusion_quad3d(int p, int n, int nk, const double *a, const int32_t *mk,
                          int64_t *rp, int32_t *ci, double *v, double *F);
 
+/* The same integral by sum factorization per element (three 1D contractions per
+ * gradient term); the form used at the benchmark sizes. */
+int  or_diffusion_sf3d(int p, int n, int nk, const double *a, const int32_t *mk,
+                       int64_t *rp, int32_t *ci, double *v, double *F);
+
 /* ---------------- amg.c : hierarchy (Sec. 3, 3.1) ---------------- */
 
 typedef struct {
@@ -143,5 +148,14 @@ int  or_pcg(const or_hier *h, const double *F, double *u, double tol, int itmax,
             int flexible, int *iters, double *relres, double *hist);
 /* l1-Jacobi-preconditioned polynomial smoother error polynomial check. */
 int  or_poly_accept(const double *coef);
+
+/* ---------------- mlp.c : learned-smoother network ---------------- */
+
+int    or_mlp_nparam(void);
+double or_bf16_value(uint16_t b);
+void   or_mlp_forward(const uint16_t *wb, const double *X, int B, double *Y);
+/* loss (mean squared error) and, if grad != NULL, its gradient */
+double or_mlp_loss_grad(const uint16_t *wb, const double *X, const double *T, int B, double *grad);
+double or_mlp_loss_grad_w(const double *w, const double *X, const double *T, int B, double *grad);
 
 #endif

@@ -21,7 +21,10 @@ EXPORTS = ["amg_params_default", "amg_setup", "pcg_solve", "pcg_solve_batched", 
            "amg_set_poly_coeffs",
            "amg_get_level_info", "amg_get_aggregates", "amg_get_coarse_matrix", "amg_setup_host", "amg_match",
            "amg_destroy", "amg_last_error", "amg_set_profiling", "amg_get_profile", "amg_get_format",
-           "amg_iga_poisson_size", "amg_iga_poisson"]
+           "amg_iga_poisson_size", "amg_iga_poisson", "amg_iga_diffusion", "amg_level_features",
+           "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_adam", "amg_set_learned_poly",
+           "amg_get_batched_variant", "amg_set_batched_variant"]
+MLP_NPARAM, MLP_NFEAT, MLP_NACT, MLP_NDEL = 4996, 8, 128, 132
 
 
 class AmgError(RuntimeError):
@@ -33,7 +36,7 @@ class AmgError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("sweeps_per_level", C.c_int), ("max_coarse", C.c_int), ("max_levels", C.c_int),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("vcycle_fp32", C.c_int), ("smoother", C.c_int),
-                ("krylov", C.c_int), ("match_positive_only", C.c_int), ("itmax", C.c_int)]
+                ("krylov", C.c_int), ("match_positive_only", C.c_int), ("itmax", C.c_int), ("nrhs", C.c_int)]
 
 
 i64p = C.POINTER(C.c_int64)
@@ -71,6 +74,14 @@ def lib():
         L.amg_get_format.argtypes = [vp, C.c_int, C.POINTER(C.c_int), i64p, C.POINTER(C.c_int)]
         L.amg_iga_poisson_size.argtypes = [C.c_int, C.c_int, C.c_int, i64p, i64p]
         L.amg_iga_poisson.argtypes = [C.c_int, C.c_int, C.c_int, i64p, i32p, f64p, f64p]
+        L.amg_iga_diffusion.argtypes = [C.c_int, C.c_int, C.c_int, f64p, i32p, i64p, i32p, f64p, f64p]
+        L.amg_level_features.argtypes = [vp, C.c_int, C.POINTER(C.c_float)]
+        L.amg_mlp_forward.argtypes = [vp, vp, C.c_int, vp, vp, vp]
+        L.amg_mlp_backward.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp, vp]
+        L.amg_mlp_adam.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_float, vp]
+        L.amg_get_batched_variant.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.amg_set_batched_variant.argtypes = [vp, C.c_int, C.c_int]
+        L.amg_set_learned_poly.argtypes = [vp, C.POINTER(C.c_uint16), f64p, C.POINTER(C.c_int), f64p]
         _lib = L
     return _lib
 
@@ -104,6 +115,19 @@ def iga_poisson(d, p, n, want_F=True):
     F = np.empty(N.value) if want_F else None
     _check(lib().amg_iga_poisson(d, p, n, _p(rp, i64p), _p(ci, i32p), _p(v, f64p),
                                  _p(F, f64p) if want_F else None))
+    return rp, ci, v, F
+
+
+def iga_diffusion(p, n, a, mk, want_F=True):
+    """Host CSR of -div(kappa grad u) with kappa(x) = exp(0.5 sum a_k cos(2 pi m_k.x))
+    on the unit cube (library's sum-factorized assembly), and F for f = 1."""
+    N = C.c_int64(); nz = C.c_int64()
+    _check(lib().amg_iga_poisson_size(3, p, n, C.byref(N), C.byref(nz)))
+    a_ = np.ascontiguousarray(a, np.float64); m_ = np.ascontiguousarray(mk, np.int32).reshape(-1)
+    rp = np.empty(N.value + 1, np.int64); ci = np.empty(nz.value, np.int32); v = np.empty(nz.value)
+    F = np.empty(N.value) if want_F else None
+    _check(lib().amg_iga_diffusion(p, n, len(a_), _p(a_, f64p), _p(m_, i32p), _p(rp, i64p), _p(ci, i32p),
+                                   _p(v, f64p), _p(F, f64p) if want_F else None))
     return rp, ci, v, F
 
 
@@ -191,6 +215,31 @@ class Context:
     def set_poly(self, level, coeffs):
         c = np.ascontiguousarray(coeffs, np.float64)
         return _check(lib().amg_set_poly_coeffs(self.h, level, _p(c, f64p)), allow=(AMG_OK, AMG_NOT_CONVERGED))
+
+    def batched_variant(self):
+        lpr = C.c_int(); thr = C.c_int()
+        _check(lib().amg_get_batched_variant(self.h, C.byref(lpr), C.byref(thr)))
+        return lpr.value, thr.value
+
+    def set_batched_variant(self, lpr, threads=256):
+        _check(lib().amg_set_batched_variant(self.h, int(lpr), int(threads)))
+
+    def features(self, level):
+        f = (C.c_float * 8)()
+        _check(lib().amg_level_features(self.h, level, f))
+        return np.array(list(f), dtype=np.float32)
+
+    def set_learned_poly(self, w_bf16, scale):
+        """Predict and set every level's polynomial smoother from the MLP weights
+        (numpy uint16 BF16 bits).  Returns (accepted flags, coefficients)."""
+        w = np.ascontiguousarray(w_bf16, np.uint16)
+        assert w.size == MLP_NPARAM
+        sc = np.ascontiguousarray(scale, np.float64)
+        nl = max(self.nlevels - 1, 0)
+        acc = (C.c_int * max(nl, 1))(); coef = np.zeros((max(nl, 1), 4))
+        _check(lib().amg_set_learned_poly(self.h, w.ctypes.data_as(C.POINTER(C.c_uint16)), _p(sc, f64p), acc,
+                                          _p(coef, f64p)))
+        return [bool(acc[i]) for i in range(nl)], coef[:nl]
 
     # ---- measurement ---------------------------------------------------------
     def set_profiling(self, on):

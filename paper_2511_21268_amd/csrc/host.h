@@ -43,6 +43,7 @@ struct HostLevel {
     std::vector<int32_t> agg;    // coarse index of each row (not on coarsest)
     std::vector<double> pc;      // prolongator coefficient of each row
     int max_members = 0;         // largest aggregate size into the next level
+    float feat[6] = {0, 0, 0, 0, 0, 0};  // level features independent of the depth
 };
 
 struct HostHierarchy {
@@ -55,6 +56,12 @@ int validate_csr(const CsrView &K, std::string &err);
 int build_hierarchy(const CsrView &K0, const double *w, const SetupParams &prm,
                     HostHierarchy &H, std::string &err);
 
+// Features of a level for the learned smoother (the first six of eight; the
+// relative depth and the coarsening ratio are added once the hierarchy is known):
+// log10(n)/7, (nnz/n)/1000, mean and min of k_ii/d_i, mean of sum_{j!=i} k_ij/d_i,
+// fraction of positive off-diagonal entries.
+void level_features(const CsrView &K, const std::vector<double> &invd, float out[6]);
+
 // Pieces exposed for the unit tests of the library's own setup.
 double cij(double kij, double kii, double kjj, double wi, double wj);
 void suitor_match(const CsrView &K, const double *w, int positive_only, int32_t *mate);
@@ -62,19 +69,22 @@ void suitor_match(const CsrView &K, const double *w, int positive_only, int32_t 
 // Workload generator.
 void iga_size(int d, int p, int n, int64_t *N, int64_t *nnz);
 int iga_poisson(int d, int p, int n, int64_t *rp, int32_t *ci, double *v, double *F);
+int iga_diffusion(int p, int n, int nk, const double *a, const int32_t *mk, int64_t *rp, int32_t *ci, double *v,
+                  double *F);
 
-// Runs f(begin, end) over [0, n) split in contiguous chunks on host threads.
-template <class F> void parallel_for(int64_t n, F f);
+// Runs f(begin, end) over [0, n) split in contiguous chunks on host threads
+// (serially when n < serial_below).
+template <class F> void parallel_for(int64_t n, F f, int64_t serial_below = 4096);
 
 }  // namespace amgiga
 
 #include <thread>
 namespace amgiga {
 int host_threads();
-template <class F> void parallel_for(int64_t n, F f)
+template <class F> void parallel_for(int64_t n, F f, int64_t serial_below)
 {
     int nt = host_threads();
-    if (n < 4096 || nt <= 1) { f((int64_t)0, n); return; }
+    if (n < serial_below || nt <= 1) { f((int64_t)0, n); return; }
     std::vector<std::thread> th;
     int64_t chunk = (n + nt - 1) / nt;
     for (int t = 0; t < nt; t++) {

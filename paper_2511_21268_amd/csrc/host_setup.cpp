@@ -293,6 +293,33 @@ static void l1_invdiag(const CsrView &K, std::vector<double> &invd)
     });
 }
 
+void level_features(const CsrView &K, const std::vector<double> &invd, float out[6])
+{
+    double s_diag = 0.0, min_diag = 1.0, s_off = 0.0;
+    int64_t npos = 0, noff = 0;
+    for (int64_t i = 0; i < K.n; i++) {
+        double kii = 0.0, off = 0.0;
+        for (int64_t k = K.rp[i]; k < K.rp[i + 1]; k++) {
+            if (K.ci[k] == i) kii = K.v[k];
+            else {
+                off += K.v[k];
+                noff++;
+                if (K.v[k] > 0.0) npos++;
+            }
+        }
+        double r = kii * invd[i];
+        s_diag += r;
+        min_diag = std::min(min_diag, r);
+        s_off += off * invd[i];
+    }
+    out[0] = (float)(std::log10((double)K.n) / 7.0);
+    out[1] = (float)((double)K.nnz() / (double)K.n / 1000.0);
+    out[2] = (float)(s_diag / (double)K.n);
+    out[3] = (float)min_diag;
+    out[4] = (float)(s_off / (double)K.n);
+    out[5] = (float)(noff ? (double)npos / (double)noff : 0.0);
+}
+
 static void make_coarsest(HostHierarchy &H, const CsrView &K)
 {
     int64_t n = K.n;
@@ -315,6 +342,7 @@ int build_hierarchy(const CsrView &K0, const double *w, const SetupParams &prm,
         L0.w.resize(K0.n);
         for (int64_t i = 0; i < K0.n; i++) L0.w[i] = w ? w[i] : 1.0;
         l1_invdiag(K0, L0.invd);
+        level_features(K0, L0.invd, L0.feat);
     }
     for (int l = 0;; l++) {
         CsrView K = l == 0 ? K0 : view(H.lev[l].K);
@@ -371,6 +399,7 @@ int build_hierarchy(const CsrView &K0, const double *w, const SetupParams &prm,
         next.K = std::move(cur);
         next.w = std::move(cw);
         l1_invdiag(view(next.K), next.invd);
+        level_features(view(next.K), next.invd, next.feat);
         H.lev.push_back(std::move(next));
     }
 }
@@ -517,6 +546,142 @@ int iga_poisson(int d, int p, int n, int64_t *rp, int32_t *ci, double *v, double
             if (F) F[g] = d == 2 ? Fi[iy + 1] * Fi[ix + 1] : (Fi[iz + 1] * Fi[iy + 1]) * Fi[ix + 1];
         }
     });
+    return 0;
+}
+
+
+// Variable-coefficient stiffness -div(kappa grad u) on the unit cube, kappa by
+// its parameters (kappa = exp(0.5 sum_k a_k cos(2 pi m_k . x))), (p+1)^3 Gauss
+// points per element, sum factorization per element (contracting x, then y,
+// then z), elements processed in (p+1)^3 colour classes so that elements of one
+// class share no basis function and can be accumulated in parallel.
+static double kappa_at(int nk, const double *a, const int32_t *mk, double x, double y, double z)
+{
+    double s = 0.0;
+    for (int k = 0; k < nk; k++)
+        s += a[k] * std::cos(2.0 * M_PI * ((double)mk[3 * k] * x + (double)mk[3 * k + 1] * y + (double)mk[3 * k + 2] * z));
+    return std::exp(0.5 * s);
+}
+
+int iga_diffusion(int p, int n, int nk, const double *a, const int32_t *mk, int64_t *rp, int32_t *ci, double *v,
+                  double *F)
+{
+    if (p < 1 || p > 7 || n < 1 || n + p - 2 < 1 || nk < 0) return -1;
+    const int m = n + p, md = m - 2, q1 = p + 1;
+    // pattern and zero values: reuse the constant-coefficient generator's layout
+    if (iga_poisson(3, p, n, rp, ci, v, nullptr)) return -1;
+    const int64_t N = (int64_t)md * md * md;
+    std::fill(v, v + rp[N], 0.0);
+    if (F) std::fill(F, F + N, 0.0);
+    std::vector<double> t(n + 2 * p + 1);
+    for (int i = 0; i <= p; i++) { t[i] = 0.0; t[n + p + i] = 1.0; }
+    for (int k = 1; k < n; k++) t[p + k] = (double)k / (double)n;
+    double xg[16], wg[16];
+    gauss_nodes(q1, xg, wg);
+    // per element index: points, weights, values and derivatives of its p+1 functions
+    std::vector<double> X(n * q1), W(n * q1), Bv(n * q1 * q1), Dv(n * q1 * q1);
+    for (int e = 0; e < n; e++) {
+        int s0 = p + e;
+        double lo = t[s0], h = t[s0 + 1] - t[s0];
+        for (int q = 0; q < q1; q++) {
+            double x = lo + 0.5 * (xg[q] + 1.0) * h;
+            X[e * q1 + q] = x;
+            W[e * q1 + q] = 0.5 * wg[q] * h;
+            double Nv[16], Dd[16];
+            span_basis(t, s0, p, x, Nv, Dd);
+            for (int l = 0; l < q1; l++) { Bv[(e * q1 + l) * q1 + q] = Nv[l]; Dv[(e * q1 + l) * q1 + q] = Dd[l]; }
+        }
+    }
+    auto len1 = [&](int i) { return std::min(md - 1, i + p) - std::max(0, i - p) + 1; };
+    // position of column (jx,jy,jz) in row (ix,iy,iz)
+    auto pos = [&](int ix, int iy, int iz, int jx, int jy, int jz) {
+        int64_t g = ix + (int64_t)md * (iy + (int64_t)md * iz);
+        int xlo = std::max(0, ix - p), ylo = std::max(0, iy - p), zlo = std::max(0, iz - p);
+        return rp[g] + ((int64_t)(jz - zlo) * len1(iy) + (jy - ylo)) * len1(ix) + (jx - xlo);
+    };
+    const int nl = q1 * q1 * q1;
+    for (int cz = 0; cz < q1; cz++)
+    for (int cy = 0; cy < q1; cy++)
+    for (int cx = 0; cx < q1; cx++) {
+        int nx = (n - cx + q1 - 1) / q1, ny = (n - cy + q1 - 1) / q1, nz = (n - cz + q1 - 1) / q1;
+        int64_t ne = (int64_t)nx * ny * nz;
+        if (ne <= 0) continue;
+        parallel_for(ne, [&](int64_t eb, int64_t ee) {
+            std::vector<double> kw(nl), A1(q1 * q1 * q1 * q1), A2(q1 * q1 * q1 * q1 * q1), Kl((size_t)nl * nl);
+            for (int64_t el = eb; el < ee; el++) {
+                int ex = cx + q1 * (int)(el % nx), ey = cy + q1 * (int)((el / nx) % ny), ez = cz + q1 * (int)(el / ((int64_t)nx * ny));
+                const double *BX = &Bv[ex * q1 * q1], *BY = &Bv[ey * q1 * q1], *BZ = &Bv[ez * q1 * q1];
+                const double *DX = &Dv[ex * q1 * q1], *DY = &Dv[ey * q1 * q1], *DZ = &Dv[ez * q1 * q1];
+                // kw[qz][qy][qx]
+                for (int qz = 0; qz < q1; qz++)
+                    for (int qy = 0; qy < q1; qy++)
+                        for (int qx = 0; qx < q1; qx++) {
+                            double w = (W[ez * q1 + qz] * W[ey * q1 + qy]) * W[ex * q1 + qx];
+                            kw[(qz * q1 + qy) * q1 + qx] =
+                                w * kappa_at(nk, a, mk, X[ex * q1 + qx], X[ey * q1 + qy], X[ez * q1 + qz]);
+                        }
+                std::fill(Kl.begin(), Kl.end(), 0.0);
+                for (int term = 0; term < 3; term++) {
+                    const double *TX = term == 0 ? DX : BX, *TY = term == 1 ? DY : BY, *TZ = term == 2 ? DZ : BZ;
+                    // A1[qz][qy][ax][bx] = sum_qx kw TX_ax TX_bx
+                    for (int qz = 0; qz < q1; qz++)
+                    for (int qy = 0; qy < q1; qy++)
+                    for (int ax = 0; ax < q1; ax++)
+                    for (int bx = 0; bx < q1; bx++) {
+                        double acc = 0.0;
+                        for (int qx = 0; qx < q1; qx++)
+                            acc += kw[(qz * q1 + qy) * q1 + qx] * (TX[ax * q1 + qx] * TX[bx * q1 + qx]);
+                        A1[((qz * q1 + qy) * q1 + ax) * q1 + bx] = acc;
+                    }
+                    // A2[qz][ay][by][ax][bx] = sum_qy A1 TY_ay TY_by
+                    for (int qz = 0; qz < q1; qz++)
+                    for (int ay = 0; ay < q1; ay++)
+                    for (int by = 0; by < q1; by++)
+                    for (int ax = 0; ax < q1; ax++)
+                    for (int bx = 0; bx < q1; bx++) {
+                        double acc = 0.0;
+                        for (int qy = 0; qy < q1; qy++)
+                            acc += A1[((qz * q1 + qy) * q1 + ax) * q1 + bx] * (TY[ay * q1 + qy] * TY[by * q1 + qy]);
+                        A2[(((qz * q1 + ay) * q1 + by) * q1 + ax) * q1 + bx] = acc;
+                    }
+                    // Kl[(az,ay,ax),(bz,by,bx)] += sum_qz A2 TZ_az TZ_bz
+                    for (int az = 0; az < q1; az++)
+                    for (int bz = 0; bz < q1; bz++)
+                    for (int ay = 0; ay < q1; ay++)
+                    for (int by = 0; by < q1; by++)
+                    for (int ax = 0; ax < q1; ax++)
+                    for (int bx = 0; bx < q1; bx++) {
+                        double acc = 0.0;
+                        for (int qz = 0; qz < q1; qz++)
+                            acc += A2[(((qz * q1 + ay) * q1 + by) * q1 + ax) * q1 + bx] * (TZ[az * q1 + qz] * TZ[bz * q1 + qz]);
+                        Kl[(size_t)((az * q1 + ay) * q1 + ax) * nl + (bz * q1 + by) * q1 + bx] += acc;
+                    }
+                }
+                for (int az = 0; az < q1; az++)
+                for (int ay = 0; ay < q1; ay++)
+                for (int ax = 0; ax < q1; ax++) {
+                    int ix = ex + ax - 1, iy = ey + ay - 1, iz = ez + az - 1;   // reduced indices
+                    if (ix < 0 || ix >= md || iy < 0 || iy >= md || iz < 0 || iz >= md) continue;
+                    if (F) {
+                        double fsum = 0.0;
+                        for (int qz = 0; qz < q1; qz++)
+                            for (int qy = 0; qy < q1; qy++)
+                                for (int qx = 0; qx < q1; qx++)
+                                    fsum += ((W[ez * q1 + qz] * W[ey * q1 + qy]) * W[ex * q1 + qx]) *
+                                            ((BZ[az * q1 + qz] * BY[ay * q1 + qy]) * BX[ax * q1 + qx]);
+                        F[ix + (int64_t)md * (iy + (int64_t)md * iz)] += fsum;
+                    }
+                    for (int bz = 0; bz < q1; bz++)
+                    for (int by = 0; by < q1; by++)
+                    for (int bx = 0; bx < q1; bx++) {
+                        int jx = ex + bx - 1, jy = ey + by - 1, jz = ez + bz - 1;
+                        if (jx < 0 || jx >= md || jy < 0 || jy >= md || jz < 0 || jz >= md) continue;
+                        v[pos(ix, iy, iz, jx, jy, jz)] += Kl[(size_t)((az * q1 + ay) * q1 + ax) * nl + (bz * q1 + by) * q1 + bx];
+                    }
+                }
+            }
+        }, 1);
+    }
     return 0;
 }
 

@@ -145,6 +145,176 @@ __global__ __launch_bounds__(256) void k_sell_blk(int64_t nrows, int64_t nslices
     }
 }
 
+// Block matrix pass with LPR lanes per row: the wave covers a slice of
+// C = 64 / LPR rows of a SELL-C image (same group layout as SELL-64 with the
+// slice height C), lane = (row r = lane / LPR, quarter q = lane % LPR), each
+// lane owning RPL = 16 / LPR consecutive columns.  The LPR lanes of a row read
+// the same matrix groups (one broadcast address) and together one contiguous
+// 16-column row of X per entry, so every X load of the wave is C contiguous
+// 64-byte (FP32) or 128-byte (FP64) runs.  Blocks of any multiple of 64
+// threads walk the slices grid-stride; per column the dot partials are summed
+// over the rows of a wave (butterfly over the row bits of the lane), then over
+// the block's waves in order: partial[(blockIdx.x * 2 + d) * NB + j].
+template <typename VT> struct RowLoad;
+template <> struct RowLoad<float> {
+    template <int RPL> static __device__ inline void load(const float *p, float (&o)[RPL])
+    {
+        if constexpr (RPL == 4) {
+            vf4 t = *reinterpret_cast<const vf4 *>(p);
+            o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < RPL; j++) o[j] = p[j];
+        }
+    }
+};
+template <> struct RowLoad<double> {
+    template <int RPL> static __device__ inline void load(const double *p, double (&o)[RPL])
+    {
+        if constexpr (RPL % 2 == 0) {
+#pragma unroll
+            for (int h = 0; h < RPL / 2; h++) {
+                vd2 t = reinterpret_cast<const vd2 *>(p)[h];
+                o[2 * h] = t.x; o[2 * h + 1] = t.y;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < RPL; j++) o[j] = p[j];
+        }
+    }
+};
+
+template <int C> __device__ inline void load8c(const double *__restrict__ val, int64_t base, int kk, int r, double v[8])
+{
+    const vd2 *p = reinterpret_cast<const vd2 *>(val + base) + (int64_t)(kk >> 1) * C + r;
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        vd2 t = __builtin_nontemporal_load(p + c * C);
+        v[2 * c] = t.x; v[2 * c + 1] = t.y;
+    }
+}
+template <int C> __device__ inline void load8c(const float *__restrict__ val, int64_t base, int kk, int r, float v[8])
+{
+    const vf4 *p = reinterpret_cast<const vf4 *>(val + base) + (int64_t)(kk >> 2) * C + r;
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        vf4 t = __builtin_nontemporal_load(p + c * C);
+        v[4 * c] = t.x; v[4 * c + 1] = t.y; v[4 * c + 2] = t.z; v[4 * c + 3] = t.w;
+    }
+}
+template <int C>
+__device__ inline void loadidx8c(const uint16_t *__restrict__ d16, int64_t base, int kk, int r, int &col, int c[8])
+{
+    vu4 t = __builtin_nontemporal_load(reinterpret_cast<const vu4 *>(d16 + base) + (int64_t)(kk >> 3) * C + r);
+    unsigned w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        col += (int)(w[q] & 0xffffu);
+        c[2 * q] = col;
+        col += (int)(w[q] >> 16);
+        c[2 * q + 1] = col;
+    }
+}
+template <int C>
+__device__ inline void loadidx8c(const int32_t *__restrict__ c32, int64_t base, int kk, int r, int &col, int c[8])
+{
+    const vi4 *p = reinterpret_cast<const vi4 *>(c32 + base) + (int64_t)(kk >> 2) * C + r;
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        vi4 t = __builtin_nontemporal_load(p + h * C);
+        c[4 * h] = t.x; c[4 * h + 1] = t.y; c[4 * h + 2] = t.z; c[4 * h + 3] = t.w;
+    }
+    col = c[7];
+}
+
+template <typename VT, typename FT, typename OT, typename IT, int EPI, int NDOT, int LPR>
+__global__ __launch_bounds__(512) void k_sellb(int64_t nrows, int64_t nslices, const int64_t *__restrict__ soff,
+                                               const VT *__restrict__ val, const IT *__restrict__ idx,
+                                               const int32_t *__restrict__ col0, const VT *__restrict__ X,
+                                               const FT *__restrict__ F, const VT *__restrict__ invd,
+                                               OT *__restrict__ Y, const double *__restrict__ G0,
+                                               const double *__restrict__ G1, double *__restrict__ partial,
+                                               VT coef)
+{
+    constexpr int C = 64 / LPR, RPL = NB / LPR;
+    __shared__ double lds[2 * 8 * NB];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int r = lane / LPR, q = lane % LPR;
+    double d0[RPL], d1[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; j++) { d0[j] = 0.0; d1[j] = 0.0; }
+    for (int64_t s = (int64_t)blockIdx.x * nw + wid; s < nslices; s += (int64_t)gridDim.x * nw) {
+        const int64_t row = s * C + r;
+        const int64_t base = soff[s];
+        const int width = (int)((soff[s + 1] - base) / C);
+        int col = (sizeof(IT) == 2) ? col0[row] : 0;
+        VT acc[RPL];
+#pragma unroll
+        for (int j = 0; j < RPL; j++) acc[j] = 0;
+        for (int kk = 0; kk < width; kk += 8) {
+            VT v[8];
+            int c[8];
+            loadidx8c<C>(idx, base, kk, r, col, c);
+            load8c<C>(val, base, kk, r, v);
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                VT xv[RPL];
+                RowLoad<VT>::template load<RPL>(X + (int64_t)c[t] * NB + q * RPL, xv);
+#pragma unroll
+                for (int j = 0; j < RPL; j++) acc[j] = fma(v[t], xv[j], acc[j]);
+            }
+        }
+        if (row < nrows) {
+            const int64_t o = row * NB + q * RPL;
+            if (EPI == EPI_SPMV) {
+#pragma unroll
+                for (int j = 0; j < RPL; j++) {
+                    Y[o + j] = (OT)acc[j];
+                    if (NDOT >= 1) d0[j] += (double)X[o + j] * (double)acc[j];
+                    if (NDOT >= 2) d1[j] += (double)X[o + j] * G1[o + j];
+                }
+            } else if (EPI == EPI_RESID) {
+#pragma unroll
+                for (int j = 0; j < RPL; j++) Y[o + j] = (OT)((VT)F[o + j] - acc[j]);
+            } else if (EPI == EPI_SMOOTH) {
+                const VT di = invd[row];
+#pragma unroll
+                for (int j = 0; j < RPL; j++) {
+                    VT out = X[o + j] + di * ((VT)F[o + j] - acc[j]);
+                    Y[o + j] = (OT)out;
+                    if (NDOT >= 1) d0[j] += (double)out * G0[o + j];
+                    if (NDOT >= 2) d1[j] += (double)out * G1[o + j];
+                }
+            } else {
+                const VT di = invd[row];
+#pragma unroll
+                for (int j = 0; j < RPL; j++) Y[o + j] = (OT)(coef * (di * (VT)F[o + j]) + di * acc[j]);
+            }
+        }
+    }
+    if (NDOT >= 1) {
+#pragma unroll
+        for (int j = 0; j < RPL; j++)
+            for (int o = LPR; o < 64; o <<= 1) {
+                d0[j] += __shfl_xor(d0[j], o, 64);
+                d1[j] += __shfl_xor(d1[j], o, 64);
+            }
+        if (r == 0)
+#pragma unroll
+            for (int j = 0; j < RPL; j++) {
+                lds[(wid * NB + q * RPL + j) * 2] = d0[j];
+                lds[(wid * NB + q * RPL + j) * 2 + 1] = d1[j];
+            }
+        __syncthreads();
+        if (threadIdx.x < 2 * NB) {
+            const int j = threadIdx.x >> 1, d = threadIdx.x & 1;
+            double t = 0.0;
+            for (int w = 0; w < nw; w++) t += lds[(w * NB + j) * 2 + d];
+            partial[(2 * blockIdx.x + d) * NB + j] = (d == 1 && NDOT < 2) ? 0.0 : t;
+        }
+    }
+}
+
 // ---- elementwise block kernels (one thread per row, 16 columns) ---------------
 
 template <typename VT, typename FT>

@@ -7,6 +7,7 @@
 #include "host.h"
 #include "kernels.h"
 #include "kernels_blk.h"
+#include "mlp.h"
 
 #include <hip/hip_runtime.h>
 
@@ -71,67 +72,69 @@ struct SellHost {
     std::vector<int32_t> c32, col0;
 };
 
-void build_sell(const CsrView &K, bool want64, bool want32, SellHost &S)
+// SELL-C image of a CSR matrix (slice height C rows; group layout of kernels.h
+// with SLICE replaced by C).
+void build_sell(const CsrView &K, int C, bool want64, bool want32, SellHost &S)
 {
     const int64_t n = K.n;
-    S.nslices = (n + SLICE - 1) / SLICE;
+    S.nslices = (n + C - 1) / C;
     S.soff.assign(S.nslices + 1, 0);
-    int maxd = 0;
     for (int64_t s = 0; s < S.nslices; s++) {
         int64_t w = 0;
-        for (int64_t r = s * SLICE; r < std::min(n, (s + 1) * SLICE); r++) w = std::max(w, K.rp[r + 1] - K.rp[r]);
+        for (int64_t r = s * C; r < std::min(n, (s + 1) * C); r++) w = std::max(w, K.rp[r + 1] - K.rp[r]);
         w = (w + 7) / 8 * 8;
-        S.soff[s + 1] = S.soff[s] + SLICE * w;
+        S.soff[s + 1] = S.soff[s] + C * w;
     }
     S.stored = S.soff[S.nslices];
-    std::vector<int> md(amgiga::host_threads() + 1, 0);
-    amgiga::parallel_for(n, [&](int64_t b, int64_t e) {
-        int m = 0;
-        for (int64_t r = b; r < e; r++)
-            for (int64_t k = K.rp[r] + 1; k < K.rp[r + 1]; k++) m = std::max(m, K.ci[k] - K.ci[k - 1]);
-        static std::mutex mx;
-        std::lock_guard<std::mutex> g(mx);
-        md[0] = std::max(md[0], m);
-    });
-    maxd = md[0];
+    int maxd = 0;
+    {
+        std::mutex mx;
+        amgiga::parallel_for(n, [&](int64_t b, int64_t e) {
+            int m = 0;
+            for (int64_t r = b; r < e; r++)
+                for (int64_t k = K.rp[r] + 1; k < K.rp[r + 1]; k++) m = std::max(m, K.ci[k] - K.ci[k - 1]);
+            std::lock_guard<std::mutex> g(mx);
+            maxd = std::max(maxd, m);
+        });
+    }
     S.idx16 = maxd <= 65535 ? 1 : 0;
     if (want64) S.v64.assign(S.stored, 0.0);
     if (want32) S.v32.assign(S.stored, 0.0f);
     if (S.idx16) {
         S.d16.assign(S.stored, 0);
-        S.col0.assign(S.nslices * SLICE, 0);
+        S.col0.assign(S.nslices * C, 0);
     } else {
         S.c32.assign(S.stored, 0);
     }
     amgiga::parallel_for(S.nslices, [&](int64_t sb, int64_t se) {
         for (int64_t s = sb; s < se; s++) {
             const int64_t base = S.soff[s];
-            const int64_t w = (S.soff[s + 1] - base) / SLICE;
-            for (int lane = 0; lane < SLICE; lane++) {
-                int64_t r = s * SLICE + lane;
+            const int64_t w = (S.soff[s + 1] - base) / C;
+            for (int lane = 0; lane < C; lane++) {
+                int64_t r = s * C + lane;
                 int64_t len = r < n ? K.rp[r + 1] - K.rp[r] : 0;
                 const int64_t r0 = r < n ? K.rp[r] : 0;
                 if (S.idx16 && r < n) S.col0[r] = K.ci[r0];
                 for (int64_t k = 0; k < w; k++) {
                     double v = k < len ? K.v[r0 + k] : 0.0;
-                    if (want64) S.v64[base + (k / 2) * 128 + lane * 2 + (k % 2)] = v;
-                    if (want32) S.v32[base + (k / 4) * 256 + lane * 4 + (k % 4)] = (float)v;
+                    if (want64) S.v64[base + (k / 2) * 2 * C + lane * 2 + (k % 2)] = v;
+                    if (want32) S.v32[base + (k / 4) * 4 * C + lane * 4 + (k % 4)] = (float)v;
                     if (S.idx16) {
                         int d = (k >= 1 && k < len) ? K.ci[r0 + k] - K.ci[r0 + k - 1] : 0;
-                        S.d16[base + (k / 8) * 512 + lane * 8 + (k % 8)] = (uint16_t)d;
+                        S.d16[base + (k / 8) * 8 * C + lane * 8 + (k % 8)] = (uint16_t)d;
                     } else {
                         int32_t c = k < len ? K.ci[r0 + k] : (len > 0 ? K.ci[r0 + len - 1] : 0);
-                        S.c32[base + (k / 4) * 256 + lane * 4 + (k % 4)] = c;
+                        S.c32[base + (k / 4) * 4 * C + lane * 4 + (k % 4)] = c;
                     }
                 }
             }
         }
-    });
+    }, 1);
 }
 
 struct DevMat {
     int64_t n = 0, nnz = 0, nslices = 0, stored = 0;
-    int idx16 = 1;
+    int idx16 = 1, C = SLICE;
     int64_t *soff = nullptr;
     int32_t *col0 = nullptr, *c32 = nullptr;
     uint16_t *d16 = nullptr;
@@ -144,7 +147,8 @@ template <> const float *DevMat::val<float>() const { return v32; }
 
 struct Level {
     int64_t n = 0, nnz = 0;
-    DevMat A;
+    DevMat A;     // SELL-64, one lane per row
+    DevMat Ab;    // SELL-(64/LPR) image of the block kernels (batched solves), if built
     double *invd64 = nullptr;
     float *invd32 = nullptr;
     // transfer to the next level
@@ -184,6 +188,8 @@ struct amg_ctx {
     // batched solve (allocated on first use)
     double *bR = nullptr, *bZ = nullptr, *bP = nullptr, *bQ = nullptr, *bU = nullptr, *bF = nullptr;
     double *bY = nullptr, *bsc = nullptr, *hbsc = nullptr, *bpartial = nullptr;
+    int blk_lpr = 1, blk_threads = 256;   // block-kernel variant (autotuned when prm.nrhs > 1)
+    std::vector<std::pair<std::string, double>> tune_log;
     double *sc = nullptr;
     double *hsc = nullptr;     // pinned host copy of the scalar block
     hipEvent_t ev_iter = nullptr;
@@ -207,6 +213,108 @@ struct amg_ctx {
         T *d = dupload(h.data(), h.size());
         allocs.push_back(d);
         return d;
+    }
+    void release(void *p)
+    {
+        if (!p) return;
+        auto it = std::find(allocs.begin(), allocs.end(), p);
+        if (it != allocs.end()) allocs.erase(it);
+        (void)hipFree(p);
+    }
+    void release(DevMat &M)
+    {
+        release(M.soff); release(M.col0); release(M.c32); release(M.d16); release(M.v64); release(M.v32);
+        M = DevMat();
+    }
+    DevMat upload_sell(const CsrView &K, int C, bool want64, bool want32)
+    {
+        SellHost S;
+        build_sell(K, C, want64, want32, S);
+        DevMat A;
+        A.n = K.n; A.nnz = K.nnz(); A.nslices = S.nslices; A.stored = S.stored; A.idx16 = S.idx16; A.C = C;
+        A.soff = upload(S.soff);
+        if (want64) A.v64 = upload(S.v64);
+        if (want32) A.v32 = upload(S.v32);
+        if (S.idx16) { A.d16 = upload(S.d16); A.col0 = upload(S.col0); }
+        else A.c32 = upload(S.c32);
+        return A;
+    }
+    // Time one batched iteration's level-0 passes (FP64 outer SpMV + two V-cycle
+    // passes in the V-cycle precision) for the current block variant.
+    template <typename VT> float time_blk_variant()
+    {
+        Level &L = lev[0];
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        float best = 1e30f;
+        for (int rep = 0; rep < 3; rep++) {
+            HIPCHK(hipEventRecord(e0, stream));
+            sell_blk<double, double, double, EPI_SPMV, 1>(0, bP, nullptr, nullptr, bQ, nullptr, nullptr);
+            sell_blk<VT, double, VT, EPI_RESID, 0>(0, (const VT *)L.bu, bR, L.invd<VT>(), (VT *)L.br, nullptr, nullptr);
+            sell_blk<VT, double, VT, EPI_RESID, 0>(0, (const VT *)L.bu, bR, L.invd<VT>(), (VT *)L.br, nullptr, nullptr);
+            HIPCHK(hipEventRecord(e1, stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) best = std::min(best, ms);
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return best;
+    }
+    // Autotuner of the block kernels: builds the level-0 block image for 4 and
+    // 16 lanes per row, times each with 256 and 512 threads per block (and the
+    // one-lane-per-row kernel on the SELL-64 image), keeps the fastest, and
+    // builds the coarse levels' block images for the chosen slice height.
+    void tune_blocks(const CsrView &K0)
+    {
+        blk_alloc();
+        const bool f32 = fp32();
+        for (double *v : {bP, bR}) {
+            hipLaunchKernelGGL((k_fill<double>), dim3(vgrid(n * NB)), dim3(256), 0, stream, n * NB, 1.0, v);
+        }
+        if (f32) hipLaunchKernelGGL((k_fill<float>), dim3(vgrid(n * NB)), dim3(256), 0, stream, n * NB, 1.0f, (float *)lev[0].bu);
+        else hipLaunchKernelGGL((k_fill<double>), dim3(vgrid(n * NB)), dim3(256), 0, stream, n * NB, 1.0, (double *)lev[0].bu);
+        HIPCHK(hipGetLastError());
+        int prof_saved = prof;
+        prof = 0;
+        struct Best { int lpr, thr; float ms; } best{1, 256, 1e30f};
+        blk_lpr = 1;
+        blk_threads = 256;
+        float t1 = f32 ? time_blk_variant<float>() : time_blk_variant<double>();
+        tune_log.push_back({"lpr=1 threads=256", t1});
+        best = {1, 256, t1};
+        DevMat keep;
+        int keep_lpr = 0;
+        for (int lpr : {4, 16}) {
+            DevMat img = upload_sell(K0, 64 / lpr, true, f32);
+            lev[0].Ab = img;
+            for (int thr : {256, 512}) {
+                blk_lpr = lpr;
+                blk_threads = thr;
+                float t = f32 ? time_blk_variant<float>() : time_blk_variant<double>();
+                tune_log.push_back({"lpr=" + std::to_string(lpr) + " threads=" + std::to_string(thr), t});
+                if (t < best.ms) best = {lpr, thr, t};
+            }
+            if (best.lpr == lpr) {
+                if (keep_lpr) release(keep);
+                keep = img;
+                keep_lpr = lpr;
+            } else {
+                release(img);
+            }
+            lev[0].Ab = DevMat();
+        }
+        prof = prof_saved;
+        blk_lpr = best.lpr;
+        blk_threads = best.thr;
+        if (best.lpr > 1) {
+            lev[0].Ab = keep;
+            for (int l = 1; l < nlev - 1; l++)
+                lev[l].Ab = upload_sell(amgiga::view(host.lev[l].K), 64 / best.lpr, !f32, f32);
+        }
+        HIPCHK(hipStreamSynchronize(stream));
     }
     ~amg_ctx()
     {
@@ -462,19 +570,50 @@ struct amg_ctx {
         bpartial = alloc<double>((size_t)partial_cap * NB);
         HIPCHK(hipHostMalloc((void **)&hbsc, B_NSLOTS * NB * sizeof(double), hipHostMallocDefault));
     }
+    unsigned blk_grid(const DevMat &B) const
+    {
+        int64_t wpb = blk_threads / 64;
+        int64_t g = (B.nslices + wpb - 1) / wpb;
+        return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, blk_threads == 512 ? 2048 : 4096));
+    }
+    template <typename VT, typename FT, typename OT, int EPI, int NDOT, int LPR>
+    unsigned launch_sellb(const DevMat &B, const VT *x, const FT *f, const VT *invd, OT *y, const double *g0,
+                          const double *g1, VT coef)
+    {
+        unsigned g = blk_grid(B);
+        if (B.idx16)
+            hipLaunchKernelGGL((k_sellb<VT, FT, OT, uint16_t, EPI, NDOT, LPR>), dim3(g), dim3(blk_threads), 0, stream,
+                               B.n, B.nslices, B.soff, B.val<VT>(), B.d16, B.col0, x, f, invd, y, g0, g1, bpartial,
+                               coef);
+        else
+            hipLaunchKernelGGL((k_sellb<VT, FT, OT, int32_t, EPI, NDOT, LPR>), dim3(g), dim3(blk_threads), 0, stream,
+                               B.n, B.nslices, B.soff, B.val<VT>(), B.c32, B.col0, x, f, invd, y, g0, g1, bpartial,
+                               coef);
+        return g;
+    }
+    // Block matrix pass on level l; returns the number of dot-partial blocks.
     template <typename VT, typename FT, typename OT, int EPI, int NDOT>
-    void sell_blk(int l, const VT *x, const FT *f, const VT *invd, OT *y, const double *g0, const double *g1,
-                  VT coef = 1)
+    unsigned sell_blk(int l, const VT *x, const FT *f, const VT *invd, OT *y, const double *g0, const double *g1,
+                      VT coef = 1)
     {
         const DevMat &A = lev[l].A;
-        unsigned nb = sell_blocks(l);
+        const DevMat &B = lev[l].Ab;
+        unsigned nb;
         if (l == 0) prof_begin();
-        if (A.idx16)
-            hipLaunchKernelGGL((k_sell_blk<VT, FT, OT, uint16_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream, A.n,
-                               A.nslices, A.soff, A.val<VT>(), A.d16, A.col0, x, f, invd, y, g0, g1, bpartial, coef);
-        else
-            hipLaunchKernelGGL((k_sell_blk<VT, FT, OT, int32_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream, A.n,
-                               A.nslices, A.soff, A.val<VT>(), A.c32, A.col0, x, f, invd, y, g0, g1, bpartial, coef);
+        if (blk_lpr > 1 && B.soff && B.val<VT>()) {
+            nb = blk_lpr == 4 ? launch_sellb<VT, FT, OT, EPI, NDOT, 4>(B, x, f, invd, y, g0, g1, coef)
+                              : launch_sellb<VT, FT, OT, EPI, NDOT, 16>(B, x, f, invd, y, g0, g1, coef);
+        } else {
+            nb = sell_blocks(l);
+            if (A.idx16)
+                hipLaunchKernelGGL((k_sell_blk<VT, FT, OT, uint16_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream, A.n,
+                                   A.nslices, A.soff, A.val<VT>(), A.d16, A.col0, x, f, invd, y, g0, g1, bpartial,
+                                   coef);
+            else
+                hipLaunchKernelGGL((k_sell_blk<VT, FT, OT, int32_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream, A.n,
+                                   A.nslices, A.soff, A.val<VT>(), A.c32, A.col0, x, f, invd, y, g0, g1, bpartial,
+                                   coef);
+        }
         HIPCHK(hipGetLastError());
         if (l == 0) {
             // 16 columns: matrix once, 16 vectors of each kind
@@ -487,6 +626,7 @@ struct amg_ctx {
                            ((EPI == EPI_SMOOTH || EPI == EPI_POLY) ? (double)sizeof(VT) * M.n : 0.0);
             prof_end(bytes);
         }
+        return nb;
     }
     void bfinalize(unsigned nblk, int op, int k = 0, double tol = 0.0)
     {
@@ -517,10 +657,11 @@ struct amg_ctx {
     {
         Level &L = lev[l];
         if (!L.poly_on) {
-            if (ndot == 2) sell_blk<VT, FT, OT, EPI_SMOOTH, 2>(l, uin, f, L.invd<VT>(), uout, g0, g1);
-            else if (ndot == 1) sell_blk<VT, FT, OT, EPI_SMOOTH, 1>(l, uin, f, L.invd<VT>(), uout, g0, g1);
-            else sell_blk<VT, FT, OT, EPI_SMOOTH, 0>(l, uin, f, L.invd<VT>(), uout, g0, g1);
-            if (ndot) vc_nb = sell_blocks(l);
+            unsigned nb;
+            if (ndot == 2) nb = sell_blk<VT, FT, OT, EPI_SMOOTH, 2>(l, uin, f, L.invd<VT>(), uout, g0, g1);
+            else if (ndot == 1) nb = sell_blk<VT, FT, OT, EPI_SMOOTH, 1>(l, uin, f, L.invd<VT>(), uout, g0, g1);
+            else nb = sell_blk<VT, FT, OT, EPI_SMOOTH, 0>(l, uin, f, L.invd<VT>(), uout, g0, g1);
+            if (ndot) vc_nb = nb;
             return;
         }
         VT *res = (VT *)L.br, *c = (VT *)L.bc, *c2 = (VT *)L.bc2;
@@ -629,7 +770,7 @@ static amg_status build_device(amg_ctx *c, const CsrView &K0)
                 SellHost S;
                 bool want64 = (l == 0) || !fp32;
                 bool want32 = fp32;
-                build_sell(K, want64, want32, S);
+                build_sell(K, SLICE, want64, want32, S);
                 DevMat &A = L.A;
                 A.n = hl.n; A.nnz = hl.nnz; A.nslices = S.nslices; A.stored = S.stored; A.idx16 = S.idx16;
                 A.soff = c->upload(S.soff);
@@ -703,11 +844,12 @@ static amg_status build_device(amg_ctx *c, const CsrView &K0)
     c->z = c->alloc<double>(c->n);
     c->p = c->alloc<double>(c->n);
     c->q = c->alloc<double>(c->n);
-    c->partial_cap = 2 * std::max<int64_t>(2048, c->sell_blocks(0));
+    c->partial_cap = 2 * std::max<int64_t>(4096, c->sell_blocks(0));
     c->partial = c->alloc<double>(c->partial_cap);
     c->sc = c->alloc<double>(S_NSLOTS);
     HIPCHK(hipHostMalloc((void **)&c->hsc, S_NSLOTS * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipEventCreateWithFlags(&c->ev_iter, hipEventDisableTiming));
+    if (c->prm.nrhs > 1) c->tune_blocks(K0);
     HIPCHK(hipStreamSynchronize(c->stream));
     return AMG_OK;
 }
@@ -727,6 +869,7 @@ amg_status amg_params_default(amg_params *p)
     p->krylov = 0;
     p->match_positive_only = 0;
     p->itmax = 1000;
+    p->nrhs = 1;
     return AMG_OK;
 }
 
@@ -744,6 +887,7 @@ static amg_status setup_common(int64_t n, const int64_t *row_ptr, const int32_t 
     if (prm) P = *prm;
     if (P.sweeps_per_level < 1 || P.sweeps_per_level > 3 || P.max_coarse < 1 || P.max_coarse > 2000 ||
         P.max_levels < 1 || P.nu_pre < 1 || P.nu_post < 0 || P.itmax < 1 || P.krylov < 0 || P.krylov > 1 ||
+        P.nrhs < 1 || P.nrhs > NB ||
         P.smoother < 0 || P.smoother > 1) {
         set_err("parameter out of range");
         return AMG_ERR_ARG;
@@ -948,9 +1092,10 @@ static amg_status solve_batched_impl(amg_ctx *c, int nrhs, const double *F, doub
         if (!flex) c->bfinalize(nb, BF_RZ0);
         c->copy<double, double>(n * NB, c->bZ, c->bP);
         for (int k = 1; k <= itmax; k++) {
-            if (flex) c->sell_blk<double, double, double, EPI_SPMV, 2>(0, c->bP, nullptr, nullptr, c->bQ, nullptr, c->bR);
-            else c->sell_blk<double, double, double, EPI_SPMV, 1>(0, c->bP, nullptr, nullptr, c->bQ, nullptr, nullptr);
-            c->bfinalize(c->sell_blocks(0), flex ? BF_PQ_FCG : BF_PQ_CG);
+            unsigned nbq;
+            if (flex) nbq = c->sell_blk<double, double, double, EPI_SPMV, 2>(0, c->bP, nullptr, nullptr, c->bQ, nullptr, c->bR);
+            else nbq = c->sell_blk<double, double, double, EPI_SPMV, 1>(0, c->bP, nullptr, nullptr, c->bQ, nullptr, nullptr);
+            c->bfinalize(nbq, flex ? BF_PQ_FCG : BF_PQ_CG);
             unsigned g = vgrid(n);
             hipLaunchKernelGGL(k_bcg_update, dim3(g), dim3(256), 0, st, n, c->bsc, c->bU, c->bR, c->bP, c->bQ,
                                c->bpartial);
@@ -1037,6 +1182,30 @@ amg_status amg_spmv(amg_ctx *c, int level, const double *x, double *y)
     } catch (Fail &f) {
         return f.st;
     }
+    return AMG_OK;
+}
+
+amg_status amg_get_batched_variant(const amg_ctx *c, int *lpr, int *threads)
+{
+    if (!c) { set_err("NULL context"); return AMG_ERR_ARG; }
+    if (lpr) *lpr = c->blk_lpr;
+    if (threads) *threads = c->blk_threads;
+    return AMG_OK;
+}
+
+amg_status amg_set_batched_variant(amg_ctx *c, int lpr, int threads)
+{
+    if (!c || (threads != 256 && threads != 512) || (lpr != 1 && lpr != 4 && lpr != 16)) {
+        set_err("lpr must be 1, 4 or 16 and threads 256 or 512");
+        return AMG_ERR_ARG;
+    }
+    if (lpr > 1 && (c->lev[0].Ab.C != 64 / lpr || !c->lev[0].Ab.soff)) {
+        set_err("no block image with that many lanes per row (build with prm.nrhs > 1)");
+        return AMG_ERR_ARG;
+    }
+    if (lpr == 1 && threads != 256) { set_err("the one-lane-per-row kernels use 256 threads"); return AMG_ERR_ARG; }
+    c->blk_lpr = lpr;
+    c->blk_threads = threads;
     return AMG_OK;
 }
 
@@ -1146,6 +1315,90 @@ amg_status amg_iga_poisson(int d, int p, int n, int64_t *row_ptr, int32_t *col, 
 {
     if (!row_ptr || !col || !val) { set_err("NULL output"); return AMG_ERR_ARG; }
     if (amgiga::iga_poisson(d, p, n, row_ptr, col, val, F)) { set_err("bad d, p or n"); return AMG_ERR_ARG; }
+    return AMG_OK;
+}
+
+amg_status amg_level_features(const amg_ctx *c, int level, float *feat)
+{
+    if (!c || !feat || level < 0 || level >= c->nlev) { set_err("bad level or NULL"); return AMG_ERR_ARG; }
+    const auto &L = c->host.lev[level];
+    for (int k = 0; k < 6; k++) feat[k] = L.feat[k];
+    feat[6] = c->nlev > 1 ? (float)level / (float)(c->nlev - 1) : 0.0f;
+    feat[7] = level + 1 < c->nlev ? (float)((double)c->host.lev[level + 1].n / (double)L.n) : 0.0f;
+    return AMG_OK;
+}
+
+amg_status amg_mlp_forward(const uint16_t *w, const float *X, int B, float *Y, float *act, void *hip_stream)
+{
+    if (!w || !X || !Y || B < 1) { set_err("NULL argument or B < 1"); return AMG_ERR_ARG; }
+    hipLaunchKernelGGL(k_mlp_fwd, dim3((B + 63) / 64), dim3(64), 0, (hipStream_t)hip_stream, w, X, B, Y, act);
+    if (hipGetLastError() != hipSuccess) { set_err("launch failed"); return AMG_ERR_HIP; }
+    return AMG_OK;
+}
+
+amg_status amg_mlp_backward(const uint16_t *w, const float *X, const float *act, const float *Y, const float *T,
+                            int B, float *del, float *grad, float *loss, void *hip_stream)
+{
+    if (!w || !X || !act || !Y || !T || !del || !grad || B < 1) { set_err("NULL argument or B < 1"); return AMG_ERR_ARG; }
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(k_mlp_delta, dim3((B + 63) / 64), dim3(64), 0, st, w, act, Y, T, B, del);
+    hipLaunchKernelGGL(k_mlp_grad, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, st, X, act, del, Y, T, B, grad, loss);
+    if (hipGetLastError() != hipSuccess) { set_err("launch failed"); return AMG_ERR_HIP; }
+    return AMG_OK;
+}
+
+amg_status amg_mlp_adam(float *master, uint16_t *w, const float *grad, float *m, float *v, int step, float lr,
+                        void *hip_stream)
+{
+    if (!master || !w || (step > 0 && (!grad || !m || !v)) || step < 0) { set_err("NULL argument"); return AMG_ERR_ARG; }
+    hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, (hipStream_t)hip_stream, master, w,
+                       grad, m, v, step, lr, 0.9f, 0.999f, 1e-8f);
+    if (hipGetLastError() != hipSuccess) { set_err("launch failed"); return AMG_ERR_HIP; }
+    return AMG_OK;
+}
+
+amg_status amg_set_learned_poly(amg_ctx *c, const uint16_t *w_host, const double scale[4], int *accepted,
+                                double *coeffs)
+{
+    g_err.clear();
+    if (!c || !w_host || !scale) { set_err("NULL argument"); return AMG_ERR_ARG; }
+    if (c->host_only) { set_err("context was built by amg_setup_host"); return AMG_ERR_STATE; }
+    if (c->prm.smoother != 1) { set_err("context not built with the polynomial smoother (prm.smoother = 1)"); return AMG_ERR_STATE; }
+    const int nl = c->nlev - 1;
+    if (nl < 1) return AMG_OK;
+    try {
+        std::vector<float> X((size_t)nl * MLP_IN), Y((size_t)nl * MLP_OUT);
+        for (int l = 0; l < nl; l++) amg_level_features(c, l, &X[(size_t)l * MLP_IN]);
+        uint16_t *dw = dalloc<uint16_t>(MLP_NPARAM);
+        float *dX = dalloc<float>(X.size()), *dY = dalloc<float>(Y.size());
+        HIPCHK(hipMemcpy(dw, w_host, MLP_NPARAM * sizeof(uint16_t), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(dX, X.data(), X.size() * sizeof(float), hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(k_mlp_fwd, dim3((nl + 63) / 64), dim3(64), 0, c->stream, dw, dX, nl, dY, (float *)nullptr);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(Y.data(), dY, Y.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        (void)hipFree(dw); (void)hipFree(dX); (void)hipFree(dY);
+        for (int l = 0; l < nl; l++) {
+            double cf[4];
+            for (int k = 0; k < 4; k++) cf[k] = scale[k] * (double)Y[(size_t)l * MLP_OUT + k];
+            if (coeffs) for (int k = 0; k < 4; k++) coeffs[l * 4 + k] = cf[k];
+            int ok = poly_ok(cf);
+            Level &L = c->lev[l];
+            if (ok) { for (int k = 0; k < 4; k++) L.poly[k] = cf[k]; L.poly_on = 1; }
+            else { L.poly[0] = 1.0; L.poly[1] = L.poly[2] = L.poly[3] = 0.0; L.poly_on = 0; }
+            if (accepted) accepted[l] = ok;
+        }
+    } catch (Fail &f) {
+        return f.st;
+    }
+    return AMG_OK;
+}
+
+amg_status amg_iga_diffusion(int p, int n, int nk, const double *a, const int32_t *mk, int64_t *row_ptr,
+                             int32_t *col, double *val, double *F)
+{
+    if (!row_ptr || !col || !val || (nk > 0 && (!a || !mk))) { set_err("NULL argument"); return AMG_ERR_ARG; }
+    if (amgiga::iga_diffusion(p, n, nk, a, mk, row_ptr, col, val, F)) { set_err("bad p, n or nk"); return AMG_ERR_ARG; }
     return AMG_OK;
 }
 

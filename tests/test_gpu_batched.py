@@ -85,3 +85,34 @@ def test_batched_itmax_and_args(oracle, amg):
     assert out["status"] == 1 and out["iters"] == [2, 2, 2]
     with pytest.raises(amg.AmgError):
         ctx.solve_batched(torch.zeros(N, 17, dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_autotuned_block_kernels(oracle, amg, fp32):
+    """Context built for batched solves (nrhs = 16): the autotuner picks the
+    lanes-per-row variant; every variant gives the same iterations as the
+    single-vector solves and solutions equal to rounding."""
+    print(f"case autotune fp32={fp32}", flush=True)
+    from paper_2511_21268_amd.workloads import rhs_block
+    rp, ci, v, _ = oracle.poisson_kron(3, 3, 18)
+    N = len(rp) - 1
+    Fh = rhs_block(N, range(16))
+    kw = dict(vcycle_fp32=1, krylov=1) if fp32 else {}
+    ctx = amg.Context(rp, ci, v, nrhs=16, **kw)
+    lpr, thr = ctx.batched_variant()
+    print(f"  autotuned: lpr={lpr} threads={thr}", flush=True)
+    assert lpr in (1, 4, 16) and thr in (256, 512)
+    Ft = torch.from_numpy(Fh).cuda()
+    singles = [ctx.solve(Ft[:, j].contiguous(), tol=1e-8) for j in range(16)]
+    variants = [(1, 256)] + ([(lpr, 256), (lpr, 512)] if lpr > 1 else [])
+    for (lp, th) in variants:
+        ctx.set_batched_variant(lp, th)
+        out = ctx.solve_batched(Ft, tol=1e-8)
+        U = out["U"].cpu().numpy()
+        assert out["status"] == 0
+        for j in range(16):
+            us = singles[j]["u"].cpu().numpy()
+            assert abs(out["iters"][j] - singles[j]["iters"]) <= (0 if not fp32 else 1), (lp, th, j)
+            tol = 1e-12 if not fp32 else 1e-6
+            assert np.linalg.norm(U[:, j] - us) <= tol * np.linalg.norm(us), (lp, th, j)
+    ctx.set_batched_variant(lpr, thr)
