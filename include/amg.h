@@ -188,6 +188,15 @@ void amg_destroy(amg_ctx *c);
 /* Message of the last error on this thread ("" if none). */
 const char *amg_last_error(void);
 
+/* Replay the iteration body of pcg_solve / pcg_solve_batched from HIP graphs
+ * (default: off).  The body is captured on the library's own stream at the first
+ * solve of each kind and replayed every iteration; the solve is ordered after
+ * and before the context's stream by events.  Graphs are re-captured after
+ * amg_set_poly_coeffs, amg_set_learned_poly or amg_set_batched_variant, and are
+ * not used while profiling is enabled.  Results are bitwise those of the eager
+ * launches. */
+amg_status amg_set_graph(amg_ctx *c, int enable);
+
 /* ------------------------------------------------------------------------
  * Measurement.  While enabled, every launch of the level-0 sparse
  * matrix-pass kernel (SpMV, residual, smoother sweep) inside the solve calls
@@ -255,12 +264,15 @@ amg_status amg_mlp_adam(float *master, uint16_t *w, const float *grad, float *m,
                         void *hip_stream);
 
 /* Predict every level's smoother with the MLP (weights: host BF16 array) on the
- * device, scale the outputs by scale[4] into coefficients, and set each level
- * through the acceptance test of amg_set_poly_coeffs; a rejected level keeps
- * l1-Jacobi.  accepted (host, may be NULL): levels-1 flags; coeffs (host, may be
- * NULL): (levels-1) x 4 predicted coefficients.  Needs prm.smoother == 1. */
-amg_status amg_set_learned_poly(amg_ctx *c, const uint16_t *w_host, const double scale[4], int *accepted,
-                                double *coeffs);
+ * device and set each level through the acceptance test of amg_set_poly_coeffs;
+ * a rejected level keeps l1-Jacobi.  The network's four outputs are the values
+ * of g(t) = 1 - e(t) = sum_k a_k t^{k+1} at the Chebyshev-Lobatto nodes
+ * t_j = (1 - cos(j pi / 4)) / 2, j = 1..4 (g(0) = 0): the degree-4 interpolant
+ * gives the coefficients a_0..a_3, and an output error of size eps moves e(t) by
+ * at most about 2 eps on [0, 1].  accepted (host, may be NULL): levels-1 flags;
+ * coeffs (host, may be NULL): (levels-1) x 4 predicted coefficients.  Needs
+ * prm.smoother == 1. */
+amg_status amg_set_learned_poly(amg_ctx *c, const uint16_t *w_host, int *accepted, double *coeffs);
 
 /*
  * Variable-coefficient workload: -div(kappa grad u) = 1 on the unit cube with

@@ -23,7 +23,7 @@ EXPORTS = ["amg_params_default", "amg_setup", "pcg_solve", "pcg_solve_batched", 
            "amg_destroy", "amg_last_error", "amg_set_profiling", "amg_get_profile", "amg_get_format",
            "amg_iga_poisson_size", "amg_iga_poisson", "amg_iga_diffusion", "amg_level_features",
            "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_adam", "amg_set_learned_poly",
-           "amg_get_batched_variant", "amg_set_batched_variant"]
+           "amg_get_batched_variant", "amg_set_batched_variant", "amg_set_graph"]
 MLP_NPARAM, MLP_NFEAT, MLP_NACT, MLP_NDEL = 4996, 8, 128, 132
 
 
@@ -79,9 +79,10 @@ def lib():
         L.amg_mlp_forward.argtypes = [vp, vp, C.c_int, vp, vp, vp]
         L.amg_mlp_backward.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp, vp]
         L.amg_mlp_adam.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_float, vp]
+        L.amg_set_graph.argtypes = [vp, C.c_int]
         L.amg_get_batched_variant.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.amg_set_batched_variant.argtypes = [vp, C.c_int, C.c_int]
-        L.amg_set_learned_poly.argtypes = [vp, C.POINTER(C.c_uint16), f64p, C.POINTER(C.c_int), f64p]
+        L.amg_set_learned_poly.argtypes = [vp, C.POINTER(C.c_uint16), C.POINTER(C.c_int), f64p]
         _lib = L
     return _lib
 
@@ -216,6 +217,9 @@ class Context:
         c = np.ascontiguousarray(coeffs, np.float64)
         return _check(lib().amg_set_poly_coeffs(self.h, level, _p(c, f64p)), allow=(AMG_OK, AMG_NOT_CONVERGED))
 
+    def set_graph(self, on):
+        _check(lib().amg_set_graph(self.h, int(on)))
+
     def batched_variant(self):
         lpr = C.c_int(); thr = C.c_int()
         _check(lib().amg_get_batched_variant(self.h, C.byref(lpr), C.byref(thr)))
@@ -229,15 +233,14 @@ class Context:
         _check(lib().amg_level_features(self.h, level, f))
         return np.array(list(f), dtype=np.float32)
 
-    def set_learned_poly(self, w_bf16, scale):
+    def set_learned_poly(self, w_bf16):
         """Predict and set every level's polynomial smoother from the MLP weights
         (numpy uint16 BF16 bits).  Returns (accepted flags, coefficients)."""
         w = np.ascontiguousarray(w_bf16, np.uint16)
         assert w.size == MLP_NPARAM
-        sc = np.ascontiguousarray(scale, np.float64)
         nl = max(self.nlevels - 1, 0)
         acc = (C.c_int * max(nl, 1))(); coef = np.zeros((max(nl, 1), 4))
-        _check(lib().amg_set_learned_poly(self.h, w.ctypes.data_as(C.POINTER(C.c_uint16)), _p(sc, f64p), acc,
+        _check(lib().amg_set_learned_poly(self.h, w.ctypes.data_as(C.POINTER(C.c_uint16)), acc,
                                           _p(coef, f64p)))
         return [bool(acc[i]) for i in range(nl)], coef[:nl]
 

@@ -497,7 +497,7 @@ __global__ void k_bcg_pupdate(int64_t n, const double *__restrict__ sc, const do
 // Final per-column sums of the partials (index order) and the scalar
 // recurrences, masks and iteration counters of the 16 independent solves.
 __global__ __launch_bounds__(256) void k_bfinalize(const double *__restrict__ partial, int nblk, double *sc,
-                                                   int op, int k, double tol)
+                                                   int op, double tol)
 {
     __shared__ double lds[8 * NB];
     double s0[NB], s1[NB];
@@ -534,10 +534,10 @@ __global__ __launch_bounds__(256) void k_bfinalize(const double *__restrict__ pa
             if (!(a > 0.0) || !isfinite(a)) *F = 1.0;
             else sc[B_ALPHA * NB + j] = (op == BF_PQ_FCG ? b : sc[B_RZ * NB + j]) / a;
             break;
-        case BF_RR:
+        case BF_RR:   // one more completed update of this column
             if (*D != 0.0 || *F != 0.0) break;
             sc[B_RR * NB + j] = a;
-            sc[B_ITERS * NB + j] = (double)k;
+            sc[B_ITERS * NB + j] += 1.0;
             if (sqrt(a) <= sc[B_THR * NB + j]) *D = 1.0;
             break;
         case BF_RZ_CG:

@@ -189,6 +189,63 @@ struct amg_ctx {
     double *bR = nullptr, *bZ = nullptr, *bP = nullptr, *bQ = nullptr, *bU = nullptr, *bF = nullptr;
     double *bY = nullptr, *bsc = nullptr, *hbsc = nullptr, *bpartial = nullptr;
     int blk_lpr = 1, blk_threads = 256;   // block-kernel variant (autotuned when prm.nrhs > 1)
+    // graph replay of the iteration body (single: [0]=CG [1]=FCG; batched likewise)
+    int use_graph = 0;
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    double *uw = nullptr;
+    hipGraphExec_t gA[2] = {nullptr, nullptr}, gB[2] = {nullptr, nullptr};
+    hipGraphExec_t gbA[2] = {nullptr, nullptr}, gbB[2] = {nullptr, nullptr};
+    void drop_graphs()
+    {
+        for (auto *arr : {gA, gB, gbA, gbB})
+            for (int i = 0; i < 2; i++)
+                if (arr[i]) { (void)hipGraphExecDestroy(arr[i]); arr[i] = nullptr; }
+    }
+    template <class Body> hipGraphExec_t capture(Body body)
+    {
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        try {
+            body();
+        } catch (...) {
+            (void)hipStreamEndCapture(stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        HIPCHK(hipStreamEndCapture(stream, &g));
+        hipGraphExec_t ex = nullptr;
+        hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(e);
+        return ex;
+    }
+    // Run the solve on the library's own stream (graphs cannot be captured on
+    // the null stream); ordered after / before the caller's stream by events.
+    struct OnGraphStream {
+        amg_ctx *c;
+        hipStream_t user;
+        bool on;
+        OnGraphStream(amg_ctx *c_, bool on_) : c(c_), user(c_->stream), on(on_)
+        {
+            if (!on) return;
+            if (!c->gstream) {
+                HIPCHK(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+                HIPCHK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+                HIPCHK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+            }
+            HIPCHK(hipEventRecord(c->ev_in, user));
+            HIPCHK(hipStreamWaitEvent(c->gstream, c->ev_in, 0));
+            c->stream = c->gstream;
+        }
+        ~OnGraphStream()
+        {
+            if (!on) return;
+            (void)hipEventRecord(c->ev_out, c->gstream);
+            (void)hipStreamWaitEvent(user, c->ev_out, 0);
+            c->stream = user;
+        }
+    };
     std::vector<std::pair<std::string, double>> tune_log;
     double *sc = nullptr;
     double *hsc = nullptr;     // pinned host copy of the scalar block
@@ -322,6 +379,10 @@ struct amg_ctx {
         for (void *p : allocs) (void)hipFree(p);
         if (hsc) (void)hipHostFree(hsc);
         if (hbsc) (void)hipHostFree(hbsc);
+        drop_graphs();
+        if (gstream) { (void)hipStreamSynchronize(gstream); (void)hipStreamDestroy(gstream); }
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
         if (ev_iter) (void)hipEventDestroy(ev_iter);
         for (auto e : evpool) (void)hipEventDestroy(e);
     }
@@ -628,9 +689,9 @@ struct amg_ctx {
         }
         return nb;
     }
-    void bfinalize(unsigned nblk, int op, int k = 0, double tol = 0.0)
+    void bfinalize(unsigned nblk, int op, double tol = 0.0)
     {
-        hipLaunchKernelGGL(k_bfinalize, dim3(1), dim3(256), 0, stream, bpartial, (int)nblk, bsc, op, k, tol);
+        hipLaunchKernelGGL(k_bfinalize, dim3(1), dim3(256), 0, stream, bpartial, (int)nblk, bsc, op, tol);
         HIPCHK(hipGetLastError());
     }
     unsigned bdot_partials(int64_t m, const double *a, const double *b, const double *c)
@@ -956,13 +1017,21 @@ amg_status amg_match(int64_t n, const int64_t *row_ptr, const int32_t *col, cons
 
 void amg_destroy(amg_ctx *c) { delete c; }
 
-static amg_status solve_impl(amg_ctx *c, const double *F, double *u, double tol, int *iters, double *relres,
+static amg_status solve_impl(amg_ctx *c, const double *F, double *u_user, double tol, int *iters, double *relres,
                              double *relres_true)
 {
     const int64_t n = c->n;
     const bool flex = c->prm.krylov == 1;
     const int itmax = c->prm.itmax;
+    const bool graph = c->use_graph && !c->prof;
+    amg_ctx::OnGraphStream on(c, graph);
     hipStream_t st = c->stream;
+    double *u = u_user;
+    if (graph) {
+        if (!c->uw) c->uw = c->alloc<double>(n);
+        u = c->uw;
+        c->copy<double, double>(n, u_user, u);
+    }
     c->evused = 0;
     c->evbytes.clear();
     hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(256), 0, st, (int64_t)S_NSLOTS, 0.0, c->sc);
@@ -977,7 +1046,7 @@ static amg_status solve_impl(amg_ctx *c, const double *F, double *u, double tol,
     if (!std::isfinite(ff)) { set_err("non-finite right-hand side"); return AMG_ERR_ARG; }
     if (iters) *iters = 0;
     if (ff == 0.0) {
-        hipLaunchKernelGGL((k_fill<double>), dim3(vgrid(n)), dim3(256), 0, st, n, 0.0, u);
+        hipLaunchKernelGGL((k_fill<double>), dim3(vgrid(n)), dim3(256), 0, st, n, 0.0, u_user);
         HIPCHK(hipStreamSynchronize(st));
         if (relres) *relres = 0.0;
         if (relres_true) *relres_true = 0.0;
@@ -987,6 +1056,25 @@ static amg_status solve_impl(amg_ctx *c, const double *F, double *u, double tol,
     double rr = c->hsc[S_RR];
     amg_status status = AMG_NOT_CONVERGED;
     int k = 0;
+    // iteration body, part A: q = K p, (p, q) [, (p, r)] -> alpha;
+    // u += alpha p, r -= alpha q, (r, r); scalars to the host
+    auto partA = [&]() {
+        if (flex) c->sell<double, double, double, EPI_SPMV, 2>(0, c->p, nullptr, nullptr, c->q, nullptr, c->r);
+        else c->sell<double, double, double, EPI_SPMV, 1>(0, c->p, nullptr, nullptr, c->q, nullptr, nullptr);
+        c->finalize(c->sell_blocks(0), flex ? FIN_PQ_FCG : FIN_PQ_CG);
+        unsigned g = vgrid(n);
+        hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(256), 0, c->stream, n, c->sc, u, c->r, c->p, c->q, c->partial);
+        HIPCHK(hipGetLastError());
+        c->finalize(g, FIN_STORE, S_RR);
+        HIPCHK(hipMemcpyAsync(c->hsc, c->sc, S_NSLOTS * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    };
+    // part B: z = B r, beta, p = z + beta p
+    auto partB = [&]() {
+        unsigned nb2 = c->vcycle(c->r, c->z, 1, flex ? c->q : c->r, nullptr);
+        c->finalize(nb2, flex ? FIN_ZQ_FCG : FIN_RZ_CG);
+        hipLaunchKernelGGL(k_cg_pupdate, dim3(vgrid(n)), dim3(256), 0, c->stream, n, c->sc, c->z, c->p);
+        HIPCHK(hipGetLastError());
+    };
     if (std::sqrt(rr) <= tol * nF) {
         status = AMG_OK;
     } else {
@@ -994,24 +1082,18 @@ static amg_status solve_impl(amg_ctx *c, const double *F, double *u, double tol,
         unsigned nb = c->vcycle(c->r, c->z, flex ? 0 : 1, c->r, nullptr);
         if (!flex) c->finalize(nb, FIN_RZ0);
         c->copy<double, double>(n, c->z, c->p);
+        if (graph && !c->gA[flex]) {
+            c->gA[flex] = c->capture(partA);
+            c->gB[flex] = c->capture(partB);
+        }
         for (k = 1; k <= itmax; k++) {
-            // q = K p, (p, q) [, (p, r)] -> alpha
-            if (flex) c->sell<double, double, double, EPI_SPMV, 2>(0, c->p, nullptr, nullptr, c->q, nullptr, c->r);
-            else c->sell<double, double, double, EPI_SPMV, 1>(0, c->p, nullptr, nullptr, c->q, nullptr, nullptr);
-            c->finalize(c->sell_blocks(0), flex ? FIN_PQ_FCG : FIN_PQ_CG);
-            // u += alpha p ; r -= alpha q ; (r, r)
-            unsigned g = vgrid(n);
-            hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(256), 0, st, n, c->sc, u, c->r, c->p, c->q, c->partial);
-            HIPCHK(hipGetLastError());
-            c->finalize(g, FIN_STORE, S_RR);
-            HIPCHK(hipMemcpyAsync(c->hsc, c->sc, S_NSLOTS * sizeof(double), hipMemcpyDeviceToHost, st));
+            if (graph) HIPCHK(hipGraphLaunch(c->gA[flex], st));
+            else partA();
             HIPCHK(hipEventRecord(c->ev_iter, st));
             // speculative: next preconditioned direction while the host tests convergence
             if (k < itmax) {
-                unsigned nb2 = c->vcycle(c->r, c->z, 1, flex ? c->q : c->r, nullptr);
-                c->finalize(nb2, flex ? FIN_ZQ_FCG : FIN_RZ_CG);
-                hipLaunchKernelGGL(k_cg_pupdate, dim3(vgrid(n)), dim3(256), 0, st, n, c->sc, c->z, c->p);
-                HIPCHK(hipGetLastError());
+                if (graph) HIPCHK(hipGraphLaunch(c->gB[flex], st));
+                else partB();
             }
             HIPCHK(hipEventSynchronize(c->ev_iter));
             if (c->hsc[S_FLAG] != 0.0) {
@@ -1025,6 +1107,7 @@ static amg_status solve_impl(amg_ctx *c, const double *F, double *u, double tol,
         }
         if (k > itmax) k = itmax;
     }
+    if (graph) c->copy<double, double>(n, u, u_user);
     HIPCHK(hipStreamSynchronize(st));
     c->prof_collect();
     if (iters) *iters = k;
@@ -1062,21 +1145,23 @@ static amg_status solve_batched_impl(amg_ctx *c, int nrhs, const double *F, doub
     const int64_t n = c->n;
     const bool flex = c->prm.krylov == 1;
     const int itmax = c->prm.itmax;
+    const bool graph = c->use_graph && !c->prof;
+    amg_ctx::OnGraphStream on(c, graph);
     hipStream_t st = c->stream;
     c->blk_alloc();
     c->evused = 0;
     c->evbytes.clear();
     hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(256), 0, st, (int64_t)(B_NSLOTS * NB), 0.0, c->bsc);
     // columns beyond nrhs are done from the start
-    std::vector<double> done0(NB, 0.0);
-    for (int j = nrhs; j < NB; j++) done0[j] = 1.0;
-    HIPCHK(hipMemcpyAsync(c->bsc + B_DONE * NB, done0.data(), NB * sizeof(double), hipMemcpyHostToDevice, st));
+    if (nrhs < NB)
+        hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(256), 0, st, (int64_t)(NB - nrhs), 1.0,
+                           c->bsc + B_DONE * NB + nrhs);
     hipLaunchKernelGGL(k_pack_blk, dim3(nblocks(n)), dim3(256), 0, st, n, nrhs, F, c->bF);
     hipLaunchKernelGGL(k_pack_blk, dim3(nblocks(n)), dim3(256), 0, st, n, nrhs, (const double *)U, c->bU);
     HIPCHK(hipGetLastError());
     // R = F - K U ; (F_j, F_j) ; (R_j, R_j)
     c->sell_blk<double, double, double, EPI_RESID, 0>(0, c->bU, c->bF, c->lev[0].invd64, c->bR, nullptr, nullptr);
-    c->bfinalize(c->bdot_partials(n, c->bF, c->bF, nullptr), BF_FF, 0, tol);
+    c->bfinalize(c->bdot_partials(n, c->bF, c->bF, nullptr), BF_FF, tol);
     c->bfinalize(c->bdot_partials(n, c->bR, c->bR, nullptr), BF_RR0);
     HIPCHK(hipMemcpyAsync(c->hbsc, c->bsc, B_NSLOTS * NB * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1091,23 +1176,35 @@ static amg_status solve_batched_impl(amg_ctx *c, int nrhs, const double *F, doub
         unsigned nb = c->vcycle_blk(c->bR, c->bZ, flex ? 0 : 1, c->bR, nullptr);
         if (!flex) c->bfinalize(nb, BF_RZ0);
         c->copy<double, double>(n * NB, c->bZ, c->bP);
-        for (int k = 1; k <= itmax; k++) {
+        auto partA = [&]() {
             unsigned nbq;
             if (flex) nbq = c->sell_blk<double, double, double, EPI_SPMV, 2>(0, c->bP, nullptr, nullptr, c->bQ, nullptr, c->bR);
             else nbq = c->sell_blk<double, double, double, EPI_SPMV, 1>(0, c->bP, nullptr, nullptr, c->bQ, nullptr, nullptr);
             c->bfinalize(nbq, flex ? BF_PQ_FCG : BF_PQ_CG);
             unsigned g = vgrid(n);
-            hipLaunchKernelGGL(k_bcg_update, dim3(g), dim3(256), 0, st, n, c->bsc, c->bU, c->bR, c->bP, c->bQ,
+            hipLaunchKernelGGL(k_bcg_update, dim3(g), dim3(256), 0, c->stream, n, c->bsc, c->bU, c->bR, c->bP, c->bQ,
                                c->bpartial);
             HIPCHK(hipGetLastError());
-            c->bfinalize(g, BF_RR, k);
-            HIPCHK(hipMemcpyAsync(c->hbsc, c->bsc, B_NSLOTS * NB * sizeof(double), hipMemcpyDeviceToHost, st));
+            c->bfinalize(g, BF_RR);
+            HIPCHK(hipMemcpyAsync(c->hbsc, c->bsc, B_NSLOTS * NB * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        };
+        auto partB = [&]() {
+            unsigned nb2 = c->vcycle_blk(c->bR, c->bZ, 1, flex ? c->bQ : c->bR, nullptr);
+            c->bfinalize(nb2, flex ? BF_ZQ_FCG : BF_RZ_CG);
+            hipLaunchKernelGGL(k_bcg_pupdate, dim3(vgrid(n)), dim3(256), 0, c->stream, n, c->bsc, c->bZ, c->bP);
+            HIPCHK(hipGetLastError());
+        };
+        if (graph && !c->gbA[flex]) {
+            c->gbA[flex] = c->capture(partA);
+            c->gbB[flex] = c->capture(partB);
+        }
+        for (int k = 1; k <= itmax; k++) {
+            if (graph) HIPCHK(hipGraphLaunch(c->gbA[flex], st));
+            else partA();
             HIPCHK(hipEventRecord(c->ev_iter, st));
             if (k < itmax) {
-                unsigned nb2 = c->vcycle_blk(c->bR, c->bZ, 1, flex ? c->bQ : c->bR, nullptr);
-                c->bfinalize(nb2, flex ? BF_ZQ_FCG : BF_RZ_CG);
-                hipLaunchKernelGGL(k_bcg_pupdate, dim3(vgrid(n)), dim3(256), 0, st, n, c->bsc, c->bZ, c->bP);
-                HIPCHK(hipGetLastError());
+                if (graph) HIPCHK(hipGraphLaunch(c->gbB[flex], st));
+                else partB();
             }
             HIPCHK(hipEventSynchronize(c->ev_iter));
             if (all_stopped()) break;
@@ -1185,6 +1282,13 @@ amg_status amg_spmv(amg_ctx *c, int level, const double *x, double *y)
     return AMG_OK;
 }
 
+amg_status amg_set_graph(amg_ctx *c, int enable)
+{
+    if (!c) { set_err("NULL context"); return AMG_ERR_ARG; }
+    c->use_graph = enable ? 1 : 0;
+    return AMG_OK;
+}
+
 amg_status amg_get_batched_variant(const amg_ctx *c, int *lpr, int *threads)
 {
     if (!c) { set_err("NULL context"); return AMG_ERR_ARG; }
@@ -1206,6 +1310,7 @@ amg_status amg_set_batched_variant(amg_ctx *c, int lpr, int threads)
     if (lpr == 1 && threads != 256) { set_err("the one-lane-per-row kernels use 256 threads"); return AMG_ERR_ARG; }
     c->blk_lpr = lpr;
     c->blk_threads = threads;
+    c->drop_graphs();
     return AMG_OK;
 }
 
@@ -1232,6 +1337,7 @@ amg_status amg_set_poly_coeffs(amg_ctx *c, int level, const double coeffs[4])
     Level &L = c->lev[level];
     for (int k = 0; k < 4; k++) L.poly[k] = coeffs[k];
     L.poly_on = c->prm.smoother == 1 ? 1 : 0;
+    c->drop_graphs();
     return AMG_OK;
 }
 
@@ -1357,11 +1463,38 @@ amg_status amg_mlp_adam(float *master, uint16_t *w, const float *grad, float *m,
     return AMG_OK;
 }
 
-amg_status amg_set_learned_poly(amg_ctx *c, const uint16_t *w_host, const double scale[4], int *accepted,
-                                double *coeffs)
+// Coefficients a_0..a_3 of g(t) = sum_k a_k t^{k+1} from its values y_j at the
+// nodes t_j = (1 - cos(j pi/4))/2, j = 1..4: solve sum_k a_k t_j^{k+1} = y_j
+// (4 x 4, Gaussian elimination with partial pivoting).
+static void poly_from_node_values(const double y[4], double a[4])
+{
+    double M[4][5];
+    for (int j = 0; j < 4; j++) {
+        double t = 0.5 * (1.0 - std::cos((j + 1) * M_PI / 4.0)), tp = t;
+        for (int k = 0; k < 4; k++) { M[j][k] = tp; tp *= t; }
+        M[j][4] = y[j];
+    }
+    for (int c = 0; c < 4; c++) {
+        int piv = c;
+        for (int r = c + 1; r < 4; r++)
+            if (std::fabs(M[r][c]) > std::fabs(M[piv][c])) piv = r;
+        for (int k = 0; k < 5; k++) std::swap(M[c][k], M[piv][k]);
+        for (int r = c + 1; r < 4; r++) {
+            double f = M[r][c] / M[c][c];
+            for (int k = c; k < 5; k++) M[r][k] -= f * M[c][k];
+        }
+    }
+    for (int c = 3; c >= 0; c--) {
+        double s = M[c][4];
+        for (int k = c + 1; k < 4; k++) s -= M[c][k] * a[k];
+        a[c] = s / M[c][c];
+    }
+}
+
+amg_status amg_set_learned_poly(amg_ctx *c, const uint16_t *w_host, int *accepted, double *coeffs)
 {
     g_err.clear();
-    if (!c || !w_host || !scale) { set_err("NULL argument"); return AMG_ERR_ARG; }
+    if (!c || !w_host) { set_err("NULL argument"); return AMG_ERR_ARG; }
     if (c->host_only) { set_err("context was built by amg_setup_host"); return AMG_ERR_STATE; }
     if (c->prm.smoother != 1) { set_err("context not built with the polynomial smoother (prm.smoother = 1)"); return AMG_ERR_STATE; }
     const int nl = c->nlev - 1;
@@ -1379,8 +1512,9 @@ amg_status amg_set_learned_poly(amg_ctx *c, const uint16_t *w_host, const double
         HIPCHK(hipStreamSynchronize(c->stream));
         (void)hipFree(dw); (void)hipFree(dX); (void)hipFree(dY);
         for (int l = 0; l < nl; l++) {
-            double cf[4];
-            for (int k = 0; k < 4; k++) cf[k] = scale[k] * (double)Y[(size_t)l * MLP_OUT + k];
+            double y[4], cf[4];
+            for (int k = 0; k < 4; k++) y[k] = (double)Y[(size_t)l * MLP_OUT + k];
+            poly_from_node_values(y, cf);
             if (coeffs) for (int k = 0; k < 4; k++) coeffs[l * 4 + k] = cf[k];
             int ok = poly_ok(cf);
             Level &L = c->lev[l];
@@ -1388,6 +1522,7 @@ amg_status amg_set_learned_poly(amg_ctx *c, const uint16_t *w_host, const double
             else { L.poly[0] = 1.0; L.poly[1] = L.poly[2] = L.poly[3] = 0.0; L.poly_on = 0; }
             if (accepted) accepted[l] = ok;
         }
+        c->drop_graphs();
     } catch (Fail &f) {
         return f.st;
     }

@@ -1,11 +1,15 @@
 """Learned degree-4 polynomial smoother: data generation, GPU training, use.
 
 The network (8 level features -> 64 -> 64 -> 4, tanh) predicts, per AMG level,
-the coefficients a_0..a_3 of the smoother correction sum_k a_k (D^{-1}K)^k D^{-1} r
-(polynomial acceleration of l1-Jacobi, paper Sec. 3.2).  Outputs are scaled by
-SCALE into coefficients; the library's acceptance test (|e(t)| <= 1, e(t) < 1 on
-(0, 1] for e(t) = 1 - sum a_k t^{k+1}) decides per level, and a rejected level
-falls back to l1-Jacobi, so the plain method still judges convergence.
+the degree-4 polynomial of the smoother correction sum_k a_k (D^{-1}K)^k D^{-1} r
+(polynomial acceleration of l1-Jacobi, paper Sec. 3.2), as the values of
+g(t) = 1 - e(t) = sum_k a_k t^{k+1} at the Chebyshev-Lobatto nodes NODES of (0, 1]
+(g(0) = 0); the library interpolates them into a_0..a_3.  In this basis an
+output error moves e(t) by about twice its size, whereas errors in the monomial
+coefficients (tens to hundreds) are amplified into e(1).  The library's
+acceptance test (|e(t)| <= 1, e(t) < 1 on (0, 1]) decides per level, and a
+rejected level falls back to l1-Jacobi, so the plain method still judges
+convergence.
 
 Labels come from the method itself: for each training problem the smoother
 family e_a(t) = T_4((1 + a - 2t)/(1 - a)) / T_4((1 + a)/(1 - a)) (the degree-4
@@ -35,7 +39,7 @@ from .workloads import kappa_params
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "learned_poly4.npz")
-SCALE = np.array([20.0, 100.0, 150.0, 75.0])
+NODES = 0.5 * (1.0 - np.cos(np.arange(1, 5) * np.pi / 4.0))
 GRID = [0.5, 0.3, 0.15, 0.08, 0.04, 0.02, 0.01, 0.005]
 # training problems: (p, n, kappa seed); seeds >= 100 are never used for evaluation
 TRAIN = [(p, n, 100 + 10 * p + k) for p, ns in [(2, (16, 24, 40)), (3, (16, 24, 32)), (4, (12, 16, 24)),
@@ -52,16 +56,20 @@ def cheb_coeffs(a):
     return c[1:5]
 
 
+def node_values(coef):
+    """g(t_j) = sum_k a_k t_j^{k+1} at NODES: the network's target for a_0..a_3."""
+    return np.array([sum(coef[k] * t ** (k + 1) for k in range(4)) for t in NODES])
+
+
 def load_weights(path=WEIGHTS):
     with np.load(path, allow_pickle=False) as z:
-        return z["w_bf16"].astype(np.uint16), z["scale"].astype(np.float64)
+        return z["w_bf16"].astype(np.uint16)
 
 
 def apply_learned(ctx, path=WEIGHTS):
     """Set every level of a context built with smoother=1 from the trained
     network; returns the per-level acceptance flags and coefficients."""
-    w, scale = load_weights(path)
-    return ctx.set_learned_poly(w, scale)
+    return ctx.set_learned_poly(load_weights(path))
 
 
 def problem(p, n, seed):
@@ -113,7 +121,7 @@ def label_problem(p, n, seed, tol=1e-6, itmax=400, log=print):
                 best = (None, it * _work(ctx, allp)); choice = trial
     it_best = _solve(ctx, Ft, tol, [cheb_coeffs(x) for x in choice])
     log(f"p={p} n={n} seed={seed}: N={ctx.n} levels={L + 1} l1 iters={base} best a={choice} iters={it_best}")
-    labels = np.stack([cheb_coeffs(a) / SCALE for a in choice])
+    labels = np.stack([node_values(cheb_coeffs(a)) for a in choice])
     return feats, labels, dict(p=p, n=n, seed=seed, l1_iters=base, iters=it_best, a=choice)
 
 
@@ -201,7 +209,7 @@ def train(data, out, steps=3000, lr=3e-3, seed=0, log=print):
         loss = tr.step(X, T, lr if s < steps * 2 // 3 else lr / 10)
         if s % 500 == 0 or s == steps - 1:
             log(f"step {s}: loss {loss:.5f}")
-    np.savez(out, w_bf16=tr.weights_bf16(), scale=SCALE, steps=steps, lr=lr, seed=seed, loss=loss)
+    np.savez(out, w_bf16=tr.weights_bf16(), nodes=NODES, steps=steps, lr=lr, seed=seed, loss=loss)
     return loss
 
 

@@ -86,10 +86,11 @@ def test_rejected_prediction_falls_back_to_l1(oracle, amg):
     rp, ci, v, F = oracle.poisson_kron(3, 3, 14)
     ctx = amg.Context(rp, ci, v, smoother=1)
     w = np.zeros(4996, np.float32)
-    w[-4:] = [3.0 / 20.0, 0, 0, 0]           # coefficients (3, 0, 0, 0): e(1) = -2, rejected
+    w[-4:] = 3.0                             # g = 3 at every node: e(1) = -2, rejected
     bits = torch.from_numpy(w).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
-    acc, coef = ctx.set_learned_poly(bits, [20.0, 100.0, 150.0, 75.0])
-    assert not any(acc) and np.allclose(coef[:, 0], 3.0, rtol=1e-2)
+    acc, coef = ctx.set_learned_poly(bits)
+    assert not any(acc)
+    assert abs(1.0 - coef[0].sum() - (-2.0)) < 1e-9      # e(1) = 1 - sum a_k
     plain = amg.Context(rp, ci, v)
     r = torch.from_numpy(np.random.default_rng(0).standard_normal(len(F))).cuda()
     assert torch.equal(ctx.vcycle(r), plain.vcycle(r))
