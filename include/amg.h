@@ -188,14 +188,20 @@ void amg_destroy(amg_ctx *c);
 /* Message of the last error on this thread ("" if none). */
 const char *amg_last_error(void);
 
-/* Replay the iteration body of pcg_solve / pcg_solve_batched from HIP graphs
- * (default: off).  The body is captured on the library's own stream at the first
- * solve of each kind and replayed every iteration; the solve is ordered after
- * and before the context's stream by events.  Graphs are re-captured after
- * amg_set_poly_coeffs, amg_set_learned_poly or amg_set_batched_variant, and are
- * not used while profiling is enabled.  Results are bitwise those of the eager
- * launches. */
-amg_status amg_set_graph(amg_ctx *c, int enable);
+/* Solve-phase options (value 0 = off, 1 = on):
+ * AMG_OPT_GRAPH (default off): replay the iteration body of pcg_solve /
+ *   pcg_solve_batched from HIP graphs, captured on the library's own stream at
+ *   the first solve of each kind (the caller's stream is joined by events) and
+ *   replayed every iteration; re-captured after amg_set_poly_coeffs,
+ *   amg_set_learned_poly or amg_set_batched_variant; not used while profiling.
+ *   Results are bitwise those of the eager launches.
+ * AMG_OPT_FUSE_POST (default on): with l1-Jacobi, fuse the prolongation into
+ *   the first post-smoothing sweep, using f - K (u + P e) = r - (K P) e with the
+ *   residual r of the pre-smoothed iterate and a stored K P (about 40% of K's
+ *   entries): one full matrix pass per level becomes a K P pass.  Equal to the
+ *   unfused V-cycle up to rounding. */
+typedef enum { AMG_OPT_GRAPH = 1, AMG_OPT_FUSE_POST = 2 } amg_option;
+amg_status amg_set_option(amg_ctx *c, int option, int value);
 
 /* ------------------------------------------------------------------------
  * Measurement.  While enabled, every launch of the level-0 sparse

@@ -23,7 +23,8 @@ EXPORTS = ["amg_params_default", "amg_setup", "pcg_solve", "pcg_solve_batched", 
            "amg_destroy", "amg_last_error", "amg_set_profiling", "amg_get_profile", "amg_get_format",
            "amg_iga_poisson_size", "amg_iga_poisson", "amg_iga_diffusion", "amg_level_features",
            "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_adam", "amg_set_learned_poly",
-           "amg_get_batched_variant", "amg_set_batched_variant", "amg_set_graph"]
+           "amg_get_batched_variant", "amg_set_batched_variant", "amg_set_option"]
+AMG_OPT_GRAPH, AMG_OPT_FUSE_POST = 1, 2
 MLP_NPARAM, MLP_NFEAT, MLP_NACT, MLP_NDEL = 4996, 8, 128, 132
 
 
@@ -79,7 +80,7 @@ def lib():
         L.amg_mlp_forward.argtypes = [vp, vp, C.c_int, vp, vp, vp]
         L.amg_mlp_backward.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp, vp]
         L.amg_mlp_adam.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_float, vp]
-        L.amg_set_graph.argtypes = [vp, C.c_int]
+        L.amg_set_option.argtypes = [vp, C.c_int, C.c_int]
         L.amg_get_batched_variant.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.amg_set_batched_variant.argtypes = [vp, C.c_int, C.c_int]
         L.amg_set_learned_poly.argtypes = [vp, C.POINTER(C.c_uint16), C.POINTER(C.c_int), f64p]
@@ -218,7 +219,10 @@ class Context:
         return _check(lib().amg_set_poly_coeffs(self.h, level, _p(c, f64p)), allow=(AMG_OK, AMG_NOT_CONVERGED))
 
     def set_graph(self, on):
-        _check(lib().amg_set_graph(self.h, int(on)))
+        _check(lib().amg_set_option(self.h, AMG_OPT_GRAPH, int(on)))
+
+    def set_fused_post(self, on):
+        _check(lib().amg_set_option(self.h, AMG_OPT_FUSE_POST, int(on)))
 
     def batched_variant(self):
         lpr = C.c_int(); thr = C.c_int()

@@ -62,6 +62,12 @@ int build_hierarchy(const CsrView &K0, const double *w, const SetupParams &prm,
 // fraction of positive off-diagonal entries.
 void level_features(const CsrView &K, const std::vector<double> &invd, float out[6]);
 
+// K P for a one-entry-per-row prolongator (agg, pc): n x nc CSR with
+// (KP)_{iJ} = sum over the stored j of row i with agg(j) = J of k_ij pc_j,
+// accumulated in ascending j, columns ascending.  Used by the fused
+// prolongation + post-smoothing pass: f - K (u + P e) = r - (K P) e.
+Csr kp_product(const CsrView &K, int64_t nc, const int32_t *agg, const double *pc);
+
 // Pieces exposed for the unit tests of the library's own setup.
 double cij(double kij, double kii, double kjj, double wi, double wj);
 void suitor_match(const CsrView &K, const double *w, int positive_only, int32_t *mate);

@@ -278,6 +278,47 @@ static Csr galerkin(const CsrView &K, int64_t nc, const std::vector<int32_t> &ag
     return C;
 }
 
+Csr kp_product(const CsrView &K, int64_t nc, const int32_t *agg, const double *pc)
+{
+    Csr C;
+    C.n = K.n;
+    C.rp.assign(K.n + 1, 0);
+    parallel_for(K.n, [&](int64_t b, int64_t e) {
+        std::vector<int32_t> cols;
+        for (int64_t i = b; i < e; i++) {
+            cols.clear();
+            for (int64_t k = K.rp[i]; k < K.rp[i + 1]; k++) cols.push_back(agg[K.ci[k]]);
+            std::sort(cols.begin(), cols.end());
+            C.rp[i + 1] = std::unique(cols.begin(), cols.end()) - cols.begin();
+        }
+    });
+    for (int64_t i = 0; i < K.n; i++) C.rp[i + 1] += C.rp[i];
+    C.ci.resize(C.rp[K.n]);
+    C.v.resize(C.rp[K.n]);
+    parallel_for(K.n, [&](int64_t b, int64_t e) {
+        std::vector<int64_t> slot(nc, -1);
+        std::vector<int32_t> cols;
+        for (int64_t i = b; i < e; i++) {
+            cols.clear();
+            for (int64_t k = K.rp[i]; k < K.rp[i + 1]; k++) cols.push_back(agg[K.ci[k]]);
+            std::sort(cols.begin(), cols.end());
+            cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+            int64_t pos = C.rp[i];
+            for (size_t t = 0; t < cols.size(); t++) {
+                slot[cols[t]] = pos + (int64_t)t;
+                C.ci[pos + t] = cols[t];
+                C.v[pos + t] = 0.0;
+            }
+            for (int64_t k = K.rp[i]; k < K.rp[i + 1]; k++) {
+                int64_t j = K.ci[k];
+                C.v[slot[agg[j]]] += K.v[k] * pc[j];
+            }
+        }
+    });
+    (void)nc;
+    return C;
+}
+
 static void l1_invdiag(const CsrView &K, std::vector<double> &invd)
 {
     invd.resize(K.n);

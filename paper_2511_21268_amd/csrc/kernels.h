@@ -174,6 +174,57 @@ __global__ __launch_bounds__(256) void k_sell(int64_t nrows, int64_t nslices, co
     }
 }
 
+// Prolongation fused with the first l1-Jacobi post-smoothing sweep:
+//   u' = u + P e,   y = u' + D^{-1} (f - K u') = u' + D^{-1} (r - (K P) e)
+// with r = f - K u kept from the residual pass and acc = ((K P) e)_row taken
+// over the SELL image of K P (its columns are coarse indices; the gathered
+// vector is e).  Dots as EPI_SMOOTH: (y, g0), (y, g1).
+template <typename VT, typename OT, typename IT, int NDOT>
+__global__ __launch_bounds__(256) void k_sell_post(int64_t nrows, int64_t nslices, const int64_t *__restrict__ soff,
+                                                   const VT *__restrict__ val, const IT *__restrict__ idx,
+                                                   const int32_t *__restrict__ col0, const VT *__restrict__ e,
+                                                   const VT *__restrict__ u, const VT *__restrict__ r,
+                                                   const VT *__restrict__ invd, const int32_t *__restrict__ agg,
+                                                   const VT *__restrict__ pc, OT *__restrict__ y,
+                                                   const double *__restrict__ g0, const double *__restrict__ g1,
+                                                   double *__restrict__ partial)
+{
+    __shared__ double lds[8];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t s = (int64_t)blockIdx.x * SELL_WAVES + wid;
+    double d0 = 0.0, d1 = 0.0;
+    if (s < nslices) {
+        const int64_t row = s * SLICE + lane;
+        const int64_t base = soff[s];
+        const int width = (int)((soff[s + 1] - base) >> 6);
+        int col = (sizeof(IT) == 2) ? col0[row] : 0;
+        VT acc = 0;
+        for (int kk = 0; kk < width; kk += 8) {
+            VT v[8];
+            int c[8];
+            load_idx8(idx, base, kk, lane, col, c);
+            load8(val, base, kk, lane, v);
+#pragma unroll
+            for (int t = 0; t < 8; t++) acc = fma(v[t], e[c[t]], acc);
+        }
+        if (row < nrows) {
+            VT up = u[row] + pc[row] * e[agg[row]];
+            VT out = up + invd[row] * (r[row] - acc);
+            y[row] = (OT)out;
+            if (NDOT >= 1) d0 = (double)out * g0[row];
+            if (NDOT >= 2) d1 = (double)out * g1[row];
+        }
+    }
+    if (NDOT >= 1) {
+        double t0 = block_sum(d0, lds);
+        double t1 = NDOT >= 2 ? block_sum(d1, lds + 4) : 0.0;
+        if (threadIdx.x == 0) {
+            partial[2 * blockIdx.x] = t0;
+            partial[2 * blockIdx.x + 1] = t1;
+        }
+    }
+}
+
 // ---- vector kernels ----------------------------------------------------------
 
 // u = invd * f  (one smoothing sweep from the zero guess: K 0 = 0)

@@ -315,6 +315,147 @@ __global__ __launch_bounds__(512) void k_sellb(int64_t nrows, int64_t nslices, c
     }
 }
 
+// Fused prolongation + first post-smoothing sweep for 16 columns (see
+// k_sell_post): acc = (K P) E over the SELL-64 image of K P, one lane per row;
+// Y = U + P E + D^{-1} (R - acc).  Per column the order of k_sell_post.
+template <typename VT, typename OT, typename IT, int NDOT>
+__global__ __launch_bounds__(256) void k_sell_blk_post(int64_t nrows, int64_t nslices,
+                                                       const int64_t *__restrict__ soff, const VT *__restrict__ val,
+                                                       const IT *__restrict__ idx, const int32_t *__restrict__ col0,
+                                                       const VT *__restrict__ E, const VT *__restrict__ U,
+                                                       const VT *__restrict__ R, const VT *__restrict__ invd,
+                                                       const int32_t *__restrict__ agg, const VT *__restrict__ pc,
+                                                       OT *__restrict__ Y, const double *__restrict__ G0,
+                                                       const double *__restrict__ G1, double *__restrict__ partial)
+{
+    __shared__ double lds[8 * NB];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t s = (int64_t)blockIdx.x * SELL_WAVES + wid;
+    double d0[NB], d1[NB];
+#pragma unroll
+    for (int j = 0; j < NB; j++) { d0[j] = 0.0; d1[j] = 0.0; }
+    if (s < nslices) {
+        const int64_t row = s * SLICE + lane;
+        const int64_t base = soff[s];
+        const int width = (int)((soff[s + 1] - base) >> 6);
+        int col = (sizeof(IT) == 2) ? col0[row] : 0;
+        VT acc[NB];
+#pragma unroll
+        for (int j = 0; j < NB; j++) acc[j] = 0;
+        for (int kk = 0; kk < width; kk += 8) {
+            VT v[8];
+            int c[8];
+            load_idx8(idx, base, kk, lane, col, c);
+            load8(val, base, kk, lane, v);
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                VT xv[NB];
+                BlkVec<VT>::load(E + (int64_t)c[t] * NB, xv);
+#pragma unroll
+                for (int j = 0; j < NB; j++) acc[j] = fma(v[t], xv[j], acc[j]);
+            }
+        }
+        if (row < nrows) {
+            const int64_t o = row * NB, a = (int64_t)agg[row] * NB;
+            const VT di = invd[row], pi = pc[row];
+#pragma unroll
+            for (int j = 0; j < NB; j++) {
+                VT up = U[o + j] + pi * E[a + j];
+                VT out = up + di * (R[o + j] - acc[j]);
+                Y[o + j] = (OT)out;
+                if (NDOT >= 1) d0[j] = (double)out * G0[o + j];
+                if (NDOT >= 2) d1[j] = (double)out * G1[o + j];
+            }
+        }
+    }
+    if (NDOT >= 1) {
+        block_sum_cols<NB>(d0, lds);
+        if (NDOT >= 2) block_sum_cols<NB>(d1, lds + 4 * NB);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int j = 0; j < NB; j++) {
+                partial[(2 * blockIdx.x) * NB + j] = d0[j];
+                partial[(2 * blockIdx.x + 1) * NB + j] = NDOT >= 2 ? d1[j] : 0.0;
+            }
+    }
+}
+
+// The same with LPR lanes per row on a SELL-(64/LPR) image of K P (layout and
+// reductions of k_sellb).
+template <typename VT, typename OT, typename IT, int NDOT, int LPR>
+__global__ __launch_bounds__(512) void k_sellb_post(int64_t nrows, int64_t nslices, const int64_t *__restrict__ soff,
+                                                    const VT *__restrict__ val, const IT *__restrict__ idx,
+                                                    const int32_t *__restrict__ col0, const VT *__restrict__ E,
+                                                    const VT *__restrict__ U, const VT *__restrict__ R,
+                                                    const VT *__restrict__ invd, const int32_t *__restrict__ agg,
+                                                    const VT *__restrict__ pc, OT *__restrict__ Y,
+                                                    const double *__restrict__ G0, const double *__restrict__ G1,
+                                                    double *__restrict__ partial)
+{
+    constexpr int C = 64 / LPR, RPL = NB / LPR;
+    __shared__ double lds[2 * 8 * NB];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int r = lane / LPR, q = lane % LPR;
+    double d0[RPL], d1[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; j++) { d0[j] = 0.0; d1[j] = 0.0; }
+    for (int64_t s = (int64_t)blockIdx.x * nw + wid; s < nslices; s += (int64_t)gridDim.x * nw) {
+        const int64_t row = s * C + r;
+        const int64_t base = soff[s];
+        const int width = (int)((soff[s + 1] - base) / C);
+        int col = (sizeof(IT) == 2) ? col0[row] : 0;
+        VT acc[RPL];
+#pragma unroll
+        for (int j = 0; j < RPL; j++) acc[j] = 0;
+        for (int kk = 0; kk < width; kk += 8) {
+            VT v[8];
+            int c[8];
+            loadidx8c<C>(idx, base, kk, r, col, c);
+            load8c<C>(val, base, kk, r, v);
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                VT xv[RPL];
+                RowLoad<VT>::template load<RPL>(E + (int64_t)c[t] * NB + q * RPL, xv);
+#pragma unroll
+                for (int j = 0; j < RPL; j++) acc[j] = fma(v[t], xv[j], acc[j]);
+            }
+        }
+        if (row < nrows) {
+            const int64_t o = row * NB + q * RPL, a = (int64_t)agg[row] * NB + q * RPL;
+            const VT di = invd[row], pi = pc[row];
+#pragma unroll
+            for (int j = 0; j < RPL; j++) {
+                VT up = U[o + j] + pi * E[a + j];
+                VT out = up + di * (R[o + j] - acc[j]);
+                Y[o + j] = (OT)out;
+                if (NDOT >= 1) d0[j] += (double)out * G0[o + j];
+                if (NDOT >= 2) d1[j] += (double)out * G1[o + j];
+            }
+        }
+    }
+    if (NDOT >= 1) {
+#pragma unroll
+        for (int j = 0; j < RPL; j++)
+            for (int o = LPR; o < 64; o <<= 1) {
+                d0[j] += __shfl_xor(d0[j], o, 64);
+                d1[j] += __shfl_xor(d1[j], o, 64);
+            }
+        if (r == 0)
+#pragma unroll
+            for (int j = 0; j < RPL; j++) {
+                lds[(wid * NB + q * RPL + j) * 2] = d0[j];
+                lds[(wid * NB + q * RPL + j) * 2 + 1] = d1[j];
+            }
+        __syncthreads();
+        if (threadIdx.x < 2 * NB) {
+            const int j = threadIdx.x >> 1, d = threadIdx.x & 1;
+            double t = 0.0;
+            for (int w = 0; w < nw; w++) t += lds[(w * NB + j) * 2 + d];
+            partial[(2 * blockIdx.x + d) * NB + j] = (d == 1 && NDOT < 2) ? 0.0 : t;
+        }
+    }
+}
+
 // ---- elementwise block kernels (one thread per row, 16 columns) ---------------
 
 template <typename VT, typename FT>

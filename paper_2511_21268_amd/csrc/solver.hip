@@ -149,6 +149,8 @@ struct Level {
     int64_t n = 0, nnz = 0;
     DevMat A;     // SELL-64, one lane per row
     DevMat Ab;    // SELL-(64/LPR) image of the block kernels (batched solves), if built
+    DevMat KP;    // SELL-64 image of K P (fused prolongation + post-smoothing), ell < L
+    DevMat KPb;   // SELL-(64/LPR) image of K P for the block kernels, if built
     double *invd64 = nullptr;
     float *invd32 = nullptr;
     // transfer to the next level
@@ -191,6 +193,7 @@ struct amg_ctx {
     int blk_lpr = 1, blk_threads = 256;   // block-kernel variant (autotuned when prm.nrhs > 1)
     // graph replay of the iteration body (single: [0]=CG [1]=FCG; batched likewise)
     int use_graph = 0;
+    int fuse_post = 1;   // fused prolongation + post-smoothing through K P (when built)
     hipStream_t gstream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     double *uw = nullptr;
@@ -370,6 +373,12 @@ struct amg_ctx {
             lev[0].Ab = keep;
             for (int l = 1; l < nlev - 1; l++)
                 lev[l].Ab = upload_sell(amgiga::view(host.lev[l].K), 64 / best.lpr, !f32, f32);
+            for (int l = 0; l < nlev - 1; l++) {
+                CsrView K = l == 0 ? K0 : amgiga::view(host.lev[l].K);
+                amgiga::Csr kp = amgiga::kp_product(K, host.lev[l + 1].n, host.lev[l].agg.data(),
+                                                    host.lev[l].pc.data());
+                lev[l].KPb = upload_sell(amgiga::view(kp), 64 / best.lpr, !f32, f32);
+            }
         }
         HIPCHK(hipStreamSynchronize(stream));
     }
@@ -458,6 +467,39 @@ struct amg_ctx {
         HIPCHK(hipGetLastError());
     }
     unsigned sell_blocks(int l) const { return (unsigned)((lev[l].A.nslices + SELL_WAVES - 1) / SELL_WAVES); }
+    // Fused prolongation + first post-smoothing sweep on level l (needs K P).
+    template <typename VT, typename OT>
+    unsigned post_fused(int l, const VT *e, const VT *u, OT *y, int ndot, const double *g0, const double *g1)
+    {
+        Level &L = lev[l];
+        const DevMat &A = L.KP;
+        unsigned nb = (unsigned)((A.nslices + SELL_WAVES - 1) / SELL_WAVES);
+        if (l == 0) prof_begin();
+#define POST_LAUNCH(IT, IDX, ND)                                                                              \
+    hipLaunchKernelGGL((k_sell_post<VT, OT, IT, ND>), dim3(nb), dim3(256), 0, stream, A.n, A.nslices, A.soff, \
+                       A.val<VT>(), IDX, A.col0, e, u, (const VT *)L.r, L.invd<VT>(), L.agg, L.pc<VT>(), y, g0, g1, \
+                       partial)
+        if (A.idx16) {
+            if (ndot == 2) POST_LAUNCH(uint16_t, A.d16, 2);
+            else if (ndot == 1) POST_LAUNCH(uint16_t, A.d16, 1);
+            else POST_LAUNCH(uint16_t, A.d16, 0);
+        } else {
+            if (ndot == 2) POST_LAUNCH(int32_t, A.c32, 2);
+            else if (ndot == 1) POST_LAUNCH(int32_t, A.c32, 1);
+            else POST_LAUNCH(int32_t, A.c32, 0);
+        }
+#undef POST_LAUNCH
+        HIPCHK(hipGetLastError());
+        if (l == 0) {
+            double ib = A.idx16 ? 2.0 : 4.0;
+            double bytes = (double)A.nnz * (sizeof(VT) + ib) + (A.idx16 ? 4.0 * A.n : 0.0) +
+                           (double)sizeof(VT) * lev[1].n +                         // e gathered once
+                           (double)sizeof(VT) * A.n * 4 + 4.0 * A.n +               // u, r, invd, pc, agg
+                           (double)sizeof(OT) * A.n + 8.0 * A.n * ndot;              // y, dot partners
+            prof_end(bytes);
+        }
+        return nb;
+    }
     void finalize(unsigned nblk, int op, int slot = 0)
     {
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, stream, partial, (int)nblk, sc, op, slot);
@@ -575,11 +617,22 @@ struct amg_ctx {
         } else {
             e = vlevel<VT, VT>(l + 1, (const VT *)C.f, nullptr, 0, nullptr, nullptr, true);
         }
-        // 4. prolongation and correction
-        hipLaunchKernelGGL((k_prolong<VT>), dim3(nblocks(L.n)), dim3(256), 0, stream, L.n, L.agg, L.pc<VT>(), e, u);
-        HIPCHK(hipGetLastError());
-        // 5. post-smoothing
-        for (int s = 1; s <= prm.nu_post; s++) {
+        // 4. + 5.: with l1-Jacobi the prolongation is fused into the first
+        // post-smoothing sweep through K P (f - K (u + P e) = r - (K P) e)
+        int s0 = 1;
+        if (!L.poly_on && prm.nu_post >= 1 && L.KP.soff && fuse_post) {
+            if (zout && prm.nu_post == 1) {
+                vc_nb = post_fused<VT, double>(l, e, u, zout, ndot, g0, g1);
+                return nullptr;
+            }
+            post_fused<VT, VT>(l, e, u, u2, 0, nullptr, nullptr);
+            std::swap(u, u2);
+            s0 = 2;
+        } else {
+            hipLaunchKernelGGL((k_prolong<VT>), dim3(nblocks(L.n)), dim3(256), 0, stream, L.n, L.agg, L.pc<VT>(), e, u);
+            HIPCHK(hipGetLastError());
+        }
+        for (int s = s0; s <= prm.nu_post; s++) {
             if (zout && s == prm.nu_post) {
                 sweep<VT, FT, double>(l, f, u, zout, ndot, g0, g1);
                 return nullptr;
@@ -701,6 +754,47 @@ struct amg_ctx {
         HIPCHK(hipGetLastError());
         return g;
     }
+    // Block fused prolongation + first post-smoothing sweep; returns the dot-partial blocks.
+    template <typename VT, typename OT>
+    unsigned bpost_fused(int l, const VT *E, const VT *U, OT *Y, int ndot, const double *g0, const double *g1)
+    {
+        Level &L = lev[l];
+        const bool multi = blk_lpr > 1 && L.KPb.soff;
+        const DevMat &A = multi ? L.KPb : L.KP;
+        unsigned nb = multi ? blk_grid(A) : (unsigned)((A.nslices + SELL_WAVES - 1) / SELL_WAVES);
+        unsigned thr = multi ? (unsigned)blk_threads : 256u;
+        if (l == 0) prof_begin();
+#define BPOST(KERN, IT, IDX)                                                                                    \
+    hipLaunchKernelGGL(KERN, dim3(nb), dim3(thr), 0, stream, A.n, A.nslices, A.soff, A.val<VT>(), IDX, A.col0, E, U, \
+                       (const VT *)L.br, L.invd<VT>(), L.agg, L.pc<VT>(), Y, g0, g1, bpartial)
+#define BPOST_ND(IT, IDX, ND)                                                                                   \
+    do {                                                                                                        \
+        if (!multi) BPOST((k_sell_blk_post<VT, OT, IT, ND>), IT, IDX);                                          \
+        else if (blk_lpr == 4) BPOST((k_sellb_post<VT, OT, IT, ND, 4>), IT, IDX);                               \
+        else BPOST((k_sellb_post<VT, OT, IT, ND, 16>), IT, IDX);                                                \
+    } while (0)
+        if (A.idx16) {
+            if (ndot == 2) BPOST_ND(uint16_t, A.d16, 2);
+            else if (ndot == 1) BPOST_ND(uint16_t, A.d16, 1);
+            else BPOST_ND(uint16_t, A.d16, 0);
+        } else {
+            if (ndot == 2) BPOST_ND(int32_t, A.c32, 2);
+            else if (ndot == 1) BPOST_ND(int32_t, A.c32, 1);
+            else BPOST_ND(int32_t, A.c32, 0);
+        }
+#undef BPOST_ND
+#undef BPOST
+        HIPCHK(hipGetLastError());
+        if (l == 0) {
+            double ib = A.idx16 ? 2.0 : 4.0;
+            double bytes = (double)A.nnz * (sizeof(VT) + ib) + (A.idx16 ? 4.0 * A.n : 0.0) +
+                           (double)NB * sizeof(VT) * lev[1].n + (double)NB * sizeof(VT) * A.n * 2 +
+                           (double)sizeof(VT) * A.n * 2 + 4.0 * A.n + (double)NB * sizeof(OT) * A.n +
+                           8.0 * NB * A.n * ndot;
+            prof_end(bytes);
+        }
+        return nb;
+    }
     template <typename VT, typename FT> VT *bpoly_apply(int l, const FT *rr, VT *&c, VT *&c2)
     {
         Level &L = lev[l];
@@ -777,10 +871,21 @@ struct amg_ctx {
         } else {
             e = vlevel_blk<VT, VT>(l + 1, (const VT *)C.bf, nullptr, 0, nullptr, nullptr, true);
         }
-        hipLaunchKernelGGL((k_prolong_blk<VT>), dim3(nblocks(L.n)), dim3(256), 0, stream, L.n, L.agg, L.pc<VT>(), e,
-                           u);
-        HIPCHK(hipGetLastError());
-        for (int s = 1; s <= prm.nu_post; s++) {
+        int s0 = 1;
+        if (!L.poly_on && prm.nu_post >= 1 && L.KP.soff && fuse_post) {
+            if (zout && prm.nu_post == 1) {
+                vc_nb = bpost_fused<VT, double>(l, e, u, zout, ndot, g0, g1);
+                return nullptr;
+            }
+            bpost_fused<VT, VT>(l, e, u, u2, 0, nullptr, nullptr);
+            std::swap(u, u2);
+            s0 = 2;
+        } else {
+            hipLaunchKernelGGL((k_prolong_blk<VT>), dim3(nblocks(L.n)), dim3(256), 0, stream, L.n, L.agg, L.pc<VT>(),
+                               e, u);
+            HIPCHK(hipGetLastError());
+        }
+        for (int s = s0; s <= prm.nu_post; s++) {
             if (zout && s == prm.nu_post) {
                 bsweep<VT, FT, double>(l, f, u, zout, ndot, g0, g1);
                 return nullptr;
@@ -847,6 +952,11 @@ static amg_status build_device(amg_ctx *c, const CsrView &K0)
             L.invd32 = c->upload(t);
         }
         if (!coarsest) {
+            {
+                CsrView K = l == 0 ? K0 : amgiga::view(hl.K);
+                amgiga::Csr kp = amgiga::kp_product(K, H.lev[l + 1].n, hl.agg.data(), hl.pc.data());
+                L.KP = c->upload_sell(amgiga::view(kp), SLICE, !fp32, fp32);
+            }
             L.agg = c->upload(hl.agg);
             L.pc64 = c->upload(hl.pc);
             if (fp32) {
@@ -1282,10 +1392,14 @@ amg_status amg_spmv(amg_ctx *c, int level, const double *x, double *y)
     return AMG_OK;
 }
 
-amg_status amg_set_graph(amg_ctx *c, int enable)
+amg_status amg_set_option(amg_ctx *c, int option, int value)
 {
     if (!c) { set_err("NULL context"); return AMG_ERR_ARG; }
-    c->use_graph = enable ? 1 : 0;
+    switch (option) {
+    case AMG_OPT_GRAPH: c->use_graph = value ? 1 : 0; break;
+    case AMG_OPT_FUSE_POST: c->fuse_post = value ? 1 : 0; c->drop_graphs(); break;
+    default: set_err("unknown option"); return AMG_ERR_ARG;
+    }
     return AMG_OK;
 }
 

@@ -116,3 +116,25 @@ def test_autotuned_block_kernels(oracle, amg, fp32):
             tol = 1e-12 if not fp32 else 1e-6
             assert np.linalg.norm(U[:, j] - us) <= tol * np.linalg.norm(us), (lp, th, j)
     ctx.set_batched_variant(lpr, thr)
+
+
+@pytest.mark.parametrize("kw", [{}, dict(vcycle_fp32=1, krylov=1)])
+def test_batched_fused_post_equals_unfused(oracle, amg, kw):
+    """Block prolongation fused into the first post-smoothing sweep through K P
+    gives the unfused block V-cycle up to rounding, and the same iterations."""
+    print(f"case batched fused post {kw}", flush=True)
+    from paper_2511_21268_amd.workloads import rhs_block
+    rp, ci, v, _ = oracle.poisson_kron(3, 3, 18)
+    N = len(rp) - 1
+    Ft = torch.from_numpy(rhs_block(N, range(16))).cuda()
+    ctx = amg.Context(rp, ci, v, **kw)
+    ctx.set_fused_post(True)
+    of = ctx.solve_batched(Ft, tol=1e-8)
+    ctx.set_fused_post(False)
+    ou = ctx.solve_batched(Ft, tol=1e-8)
+    assert of["status"] == 0 and ou["status"] == 0
+    tol = 1e-12 if not kw else 1e-6
+    for j in range(16):
+        assert abs(of["iters"][j] - ou["iters"][j]) <= (0 if not kw else 1), j
+        a, b = of["U"][:, j], ou["U"][:, j]
+        assert torch.linalg.norm(a - b) <= tol * torch.linalg.norm(b), j

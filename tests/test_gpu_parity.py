@@ -114,3 +114,26 @@ def test_determinism(oracle, amg):
     a = ctx.solve(F)
     b = ctx.solve(F)
     assert a["iters"] == b["iters"] and torch.equal(a["u"], b["u"])
+
+
+@pytest.mark.parametrize("kw", [{}, {"vcycle_fp32": 1, "krylov": 1}])
+def test_fused_post_smoothing_equals_unfused(oracle, amg, kw):
+    """Prolongation fused into the first post-smoothing sweep through K P gives
+    the unfused V-cycle up to rounding, and the same iterations."""
+    print(f"case fused post {kw}", flush=True)
+    from paper_2511_21268_amd.workloads import rhs_normal
+    rp, ci, v, _ = oracle.poisson_kron(3, 3, 20)
+    N = len(rp) - 1
+    ctx = amg.Context(rp, ci, v, **kw)
+    r = torch.from_numpy(np.random.default_rng(8).standard_normal(N)).cuda()
+    F = torch.from_numpy(rhs_normal(N, 8)).cuda()
+    ctx.set_fused_post(True)
+    zf = ctx.vcycle(r)
+    of = ctx.solve(F)
+    ctx.set_fused_post(False)
+    zu = ctx.vcycle(r)
+    ou = ctx.solve(F)
+    tol = 1e-13 if not kw else 1e-5
+    assert torch.linalg.norm(zf - zu) <= tol * torch.linalg.norm(zu)
+    assert abs(of["iters"] - ou["iters"]) <= (0 if not kw else 1)
+    assert of["relres_true"] <= 1e-8
