@@ -65,6 +65,11 @@ typedef struct {
                                also build the layout of the block kernels used by
                                pcg_solve_batched and autotune it (lanes per row
                                and block size, timed on the level-0 matrix)     */
+    int slice_offsets;      /* 1 (default): a 64-row slice whose rows share one
+                               list of column offsets (column - row) no longer
+                               than its longest row stores that list once
+                               instead of per-entry indices (stencil matrices);
+                               0: per-entry indices in every slice              */
 } amg_params;
 
 /* Fill p with the defaults above.  p must not be NULL. */
@@ -213,10 +218,12 @@ amg_status amg_set_option(amg_ctx *c, int option, int value);
  */
 amg_status amg_set_profiling(amg_ctx *c, int enable);
 amg_status amg_get_profile(amg_ctx *c, int64_t *launches, double *ms, double *bytes);
-/* Description of the level-0 layout: slice height, stored entries with
- * padding, index bytes per entry (2 or 4). */
+/* Description of a level's single-vector layout: slice height, stored
+ * entries with padding, index bytes per entry in slices with per-entry
+ * indices (2 or 4), and the number of slices (of ceil(n / slice)) that store
+ * shared column offsets instead.  Any output may be NULL. */
 amg_status amg_get_format(const amg_ctx *c, int level, int *slice, int64_t *stored,
-                          int *index_bytes);
+                          int *index_bytes, int64_t *shared_slices);
 
 /* ------------------------------------------------------------------------
  * Workload generator (Sec. 2): the Dirichlet-reduced stiffness matrix of the

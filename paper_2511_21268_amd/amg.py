@@ -37,7 +37,8 @@ class AmgError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("sweeps_per_level", C.c_int), ("max_coarse", C.c_int), ("max_levels", C.c_int),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("vcycle_fp32", C.c_int), ("smoother", C.c_int),
-                ("krylov", C.c_int), ("match_positive_only", C.c_int), ("itmax", C.c_int), ("nrhs", C.c_int)]
+                ("krylov", C.c_int), ("match_positive_only", C.c_int), ("itmax", C.c_int), ("nrhs", C.c_int),
+                ("slice_offsets", C.c_int)]
 
 
 i64p = C.POINTER(C.c_int64)
@@ -72,7 +73,7 @@ def lib():
         L.amg_last_error.restype = C.c_char_p
         L.amg_set_profiling.argtypes = [vp, C.c_int]
         L.amg_get_profile.argtypes = [vp, i64p, f64p, f64p]
-        L.amg_get_format.argtypes = [vp, C.c_int, C.POINTER(C.c_int), i64p, C.POINTER(C.c_int)]
+        L.amg_get_format.argtypes = [vp, C.c_int, C.POINTER(C.c_int), i64p, C.POINTER(C.c_int), i64p]
         L.amg_iga_poisson_size.argtypes = [C.c_int, C.c_int, C.c_int, i64p, i64p]
         L.amg_iga_poisson.argtypes = [C.c_int, C.c_int, C.c_int, i64p, i32p, f64p, f64p]
         L.amg_iga_diffusion.argtypes = [C.c_int, C.c_int, C.c_int, f64p, i32p, i64p, i32p, f64p, f64p]
@@ -210,9 +211,9 @@ class Context:
         return rp, ci, v
 
     def format(self, level=0):
-        sl = C.c_int(); stored = C.c_int64(); ib = C.c_int()
-        _check(lib().amg_get_format(self.h, level, C.byref(sl), C.byref(stored), C.byref(ib)))
-        return dict(slice=sl.value, stored=stored.value, index_bytes=ib.value)
+        sl = C.c_int(); stored = C.c_int64(); ib = C.c_int(); sh = C.c_int64()
+        _check(lib().amg_get_format(self.h, level, C.byref(sl), C.byref(stored), C.byref(ib), C.byref(sh)))
+        return dict(slice=sl.value, stored=stored.value, index_bytes=ib.value, shared_slices=sh.value)
 
     def set_poly(self, level, coeffs):
         c = np.ascontiguousarray(coeffs, np.float64)

@@ -1,17 +1,27 @@
 // Device kernels of the solve phase (gfx950, wave64).
 //
-// Sparse matrices are held in a sliced-ELL layout (SELL-C with C = 64 rows per
-// slice, one slice per wavefront, lane = row): each slice stores width w_s
-// entries per row (w_s = the slice's longest row, rounded up to 8), column-major
-// across the 64 rows so that every load of the wave is one contiguous run.
-// Entries are interleaved in groups of G per lane so that each lane issues
-// 16-byte loads: element (k, lane) of a slice starting at element `base` lives at
-//     base + (k / G) * 64 * G + lane * G + (k % G),
+// Sparse matrices are held in a sliced-ELL layout (SELL-C: C consecutive rows
+// per slice; C = 64 gives one slice per wavefront, lane = row): each slice
+// stores width w_s entries per row, column-major across its C rows so that every
+// load of the wave is one contiguous run.  Entries are interleaved in groups of
+// G per lane so that each lane issues 16-byte loads: element (k, r) of a slice
+// whose stream starts at element `base` lives at
+//     base + (k / G) * C * G + r * G + (k % G),
 // with G = 2 for FP64 values, 4 for FP32 values and int32 columns, and 8 for
-// 16-bit column deltas.  A lane walks its row in ascending column order; with
-// 16-bit deltas the column is a running sum starting at col0[row] (the row's
-// first column), so the index stream costs 2 bytes per entry.  Padding entries
-// hold value 0 and delta 0.
+// 16-bit column deltas.  A lane walks its row in ascending column order.
+//
+// A slice stores its columns in one of two ways.
+//  * Shared offsets: when the column offsets (column - row) of all rows of the
+//    slice fit in one ascending list no longer than the slice's widest row
+//    (stencil-like matrices: the rows of a slice differ only at boundaries),
+//    the list is stored once per slice and lane r of row `row` reads column
+//    row + offset[k]; entries a row does not have hold the value 0 (their
+//    column is clamped into [0, ncols)).  The index stream costs ~0 bytes per
+//    entry.
+//  * Per-row indices: 16-bit column deltas (the column is a running sum from
+//    col0[row], the row's first column) when every gap fits, else int32
+//    columns; padding holds value 0 and delta 0 (or the last column).
+// w_s is the longer of the row lengths or the offset list, rounded up to 8.
 //
 // Every reduction is deterministic: fixed grid, butterfly within the wave, a
 // fixed-order sum across the block's waves, one partial per block, and a
@@ -57,35 +67,31 @@ __device__ inline double block_sum(double v, double *lds)
     return s;
 }
 
-// ---- loads of 8 consecutive entries (k .. k+7) of one lane -------------------
+// ---- loads of 8 consecutive entries (k .. k+7) of lane r of a C-row slice ----
 
-__device__ inline void load8(const double *__restrict__ val, int64_t base, int kk, int lane, double v[8])
+template <int C> __device__ inline void load8c(const double *__restrict__ val, int64_t base, int kk, int r, double v[8])
 {
-    const vd2 *p = reinterpret_cast<const vd2 *>(val + base) + (int64_t)(kk >> 1) * SLICE + lane;
+    const vd2 *p = reinterpret_cast<const vd2 *>(val + base) + (int64_t)(kk >> 1) * C + r;
 #pragma unroll
     for (int c = 0; c < 4; c++) {
-        vd2 t = __builtin_nontemporal_load(p + c * SLICE);
-        v[2 * c] = t.x;
-        v[2 * c + 1] = t.y;
+        vd2 t = __builtin_nontemporal_load(p + c * C);
+        v[2 * c] = t.x; v[2 * c + 1] = t.y;
     }
 }
-
-__device__ inline void load8(const float *__restrict__ val, int64_t base, int kk, int lane, float v[8])
+template <int C> __device__ inline void load8c(const float *__restrict__ val, int64_t base, int kk, int r, float v[8])
 {
-    const vf4 *p = reinterpret_cast<const vf4 *>(val + base) + (int64_t)(kk >> 2) * SLICE + lane;
+    const vf4 *p = reinterpret_cast<const vf4 *>(val + base) + (int64_t)(kk >> 2) * C + r;
 #pragma unroll
     for (int c = 0; c < 2; c++) {
-        vf4 t = __builtin_nontemporal_load(p + c * SLICE);
+        vf4 t = __builtin_nontemporal_load(p + c * C);
         v[4 * c] = t.x; v[4 * c + 1] = t.y; v[4 * c + 2] = t.z; v[4 * c + 3] = t.w;
     }
 }
-
 // 16-bit deltas: one 16-byte load holds the 8 deltas of entries kk .. kk+7.
-__device__ inline void load_idx8(const uint16_t *__restrict__ d16, int64_t base, int kk, int lane, int &col,
-                                 int c[8])
+template <int C>
+__device__ inline void loadidx8c(const uint16_t *__restrict__ d16, int64_t base, int kk, int r, int &col, int c[8])
 {
-    const vu4 *p = reinterpret_cast<const vu4 *>(d16 + base) + (int64_t)(kk >> 3) * SLICE + lane;
-    vu4 t = __builtin_nontemporal_load(p);
+    vu4 t = __builtin_nontemporal_load(reinterpret_cast<const vu4 *>(d16 + base) + (int64_t)(kk >> 3) * C + r);
     unsigned w[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
     for (int q = 0; q < 4; q++) {
@@ -95,18 +101,63 @@ __device__ inline void load_idx8(const uint16_t *__restrict__ d16, int64_t base,
         c[2 * q + 1] = col;
     }
 }
-
-__device__ inline void load_idx8(const int32_t *__restrict__ c32, int64_t base, int kk, int lane, int &col,
-                                 int c[8])
+template <int C>
+__device__ inline void loadidx8c(const int32_t *__restrict__ c32, int64_t base, int kk, int r, int &col, int c[8])
 {
-    const vi4 *p = reinterpret_cast<const vi4 *>(c32 + base) + (int64_t)(kk >> 2) * SLICE + lane;
+    const vi4 *p = reinterpret_cast<const vi4 *>(c32 + base) + (int64_t)(kk >> 2) * C + r;
 #pragma unroll
     for (int h = 0; h < 2; h++) {
-        vi4 t = __builtin_nontemporal_load(p + h * SLICE);
+        vi4 t = __builtin_nontemporal_load(p + h * C);
         c[4 * h] = t.x; c[4 * h + 1] = t.y; c[4 * h + 2] = t.z; c[4 * h + 3] = t.w;
     }
     col = c[7];
 }
+
+// Device view of one SELL-C image (layout at the top of this file).
+template <typename VT, typename IT> struct Sell {
+    int64_t nrows, ncols, nslices;
+    const int64_t *soff;    // values of slice s: soff[s] .. soff[s+1]; width (soff[s+1] - soff[s]) / C
+    const int64_t *ibase;   // >= 0: start of slice s in idx; < 0: offsets at shoff[-1 - ibase[s]]
+    const VT *val;
+    const IT *idx;          // per-row indices: 16-bit deltas or int32 columns
+    const int32_t *col0;    // first column of each row (16-bit deltas)
+    const int32_t *shoff;   // shared offsets, w_s per shared slice, ascending
+};
+
+// Walk row s * C + r of slice s (s uniform across the wavefront) in groups of
+// 8 entries in ascending column order: body(v, c) gets the values and columns.
+template <int C, typename VT, typename IT, typename Body>
+__device__ __forceinline__ void sell_row(const Sell<VT, IT> &A, int64_t s, int r, Body &&body)
+{
+    const int64_t base = A.soff[s];
+    const int width = (int)((A.soff[s + 1] - base) / C);
+    const int64_t ib = A.ibase[s];
+    const int row = (int)(s * C + r);
+    if (ib < 0) {
+        const int32_t *so = A.shoff + (-1 - ib);
+        const int hi = (int)A.ncols - 1;   // columns of lanes without the entry stay in range
+        for (int kk = 0; kk < width; kk += 8) {
+            VT v[8];
+            int c[8];
+            load8c<C>(A.val, base, kk, r, v);
+#pragma unroll
+            for (int t = 0; t < 8; t++) c[t] = min(max(row + so[kk + t], 0), hi);
+            body(v, c);
+        }
+    } else {
+        int col = (sizeof(IT) == 2) ? A.col0[row] : 0;
+        for (int kk = 0; kk < width; kk += 8) {
+            VT v[8];
+            int c[8];
+            loadidx8c<C>(A.idx, ib, kk, r, col, c);
+            load8c<C>(A.val, base, kk, r, v);
+            body(v, c);
+        }
+    }
+}
+
+// wavefront index within the block, as a wave-uniform (scalar) value
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
 // ---- the sparse matrix-pass kernel -------------------------------------------
 //
@@ -120,32 +171,24 @@ __device__ inline void load_idx8(const int32_t *__restrict__ c32, int64_t base, 
 // (uint16_t deltas or int32_t columns).  NDOT dots are accumulated in FP64 and
 // written as one partial per block to partial[blockIdx.x * 2 + d].
 template <typename VT, typename FT, typename OT, typename IT, int EPI, int NDOT>
-__global__ __launch_bounds__(256) void k_sell(int64_t nrows, int64_t nslices, const int64_t *__restrict__ soff,
-                                              const VT *__restrict__ val, const IT *__restrict__ idx,
-                                              const int32_t *__restrict__ col0, const VT *__restrict__ x,
+__global__ __launch_bounds__(256) void k_sell(const Sell<VT, IT> A, const VT *__restrict__ x,
                                               const FT *__restrict__ f, const VT *__restrict__ invd,
                                               OT *__restrict__ y, const double *__restrict__ g0,
                                               const double *__restrict__ g1, double *__restrict__ partial,
                                               VT coef)
 {
     __shared__ double lds[8];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = wave_id();
     const int64_t s = (int64_t)blockIdx.x * SELL_WAVES + wid;
+    const int64_t nrows = A.nrows;
     double d0 = 0.0, d1 = 0.0;
-    if (s < nslices) {
+    if (s < A.nslices) {
         const int64_t row = s * SLICE + lane;
-        const int64_t base = soff[s];
-        const int width = (int)((soff[s + 1] - base) >> 6);
-        int col = (sizeof(IT) == 2) ? col0[row] : 0;
         VT acc = 0;
-        for (int kk = 0; kk < width; kk += 8) {
-            VT v[8];
-            int c[8];
-            load_idx8(idx, base, kk, lane, col, c);
-            load8(val, base, kk, lane, v);
+        sell_row<SLICE>(A, s, lane, [&](const VT *v, const int *c) {
 #pragma unroll
             for (int t = 0; t < 8; t++) acc = fma(v[t], x[c[t]], acc);
-        }
+        });
         if (row < nrows) {
             if (EPI == EPI_SPMV) {
                 y[row] = (OT)acc;
@@ -180,9 +223,7 @@ __global__ __launch_bounds__(256) void k_sell(int64_t nrows, int64_t nslices, co
 // over the SELL image of K P (its columns are coarse indices; the gathered
 // vector is e).  Dots as EPI_SMOOTH: (y, g0), (y, g1).
 template <typename VT, typename OT, typename IT, int NDOT>
-__global__ __launch_bounds__(256) void k_sell_post(int64_t nrows, int64_t nslices, const int64_t *__restrict__ soff,
-                                                   const VT *__restrict__ val, const IT *__restrict__ idx,
-                                                   const int32_t *__restrict__ col0, const VT *__restrict__ e,
+__global__ __launch_bounds__(256) void k_sell_post(const Sell<VT, IT> A, const VT *__restrict__ e,
                                                    const VT *__restrict__ u, const VT *__restrict__ r,
                                                    const VT *__restrict__ invd, const int32_t *__restrict__ agg,
                                                    const VT *__restrict__ pc, OT *__restrict__ y,
@@ -190,24 +231,17 @@ __global__ __launch_bounds__(256) void k_sell_post(int64_t nrows, int64_t nslice
                                                    double *__restrict__ partial)
 {
     __shared__ double lds[8];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = wave_id();
     const int64_t s = (int64_t)blockIdx.x * SELL_WAVES + wid;
     double d0 = 0.0, d1 = 0.0;
-    if (s < nslices) {
+    if (s < A.nslices) {
         const int64_t row = s * SLICE + lane;
-        const int64_t base = soff[s];
-        const int width = (int)((soff[s + 1] - base) >> 6);
-        int col = (sizeof(IT) == 2) ? col0[row] : 0;
         VT acc = 0;
-        for (int kk = 0; kk < width; kk += 8) {
-            VT v[8];
-            int c[8];
-            load_idx8(idx, base, kk, lane, col, c);
-            load8(val, base, kk, lane, v);
+        sell_row<SLICE>(A, s, lane, [&](const VT *v, const int *c) {
 #pragma unroll
             for (int t = 0; t < 8; t++) acc = fma(v[t], e[c[t]], acc);
-        }
-        if (row < nrows) {
+        });
+        if (row < A.nrows) {
             VT up = u[row] + pc[row] * e[agg[row]];
             VT out = up + invd[row] * (r[row] - acc);
             y[row] = (OT)out;

@@ -70,33 +70,24 @@ template <> struct BlkVec<double> {
 //   EPI_POLY : Y = a D^{-1} F + D^{-1} K X
 // Partials: partial[(blockIdx.x * 2 + d) * NB + j].
 template <typename VT, typename FT, typename OT, typename IT, int EPI, int NDOT>
-__global__ __launch_bounds__(256) void k_sell_blk(int64_t nrows, int64_t nslices, const int64_t *__restrict__ soff,
-                                                  const VT *__restrict__ val, const IT *__restrict__ idx,
-                                                  const int32_t *__restrict__ col0, const VT *__restrict__ X,
+__global__ __launch_bounds__(256) void k_sell_blk(const Sell<VT, IT> A, const VT *__restrict__ X,
                                                   const FT *__restrict__ F, const VT *__restrict__ invd,
                                                   OT *__restrict__ Y, const double *__restrict__ G0,
                                                   const double *__restrict__ G1, double *__restrict__ partial,
                                                   VT coef)
 {
     __shared__ double lds[8 * NB];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = wave_id();
     const int64_t s = (int64_t)blockIdx.x * SELL_WAVES + wid;
     double d0[NB], d1[NB];
 #pragma unroll
     for (int j = 0; j < NB; j++) { d0[j] = 0.0; d1[j] = 0.0; }
-    if (s < nslices) {
+    if (s < A.nslices) {
         const int64_t row = s * SLICE + lane;
-        const int64_t base = soff[s];
-        const int width = (int)((soff[s + 1] - base) >> 6);
-        int col = (sizeof(IT) == 2) ? col0[row] : 0;
         VT acc[NB];
 #pragma unroll
         for (int j = 0; j < NB; j++) acc[j] = 0;
-        for (int kk = 0; kk < width; kk += 8) {
-            VT v[8];
-            int c[8];
-            load_idx8(idx, base, kk, lane, col, c);
-            load8(val, base, kk, lane, v);
+        sell_row<SLICE>(A, s, lane, [&](const VT *v, const int *c) {
 #pragma unroll
             for (int t = 0; t < 8; t++) {
                 VT xv[NB];
@@ -104,8 +95,8 @@ __global__ __launch_bounds__(256) void k_sell_blk(int64_t nrows, int64_t nslices
 #pragma unroll
                 for (int j = 0; j < NB; j++) acc[j] = fma(v[t], xv[j], acc[j]);
             }
-        }
-        if (row < nrows) {
+        });
+        if (row < A.nrows) {
             const int64_t o = row * NB;
             if (EPI == EPI_SPMV) {
 #pragma unroll
@@ -184,53 +175,8 @@ template <> struct RowLoad<double> {
     }
 };
 
-template <int C> __device__ inline void load8c(const double *__restrict__ val, int64_t base, int kk, int r, double v[8])
-{
-    const vd2 *p = reinterpret_cast<const vd2 *>(val + base) + (int64_t)(kk >> 1) * C + r;
-#pragma unroll
-    for (int c = 0; c < 4; c++) {
-        vd2 t = __builtin_nontemporal_load(p + c * C);
-        v[2 * c] = t.x; v[2 * c + 1] = t.y;
-    }
-}
-template <int C> __device__ inline void load8c(const float *__restrict__ val, int64_t base, int kk, int r, float v[8])
-{
-    const vf4 *p = reinterpret_cast<const vf4 *>(val + base) + (int64_t)(kk >> 2) * C + r;
-#pragma unroll
-    for (int c = 0; c < 2; c++) {
-        vf4 t = __builtin_nontemporal_load(p + c * C);
-        v[4 * c] = t.x; v[4 * c + 1] = t.y; v[4 * c + 2] = t.z; v[4 * c + 3] = t.w;
-    }
-}
-template <int C>
-__device__ inline void loadidx8c(const uint16_t *__restrict__ d16, int64_t base, int kk, int r, int &col, int c[8])
-{
-    vu4 t = __builtin_nontemporal_load(reinterpret_cast<const vu4 *>(d16 + base) + (int64_t)(kk >> 3) * C + r);
-    unsigned w[4] = {t.x, t.y, t.z, t.w};
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        col += (int)(w[q] & 0xffffu);
-        c[2 * q] = col;
-        col += (int)(w[q] >> 16);
-        c[2 * q + 1] = col;
-    }
-}
-template <int C>
-__device__ inline void loadidx8c(const int32_t *__restrict__ c32, int64_t base, int kk, int r, int &col, int c[8])
-{
-    const vi4 *p = reinterpret_cast<const vi4 *>(c32 + base) + (int64_t)(kk >> 2) * C + r;
-#pragma unroll
-    for (int h = 0; h < 2; h++) {
-        vi4 t = __builtin_nontemporal_load(p + h * C);
-        c[4 * h] = t.x; c[4 * h + 1] = t.y; c[4 * h + 2] = t.z; c[4 * h + 3] = t.w;
-    }
-    col = c[7];
-}
-
 template <typename VT, typename FT, typename OT, typename IT, int EPI, int NDOT, int LPR>
-__global__ __launch_bounds__(512) void k_sellb(int64_t nrows, int64_t nslices, const int64_t *__restrict__ soff,
-                                               const VT *__restrict__ val, const IT *__restrict__ idx,
-                                               const int32_t *__restrict__ col0, const VT *__restrict__ X,
+__global__ __launch_bounds__(512) void k_sellb(const Sell<VT, IT> A, const VT *__restrict__ X,
                                                const FT *__restrict__ F, const VT *__restrict__ invd,
                                                OT *__restrict__ Y, const double *__restrict__ G0,
                                                const double *__restrict__ G1, double *__restrict__ partial,
@@ -238,24 +184,17 @@ __global__ __launch_bounds__(512) void k_sellb(int64_t nrows, int64_t nslices, c
 {
     constexpr int C = 64 / LPR, RPL = NB / LPR;
     __shared__ double lds[2 * 8 * NB];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wid = wave_id(), nw = blockDim.x >> 6;
     const int r = lane / LPR, q = lane % LPR;
     double d0[RPL], d1[RPL];
 #pragma unroll
     for (int j = 0; j < RPL; j++) { d0[j] = 0.0; d1[j] = 0.0; }
-    for (int64_t s = (int64_t)blockIdx.x * nw + wid; s < nslices; s += (int64_t)gridDim.x * nw) {
+    for (int64_t s = (int64_t)blockIdx.x * nw + wid; s < A.nslices; s += (int64_t)gridDim.x * nw) {
         const int64_t row = s * C + r;
-        const int64_t base = soff[s];
-        const int width = (int)((soff[s + 1] - base) / C);
-        int col = (sizeof(IT) == 2) ? col0[row] : 0;
         VT acc[RPL];
 #pragma unroll
         for (int j = 0; j < RPL; j++) acc[j] = 0;
-        for (int kk = 0; kk < width; kk += 8) {
-            VT v[8];
-            int c[8];
-            loadidx8c<C>(idx, base, kk, r, col, c);
-            load8c<C>(val, base, kk, r, v);
+        sell_row<C>(A, s, r, [&](const VT *v, const int *c) {
 #pragma unroll
             for (int t = 0; t < 8; t++) {
                 VT xv[RPL];
@@ -263,8 +202,8 @@ __global__ __launch_bounds__(512) void k_sellb(int64_t nrows, int64_t nslices, c
 #pragma unroll
                 for (int j = 0; j < RPL; j++) acc[j] = fma(v[t], xv[j], acc[j]);
             }
-        }
-        if (row < nrows) {
+        });
+        if (row < A.nrows) {
             const int64_t o = row * NB + q * RPL;
             if (EPI == EPI_SPMV) {
 #pragma unroll
@@ -319,34 +258,24 @@ __global__ __launch_bounds__(512) void k_sellb(int64_t nrows, int64_t nslices, c
 // k_sell_post): acc = (K P) E over the SELL-64 image of K P, one lane per row;
 // Y = U + P E + D^{-1} (R - acc).  Per column the order of k_sell_post.
 template <typename VT, typename OT, typename IT, int NDOT>
-__global__ __launch_bounds__(256) void k_sell_blk_post(int64_t nrows, int64_t nslices,
-                                                       const int64_t *__restrict__ soff, const VT *__restrict__ val,
-                                                       const IT *__restrict__ idx, const int32_t *__restrict__ col0,
-                                                       const VT *__restrict__ E, const VT *__restrict__ U,
+__global__ __launch_bounds__(256) void k_sell_blk_post(const Sell<VT, IT> A, const VT *__restrict__ E, const VT *__restrict__ U,
                                                        const VT *__restrict__ R, const VT *__restrict__ invd,
                                                        const int32_t *__restrict__ agg, const VT *__restrict__ pc,
                                                        OT *__restrict__ Y, const double *__restrict__ G0,
                                                        const double *__restrict__ G1, double *__restrict__ partial)
 {
     __shared__ double lds[8 * NB];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = wave_id();
     const int64_t s = (int64_t)blockIdx.x * SELL_WAVES + wid;
     double d0[NB], d1[NB];
 #pragma unroll
     for (int j = 0; j < NB; j++) { d0[j] = 0.0; d1[j] = 0.0; }
-    if (s < nslices) {
+    if (s < A.nslices) {
         const int64_t row = s * SLICE + lane;
-        const int64_t base = soff[s];
-        const int width = (int)((soff[s + 1] - base) >> 6);
-        int col = (sizeof(IT) == 2) ? col0[row] : 0;
         VT acc[NB];
 #pragma unroll
         for (int j = 0; j < NB; j++) acc[j] = 0;
-        for (int kk = 0; kk < width; kk += 8) {
-            VT v[8];
-            int c[8];
-            load_idx8(idx, base, kk, lane, col, c);
-            load8(val, base, kk, lane, v);
+        sell_row<SLICE>(A, s, lane, [&](const VT *v, const int *c) {
 #pragma unroll
             for (int t = 0; t < 8; t++) {
                 VT xv[NB];
@@ -354,8 +283,8 @@ __global__ __launch_bounds__(256) void k_sell_blk_post(int64_t nrows, int64_t ns
 #pragma unroll
                 for (int j = 0; j < NB; j++) acc[j] = fma(v[t], xv[j], acc[j]);
             }
-        }
-        if (row < nrows) {
+        });
+        if (row < A.nrows) {
             const int64_t o = row * NB, a = (int64_t)agg[row] * NB;
             const VT di = invd[row], pi = pc[row];
 #pragma unroll
@@ -383,9 +312,7 @@ __global__ __launch_bounds__(256) void k_sell_blk_post(int64_t nrows, int64_t ns
 // The same with LPR lanes per row on a SELL-(64/LPR) image of K P (layout and
 // reductions of k_sellb).
 template <typename VT, typename OT, typename IT, int NDOT, int LPR>
-__global__ __launch_bounds__(512) void k_sellb_post(int64_t nrows, int64_t nslices, const int64_t *__restrict__ soff,
-                                                    const VT *__restrict__ val, const IT *__restrict__ idx,
-                                                    const int32_t *__restrict__ col0, const VT *__restrict__ E,
+__global__ __launch_bounds__(512) void k_sellb_post(const Sell<VT, IT> A, const VT *__restrict__ E,
                                                     const VT *__restrict__ U, const VT *__restrict__ R,
                                                     const VT *__restrict__ invd, const int32_t *__restrict__ agg,
                                                     const VT *__restrict__ pc, OT *__restrict__ Y,
@@ -394,24 +321,17 @@ __global__ __launch_bounds__(512) void k_sellb_post(int64_t nrows, int64_t nslic
 {
     constexpr int C = 64 / LPR, RPL = NB / LPR;
     __shared__ double lds[2 * 8 * NB];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wid = wave_id(), nw = blockDim.x >> 6;
     const int r = lane / LPR, q = lane % LPR;
     double d0[RPL], d1[RPL];
 #pragma unroll
     for (int j = 0; j < RPL; j++) { d0[j] = 0.0; d1[j] = 0.0; }
-    for (int64_t s = (int64_t)blockIdx.x * nw + wid; s < nslices; s += (int64_t)gridDim.x * nw) {
+    for (int64_t s = (int64_t)blockIdx.x * nw + wid; s < A.nslices; s += (int64_t)gridDim.x * nw) {
         const int64_t row = s * C + r;
-        const int64_t base = soff[s];
-        const int width = (int)((soff[s + 1] - base) / C);
-        int col = (sizeof(IT) == 2) ? col0[row] : 0;
         VT acc[RPL];
 #pragma unroll
         for (int j = 0; j < RPL; j++) acc[j] = 0;
-        for (int kk = 0; kk < width; kk += 8) {
-            VT v[8];
-            int c[8];
-            loadidx8c<C>(idx, base, kk, r, col, c);
-            load8c<C>(val, base, kk, r, v);
+        sell_row<C>(A, s, r, [&](const VT *v, const int *c) {
 #pragma unroll
             for (int t = 0; t < 8; t++) {
                 VT xv[RPL];
@@ -419,8 +339,8 @@ __global__ __launch_bounds__(512) void k_sellb_post(int64_t nrows, int64_t nslic
 #pragma unroll
                 for (int j = 0; j < RPL; j++) acc[j] = fma(v[t], xv[j], acc[j]);
             }
-        }
-        if (row < nrows) {
+        });
+        if (row < A.nrows) {
             const int64_t o = row * NB + q * RPL, a = (int64_t)agg[row] * NB + q * RPL;
             const VT di = invd[row], pi = pc[row];
 #pragma unroll

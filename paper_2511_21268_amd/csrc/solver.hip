@@ -63,68 +63,137 @@ inline unsigned vgrid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::mi
 
 // Host-side sliced-ELL image of one level (layout described in kernels.h).
 struct SellHost {
-    int64_t nslices = 0, stored = 0;
+    int64_t nslices = 0, stored = 0, nshared = 0;
+    double index_bytes = 0.0;   // index data a pass must read (no padding)
     int idx16 = 1;
-    std::vector<int64_t> soff;
+    std::vector<int64_t> soff, ibase;
     std::vector<double> v64;
     std::vector<float> v32;
     std::vector<uint16_t> d16;
-    std::vector<int32_t> c32, col0;
+    std::vector<int32_t> c32, col0, shoff;
 };
 
-// SELL-C image of a CSR matrix (slice height C rows; group layout of kernels.h
-// with SLICE replaced by C).
-void build_sell(const CsrView &K, int C, bool want64, bool want32, SellHost &S)
+// Ascending union of the column offsets (column - row) of the rows of slice s,
+// or an empty list when it would be longer than `limit`.
+static std::vector<int32_t> slice_offsets(const CsrView &K, int64_t s, int C, int64_t limit)
+{
+    std::vector<int32_t> u, m;
+    for (int64_t r = s * C; r < std::min(K.n, (s + 1) * C); r++) {
+        m.clear();
+        size_t a = 0;
+        for (int64_t k = K.rp[r]; k < K.rp[r + 1]; k++) {
+            const int32_t o = (int32_t)(K.ci[k] - r);
+            while (a < u.size() && u[a] < o) m.push_back(u[a++]);
+            if (a < u.size() && u[a] == o) a++;
+            m.push_back(o);
+        }
+        while (a < u.size()) m.push_back(u[a++]);
+        if ((int64_t)m.size() > limit) return {};
+        u.swap(m);
+    }
+    return u;
+}
+
+// SELL-C image of a CSR matrix (slice height C rows; group layout of kernels.h).
+// With `shared`, a slice whose offset union is no wider than its longest row
+// (both rounded up to 8) stores the union once; the others keep per-row indices.
+void build_sell(const CsrView &K, int C, bool want64, bool want32, bool shared, SellHost &S)
 {
     const int64_t n = K.n;
     S.nslices = (n + C - 1) / C;
+    std::vector<int64_t> wd(S.nslices);
+    std::vector<std::vector<int32_t>> U(S.nslices);
+    amgiga::parallel_for(S.nslices, [&](int64_t sb, int64_t se) {
+        for (int64_t s = sb; s < se; s++) {
+            int64_t w = 0;
+            for (int64_t r = s * C; r < std::min(n, (s + 1) * C); r++) w = std::max(w, K.rp[r + 1] - K.rp[r]);
+            wd[s] = (w + 7) / 8 * 8;
+            if (shared && w > 0) U[s] = slice_offsets(K, s, C, wd[s]);
+        }
+    }, 1);
     S.soff.assign(S.nslices + 1, 0);
+    S.ibase.assign(S.nslices, 0);
+    int64_t ib = 0, sh = 0;
+    S.nshared = 0;
+    S.index_bytes = 0.0;
     for (int64_t s = 0; s < S.nslices; s++) {
-        int64_t w = 0;
-        for (int64_t r = s * C; r < std::min(n, (s + 1) * C); r++) w = std::max(w, K.rp[r + 1] - K.rp[r]);
-        w = (w + 7) / 8 * 8;
+        const int64_t w = U[s].empty() ? wd[s] : (int64_t)(U[s].size() + 7) / 8 * 8;
         S.soff[s + 1] = S.soff[s] + C * w;
+        if (U[s].empty()) {
+            S.ibase[s] = ib;
+            ib += C * w;
+        } else {
+            S.ibase[s] = -1 - sh;
+            sh += w;
+            S.nshared++;
+            S.index_bytes += 4.0 * (double)U[s].size();
+        }
     }
     S.stored = S.soff[S.nslices];
     int maxd = 0;
+    int64_t dnnz = 0, drows = 0;
     {
         std::mutex mx;
-        amgiga::parallel_for(n, [&](int64_t b, int64_t e) {
+        amgiga::parallel_for(S.nslices, [&](int64_t sb, int64_t se) {
             int m = 0;
-            for (int64_t r = b; r < e; r++)
-                for (int64_t k = K.rp[r] + 1; k < K.rp[r + 1]; k++) m = std::max(m, K.ci[k] - K.ci[k - 1]);
+            int64_t z = 0, nr = 0;
+            for (int64_t s = sb; s < se; s++) {
+                if (!U[s].empty()) continue;
+                for (int64_t r = s * C; r < std::min(n, (s + 1) * C); r++) {
+                    for (int64_t k = K.rp[r] + 1; k < K.rp[r + 1]; k++) m = std::max(m, K.ci[k] - K.ci[k - 1]);
+                    z += K.rp[r + 1] - K.rp[r];
+                    nr++;
+                }
+            }
             std::lock_guard<std::mutex> g(mx);
             maxd = std::max(maxd, m);
-        });
+            dnnz += z;
+            drows += nr;
+        }, 1);
     }
     S.idx16 = maxd <= 65535 ? 1 : 0;
+    S.index_bytes += S.idx16 ? 2.0 * (double)dnnz + 4.0 * (double)drows : 4.0 * (double)dnnz;
     if (want64) S.v64.assign(S.stored, 0.0);
     if (want32) S.v32.assign(S.stored, 0.0f);
-    if (S.idx16) {
-        S.d16.assign(S.stored, 0);
-        S.col0.assign(S.nslices * C, 0);
-    } else {
-        S.c32.assign(S.stored, 0);
+    if (ib > 0) {
+        if (S.idx16) {
+            S.d16.assign(ib, 0);
+            S.col0.assign(S.nslices * C, 0);
+        } else {
+            S.c32.assign(ib, 0);
+        }
     }
+    S.shoff.assign(sh, 0);
     amgiga::parallel_for(S.nslices, [&](int64_t sb, int64_t se) {
         for (int64_t s = sb; s < se; s++) {
             const int64_t base = S.soff[s];
             const int64_t w = (S.soff[s + 1] - base) / C;
+            const bool sl = !U[s].empty();
+            if (sl) std::copy(U[s].begin(), U[s].end(), S.shoff.begin() + (-1 - S.ibase[s]));
             for (int lane = 0; lane < C; lane++) {
-                int64_t r = s * C + lane;
-                int64_t len = r < n ? K.rp[r + 1] - K.rp[r] : 0;
+                const int64_t r = s * C + lane;
+                const int64_t len = r < n ? K.rp[r + 1] - K.rp[r] : 0;
                 const int64_t r0 = r < n ? K.rp[r] : 0;
-                if (S.idx16 && r < n) S.col0[r] = K.ci[r0];
-                for (int64_t k = 0; k < w; k++) {
-                    double v = k < len ? K.v[r0 + k] : 0.0;
+                auto put = [&](int64_t k, double v) {
                     if (want64) S.v64[base + (k / 2) * 2 * C + lane * 2 + (k % 2)] = v;
                     if (want32) S.v32[base + (k / 4) * 4 * C + lane * 4 + (k % 4)] = (float)v;
+                };
+                if (sl) {
+                    int64_t j = 0;
+                    for (int64_t k = 0; k < (int64_t)U[s].size() && j < len; k++)
+                        if (K.ci[r0 + j] - r == U[s][k]) put(k, K.v[r0 + j++]);
+                    continue;
+                }
+                const int64_t ibs = S.ibase[s];
+                if (S.idx16 && r < n) S.col0[r] = K.ci[r0];
+                for (int64_t k = 0; k < w; k++) {
+                    put(k, k < len ? K.v[r0 + k] : 0.0);
                     if (S.idx16) {
                         int d = (k >= 1 && k < len) ? K.ci[r0 + k] - K.ci[r0 + k - 1] : 0;
-                        S.d16[base + (k / 8) * 8 * C + lane * 8 + (k % 8)] = (uint16_t)d;
+                        S.d16[ibs + (k / 8) * 8 * C + lane * 8 + (k % 8)] = (uint16_t)d;
                     } else {
                         int32_t c = k < len ? K.ci[r0 + k] : (len > 0 ? K.ci[r0 + len - 1] : 0);
-                        S.c32[base + (k / 4) * 4 * C + lane * 4 + (k % 4)] = c;
+                        S.c32[ibs + (k / 4) * 4 * C + lane * 4 + (k % 4)] = c;
                     }
                 }
             }
@@ -133,17 +202,25 @@ void build_sell(const CsrView &K, int C, bool want64, bool want32, SellHost &S)
 }
 
 struct DevMat {
-    int64_t n = 0, nnz = 0, nslices = 0, stored = 0;
+    int64_t n = 0, ncols = 0, nnz = 0, nslices = 0, stored = 0, nshared = 0;
+    double index_bytes = 0.0;
     int idx16 = 1, C = SLICE;
-    int64_t *soff = nullptr;
-    int32_t *col0 = nullptr, *c32 = nullptr;
+    int64_t *soff = nullptr, *ibase = nullptr;
+    int32_t *col0 = nullptr, *c32 = nullptr, *shoff = nullptr;
     uint16_t *d16 = nullptr;
     double *v64 = nullptr;
     float *v32 = nullptr;
     template <typename VT> const VT *val() const;
+    template <typename IT> const IT *idx() const;
+    template <typename VT, typename IT> Sell<VT, IT> sv() const
+    {
+        return Sell<VT, IT>{n, ncols, nslices, soff, ibase, val<VT>(), idx<IT>(), col0, shoff};
+    }
 };
 template <> const double *DevMat::val<double>() const { return v64; }
 template <> const float *DevMat::val<float>() const { return v32; }
+template <> const uint16_t *DevMat::idx<uint16_t>() const { return d16; }
+template <> const int32_t *DevMat::idx<int32_t>() const { return c32; }
 
 struct Level {
     int64_t n = 0, nnz = 0;
@@ -283,20 +360,30 @@ struct amg_ctx {
     }
     void release(DevMat &M)
     {
-        release(M.soff); release(M.col0); release(M.c32); release(M.d16); release(M.v64); release(M.v32);
+        release(M.soff); release(M.ibase); release(M.shoff); release(M.col0); release(M.c32); release(M.d16);
+        release(M.v64); release(M.v32);
         M = DevMat();
     }
-    DevMat upload_sell(const CsrView &K, int C, bool want64, bool want32)
+    // SELL-C image of a square level matrix (shared offsets where they fit,
+    // if enabled), or with ncols > 0 of a rectangular one (K P: per-entry
+    // indices only; its column offsets are not shared between rows).
+    DevMat upload_sell(const CsrView &K, int C, bool want64, bool want32, int64_t ncols = 0)
     {
         SellHost S;
-        build_sell(K, C, want64, want32, S);
+        const bool square = ncols <= 0;
+        build_sell(K, C, want64, want32, square && prm.slice_offsets != 0, S);
         DevMat A;
-        A.n = K.n; A.nnz = K.nnz(); A.nslices = S.nslices; A.stored = S.stored; A.idx16 = S.idx16; A.C = C;
+        A.n = K.n; A.ncols = square ? K.n : ncols;
+        A.nnz = K.nnz(); A.nslices = S.nslices; A.stored = S.stored; A.idx16 = S.idx16; A.C = C;
+        A.nshared = S.nshared; A.index_bytes = S.index_bytes;
         A.soff = upload(S.soff);
+        A.ibase = upload(S.ibase);
+        if (!S.shoff.empty()) A.shoff = upload(S.shoff);
         if (want64) A.v64 = upload(S.v64);
         if (want32) A.v32 = upload(S.v32);
-        if (S.idx16) { A.d16 = upload(S.d16); A.col0 = upload(S.col0); }
-        else A.c32 = upload(S.c32);
+        if (!S.d16.empty()) A.d16 = upload(S.d16);
+        if (!S.col0.empty()) A.col0 = upload(S.col0);
+        if (!S.c32.empty()) A.c32 = upload(S.c32);
         return A;
     }
     // Time one batched iteration's level-0 passes (FP64 outer SpMV + two V-cycle
@@ -377,7 +464,7 @@ struct amg_ctx {
                 CsrView K = l == 0 ? K0 : amgiga::view(host.lev[l].K);
                 amgiga::Csr kp = amgiga::kp_product(K, host.lev[l + 1].n, host.lev[l].agg.data(),
                                                     host.lev[l].pc.data());
-                lev[l].KPb = upload_sell(amgiga::view(kp), 64 / best.lpr, !f32, f32);
+                lev[l].KPb = upload_sell(amgiga::view(kp), 64 / best.lpr, !f32, f32, host.lev[l + 1].n);
             }
         }
         HIPCHK(hipStreamSynchronize(stream));
@@ -433,8 +520,7 @@ struct amg_ctx {
     double pass_bytes(int vb, int nvec) const
     {
         const DevMat &A = lev[0].A;
-        double ib = A.idx16 ? 2.0 : 4.0;
-        return (double)A.nnz * (vb + ib) + (A.idx16 ? 4.0 * A.n : 0.0) + (double)nvec * 8.0 * A.n;
+        return (double)A.nnz * vb + A.index_bytes + (double)nvec * 8.0 * A.n;
     }
 
     // ---- kernel launchers --------------------------------------------------
@@ -459,11 +545,11 @@ struct amg_ctx {
                      const double *g0, const double *g1, VT coef)
     {
         if (A.idx16)
-            hipLaunchKernelGGL((k_sell<VT, FT, OT, uint16_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream, A.n,
-                               A.nslices, A.soff, A.val<VT>(), A.d16, A.col0, x, f, invd, y, g0, g1, partial, coef);
+            hipLaunchKernelGGL((k_sell<VT, FT, OT, uint16_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream,
+                               A.sv<VT, uint16_t>(), x, f, invd, y, g0, g1, partial, coef);
         else
-            hipLaunchKernelGGL((k_sell<VT, FT, OT, int32_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream, A.n,
-                               A.nslices, A.soff, A.val<VT>(), A.c32, A.col0, x, f, invd, y, g0, g1, partial, coef);
+            hipLaunchKernelGGL((k_sell<VT, FT, OT, int32_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream,
+                               A.sv<VT, int32_t>(), x, f, invd, y, g0, g1, partial, coef);
         HIPCHK(hipGetLastError());
     }
     unsigned sell_blocks(int l) const { return (unsigned)((lev[l].A.nslices + SELL_WAVES - 1) / SELL_WAVES); }
@@ -476,9 +562,8 @@ struct amg_ctx {
         unsigned nb = (unsigned)((A.nslices + SELL_WAVES - 1) / SELL_WAVES);
         if (l == 0) prof_begin();
 #define POST_LAUNCH(IT, IDX, ND)                                                                              \
-    hipLaunchKernelGGL((k_sell_post<VT, OT, IT, ND>), dim3(nb), dim3(256), 0, stream, A.n, A.nslices, A.soff, \
-                       A.val<VT>(), IDX, A.col0, e, u, (const VT *)L.r, L.invd<VT>(), L.agg, L.pc<VT>(), y, g0, g1, \
-                       partial)
+    hipLaunchKernelGGL((k_sell_post<VT, OT, IT, ND>), dim3(nb), dim3(256), 0, stream, A.sv<VT, IT>(), e, u,     \
+                       (const VT *)L.r, L.invd<VT>(), L.agg, L.pc<VT>(), y, g0, g1, partial)
         if (A.idx16) {
             if (ndot == 2) POST_LAUNCH(uint16_t, A.d16, 2);
             else if (ndot == 1) POST_LAUNCH(uint16_t, A.d16, 1);
@@ -491,8 +576,7 @@ struct amg_ctx {
 #undef POST_LAUNCH
         HIPCHK(hipGetLastError());
         if (l == 0) {
-            double ib = A.idx16 ? 2.0 : 4.0;
-            double bytes = (double)A.nnz * (sizeof(VT) + ib) + (A.idx16 ? 4.0 * A.n : 0.0) +
+            double bytes = (double)A.nnz * sizeof(VT) + A.index_bytes +
                            (double)sizeof(VT) * lev[1].n +                         // e gathered once
                            (double)sizeof(VT) * A.n * 4 + 4.0 * A.n +               // u, r, invd, pc, agg
                            (double)sizeof(OT) * A.n + 8.0 * A.n * ndot;              // y, dot partners
@@ -697,12 +781,10 @@ struct amg_ctx {
         unsigned g = blk_grid(B);
         if (B.idx16)
             hipLaunchKernelGGL((k_sellb<VT, FT, OT, uint16_t, EPI, NDOT, LPR>), dim3(g), dim3(blk_threads), 0, stream,
-                               B.n, B.nslices, B.soff, B.val<VT>(), B.d16, B.col0, x, f, invd, y, g0, g1, bpartial,
-                               coef);
+                               B.sv<VT, uint16_t>(), x, f, invd, y, g0, g1, bpartial, coef);
         else
             hipLaunchKernelGGL((k_sellb<VT, FT, OT, int32_t, EPI, NDOT, LPR>), dim3(g), dim3(blk_threads), 0, stream,
-                               B.n, B.nslices, B.soff, B.val<VT>(), B.c32, B.col0, x, f, invd, y, g0, g1, bpartial,
-                               coef);
+                               B.sv<VT, int32_t>(), x, f, invd, y, g0, g1, bpartial, coef);
         return g;
     }
     // Block matrix pass on level l; returns the number of dot-partial blocks.
@@ -720,23 +802,19 @@ struct amg_ctx {
         } else {
             nb = sell_blocks(l);
             if (A.idx16)
-                hipLaunchKernelGGL((k_sell_blk<VT, FT, OT, uint16_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream, A.n,
-                                   A.nslices, A.soff, A.val<VT>(), A.d16, A.col0, x, f, invd, y, g0, g1, bpartial,
-                                   coef);
+                hipLaunchKernelGGL((k_sell_blk<VT, FT, OT, uint16_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream,
+                                   A.sv<VT, uint16_t>(), x, f, invd, y, g0, g1, bpartial, coef);
             else
-                hipLaunchKernelGGL((k_sell_blk<VT, FT, OT, int32_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream, A.n,
-                                   A.nslices, A.soff, A.val<VT>(), A.c32, A.col0, x, f, invd, y, g0, g1, bpartial,
-                                   coef);
+                hipLaunchKernelGGL((k_sell_blk<VT, FT, OT, int32_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream,
+                                   A.sv<VT, int32_t>(), x, f, invd, y, g0, g1, bpartial, coef);
         }
         HIPCHK(hipGetLastError());
         if (l == 0) {
             // 16 columns: matrix once, 16 vectors of each kind
             const DevMat &M = lev[0].A;
-            double ib = M.idx16 ? 2.0 : 4.0;
             int nvec = 2 + (EPI == EPI_RESID ? 1 : 0) + (EPI == EPI_SMOOTH ? 1 : 0) + (EPI == EPI_POLY ? 1 : 0) +
                        (NDOT >= 2 ? 1 : 0) + (EPI == EPI_SMOOTH && NDOT >= 1 ? 1 : 0);
-            double bytes = (double)M.nnz * (sizeof(VT) + ib) + (M.idx16 ? 4.0 * M.n : 0.0) +
-                           (double)nvec * NB * sizeof(VT) * M.n +
+            double bytes = (double)M.nnz * sizeof(VT) + M.index_bytes + (double)nvec * NB * sizeof(VT) * M.n +
                            ((EPI == EPI_SMOOTH || EPI == EPI_POLY) ? (double)sizeof(VT) * M.n : 0.0);
             prof_end(bytes);
         }
@@ -765,8 +843,8 @@ struct amg_ctx {
         unsigned thr = multi ? (unsigned)blk_threads : 256u;
         if (l == 0) prof_begin();
 #define BPOST(KERN, IT, IDX)                                                                                    \
-    hipLaunchKernelGGL(KERN, dim3(nb), dim3(thr), 0, stream, A.n, A.nslices, A.soff, A.val<VT>(), IDX, A.col0, E, U, \
-                       (const VT *)L.br, L.invd<VT>(), L.agg, L.pc<VT>(), Y, g0, g1, bpartial)
+    hipLaunchKernelGGL(KERN, dim3(nb), dim3(thr), 0, stream, A.sv<VT, IT>(), E, U, (const VT *)L.br, L.invd<VT>(), \
+                       L.agg, L.pc<VT>(), Y, g0, g1, bpartial)
 #define BPOST_ND(IT, IDX, ND)                                                                                   \
     do {                                                                                                        \
         if (!multi) BPOST((k_sell_blk_post<VT, OT, IT, ND>), IT, IDX);                                          \
@@ -786,9 +864,7 @@ struct amg_ctx {
 #undef BPOST
         HIPCHK(hipGetLastError());
         if (l == 0) {
-            double ib = A.idx16 ? 2.0 : 4.0;
-            double bytes = (double)A.nnz * (sizeof(VT) + ib) + (A.idx16 ? 4.0 * A.n : 0.0) +
-                           (double)NB * sizeof(VT) * lev[1].n + (double)NB * sizeof(VT) * A.n * 2 +
+            double bytes = (double)A.nnz * sizeof(VT) + A.index_bytes + (double)NB * sizeof(VT) * lev[1].n + (double)NB * sizeof(VT) * A.n * 2 +
                            (double)sizeof(VT) * A.n * 2 + 4.0 * A.n + (double)NB * sizeof(OT) * A.n +
                            8.0 * NB * A.n * ndot;
             prof_end(bytes);
@@ -933,17 +1009,7 @@ static amg_status build_device(amg_ctx *c, const CsrView &K0)
         if (!coarsest || l == 0) {
             {
                 CsrView K = l == 0 ? K0 : amgiga::view(hl.K);
-                SellHost S;
-                bool want64 = (l == 0) || !fp32;
-                bool want32 = fp32;
-                build_sell(K, SLICE, want64, want32, S);
-                DevMat &A = L.A;
-                A.n = hl.n; A.nnz = hl.nnz; A.nslices = S.nslices; A.stored = S.stored; A.idx16 = S.idx16;
-                A.soff = c->upload(S.soff);
-                if (want64) A.v64 = c->upload(S.v64);
-                if (want32) A.v32 = c->upload(S.v32);
-                if (S.idx16) { A.d16 = c->upload(S.d16); A.col0 = c->upload(S.col0); }
-                else A.c32 = c->upload(S.c32);
+                L.A = c->upload_sell(K, SLICE, (l == 0) || !fp32, fp32);
             }
         }
         L.invd64 = c->upload(hl.invd);
@@ -955,7 +1021,7 @@ static amg_status build_device(amg_ctx *c, const CsrView &K0)
             {
                 CsrView K = l == 0 ? K0 : amgiga::view(hl.K);
                 amgiga::Csr kp = amgiga::kp_product(K, H.lev[l + 1].n, hl.agg.data(), hl.pc.data());
-                L.KP = c->upload_sell(amgiga::view(kp), SLICE, !fp32, fp32);
+                L.KP = c->upload_sell(amgiga::view(kp), SLICE, !fp32, fp32, H.lev[l + 1].n);
             }
             L.agg = c->upload(hl.agg);
             L.pc64 = c->upload(hl.pc);
@@ -1041,6 +1107,7 @@ amg_status amg_params_default(amg_params *p)
     p->match_positive_only = 0;
     p->itmax = 1000;
     p->nrhs = 1;
+    p->slice_offsets = 1;
     return AMG_OK;
 }
 
@@ -1059,7 +1126,7 @@ static amg_status setup_common(int64_t n, const int64_t *row_ptr, const int32_t 
     if (P.sweeps_per_level < 1 || P.sweeps_per_level > 3 || P.max_coarse < 1 || P.max_coarse > 2000 ||
         P.max_levels < 1 || P.nu_pre < 1 || P.nu_post < 0 || P.itmax < 1 || P.krylov < 0 || P.krylov > 1 ||
         P.nrhs < 1 || P.nrhs > NB ||
-        P.smoother < 0 || P.smoother > 1) {
+        P.smoother < 0 || P.smoother > 1 || P.slice_offsets < 0 || P.slice_offsets > 1) {
         set_err("parameter out of range");
         return AMG_ERR_ARG;
     }
@@ -1508,7 +1575,8 @@ amg_status amg_get_profile(amg_ctx *c, int64_t *launches, double *ms, double *by
     return AMG_OK;
 }
 
-amg_status amg_get_format(const amg_ctx *c, int level, int *slice, int64_t *stored, int *index_bytes)
+amg_status amg_get_format(const amg_ctx *c, int level, int *slice, int64_t *stored, int *index_bytes,
+                          int64_t *shared_slices)
 {
     if (!c || c->host_only || level < 0 || level >= c->nlev || (level == c->nlev - 1 && level > 0)) {
         set_err("level has no sparse device matrix");
@@ -1518,6 +1586,7 @@ amg_status amg_get_format(const amg_ctx *c, int level, int *slice, int64_t *stor
     if (slice) *slice = SLICE;
     if (stored) *stored = A.stored;
     if (index_bytes) *index_bytes = A.idx16 ? 2 : 4;
+    if (shared_slices) *shared_slices = A.nshared;
     return AMG_OK;
 }
 
