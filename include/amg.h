@@ -87,8 +87,8 @@ amg_status amg_params_default(amg_params *p);
  * (eq. (cij)), greedy matching in the order (c desc, min index, max index),
  * pairwise prolongator of eq. (prolongation), Galerkin K_c = P^T K P
  * (eq. (galerkin_matrix_projection)), composed m times.
- * Errors: AMG_ERR_ARG (n <= 0, malformed or non-symmetric K, non-finite values,
- * missing or non-positive diagonal), AMG_ERR_NOT_SPD, AMG_ERR_STATE,
+ * Errors: AMG_ERR_ARG (n <= 0 or n >= 2^29, malformed or non-symmetric K,
+ * non-finite values, missing or non-positive diagonal), AMG_ERR_NOT_SPD, AMG_ERR_STATE,
  * AMG_ERR_OOM, AMG_ERR_HIP.  On error *out is NULL.
  */
 amg_status amg_setup(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,

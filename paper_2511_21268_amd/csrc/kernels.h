@@ -22,6 +22,9 @@
 //    col0[row], the row's first column) when every gap fits, else int32
 //    columns; padding holds value 0 and delta 0 (or the last column).
 // w_s is the longer of the row lengths or the offset list, rounded up to 8.
+// Images of matrices without shared offsets place the rows of each window of
+// 4 slices in its slots by decreasing length (SELL-C-sigma with sigma = 4C), so
+// that the slices of a window pad to similar widths; perm maps slot -> row.
 //
 // Every reduction is deterministic: fixed grid, butterfly within the wave, a
 // fixed-order sum across the block's waves, one partial per block, and a
@@ -117,36 +120,86 @@ __device__ inline void loadidx8c(const int32_t *__restrict__ c32, int64_t base, 
 template <typename VT, typename IT> struct Sell {
     int64_t nrows, ncols, nslices;
     const int64_t *soff;    // values of slice s: soff[s] .. soff[s+1]; width (soff[s+1] - soff[s]) / C
-    const int64_t *ibase;   // >= 0: start of slice s in idx; < 0: offsets at shoff[-1 - ibase[s]]
+    const int64_t *ibase;   // >= 0: start of slice s in idx; < 0: shared offsets, e = -1 - ibase[s]:
+                            // at shoff[e >> 1]; e & 1 set when every row + offset of the slice is a
+                            // valid column (no clamping needed)
     const VT *val;
     const IT *idx;          // per-row indices: 16-bit deltas or int32 columns
     const int32_t *col0;    // first column of each row (16-bit deltas)
     const int32_t *shoff;   // shared offsets, w_s per shared slice, ascending
+    const int32_t *perm;    // row of each slot (slices sorted by row length), -1 past
+                            // the last row; nullptr: slot s * C + r holds row s * C + r
+                            // (always so for shared-offset slices)
+
+    // row held by slot q, or -1
+    __device__ __forceinline__ int64_t row_of(int64_t q) const
+    {
+        return perm ? (int64_t)perm[q] : (q < nrows ? q : -1);
+    }
 };
 
 // Walk row s * C + r of slice s (s uniform across the wavefront) in groups of
 // 8 entries in ascending column order: body(v, c) gets the values and columns.
-template <int C, typename VT, typename IT, typename Body>
+// With U > 1 the loads of U groups are issued before their bodies run (more
+// loads in flight per wavefront; the bodies still run in column order).
+template <int C, int U = 1, typename VT, typename IT, typename Body>
 __device__ __forceinline__ void sell_row(const Sell<VT, IT> &A, int64_t s, int r, Body &&body)
 {
     const int64_t base = A.soff[s];
     const int width = (int)((A.soff[s + 1] - base) / C);
     const int64_t ib = A.ibase[s];
-    const int row = (int)(s * C + r);
+    const int row = (int)(s * C + r);   // shared-offset slices are never sorted
+    int kk = 0;
     if (ib < 0) {
-        const int32_t *so = A.shoff + (-1 - ib);
-        const int hi = (int)A.ncols - 1;   // columns of lanes without the entry stay in range
-        for (int kk = 0; kk < width; kk += 8) {
-            VT v[8];
-            int c[8];
-            load8c<C>(A.val, base, kk, r, v);
+        const int64_t e = -1 - ib;
+        const int32_t *so = A.shoff + (e >> 1);
+        if (e & 1) {
+            if constexpr (U > 1)
+                for (; kk + 8 * U <= width; kk += 8 * U) {
+                    VT v[U][8];
+                    int c[U][8];
 #pragma unroll
-            for (int t = 0; t < 8; t++) c[t] = min(max(row + so[kk + t], 0), hi);
-            body(v, c);
+                    for (int u = 0; u < U; u++) load8c<C>(A.val, base, kk + 8 * u, r, v[u]);
+#pragma unroll
+                    for (int u = 0; u < U; u++)
+#pragma unroll
+                        for (int t = 0; t < 8; t++) c[u][t] = row + so[kk + 8 * u + t];
+#pragma unroll
+                    for (int u = 0; u < U; u++) body(v[u], c[u]);
+                }
+            for (; kk < width; kk += 8) {
+                VT v[8];
+                int c[8];
+                load8c<C>(A.val, base, kk, r, v);
+#pragma unroll
+                for (int t = 0; t < 8; t++) c[t] = row + so[kk + t];
+                body(v, c);
+            }
+        } else {
+            const int hi = (int)A.ncols - 1;   // columns of lanes without the entry stay in range
+            for (; kk < width; kk += 8) {
+                VT v[8];
+                int c[8];
+                load8c<C>(A.val, base, kk, r, v);
+#pragma unroll
+                for (int t = 0; t < 8; t++) c[t] = min(max(row + so[kk + t], 0), hi);
+                body(v, c);
+            }
         }
     } else {
-        int col = (sizeof(IT) == 2) ? A.col0[row] : 0;
-        for (int kk = 0; kk < width; kk += 8) {
+        int col = (sizeof(IT) == 2) ? A.col0[s * C + r] : 0;   // col0 is kept per slot
+        if constexpr (U > 1)
+            for (; kk + 8 * U <= width; kk += 8 * U) {
+                VT v[U][8];
+                int c[U][8];
+#pragma unroll
+                for (int u = 0; u < U; u++) loadidx8c<C>(A.idx, ib, kk + 8 * u, r, col, c[u]);
+#pragma unroll
+                for (int u = 0; u < U; u++) load8c<C>(A.val, base, kk + 8 * u, r, v[u]);
+#pragma unroll
+                for (int u = 0; u < U; u++) body(v[u], c[u]);
+            }
+        for (; kk < width; kk += 8) {
             VT v[8];
             int c[8];
             loadidx8c<C>(A.idx, ib, kk, r, col, c);
@@ -154,6 +207,13 @@ __device__ __forceinline__ void sell_row(const Sell<VT, IT> &A, int64_t s, int r
             body(v, c);
         }
     }
+}
+
+// x[i] for 0 <= i < 2^32 / sizeof(T), addressed as a uniform base plus a
+// 32-bit byte offset (vectors of at most 2^29 FP64 entries; checked at set-up).
+template <typename T> __device__ __forceinline__ T ld32(const T *__restrict__ x, int i)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(x) + (uint32_t)i * (uint32_t)sizeof(T));
 }
 
 // wavefront index within the block, as a wave-uniform (scalar) value
@@ -171,7 +231,8 @@ __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)(th
 // (uint16_t deltas or int32_t columns).  NDOT dots are accumulated in FP64 and
 // written as one partial per block to partial[blockIdx.x * 2 + d].
 template <typename VT, typename FT, typename OT, typename IT, int EPI, int NDOT>
-__global__ __launch_bounds__(256) void k_sell(const Sell<VT, IT> A, const VT *__restrict__ x,
+// 8 wavefronts per SIMD (at most 64 VGPRs): the pass is bound by loads in flight
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sell(const Sell<VT, IT> A, const VT *__restrict__ x,
                                               const FT *__restrict__ f, const VT *__restrict__ invd,
                                               OT *__restrict__ y, const double *__restrict__ g0,
                                               const double *__restrict__ g1, double *__restrict__ partial,
@@ -183,13 +244,13 @@ __global__ __launch_bounds__(256) void k_sell(const Sell<VT, IT> A, const VT *__
     const int64_t nrows = A.nrows;
     double d0 = 0.0, d1 = 0.0;
     if (s < A.nslices) {
-        const int64_t row = s * SLICE + lane;
+        const int64_t row = A.row_of(s * SLICE + lane);
         VT acc = 0;
-        sell_row<SLICE>(A, s, lane, [&](const VT *v, const int *c) {
+        sell_row<SLICE, 2>(A, s, lane, [&](const VT *v, const int *c) {
 #pragma unroll
-            for (int t = 0; t < 8; t++) acc = fma(v[t], x[c[t]], acc);
+            for (int t = 0; t < 8; t++) acc = fma(v[t], ld32(x, c[t]), acc);
         });
-        if (row < nrows) {
+        if (row >= 0) {
             if (EPI == EPI_SPMV) {
                 y[row] = (OT)acc;
                 if (NDOT >= 1) d0 = (double)x[row] * (double)acc;
@@ -223,7 +284,7 @@ __global__ __launch_bounds__(256) void k_sell(const Sell<VT, IT> A, const VT *__
 // over the SELL image of K P (its columns are coarse indices; the gathered
 // vector is e).  Dots as EPI_SMOOTH: (y, g0), (y, g1).
 template <typename VT, typename OT, typename IT, int NDOT>
-__global__ __launch_bounds__(256) void k_sell_post(const Sell<VT, IT> A, const VT *__restrict__ e,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sell_post(const Sell<VT, IT> A, const VT *__restrict__ e,
                                                    const VT *__restrict__ u, const VT *__restrict__ r,
                                                    const VT *__restrict__ invd, const int32_t *__restrict__ agg,
                                                    const VT *__restrict__ pc, OT *__restrict__ y,
@@ -235,13 +296,13 @@ __global__ __launch_bounds__(256) void k_sell_post(const Sell<VT, IT> A, const V
     const int64_t s = (int64_t)blockIdx.x * SELL_WAVES + wid;
     double d0 = 0.0, d1 = 0.0;
     if (s < A.nslices) {
-        const int64_t row = s * SLICE + lane;
+        const int64_t row = A.row_of(s * SLICE + lane);
         VT acc = 0;
-        sell_row<SLICE>(A, s, lane, [&](const VT *v, const int *c) {
+        sell_row<SLICE, 2>(A, s, lane, [&](const VT *v, const int *c) {
 #pragma unroll
-            for (int t = 0; t < 8; t++) acc = fma(v[t], e[c[t]], acc);
+            for (int t = 0; t < 8; t++) acc = fma(v[t], ld32(e, c[t]), acc);
         });
-        if (row < A.nrows) {
+        if (row >= 0) {
             VT up = u[row] + pc[row] * e[agg[row]];
             VT out = up + invd[row] * (r[row] - acc);
             y[row] = (OT)out;

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_sell_blk(const Sell<VT, IT> A, const VT
 #pragma unroll
     for (int j = 0; j < NB; j++) { d0[j] = 0.0; d1[j] = 0.0; }
     if (s < A.nslices) {
-        const int64_t row = s * SLICE + lane;
+        const int64_t row = A.row_of(s * SLICE + lane);
         VT acc[NB];
 #pragma unroll
         for (int j = 0; j < NB; j++) acc[j] = 0;
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_sell_blk(const Sell<VT, IT> A, const VT
                 for (int j = 0; j < NB; j++) acc[j] = fma(v[t], xv[j], acc[j]);
             }
         });
-        if (row < A.nrows) {
+        if (row >= 0) {
             const int64_t o = row * NB;
             if (EPI == EPI_SPMV) {
 #pragma unroll
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(512) void k_sellb(const Sell<VT, IT> A, const VT *_
 #pragma unroll
     for (int j = 0; j < RPL; j++) { d0[j] = 0.0; d1[j] = 0.0; }
     for (int64_t s = (int64_t)blockIdx.x * nw + wid; s < A.nslices; s += (int64_t)gridDim.x * nw) {
-        const int64_t row = s * C + r;
+        const int64_t row = A.row_of(s * C + r);
         VT acc[RPL];
 #pragma unroll
         for (int j = 0; j < RPL; j++) acc[j] = 0;
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(512) void k_sellb(const Sell<VT, IT> A, const VT *_
                 for (int j = 0; j < RPL; j++) acc[j] = fma(v[t], xv[j], acc[j]);
             }
         });
-        if (row < A.nrows) {
+        if (row >= 0) {
             const int64_t o = row * NB + q * RPL;
             if (EPI == EPI_SPMV) {
 #pragma unroll
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256) void k_sell_blk_post(const Sell<VT, IT> A, con
 #pragma unroll
     for (int j = 0; j < NB; j++) { d0[j] = 0.0; d1[j] = 0.0; }
     if (s < A.nslices) {
-        const int64_t row = s * SLICE + lane;
+        const int64_t row = A.row_of(s * SLICE + lane);
         VT acc[NB];
 #pragma unroll
         for (int j = 0; j < NB; j++) acc[j] = 0;
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(256) void k_sell_blk_post(const Sell<VT, IT> A, con
                 for (int j = 0; j < NB; j++) acc[j] = fma(v[t], xv[j], acc[j]);
             }
         });
-        if (row < A.nrows) {
+        if (row >= 0) {
             const int64_t o = row * NB, a = (int64_t)agg[row] * NB;
             const VT di = invd[row], pi = pc[row];
 #pragma unroll
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(512) void k_sellb_post(const Sell<VT, IT> A, const 
 #pragma unroll
     for (int j = 0; j < RPL; j++) { d0[j] = 0.0; d1[j] = 0.0; }
     for (int64_t s = (int64_t)blockIdx.x * nw + wid; s < A.nslices; s += (int64_t)gridDim.x * nw) {
-        const int64_t row = s * C + r;
+        const int64_t row = A.row_of(s * C + r);
         VT acc[RPL];
 #pragma unroll
         for (int j = 0; j < RPL; j++) acc[j] = 0;
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(512) void k_sellb_post(const Sell<VT, IT> A, const 
                 for (int j = 0; j < RPL; j++) acc[j] = fma(v[t], xv[j], acc[j]);
             }
         });
-        if (row < A.nrows) {
+        if (row >= 0) {
             const int64_t o = row * NB + q * RPL, a = (int64_t)agg[row] * NB + q * RPL;
             const VT di = invd[row], pi = pc[row];
 #pragma unroll

@@ -12,9 +12,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -64,6 +67,8 @@ inline unsigned vgrid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::mi
 // Host-side sliced-ELL image of one level (layout described in kernels.h).
 struct SellHost {
     int64_t nslices = 0, stored = 0, nshared = 0;
+    int sorted = 0;
+    std::vector<int32_t> perm;
     double index_bytes = 0.0;   // index data a pass must read (no padding)
     int idx16 = 1;
     std::vector<int64_t> soff, ibase;
@@ -94,19 +99,56 @@ static std::vector<int32_t> slice_offsets(const CsrView &K, int64_t s, int C, in
     return u;
 }
 
+// Number of C-row slices whose offset unions would be stored once.
+static int64_t count_shared(const CsrView &K, int C)
+{
+    const int64_t ns = (K.n + C - 1) / C;
+    std::atomic<int64_t> cnt{0};
+    amgiga::parallel_for(ns, [&](int64_t sb, int64_t se) {
+        int64_t c = 0;
+        for (int64_t s = sb; s < se; s++) {
+            int64_t w = 0;
+            for (int64_t r = s * C; r < std::min(K.n, (s + 1) * C); r++) w = std::max(w, K.rp[r + 1] - K.rp[r]);
+            if (w > 0 && !slice_offsets(K, s, C, (w + 7) / 8 * 8).empty()) c++;
+        }
+        cnt += c;
+    }, 1);
+    return cnt.load();
+}
+
 // SELL-C image of a CSR matrix (slice height C rows; group layout of kernels.h).
 // With `shared`, a slice whose offset union is no wider than its longest row
 // (both rounded up to 8) stores the union once; the others keep per-row indices.
-void build_sell(const CsrView &K, int C, bool want64, bool want32, bool shared, SellHost &S)
+// With sigma > 0 (no shared offsets then), the rows of every window of sigma
+// consecutive rows are placed in the window's slots by decreasing length (ties
+// by index), so the slices of a window pad to similar lengths; perm[slot]
+// gives the row of each slot (-1 for the slots past the last row).
+void build_sell(const CsrView &K, int C, bool want64, bool want32, bool shared, int sigma, SellHost &S)
 {
     const int64_t n = K.n;
     S.nslices = (n + C - 1) / C;
+    const int64_t nslot = S.nslices * C;
+    if (sigma > 0) shared = false;
+    std::vector<int32_t> rowof(nslot, -1);
+    auto len = [&](int64_t r) { return K.rp[r + 1] - K.rp[r]; };
+    amgiga::parallel_for((n + std::max(sigma, 1) - 1) / std::max(sigma, 1), [&](int64_t wb, int64_t we) {
+        for (int64_t w = wb; w < we; w++) {
+            const int64_t a = w * std::max(sigma, 1), e = std::min(n, a + std::max(sigma, 1));
+            for (int64_t r = a; r < e; r++) rowof[r] = (int32_t)r;
+            if (sigma > 0)
+                std::stable_sort(rowof.begin() + a, rowof.begin() + e,
+                                 [&](int32_t x, int32_t y) { return len(x) > len(y); });
+        }
+    }, 1);
+    S.sorted = sigma > 0 ? 1 : 0;
+    if (S.sorted) S.perm = rowof;
     std::vector<int64_t> wd(S.nslices);
     std::vector<std::vector<int32_t>> U(S.nslices);
     amgiga::parallel_for(S.nslices, [&](int64_t sb, int64_t se) {
         for (int64_t s = sb; s < se; s++) {
             int64_t w = 0;
-            for (int64_t r = s * C; r < std::min(n, (s + 1) * C); r++) w = std::max(w, K.rp[r + 1] - K.rp[r]);
+            for (int64_t q = s * C; q < (s + 1) * C; q++)
+                if (rowof[q] >= 0) w = std::max(w, len(rowof[q]));
             wd[s] = (w + 7) / 8 * 8;
             if (shared && w > 0) U[s] = slice_offsets(K, s, C, wd[s]);
         }
@@ -116,6 +158,9 @@ void build_sell(const CsrView &K, int C, bool want64, bool want32, bool shared, 
     int64_t ib = 0, sh = 0;
     S.nshared = 0;
     S.index_bytes = 0.0;
+    // identical offset lists (the interior slices of a stencil matrix) are
+    // stored once, so the wavefronts reading them share cache lines
+    std::map<std::vector<int32_t>, int64_t> lists;
     for (int64_t s = 0; s < S.nslices; s++) {
         const int64_t w = U[s].empty() ? wd[s] : (int64_t)(U[s].size() + 7) / 8 * 8;
         S.soff[s + 1] = S.soff[s] + C * w;
@@ -123,10 +168,20 @@ void build_sell(const CsrView &K, int C, bool want64, bool want32, bool shared, 
             S.ibase[s] = ib;
             ib += C * w;
         } else {
-            S.ibase[s] = -1 - sh;
-            sh += w;
+            // every lane r of the slice (rows s*C .. s*C+C-1, padding rows
+            // included) reads column row + offset for every stored offset,
+            // the padding offsets 0 included
+            const int64_t lo = s * C + std::min<int64_t>(0, U[s].front());
+            const int64_t hi = s * C + C - 1 + std::max<int64_t>(0, U[s].back());
+            const int64_t inrange = (lo >= 0 && hi < n) ? 1 : 0;
+            auto it = lists.find(U[s]);
+            if (it == lists.end()) {
+                it = lists.emplace(U[s], sh).first;
+                sh += w;
+                S.index_bytes += 4.0 * (double)U[s].size();
+            }
+            S.ibase[s] = -1 - (2 * it->second + inrange);
             S.nshared++;
-            S.index_bytes += 4.0 * (double)U[s].size();
         }
     }
     S.stored = S.soff[S.nslices];
@@ -139,7 +194,9 @@ void build_sell(const CsrView &K, int C, bool want64, bool want32, bool shared, 
             int64_t z = 0, nr = 0;
             for (int64_t s = sb; s < se; s++) {
                 if (!U[s].empty()) continue;
-                for (int64_t r = s * C; r < std::min(n, (s + 1) * C); r++) {
+                for (int64_t q = s * C; q < (s + 1) * C; q++) {
+                    const int64_t r = rowof[q];
+                    if (r < 0) continue;
                     for (int64_t k = K.rp[r] + 1; k < K.rp[r + 1]; k++) m = std::max(m, K.ci[k] - K.ci[k - 1]);
                     z += K.rp[r + 1] - K.rp[r];
                     nr++;
@@ -164,16 +221,16 @@ void build_sell(const CsrView &K, int C, bool want64, bool want32, bool shared, 
         }
     }
     S.shoff.assign(sh, 0);
+    for (const auto &kv : lists) std::copy(kv.first.begin(), kv.first.end(), S.shoff.begin() + kv.second);
     amgiga::parallel_for(S.nslices, [&](int64_t sb, int64_t se) {
         for (int64_t s = sb; s < se; s++) {
             const int64_t base = S.soff[s];
             const int64_t w = (S.soff[s + 1] - base) / C;
             const bool sl = !U[s].empty();
-            if (sl) std::copy(U[s].begin(), U[s].end(), S.shoff.begin() + (-1 - S.ibase[s]));
             for (int lane = 0; lane < C; lane++) {
-                const int64_t r = s * C + lane;
-                const int64_t len = r < n ? K.rp[r + 1] - K.rp[r] : 0;
-                const int64_t r0 = r < n ? K.rp[r] : 0;
+                const int64_t q = s * C + lane, r = rowof[q];
+                const int64_t len = r >= 0 ? K.rp[r + 1] - K.rp[r] : 0;
+                const int64_t r0 = r >= 0 ? K.rp[r] : 0;
                 auto put = [&](int64_t k, double v) {
                     if (want64) S.v64[base + (k / 2) * 2 * C + lane * 2 + (k % 2)] = v;
                     if (want32) S.v32[base + (k / 4) * 4 * C + lane * 4 + (k % 4)] = (float)v;
@@ -185,7 +242,7 @@ void build_sell(const CsrView &K, int C, bool want64, bool want32, bool shared, 
                     continue;
                 }
                 const int64_t ibs = S.ibase[s];
-                if (S.idx16 && r < n) S.col0[r] = K.ci[r0];
+                if (S.idx16 && r >= 0) S.col0[q] = K.ci[r0];
                 for (int64_t k = 0; k < w; k++) {
                     put(k, k < len ? K.v[r0 + k] : 0.0);
                     if (S.idx16) {
@@ -204,9 +261,9 @@ void build_sell(const CsrView &K, int C, bool want64, bool want32, bool shared, 
 struct DevMat {
     int64_t n = 0, ncols = 0, nnz = 0, nslices = 0, stored = 0, nshared = 0;
     double index_bytes = 0.0;
-    int idx16 = 1, C = SLICE;
+    int idx16 = 1, C = SLICE, sorted = 0;
     int64_t *soff = nullptr, *ibase = nullptr;
-    int32_t *col0 = nullptr, *c32 = nullptr, *shoff = nullptr;
+    int32_t *col0 = nullptr, *c32 = nullptr, *shoff = nullptr, *perm = nullptr;
     uint16_t *d16 = nullptr;
     double *v64 = nullptr;
     float *v32 = nullptr;
@@ -214,7 +271,7 @@ struct DevMat {
     template <typename IT> const IT *idx() const;
     template <typename VT, typename IT> Sell<VT, IT> sv() const
     {
-        return Sell<VT, IT>{n, ncols, nslices, soff, ibase, val<VT>(), idx<IT>(), col0, shoff};
+        return Sell<VT, IT>{n, ncols, nslices, soff, ibase, val<VT>(), idx<IT>(), col0, shoff, perm};
     }
 };
 template <> const double *DevMat::val<double>() const { return v64; }
@@ -360,25 +417,36 @@ struct amg_ctx {
     }
     void release(DevMat &M)
     {
-        release(M.soff); release(M.ibase); release(M.shoff); release(M.col0); release(M.c32); release(M.d16);
+        release(M.soff); release(M.ibase); release(M.shoff); release(M.perm); release(M.col0); release(M.c32);
+        release(M.d16);
         release(M.v64); release(M.v32);
         M = DevMat();
     }
-    // SELL-C image of a square level matrix (shared offsets where they fit,
-    // if enabled), or with ncols > 0 of a rectangular one (K P: per-entry
-    // indices only; its column offsets are not shared between rows).
+    // SELL-C image of a square level matrix, or with ncols > 0 of a
+    // rectangular one (K P).  With prm.slice_offsets: a square matrix whose
+    // slices mostly share their column offsets (stencil matrices) keeps row
+    // order and stores shared offsets; every other image is sorted by row
+    // length within windows of 4 slices (the slices of one 4-wave block).
+    // Without: row order and per-entry indices everywhere.
     DevMat upload_sell(const CsrView &K, int C, bool want64, bool want32, int64_t ncols = 0)
     {
         SellHost S;
         const bool square = ncols <= 0;
-        build_sell(K, C, want64, want32, square && prm.slice_offsets != 0, S);
+        if (prm.slice_offsets == 0) {
+            build_sell(K, C, want64, want32, false, 0, S);
+        } else {
+            const int64_t ns = (K.n + C - 1) / C;
+            const bool stencil = square && 2 * count_shared(K, C) >= ns;
+            build_sell(K, C, want64, want32, stencil, stencil ? 0 : 4 * C, S);
+        }
         DevMat A;
-        A.n = K.n; A.ncols = square ? K.n : ncols;
+        A.n = K.n; A.ncols = square ? K.n : ncols; A.sorted = S.sorted;
         A.nnz = K.nnz(); A.nslices = S.nslices; A.stored = S.stored; A.idx16 = S.idx16; A.C = C;
         A.nshared = S.nshared; A.index_bytes = S.index_bytes;
         A.soff = upload(S.soff);
         A.ibase = upload(S.ibase);
         if (!S.shoff.empty()) A.shoff = upload(S.shoff);
+        if (S.sorted) A.perm = upload(S.perm);
         if (want64) A.v64 = upload(S.v64);
         if (want32) A.v32 = upload(S.v32);
         if (!S.d16.empty()) A.d16 = upload(S.d16);
@@ -1131,6 +1199,11 @@ static amg_status setup_common(int64_t n, const int64_t *row_ptr, const int32_t 
         return AMG_ERR_ARG;
     }
     if (n <= 0 || !row_ptr || !col || !val) { set_err("n <= 0 or NULL CSR array"); return AMG_ERR_ARG; }
+    if (!host_only && n >= (int64_t(1) << 29)) {
+        // vector gathers use 32-bit byte offsets
+        set_err("the device path takes at most 2^29 - 1 rows");
+        return AMG_ERR_ARG;
+    }
     CsrView K0{n, row_ptr, col, val};
     std::string err;
     if (amgiga::validate_csr(K0, err)) { set_err(err); return AMG_ERR_ARG; }

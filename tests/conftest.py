@@ -18,3 +18,40 @@ def oracle():
     import oracle as o
     o.lib()
     return o
+
+
+def _iters_match(gpu_iters, ref, tol, margin=1e-2):
+    """FP64 iteration counts against the oracle's: equal, except that the stop
+    may move by one iteration when it is marginal, i.e. when the oracle's
+    recursive relative residual at the earlier of the two counts lies within
+    `margin` (relative) of tol.  The GPU sums its dots in blocks, the oracle in
+    index order; over hundreds of CG iterations on a badly conditioned system
+    the two residual histories drift apart by up to about a percent (measured:
+    0.7% after 463 FCG(1) iterations, 3D p = 4, n = 12).  Callers then compare
+    the GPU iterate with the oracle's iterate at the same count."""
+    o = ref["iters"]
+    if gpu_iters == o:
+        return True
+    if abs(gpu_iters - o) != 1:
+        return False
+    h = ref["hist"][min(gpu_iters, o)]
+    print(f"  stop moved by one: oracle {o}, gpu {gpu_iters}, oracle relres there {h:.6e} (tol {tol:.1e})", flush=True)
+    return abs(h - tol) <= margin * tol
+
+
+@pytest.fixture(scope="session")
+def iters_match():
+    return _iters_match
+
+
+def _oracle_iterate(h, F, ref, iters, flexible=False):
+    """The oracle's iterate after `iters` iterations (ref's own solution when
+    the counts agree)."""
+    if iters == ref["iters"]:
+        return ref["u"]
+    return h.solve(F, tol=0.0, itmax=iters, flexible=flexible)["u"]
+
+
+@pytest.fixture(scope="session")
+def oracle_iterate():
+    return _oracle_iterate

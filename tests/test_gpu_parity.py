@@ -57,7 +57,7 @@ def test_vcycle_matches_oracle(oracle, amg, d, p, n):
 
 
 @pytest.mark.parametrize("d,p,n,seed", [(2, 2, 32, 0), (2, 2, 32, 1), (3, 2, 12, 0), (3, 3, 16, 2), (3, 3, 20, 3)])
-def test_pcg_parity(oracle, amg, d, p, n, seed):
+def test_pcg_parity(oracle, amg, iters_match, oracle_iterate, d, p, n, seed):
     print(f"case pcg d={d} p={p} n={n} seed={seed}", flush=True)
     from paper_2511_21268_amd.workloads import rhs_normal
     rp, ci, v, _ = oracle.poisson_kron(d, p, n)
@@ -74,8 +74,9 @@ def test_pcg_parity(oracle, amg, d, p, n, seed):
     out = ctx.solve(torch.from_numpy(F).cuda(), tol=1e-8)
     u = out["u"].cpu().numpy()
     assert out["status"] == 0 and ref["rc"] == 0
-    assert out["iters"] == ref["iters"]
-    assert np.linalg.norm(u - ref["u"]) <= 1e-10 * np.linalg.norm(ref["u"])
+    assert iters_match(out["iters"], ref, 1e-8)
+    uo = oracle_iterate(h, F, ref, out["iters"])
+    assert np.linalg.norm(u - uo) <= 1e-10 * np.linalg.norm(uo)
     assert out["relres_true"] <= 1e-8
     true = np.linalg.norm(F - _csr(rp, ci, v) @ u) / np.linalg.norm(F)
     assert true <= 1e-8
@@ -159,10 +160,13 @@ def _layout_case(oracle, case):
 
 @pytest.mark.parametrize("case", ["2d-p2", "3d-p3", "3d-kappa-p5", "permuted"])
 def test_shared_offset_slices(oracle, amg, case):
-    """Slices whose rows share one list of column offsets store it once.  The
-    extra entries this adds hold exact zeros and every row is summed in the
-    same column order, so SpMV, V-cycle, single and batched solves carry the
-    same bits as with per-entry indices; the SpMV also matches the oracle."""
+    """Slices whose rows share one list of column offsets store it once, and
+    the other images are sorted by row length within 4-slice windows.  The
+    extra entries hold exact zeros and every row is summed in the same column
+    order, so SpMV and V-cycle carry the same bits as the plain row-ordered
+    layout with per-entry indices; the SpMV also matches the oracle.  Solves
+    agree to rounding (sorted rows change the summation order of the dots
+    fused into the matrix passes), amplified by the conditioning of K."""
     print(f"case shared offsets {case}", flush=True)
     rp, ci, v = _layout_case(oracle, case)
     N = len(rp) - 1
@@ -185,18 +189,18 @@ def test_shared_offset_slices(oracle, amg, case):
     scale = _csr(rp, ci, np.abs(v)) @ np.abs(x.cpu().numpy())
     assert np.all(np.abs(ya.cpu().numpy() - ref) <= 8 * np.finfo(float).eps * scale + 1e-300)
     assert torch.equal(a.vcycle(x), b.vcycle(x))
+    rel = 1e-6 if case == "3d-kappa-p5" else 1e-12   # p = 5, variable kappa: far worse conditioned
     F = torch.from_numpy(rng.standard_normal(N)).cuda()
     sa, sb = a.solve(F), b.solve(F)
-    assert sa["iters"] == sb["iters"] and torch.equal(sa["u"], sb["u"])
+    assert sa["iters"] == sb["iters"]
+    assert torch.linalg.norm(sa["u"] - sb["u"]) <= rel * torch.linalg.norm(sb["u"])
     Fb = torch.from_numpy(rng.standard_normal((N, 3))).cuda()
     ba, bb = a.solve_batched(Fb), b.solve_batched(Fb)
-    assert ba["iters"] == bb["iters"] and torch.equal(ba["U"], bb["U"])
+    assert ba["iters"] == bb["iters"]
+    assert torch.linalg.norm(ba["U"] - bb["U"]) <= rel * torch.linalg.norm(bb["U"])
     if case in ("3d-p3", "3d-kappa-p5"):
         # the autotuned block images (64 / lanes-per-row rows per slice); with
-        # several lanes per row the dots are summed in another order, so the
-        # solutions agree to rounding amplified by the conditioning of K (the
-        # p = 5 variable-coefficient matrix is far worse conditioned)
-        rel = 1e-12 if case == "3d-p3" else 1e-6
+        # several lanes per row the dots are summed in another order too
         t = amg.Context(rp, ci, v, slice_offsets=1, nrhs=16)
         lpr, _ = t.batched_variant()
         print(f"  block variant lpr={lpr}", flush=True)
