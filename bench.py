@@ -86,6 +86,7 @@ def main():
                          "learned: FP64 PCG with the MLP-predicted degree-4 polynomial smoothers")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--itmax", type=int, default=0, help="iteration limit (0: the workload's, else 1000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -135,7 +136,8 @@ def main():
         F = torch.from_numpy(rhs_block(N, range(args.seed, args.seed + nrhs))).cuda()
     torch.cuda.synchronize()
     t = time.time()
-    kw = {"fp64": {}, "learned": {"smoother": 1}}.get(args.mode, {"vcycle_fp32": 1, "krylov": 1})
+    kw = dict({"fp64": {}, "learned": {"smoother": 1}}.get(args.mode, {"vcycle_fp32": 1, "krylov": 1}))
+    kw["itmax"] = args.itmax or cfg.get("itmax", 1000)
     if nrhs > 1:
         kw["nrhs"] = nrhs
     ctx = amg.Context(rp, ci, v, **kw)

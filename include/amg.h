@@ -254,10 +254,12 @@ amg_status amg_iga_poisson(int d, int p, int n, int64_t *row_ptr, int32_t *col, 
 #define AMG_MLP_NACT 128     /* stored activations per sample (h1, h2)        */
 #define AMG_MLP_NDEL 132     /* stored deltas per sample (dy, dh2, dh1)        */
 
-/* Features of level `level` (host output, AMG_MLP_NFEAT floats):
- * log10(n)/7, (nnz/n)/1000, mean and min over rows of k_ii/d_i (d = l1 diagonal),
- * mean of sum_{j!=i} k_ij / d_i, fraction of positive off-diagonal entries,
- * level / (levels-1), n_{level+1}/n_level (0 on the coarsest). */
+/* Features of level `level` (host output, AMG_MLP_NFEAT floats), all
+ * independent of the problem size: log10(nnz/n)/3, (longest row)/(nnz/n) - 1,
+ * mean and min over rows of k_ii/d_i (d = l1 diagonal), mean of
+ * sum_{j!=i} k_ij / d_i, fraction of positive off-diagonal entries,
+ * log10((nnz/n) / (nnz_0/n_0))/2 (row density against the finest level),
+ * n_{level+1}/n_level (0 on the coarsest). */
 amg_status amg_level_features(const amg_ctx *c, int level, float *feat);
 
 /* Y[B][4] = MLP(X[B][8]) with BF16 weights w; act (may be NULL) receives the

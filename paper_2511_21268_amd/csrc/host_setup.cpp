@@ -337,9 +337,10 @@ static void l1_invdiag(const CsrView &K, std::vector<double> &invd)
 void level_features(const CsrView &K, const std::vector<double> &invd, float out[6])
 {
     double s_diag = 0.0, min_diag = 1.0, s_off = 0.0;
-    int64_t npos = 0, noff = 0;
+    int64_t npos = 0, noff = 0, maxlen = 0;
     for (int64_t i = 0; i < K.n; i++) {
         double kii = 0.0, off = 0.0;
+        maxlen = std::max<int64_t>(maxlen, K.rp[i + 1] - K.rp[i]);
         for (int64_t k = K.rp[i]; k < K.rp[i + 1]; k++) {
             if (K.ci[k] == i) kii = K.v[k];
             else {
@@ -353,8 +354,10 @@ void level_features(const CsrView &K, const std::vector<double> &invd, float out
         min_diag = std::min(min_diag, r);
         s_off += off * invd[i];
     }
-    out[0] = (float)(std::log10((double)K.n) / 7.0);
-    out[1] = (float)((double)K.nnz() / (double)K.n / 1000.0);
+    // every feature is independent of the problem size
+    const double mean_len = (double)K.nnz() / (double)K.n;
+    out[0] = (float)(std::log10(mean_len) / 3.0);
+    out[1] = (float)((double)maxlen / mean_len - 1.0);
     out[2] = (float)(s_diag / (double)K.n);
     out[3] = (float)min_diag;
     out[4] = (float)(s_off / (double)K.n);

@@ -1685,7 +1685,9 @@ amg_status amg_level_features(const amg_ctx *c, int level, float *feat)
     if (!c || !feat || level < 0 || level >= c->nlev) { set_err("bad level or NULL"); return AMG_ERR_ARG; }
     const auto &L = c->host.lev[level];
     for (int k = 0; k < 6; k++) feat[k] = L.feat[k];
-    feat[6] = c->nlev > 1 ? (float)level / (float)(c->nlev - 1) : 0.0f;
+    const auto &L0 = c->host.lev[0];
+    const double dens = ((double)L.nnz / (double)L.n) / ((double)L0.nnz / (double)L0.n);
+    feat[6] = (float)(std::log10(dens) / 2.0);
     feat[7] = level + 1 < c->nlev ? (float)((double)c->host.lev[level + 1].n / (double)L.n) : 0.0f;
     return AMG_OK;
 }

@@ -42,8 +42,8 @@ WEIGHTS = os.path.join(HERE, "learned_poly4.npz")
 NODES = 0.5 * (1.0 - np.cos(np.arange(1, 5) * np.pi / 4.0))
 GRID = [0.5, 0.3, 0.15, 0.08, 0.04, 0.02, 0.01, 0.005]
 # training problems: (p, n, kappa seed); seeds >= 100 are never used for evaluation
-TRAIN = [(p, n, 100 + 10 * p + k) for p, ns in [(2, (16, 24, 40)), (3, (16, 24, 32)), (4, (12, 16, 24)),
-                                                 (5, (10, 14, 18))] for k, n in enumerate(ns)]
+TRAIN = [(p, n, 100 + 10 * p + k) for p, ns in [(2, (16, 24, 40, 48)), (3, (16, 24, 32, 48)), (4, (12, 16, 24, 32)),
+                                                 (5, (10, 14, 18, 24))] for k, n in enumerate(ns)]
 
 
 def cheb_coeffs(a):

@@ -14,7 +14,7 @@ CONFIGS = {
     "c2": dict(d=3, p=3, n=64, kind="poisson"),     # N = 65^3   = 274,625
     "c3": dict(d=3, p=4, n=96, kind="poisson"),     # N = 98^3   = 941,192
     "c4": dict(d=3, p=3, n=128, kind="poisson"),    # N = 129^3  = 2,146,689
-    "c5": dict(d=3, p=5, n=64, kind="diffusion"),   # N = 67^3   = 300,763
+    "c5": dict(d=3, p=5, n=64, kind="diffusion", itmax=6000),   # N = 67^3 = 300,763; plain l1: ~3000 iterations
 }
 
 
