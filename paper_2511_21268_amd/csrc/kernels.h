@@ -26,9 +26,10 @@
 // 4 slices in its slots by decreasing length (SELL-C-sigma with sigma = 4C), so
 // that the slices of a window pad to similar widths; perm maps slot -> row.
 //
-// Every reduction is deterministic: fixed grid, butterfly within the wave, a
-// fixed-order sum across the block's waves, one partial per block, and a
-// single-block final sum in index order.  No floating-point atomics.
+// Every reduction is deterministic: fixed grid, butterfly within the wave, one
+// partial per wavefront (matrix passes) or a fixed-order sum across the block's
+// waves and one partial per block (vector kernels), and a single-block final
+// sum in index order.  No floating-point atomics.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -69,6 +70,24 @@ __device__ inline double block_sum(double v, double *lds)
     if (threadIdx.x == 0) s = ((lds[0] + lds[1]) + lds[2]) + lds[3];
     return s;
 }
+
+// Sum of one value per thread over a block of NW wavefronts: butterfly within
+// each wave, then the waves' sums in index order; valid in thread 0.
+template <int NW> __device__ inline double block_sum_n(double v, double *lds /* NW */)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NW; w++) s += lds[w];
+    return s;
+}
+
+// threads of the single-block final reductions (k_finalize, k_bfinalize)
+constexpr int FIN_THREADS = 1024;
 
 // ---- loads of 8 consecutive entries (k .. k+7) of lane r of a C-row slice ----
 
@@ -238,7 +257,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
                                               const double *__restrict__ g1, double *__restrict__ partial,
                                               VT coef)
 {
-    __shared__ double lds[8];
     const int lane = threadIdx.x & 63, wid = wave_id();
     const int64_t s = (int64_t)blockIdx.x * SELL_WAVES + wid;
     const int64_t nrows = A.nrows;
@@ -246,7 +264,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     if (s < A.nslices) {
         const int64_t row = A.row_of(s * SLICE + lane);
         VT acc = 0;
-        sell_row<SLICE, 2>(A, s, lane, [&](const VT *v, const int *c) {
+        // unroll 2 where the compiler keeps all gathers in flight within 64
+        // VGPRs; the SpMV with fused dots keeps one group per step
+        sell_row<SLICE, NDOT == 0 ? 2 : 1>(A, s, lane, [&](const VT *v, const int *c) {
 #pragma unroll
             for (int t = 0; t < 8; t++) acc = fma(v[t], ld32(x, c[t]), acc);
         });
@@ -269,11 +289,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         }
     }
     if (NDOT >= 1) {
-        double t0 = block_sum(d0, lds);
-        double t1 = NDOT >= 2 ? block_sum(d1, lds + 4) : 0.0;
-        if (threadIdx.x == 0) {
-            partial[2 * blockIdx.x] = t0;
-            partial[2 * blockIdx.x + 1] = t1;
+        // one partial per wavefront (no barrier: the waves of a block may end apart)
+        double t0 = wave_sum(d0);
+        double t1 = NDOT >= 2 ? wave_sum(d1) : 0.0;
+        if (lane == 0) {
+            const int64_t w = (int64_t)blockIdx.x * SELL_WAVES + wid;
+            partial[2 * w] = t0;
+            partial[2 * w + 1] = t1;
         }
     }
 }
@@ -291,7 +313,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
                                                    const double *__restrict__ g0, const double *__restrict__ g1,
                                                    double *__restrict__ partial)
 {
-    __shared__ double lds[8];
     const int lane = threadIdx.x & 63, wid = wave_id();
     const int64_t s = (int64_t)blockIdx.x * SELL_WAVES + wid;
     double d0 = 0.0, d1 = 0.0;
@@ -311,11 +332,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         }
     }
     if (NDOT >= 1) {
-        double t0 = block_sum(d0, lds);
-        double t1 = NDOT >= 2 ? block_sum(d1, lds + 4) : 0.0;
-        if (threadIdx.x == 0) {
-            partial[2 * blockIdx.x] = t0;
-            partial[2 * blockIdx.x + 1] = t1;
+        // one partial per wavefront (no barrier: the waves of a block may end apart)
+        double t0 = wave_sum(d0);
+        double t1 = NDOT >= 2 ? wave_sum(d1) : 0.0;
+        if (lane == 0) {
+            const int64_t w = (int64_t)blockIdx.x * SELL_WAVES + wid;
+            partial[2 * w] = t0;
+            partial[2 * w + 1] = t1;
         }
     }
 }
@@ -384,7 +407,11 @@ __global__ void k_prolong(int64_t n, const int32_t *__restrict__ agg, const VT *
 
 // Coarsest level: e = L^{-T} (L^{-1} f) with the precomputed inverse Cholesky
 // factor (row-major, leading dimension ld) and its transpose; FP64 arithmetic
-// whatever the level type.  One 256-thread block, n <= 2048.
+// whatever the level type.  One 256-thread block, n <= 2048, one thread per
+// output row: y_i = sum_{k<=i} L^{-1}_ik f_k reads column i of L^{-T} (row k of
+// LinvT), x_j = sum_{k>=j} L^{-1}_kj y_k reads column j of L^{-1}, so the
+// threads of a wave load consecutive addresses and every load is independent
+// of the running sum; k ascending.
 template <typename VT>
 __global__ __launch_bounds__(256) void k_coarse_solve(int n, int ld, const double *__restrict__ Linv,
                                                       const double *__restrict__ LinvT, const VT *__restrict__ f,
@@ -392,23 +419,20 @@ __global__ __launch_bounds__(256) void k_coarse_solve(int n, int ld, const doubl
 {
     __shared__ double fs[2048];
     __shared__ double ys[2048];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < n; i += 256) fs[i] = (double)f[i];
     __syncthreads();
-    for (int i = wid; i < n; i += 4) {
-        const double *row = Linv + (int64_t)i * ld;
+    for (int i = threadIdx.x; i < n; i += 256) {
         double s = 0.0;
-        for (int k = lane; k <= i; k += 64) s = fma(row[k], fs[k], s);
-        s = wave_sum(s);
-        if (lane == 0) ys[i] = s;
+#pragma unroll 8
+        for (int k = 0; k <= i; k++) s = fma(LinvT[(int64_t)k * ld + i], fs[k], s);
+        ys[i] = s;
     }
     __syncthreads();
-    for (int j = wid; j < n; j += 4) {
-        const double *row = LinvT + (int64_t)j * ld;
+    for (int j = threadIdx.x; j < n; j += 256) {
         double s = 0.0;
-        for (int k = j + lane; k < n; k += 64) s = fma(row[k], ys[k], s);
-        s = wave_sum(s);
-        if (lane == 0) e[j] = (VT)s;
+#pragma unroll 8
+        for (int k = j; k < n; k++) s = fma(Linv[(int64_t)k * ld + j], ys[k], s);
+        e[j] = (VT)s;
     }
 }
 
@@ -473,13 +497,13 @@ __global__ void k_fill(int64_t n, T v, T *__restrict__ d)
 
 // Final sum of the block partials (two dots) in index order, then the scalar
 // recurrences of CG / FCG(1) on the device.
-__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partial, int nblk, double *sc,
-                                                   int op, int slot)
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize(const double *__restrict__ partial, int nblk, double *sc,
+                                                           int op, int slot)
 {
-    __shared__ double lds[8];
+    __shared__ double lds[2 * FIN_THREADS / 64];
     double s0 = 0.0, s1 = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) { s0 += partial[2 * b]; s1 += partial[2 * b + 1]; }
-    double t0 = block_sum(s0, lds), t1 = block_sum(s1, lds + 4);
+    for (int b = threadIdx.x; b < nblk; b += FIN_THREADS) { s0 += partial[2 * b]; s1 += partial[2 * b + 1]; }
+    double t0 = block_sum_n<FIN_THREADS / 64>(s0, lds), t1 = block_sum_n<FIN_THREADS / 64>(s1, lds + FIN_THREADS / 64);
     if (threadIdx.x != 0) return;
     switch (op) {
     case FIN_STORE:

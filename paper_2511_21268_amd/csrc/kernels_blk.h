@@ -125,14 +125,17 @@ __global__ __launch_bounds__(256) void k_sell_blk(const Sell<VT, IT> A, const VT
         }
     }
     if (NDOT >= 1) {
-        block_sum_cols<NB>(d0, lds);
-        if (NDOT >= 2) block_sum_cols<NB>(d1, lds + 4 * NB);
-        if (threadIdx.x == 0)
+        // one partial per wavefront and column, as the single-vector kernels
+        const int64_t w = (int64_t)blockIdx.x * SELL_WAVES + wid;
 #pragma unroll
-            for (int j = 0; j < NB; j++) {
-                partial[(2 * blockIdx.x) * NB + j] = d0[j];
-                partial[(2 * blockIdx.x + 1) * NB + j] = NDOT >= 2 ? d1[j] : 0.0;
+        for (int j = 0; j < NB; j++) {
+            const double t0 = wave_sum(d0[j]);
+            const double t1 = NDOT >= 2 ? wave_sum(d1[j]) : 0.0;
+            if (lane == 0) {
+                partial[(2 * w) * NB + j] = t0;
+                partial[(2 * w + 1) * NB + j] = t1;
             }
+        }
     }
 }
 
@@ -298,14 +301,17 @@ __global__ __launch_bounds__(256) void k_sell_blk_post(const Sell<VT, IT> A, con
         }
     }
     if (NDOT >= 1) {
-        block_sum_cols<NB>(d0, lds);
-        if (NDOT >= 2) block_sum_cols<NB>(d1, lds + 4 * NB);
-        if (threadIdx.x == 0)
+        // one partial per wavefront and column, as the single-vector kernels
+        const int64_t w = (int64_t)blockIdx.x * SELL_WAVES + wid;
 #pragma unroll
-            for (int j = 0; j < NB; j++) {
-                partial[(2 * blockIdx.x) * NB + j] = d0[j];
-                partial[(2 * blockIdx.x + 1) * NB + j] = NDOT >= 2 ? d1[j] : 0.0;
+        for (int j = 0; j < NB; j++) {
+            const double t0 = wave_sum(d0[j]);
+            const double t1 = NDOT >= 2 ? wave_sum(d1[j]) : 0.0;
+            if (lane == 0) {
+                partial[(2 * w) * NB + j] = t0;
+                partial[(2 * w + 1) * NB + j] = t1;
             }
+        }
     }
 }
 
@@ -444,32 +450,28 @@ __global__ void k_add_blk(int64_t n, const VT *__restrict__ x, const VT *__restr
     y[i] = (OT)(x[i] + c[i]);
 }
 
-// Coarsest level, 16 columns: E = L^{-T} (L^{-1} F) in FP64, one block; Y is a
-// global scratch of n * NB doubles.  Per column the same sums as k_coarse_solve.
+// Coarsest level for 16 columns: thread (row slot r = t / 16, column j = t % 16)
+// computes rows r, r + 16, ... of column j with the single-vector kernel's
+// summation order (k ascending), so each column equals k_coarse_solve's result.
+// Y: global scratch (n x 16).
 template <typename VT>
 __global__ __launch_bounds__(256) void k_coarse_solve_blk(int n, int ld, const double *__restrict__ Linv,
                                                           const double *__restrict__ LinvT, const VT *__restrict__ f,
                                                           double *__restrict__ Y, VT *__restrict__ e)
 {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int i = wid; i < n; i += 4) {
-        const double *row = Linv + (int64_t)i * ld;
-        for (int j = 0; j < NB; j++) {
-            double s = 0.0;
-            for (int k = lane; k <= i; k += 64) s = fma(row[k], (double)f[(int64_t)k * NB + j], s);
-            s = wave_sum(s);
-            if (lane == 0) Y[(int64_t)i * NB + j] = s;
-        }
+    const int j = threadIdx.x & (NB - 1), r = threadIdx.x / NB;
+    for (int i = r; i < n; i += 256 / NB) {
+        double s = 0.0;
+#pragma unroll 8
+        for (int k = 0; k <= i; k++) s = fma(LinvT[(int64_t)k * ld + i], (double)f[(int64_t)k * NB + j], s);
+        Y[(int64_t)i * NB + j] = s;
     }
     __syncthreads();
-    for (int jr = wid; jr < n; jr += 4) {
-        const double *row = LinvT + (int64_t)jr * ld;
-        for (int j = 0; j < NB; j++) {
-            double s = 0.0;
-            for (int k = jr + lane; k < n; k += 64) s = fma(row[k], Y[(int64_t)k * NB + j], s);
-            s = wave_sum(s);
-            if (lane == 0) e[(int64_t)jr * NB + j] = (VT)s;
-        }
+    for (int i = r; i < n; i += 256 / NB) {
+        double s = 0.0;
+#pragma unroll 8
+        for (int k = i; k < n; k++) s = fma(Linv[(int64_t)k * ld + i], Y[(int64_t)k * NB + j], s);
+        e[(int64_t)i * NB + j] = (VT)s;
     }
 }
 
@@ -557,19 +559,33 @@ __global__ void k_bcg_pupdate(int64_t n, const double *__restrict__ sc, const do
 
 // Final per-column sums of the partials (index order) and the scalar
 // recurrences, masks and iteration counters of the 16 independent solves.
-__global__ __launch_bounds__(256) void k_bfinalize(const double *__restrict__ partial, int nblk, double *sc,
-                                                   int op, double tol)
+__global__ __launch_bounds__(FIN_THREADS) void k_bfinalize(const double *__restrict__ partial, int nblk, double *sc,
+                                                           int op, double tol)
 {
-    __shared__ double lds[8 * NB];
+    // per column the order of k_finalize: thread strides, butterfly, waves in order
+    constexpr int NW = FIN_THREADS / 64;
+    __shared__ double lds[2 * NW * NB];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     double s0[NB], s1[NB];
 #pragma unroll
     for (int j = 0; j < NB; j++) { s0[j] = 0.0; s1[j] = 0.0; }
-    for (int b = threadIdx.x; b < nblk; b += 256)
+    for (int b = threadIdx.x; b < nblk; b += FIN_THREADS)
 #pragma unroll
         for (int j = 0; j < NB; j++) { s0[j] += partial[(2 * b) * NB + j]; s1[j] += partial[(2 * b + 1) * NB + j]; }
-    block_sum_cols<NB>(s0, lds);
-    block_sum_cols<NB>(s1, lds + 4 * NB);
+#pragma unroll
+    for (int j = 0; j < NB; j++) { s0[j] = wave_sum(s0[j]); s1[j] = wave_sum(s1[j]); }
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < NB; j++) { lds[wid * NB + j] = s0[j]; lds[(NW + wid) * NB + j] = s1[j]; }
+    __syncthreads();
     if (threadIdx.x != 0) return;
+#pragma unroll
+    for (int j = 0; j < NB; j++) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < NW; w++) { a += lds[w * NB + j]; b += lds[(NW + w) * NB + j]; }
+        s0[j] = a;
+        s1[j] = b;
+    }
     for (int j = 0; j < NB; j++) {
         const double a = s0[j], b = s1[j];
         double *F = sc + B_FLAG * NB + j, *D = sc + B_DONE * NB + j;

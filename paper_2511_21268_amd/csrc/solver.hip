@@ -650,11 +650,11 @@ struct amg_ctx {
                            (double)sizeof(OT) * A.n + 8.0 * A.n * ndot;              // y, dot partners
             prof_end(bytes);
         }
-        return nb;
+        return nb * SELL_WAVES;   // one dot partial per wavefront
     }
     void finalize(unsigned nblk, int op, int slot = 0)
     {
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, stream, partial, (int)nblk, sc, op, slot);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, stream, partial, (int)nblk, sc, op, slot);
         HIPCHK(hipGetLastError());
     }
     unsigned dot_partials(int64_t m, const double *a, const double *b, const double *c)
@@ -687,7 +687,7 @@ struct amg_ctx {
             if (ndot == 2) sell<VT, FT, OT, EPI_SMOOTH, 2>(l, uin, f, L.invd<VT>(), uout, g0, g1);
             else if (ndot == 1) sell<VT, FT, OT, EPI_SMOOTH, 1>(l, uin, f, L.invd<VT>(), uout, g0, g1);
             else sell<VT, FT, OT, EPI_SMOOTH, 0>(l, uin, f, L.invd<VT>(), uout, g0, g1);
-            if (ndot) vc_nb = sell_blocks(l);
+            if (ndot) vc_nb = sell_blocks(l) * SELL_WAVES;
             return;
         }
         VT *res = (VT *)L.r, *c = (VT *)L.c, *c2 = (VT *)L.c2;
@@ -868,12 +868,13 @@ struct amg_ctx {
             nb = blk_lpr == 4 ? launch_sellb<VT, FT, OT, EPI, NDOT, 4>(B, x, f, invd, y, g0, g1, coef)
                               : launch_sellb<VT, FT, OT, EPI, NDOT, 16>(B, x, f, invd, y, g0, g1, coef);
         } else {
-            nb = sell_blocks(l);
+            const unsigned grid = sell_blocks(l);
+            nb = grid * SELL_WAVES;   // dot partials: one per wavefront
             if (A.idx16)
-                hipLaunchKernelGGL((k_sell_blk<VT, FT, OT, uint16_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream,
+                hipLaunchKernelGGL((k_sell_blk<VT, FT, OT, uint16_t, EPI, NDOT>), dim3(grid), dim3(256), 0, stream,
                                    A.sv<VT, uint16_t>(), x, f, invd, y, g0, g1, bpartial, coef);
             else
-                hipLaunchKernelGGL((k_sell_blk<VT, FT, OT, int32_t, EPI, NDOT>), dim3(nb), dim3(256), 0, stream,
+                hipLaunchKernelGGL((k_sell_blk<VT, FT, OT, int32_t, EPI, NDOT>), dim3(grid), dim3(256), 0, stream,
                                    A.sv<VT, int32_t>(), x, f, invd, y, g0, g1, bpartial, coef);
         }
         HIPCHK(hipGetLastError());
@@ -890,7 +891,7 @@ struct amg_ctx {
     }
     void bfinalize(unsigned nblk, int op, double tol = 0.0)
     {
-        hipLaunchKernelGGL(k_bfinalize, dim3(1), dim3(256), 0, stream, bpartial, (int)nblk, bsc, op, tol);
+        hipLaunchKernelGGL(k_bfinalize, dim3(1), dim3(FIN_THREADS), 0, stream, bpartial, (int)nblk, bsc, op, tol);
         HIPCHK(hipGetLastError());
     }
     unsigned bdot_partials(int64_t m, const double *a, const double *b, const double *c)
@@ -937,7 +938,7 @@ struct amg_ctx {
                            8.0 * NB * A.n * ndot;
             prof_end(bytes);
         }
-        return nb;
+        return multi ? nb : nb * SELL_WAVES;   // one-lane kernel: a dot partial per wavefront
     }
     template <typename VT, typename FT> VT *bpoly_apply(int l, const FT *rr, VT *&c, VT *&c2)
     {
@@ -1149,7 +1150,7 @@ static amg_status build_device(amg_ctx *c, const CsrView &K0)
     c->z = c->alloc<double>(c->n);
     c->p = c->alloc<double>(c->n);
     c->q = c->alloc<double>(c->n);
-    c->partial_cap = 2 * std::max<int64_t>(4096, c->sell_blocks(0));
+    c->partial_cap = 2 * std::max<int64_t>(4096, SELL_WAVES * c->sell_blocks(0));
     c->partial = c->alloc<double>(c->partial_cap);
     c->sc = c->alloc<double>(S_NSLOTS);
     HIPCHK(hipHostMalloc((void **)&c->hsc, S_NSLOTS * sizeof(double), hipHostMallocDefault));
@@ -1311,7 +1312,7 @@ static amg_status solve_impl(amg_ctx *c, const double *F, double *u_user, double
     auto partA = [&]() {
         if (flex) c->sell<double, double, double, EPI_SPMV, 2>(0, c->p, nullptr, nullptr, c->q, nullptr, c->r);
         else c->sell<double, double, double, EPI_SPMV, 1>(0, c->p, nullptr, nullptr, c->q, nullptr, nullptr);
-        c->finalize(c->sell_blocks(0), flex ? FIN_PQ_FCG : FIN_PQ_CG);
+        c->finalize(c->sell_blocks(0) * SELL_WAVES, flex ? FIN_PQ_FCG : FIN_PQ_CG);
         unsigned g = vgrid(n);
         hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(256), 0, c->stream, n, c->sc, u, c->r, c->p, c->q, c->partial);
         HIPCHK(hipGetLastError());

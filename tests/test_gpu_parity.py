@@ -170,8 +170,8 @@ def test_shared_offset_slices(oracle, amg, case):
     print(f"case shared offsets {case}", flush=True)
     rp, ci, v = _layout_case(oracle, case)
     N = len(rp) - 1
-    a = amg.Context(rp, ci, v, slice_offsets=1)
-    b = amg.Context(rp, ci, v, slice_offsets=0)
+    a = amg.Context(rp, ci, v, slice_offsets=1, itmax=6000)
+    b = amg.Context(rp, ci, v, slice_offsets=0, itmax=6000)
     fa, fb = a.format(0), b.format(0)
     nsl = (N + 63) // 64
     print(f"  N={N} shared slices {fa['shared_slices']} of {nsl}", flush=True)
@@ -189,24 +189,39 @@ def test_shared_offset_slices(oracle, amg, case):
     scale = _csr(rp, ci, np.abs(v)) @ np.abs(x.cpu().numpy())
     assert np.all(np.abs(ya.cpu().numpy() - ref) <= 8 * np.finfo(float).eps * scale + 1e-300)
     assert torch.equal(a.vcycle(x), b.vcycle(x))
-    rel = 1e-6 if case == "3d-kappa-p5" else 1e-12   # p = 5, variable kappa: far worse conditioned
+    K = _csr(rp, ci, v)
+
+    def close(ua, ub, Fv):
+        # Poisson: the solutions agree to 1e-12.  p = 5 with variable kappa is
+        # far worse conditioned: there the guarantee is in the residual norm,
+        # both solves ending at ||F - K u|| <= 1e-8 ||F||
+        ua, ub, Fv = ua.cpu().numpy(), ub.cpu().numpy(), Fv.cpu().numpy()
+        if case != "3d-kappa-p5":
+            return np.linalg.norm(ua - ub) <= 1e-12 * np.linalg.norm(ub)
+        return np.linalg.norm(K @ (ua - ub)) <= 2.5e-8 * np.linalg.norm(Fv)
+
+    def same_iters(ia, ib):
+        # ~2000 CG iterations on the p = 5 matrix: rounding moves the stop by a few
+        return ia == ib if case != "3d-kappa-p5" else abs(ia - ib) <= max(2, 0.005 * ib)
+
     F = torch.from_numpy(rng.standard_normal(N)).cuda()
     sa, sb = a.solve(F), b.solve(F)
-    assert sa["iters"] == sb["iters"]
-    assert torch.linalg.norm(sa["u"] - sb["u"]) <= rel * torch.linalg.norm(sb["u"])
+    assert sa["status"] == 0 and sb["status"] == 0
+    assert same_iters(sa["iters"], sb["iters"]) and close(sa["u"], sb["u"], F)
     Fb = torch.from_numpy(rng.standard_normal((N, 3))).cuda()
     ba, bb = a.solve_batched(Fb), b.solve_batched(Fb)
-    assert ba["iters"] == bb["iters"]
-    assert torch.linalg.norm(ba["U"] - bb["U"]) <= rel * torch.linalg.norm(bb["U"])
+    assert ba["status"] == 0 and bb["status"] == 0
+    assert all(same_iters(x, y) for x, y in zip(ba["iters"], bb["iters"]))
+    assert all(close(ba["U"][:, j], bb["U"][:, j], Fb[:, j]) for j in range(3))
     if case in ("3d-p3", "3d-kappa-p5"):
         # the autotuned block images (64 / lanes-per-row rows per slice); with
         # several lanes per row the dots are summed in another order too
-        t = amg.Context(rp, ci, v, slice_offsets=1, nrhs=16)
+        t = amg.Context(rp, ci, v, slice_offsets=1, nrhs=16, itmax=6000)
         lpr, _ = t.batched_variant()
         print(f"  block variant lpr={lpr}", flush=True)
         for thr in ((256, 512) if lpr > 1 else (256,)):
             t.set_batched_variant(lpr, thr)
             bt = t.solve_batched(Fb)
-            assert bt["iters"] == bb["iters"], (lpr, thr)
-            assert torch.linalg.norm(bt["U"] - bb["U"]) <= rel * torch.linalg.norm(bb["U"]), (lpr, thr)
+            assert bt["status"] == 0 and all(same_iters(x, y) for x, y in zip(bt["iters"], bb["iters"])), (lpr, thr)
+            assert all(close(bt["U"][:, j], bb["U"][:, j], Fb[:, j]) for j in range(3)), (lpr, thr)
         t.close()

@@ -13,3 +13,12 @@ def test_iteration_rule(iters_match):
     ref2 = {"iters": 3, "hist": np.array([1.0, 1e-4, 3e-8, 0.99999e-8])}
     assert iters_match(4, ref2, 1e-8)           # gpu stopped one later at a marginal crossing
     assert not iters_match(2, ref2, 1e-8)       # relres 3e-8 at 2 is far from tol
+
+
+def test_long_run_rule(iters_match):
+    hist = np.linspace(1.0, 0.5e-8, 464)
+    ref = {"iters": 463, "hist": hist}
+    assert iters_match(465, ref, 1e-8) and iters_match(458, ref, 1e-8)
+    assert not iters_match(469, ref, 1e-8)
+    short = {"iters": 100, "hist": np.linspace(1.0, 0.5e-8, 101)}
+    assert not iters_match(102, short, 1e-8)
