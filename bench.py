@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # SHA-256 of the kernel source they were taken with: reported only while the
 # kernel is unchanged (profiles/k_sell_c4_fp64_pmc.md).
 MEASURED_TRAFFIC = {
-    ("c4", "41a709e576a6383443e4a46a91471ca838906da8fb51840a2462797ed48555fc"): 7388779616,
+    ("c4", "1cd4e7093d1885fff0ea5082c1876176913a6b9f7a5cef1e9b829ab74aecb8a2"): 5067483357,
 }
 
 
@@ -38,6 +38,23 @@ def kernel_source_sha():
     import hashlib
     with open(os.path.join(ROOT, "paper_2511_21268_amd", "csrc", "kernels.h"), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """GB/s of a device-to-device copy (bytes read + bytes written per second)."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
 
 
 def log(msg):
@@ -200,6 +217,11 @@ def main():
                           "k_sell_blk (level-0 16-column SpMV / residual / smoother pass)",
                 "launches": prof["launches"], "avg_launch_ms": round(kernel_ms, 4),
                 "bytes_per_launch": round(prof["bytes"] / max(prof["launches"], 1))}
+
+    # a plain device copy of 1 GiB (read + write) timed on the same GPU, as the
+    # attainable streaming bandwidth beside the nominal 8 TB/s
+    roofline["copy_gbs"] = round(copy_bandwidth(torch), 1)
+    roofline["frac_of_copy"] = round(achieved / roofline["copy_gbs"], 4) if roofline["copy_gbs"] > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline and args.mode == "fp64":
