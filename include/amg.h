@@ -140,10 +140,10 @@ amg_status amg_spmv(amg_ctx *c, int level, const double *x, double *y);
 /*
  * Variant of the block kernels used by pcg_solve_batched: lpr lanes per matrix
  * row (1: the single-vector SELL-64 image, one lane per row and 16 columns per
- * lane; 4 or 16: the SELL-(64/lpr) block image, 16/lpr columns per lane) and
- * threads per block (256 or 512).  amg_setup with prm.nrhs > 1 sets the fastest
- * by timing; amg_set_batched_variant overrides it (lpr 4/16 only when that
- * image was built, i.e. the autotuner's choice).
+ * lane; 4, 8 or 16: the SELL-(64/lpr) block image, 16/lpr columns per lane)
+ * and threads per block (256 or 512).  amg_setup with prm.nrhs > 1 sets the
+ * fastest by timing; amg_set_batched_variant overrides it (lpr 4/8/16 only when
+ * that image was built, i.e. the autotuner's choice).
  */
 amg_status amg_get_batched_variant(const amg_ctx *c, int *lpr, int *threads);
 amg_status amg_set_batched_variant(amg_ctx *c, int lpr, int threads);

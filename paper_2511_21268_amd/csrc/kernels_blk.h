@@ -5,9 +5,11 @@
 // The matrix is the same SELL-64 image as the single-vector kernels (layout in
 // kernels.h).  A wavefront covers a 64-row slice; with LPR lanes per row it
 // walks the slice in LPR sub-slices of 64/LPR rows, each lane owning 16/LPR
-// columns.  Per column, every row sum, every dot partial and every vector
-// update uses the same operation order as the single-vector kernels, so a
-// column of the block solve carries the same bits as the single solve.
+// columns.  With one lane per row, every row sum, every matrix-pass dot
+// partial and every vector update of a column uses the single-vector kernels'
+// operation order, so a column of the block solve carries the same bits as the
+// single solve; only the norms of the stopping test ((F,F), (r,r)), summed by
+// the element-parallel vector kernels, take another order.
 #pragma once
 #include "kernels.h"
 
@@ -150,12 +152,16 @@ __global__ __launch_bounds__(256) void k_sell_blk(const Sell<VT, IT> A, const VT
 // over the rows of a wave (butterfly over the row bits of the lane), then over
 // the block's waves in order: partial[(blockIdx.x * 2 + d) * NB + j].
 template <typename VT> struct RowLoad;
+typedef float vf2 __attribute__((ext_vector_type(2)));
 template <> struct RowLoad<float> {
     template <int RPL> static __device__ inline void load(const float *p, float (&o)[RPL])
     {
         if constexpr (RPL == 4) {
             vf4 t = *reinterpret_cast<const vf4 *>(p);
             o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+        } else if constexpr (RPL == 2) {
+            vf2 t = *reinterpret_cast<const vf2 *>(p);
+            o[0] = t.x; o[1] = t.y;
         } else {
 #pragma unroll
             for (int j = 0; j < RPL; j++) o[j] = p[j];
@@ -450,25 +456,25 @@ __global__ void k_add_blk(int64_t n, const VT *__restrict__ x, const VT *__restr
     y[i] = (OT)(x[i] + c[i]);
 }
 
-// Coarsest level for 16 columns: thread (row slot r = t / 16, column j = t % 16)
-// computes rows r, r + 16, ... of column j with the single-vector kernel's
-// summation order (k ascending), so each column equals k_coarse_solve's result.
-// Y: global scratch (n x 16).
+// Coarsest level for 16 columns, in two launches over 16-row tiles (block =
+// 16 rows x 16 columns, thread = one output element):
+//   phase 0: Y = L^{-1} F,   phase 1: E = L^{-T} Y   (Y: global scratch, n x 16).
+// Per element the single-vector kernel's order (k ascending), so each column
+// equals k_coarse_solve's result.
 template <typename VT>
 __global__ __launch_bounds__(256) void k_coarse_solve_blk(int n, int ld, const double *__restrict__ Linv,
                                                           const double *__restrict__ LinvT, const VT *__restrict__ f,
-                                                          double *__restrict__ Y, VT *__restrict__ e)
+                                                          double *__restrict__ Y, VT *__restrict__ e, int phase)
 {
-    const int j = threadIdx.x & (NB - 1), r = threadIdx.x / NB;
-    for (int i = r; i < n; i += 256 / NB) {
-        double s = 0.0;
+    const int j = threadIdx.x & (NB - 1);
+    const int i = blockIdx.x * (256 / NB) + threadIdx.x / NB;
+    if (i >= n) return;
+    double s = 0.0;
+    if (phase == 0) {
 #pragma unroll 8
         for (int k = 0; k <= i; k++) s = fma(LinvT[(int64_t)k * ld + i], (double)f[(int64_t)k * NB + j], s);
         Y[(int64_t)i * NB + j] = s;
-    }
-    __syncthreads();
-    for (int i = r; i < n; i += 256 / NB) {
-        double s = 0.0;
+    } else {
 #pragma unroll 8
         for (int k = i; k < n; k++) s = fma(Linv[(int64_t)k * ld + i], Y[(int64_t)k * NB + j], s);
         e[(int64_t)i * NB + j] = (VT)s;
@@ -491,70 +497,82 @@ __global__ void k_unpack_blk(int64_t n, int k, const double *__restrict__ rm, do
     for (int j = 0; j < k; j++) cm[(int64_t)j * n + i] = rm[i * NB + j];
 }
 
-// Dot partials per column, same grid-stride order as k_dot2.
-__global__ void k_dot2_blk(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
-                           const double *__restrict__ c, double *__restrict__ partial)
+// ---- element-parallel block vector kernels ----------------------------------
+//
+// Thread t of the grid handles the elements e = t, t + T, ... (T = threads in
+// the grid, a multiple of 16) of the row-major N x 16 arrays, so a wave's load
+// is 64 consecutive values and every thread keeps one column j = e % 16.  Dot
+// partials per column: the thread's running sum, the 4 lanes of each column in
+// a wave (butterfly over lane bits 4 and 5), then the block's waves in order:
+// partial[(2 * blockIdx.x + d) * NB + j].
+
+__device__ inline void blk_col_partials(double s0, double s1, double *lds /* 2 * 4 * NB */, double *partial)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    s0 += __shfl_xor(s0, 16, 64);
+    s0 += __shfl_xor(s0, 32, 64);
+    s1 += __shfl_xor(s1, 16, 64);
+    s1 += __shfl_xor(s1, 32, 64);
+    if (lane < NB) {
+        lds[wid * NB + lane] = s0;
+        lds[(4 + wid) * NB + lane] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x < NB) {
+        const int j = threadIdx.x;
+        partial[(2 * blockIdx.x) * NB + j] = ((lds[j] + lds[NB + j]) + lds[2 * NB + j]) + lds[3 * NB + j];
+        partial[(2 * blockIdx.x + 1) * NB + j] =
+            ((lds[4 * NB + j] + lds[5 * NB + j]) + lds[6 * NB + j]) + lds[7 * NB + j];
+    }
+}
+
+// per-column partials of (a, b) and (a, c) (c may be NULL)
+__global__ __launch_bounds__(256) void k_dot2_blk(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                                                  const double *__restrict__ c, double *__restrict__ partial)
 {
     __shared__ double lds[8 * NB];
-    double s0[NB], s1[NB];
-#pragma unroll
-    for (int j = 0; j < NB; j++) { s0[j] = 0.0; s1[j] = 0.0; }
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-#pragma unroll
-        for (int j = 0; j < NB; j++) {
-            s0[j] = fma(a[i * NB + j], b[i * NB + j], s0[j]);
-            if (c) s1[j] = fma(a[i * NB + j], c[i * NB + j], s1[j]);
-        }
+    double s0 = 0.0, s1 = 0.0;
+    const int64_t m = n * NB;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < m; e += (int64_t)gridDim.x * 256) {
+        s0 = fma(a[e], b[e], s0);
+        if (c) s1 = fma(a[e], c[e], s1);
     }
-    block_sum_cols<NB>(s0, lds);
-    block_sum_cols<NB>(s1, lds + 4 * NB);
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int j = 0; j < NB; j++) {
-            partial[(2 * blockIdx.x) * NB + j] = s0[j];
-            partial[(2 * blockIdx.x + 1) * NB + j] = s1[j];
-        }
+    blk_col_partials(s0, s1, lds, partial);
 }
 
 // u += alpha p ; r -= alpha q for the active columns; partials of (r, r).
-__global__ void k_bcg_update(int64_t n, const double *__restrict__ sc, double *__restrict__ u,
-                             double *__restrict__ r, const double *__restrict__ p, const double *__restrict__ q,
-                             double *__restrict__ partial)
+__global__ __launch_bounds__(256) void k_bcg_update(int64_t n, const double *__restrict__ sc, double *__restrict__ u,
+                                                    double *__restrict__ r, const double *__restrict__ p,
+                                                    const double *__restrict__ q, double *__restrict__ partial)
 {
-    __shared__ double lds[4 * NB];
-    double al[NB], s[NB];
-    bool act[NB];
-#pragma unroll
-    for (int j = 0; j < NB; j++) { act[j] = bactive(sc, j); al[j] = sc[B_ALPHA * NB + j]; s[j] = 0.0; }
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-#pragma unroll
-        for (int j = 0; j < NB; j++) {
-            double ri = r[i * NB + j];
-            if (act[j]) {
-                u[i * NB + j] = fma(al[j], p[i * NB + j], u[i * NB + j]);
-                ri = fma(-al[j], q[i * NB + j], ri);
-                r[i * NB + j] = ri;
-            }
-            s[j] = fma(ri, ri, s[j]);
+    __shared__ double lds[8 * NB];
+    const int j = threadIdx.x & (NB - 1);
+    const bool act = bactive(sc, j);
+    const double al = sc[B_ALPHA * NB + j];
+    double s = 0.0;
+    const int64_t m = n * NB;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < m; e += (int64_t)gridDim.x * 256) {
+        double ri = r[e];
+        if (act) {
+            u[e] = fma(al, p[e], u[e]);
+            ri = fma(-al, q[e], ri);
+            r[e] = ri;
         }
+        s = fma(ri, ri, s);
     }
-    block_sum_cols<NB>(s, lds);
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int j = 0; j < NB; j++) { partial[(2 * blockIdx.x) * NB + j] = s[j]; partial[(2 * blockIdx.x + 1) * NB + j] = 0.0; }
+    blk_col_partials(s, 0.0, lds, partial);
 }
 
-__global__ void k_bcg_pupdate(int64_t n, const double *__restrict__ sc, const double *__restrict__ z,
-                              double *__restrict__ p)
+// p = z + beta p for the active columns
+__global__ __launch_bounds__(256) void k_bcg_pupdate(int64_t n, const double *__restrict__ sc,
+                                                     const double *__restrict__ z, double *__restrict__ p)
 {
-    double be[NB];
-    bool act[NB];
-#pragma unroll
-    for (int j = 0; j < NB; j++) { act[j] = bactive(sc, j); be[j] = sc[B_BETA * NB + j]; }
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-#pragma unroll
-        for (int j = 0; j < NB; j++)
-            if (act[j]) p[i * NB + j] = fma(be[j], p[i * NB + j], z[i * NB + j]);
+    const int j = threadIdx.x & (NB - 1);
+    if (!bactive(sc, j)) return;
+    const double be = sc[B_BETA * NB + j];
+    const int64_t m = n * NB;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < m; e += (int64_t)gridDim.x * 256)
+        p[e] = fma(be, p[e], z[e]);
 }
 
 // Final per-column sums of the partials (index order) and the scalar

@@ -478,8 +478,8 @@ struct amg_ctx {
         (void)hipEventDestroy(e1);
         return best;
     }
-    // Autotuner of the block kernels: builds the level-0 block image for 4 and
-    // 16 lanes per row, times each with 256 and 512 threads per block (and the
+    // Autotuner of the block kernels: builds the level-0 block image for 4, 8
+    // and 16 lanes per row, times each with 256 and 512 threads per block (and the
     // one-lane-per-row kernel on the SELL-64 image), keeps the fastest, and
     // builds the coarse levels' block images for the chosen slice height.
     void tune_blocks(const CsrView &K0)
@@ -502,7 +502,7 @@ struct amg_ctx {
         best = {1, 256, t1};
         DevMat keep;
         int keep_lpr = 0;
-        for (int lpr : {4, 16}) {
+        for (int lpr : {4, 8, 16}) {
             DevMat img = upload_sell(K0, 64 / lpr, true, f32);
             lev[0].Ab = img;
             for (int thr : {256, 512}) {
@@ -865,8 +865,9 @@ struct amg_ctx {
         unsigned nb;
         if (l == 0) prof_begin();
         if (blk_lpr > 1 && B.soff && B.val<VT>()) {
-            nb = blk_lpr == 4 ? launch_sellb<VT, FT, OT, EPI, NDOT, 4>(B, x, f, invd, y, g0, g1, coef)
-                              : launch_sellb<VT, FT, OT, EPI, NDOT, 16>(B, x, f, invd, y, g0, g1, coef);
+            nb = blk_lpr == 4   ? launch_sellb<VT, FT, OT, EPI, NDOT, 4>(B, x, f, invd, y, g0, g1, coef)
+                 : blk_lpr == 8 ? launch_sellb<VT, FT, OT, EPI, NDOT, 8>(B, x, f, invd, y, g0, g1, coef)
+                                : launch_sellb<VT, FT, OT, EPI, NDOT, 16>(B, x, f, invd, y, g0, g1, coef);
         } else {
             const unsigned grid = sell_blocks(l);
             nb = grid * SELL_WAVES;   // dot partials: one per wavefront
@@ -894,9 +895,21 @@ struct amg_ctx {
         hipLaunchKernelGGL(k_bfinalize, dim3(1), dim3(FIN_THREADS), 0, stream, bpartial, (int)nblk, bsc, op, tol);
         HIPCHK(hipGetLastError());
     }
+    // grid of the element-parallel block vector kernels (a multiple of 16 threads)
+    unsigned bgrid(int64_t rows) const
+    {
+        return (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (rows * NB + 255) / 256));
+    }
+    template <typename VT> void coarse_blk(const VT *f, VT *e)
+    {
+        const unsigned g = (unsigned)((nL + 256 / NB - 1) / (256 / NB));
+        hipLaunchKernelGGL((k_coarse_solve_blk<VT>), dim3(g), dim3(256), 0, stream, nL, ldL, Linv, LinvT, f, bY, e, 0);
+        hipLaunchKernelGGL((k_coarse_solve_blk<VT>), dim3(g), dim3(256), 0, stream, nL, ldL, Linv, LinvT, f, bY, e, 1);
+        HIPCHK(hipGetLastError());
+    }
     unsigned bdot_partials(int64_t m, const double *a, const double *b, const double *c)
     {
-        unsigned g = vgrid(m);
+        unsigned g = bgrid(m);
         hipLaunchKernelGGL(k_dot2_blk, dim3(g), dim3(256), 0, stream, m, a, b, c, bpartial);
         HIPCHK(hipGetLastError());
         return g;
@@ -918,6 +931,7 @@ struct amg_ctx {
     do {                                                                                                        \
         if (!multi) BPOST((k_sell_blk_post<VT, OT, IT, ND>), IT, IDX);                                          \
         else if (blk_lpr == 4) BPOST((k_sellb_post<VT, OT, IT, ND, 4>), IT, IDX);                               \
+        else if (blk_lpr == 8) BPOST((k_sellb_post<VT, OT, IT, ND, 8>), IT, IDX);                               \
         else BPOST((k_sellb_post<VT, OT, IT, ND, 16>), IT, IDX);                                                \
     } while (0)
         if (A.idx16) {
@@ -1010,9 +1024,7 @@ struct amg_ctx {
         VT *e;
         if (coarsest) {
             e = (VT *)C.bu;
-            hipLaunchKernelGGL((k_coarse_solve_blk<VT>), dim3(1), dim3(256), 0, stream, nL, ldL, Linv, LinvT,
-                               (const VT *)C.bf, bY, e);
-            HIPCHK(hipGetLastError());
+            coarse_blk<VT>((const VT *)C.bf, e);
         } else {
             e = vlevel_blk<VT, VT>(l + 1, (const VT *)C.bf, nullptr, 0, nullptr, nullptr, true);
         }
@@ -1049,9 +1061,7 @@ struct amg_ctx {
     {
         vc_nb = 0;
         if (nlev == 1) {
-            hipLaunchKernelGGL((k_coarse_solve_blk<double>), dim3(1), dim3(256), 0, stream, nL, ldL, Linv, LinvT,
-                               rin, bY, zout);
-            HIPCHK(hipGetLastError());
+            coarse_blk<double>(rin, zout);
             if (ndot) vc_nb = bdot_partials(n, zout, g0, g1);
             return vc_nb;
         }
@@ -1432,7 +1442,7 @@ static amg_status solve_batched_impl(amg_ctx *c, int nrhs, const double *F, doub
             if (flex) nbq = c->sell_blk<double, double, double, EPI_SPMV, 2>(0, c->bP, nullptr, nullptr, c->bQ, nullptr, c->bR);
             else nbq = c->sell_blk<double, double, double, EPI_SPMV, 1>(0, c->bP, nullptr, nullptr, c->bQ, nullptr, nullptr);
             c->bfinalize(nbq, flex ? BF_PQ_FCG : BF_PQ_CG);
-            unsigned g = vgrid(n);
+            unsigned g = c->bgrid(n);
             hipLaunchKernelGGL(k_bcg_update, dim3(g), dim3(256), 0, c->stream, n, c->bsc, c->bU, c->bR, c->bP, c->bQ,
                                c->bpartial);
             HIPCHK(hipGetLastError());
@@ -1442,7 +1452,7 @@ static amg_status solve_batched_impl(amg_ctx *c, int nrhs, const double *F, doub
         auto partB = [&]() {
             unsigned nb2 = c->vcycle_blk(c->bR, c->bZ, 1, flex ? c->bQ : c->bR, nullptr);
             c->bfinalize(nb2, flex ? BF_ZQ_FCG : BF_RZ_CG);
-            hipLaunchKernelGGL(k_bcg_pupdate, dim3(vgrid(n)), dim3(256), 0, c->stream, n, c->bsc, c->bZ, c->bP);
+            hipLaunchKernelGGL(k_bcg_pupdate, dim3(c->bgrid(n)), dim3(256), 0, c->stream, n, c->bsc, c->bZ, c->bP);
             HIPCHK(hipGetLastError());
         };
         if (graph && !c->gbA[flex]) {
@@ -1554,8 +1564,8 @@ amg_status amg_get_batched_variant(const amg_ctx *c, int *lpr, int *threads)
 
 amg_status amg_set_batched_variant(amg_ctx *c, int lpr, int threads)
 {
-    if (!c || (threads != 256 && threads != 512) || (lpr != 1 && lpr != 4 && lpr != 16)) {
-        set_err("lpr must be 1, 4 or 16 and threads 256 or 512");
+    if (!c || (threads != 256 && threads != 512) || (lpr != 1 && lpr != 4 && lpr != 8 && lpr != 16)) {
+        set_err("lpr must be 1, 4, 8 or 16 and threads 256 or 512");
         return AMG_ERR_ARG;
     }
     if (lpr > 1 && (c->lev[0].Ab.C != 64 / lpr || !c->lev[0].Ab.soff)) {

@@ -102,7 +102,7 @@ def test_autotuned_block_kernels(oracle, amg, fp32):
     ctx = amg.Context(rp, ci, v, nrhs=16, **kw)
     lpr, thr = ctx.batched_variant()
     print(f"  autotuned: lpr={lpr} threads={thr}", flush=True)
-    assert lpr in (1, 4, 16) and thr in (256, 512)
+    assert lpr in (1, 4, 8, 16) and thr in (256, 512)
     Ft = torch.from_numpy(Fh).cuda()
     singles = [ctx.solve(Ft[:, j].contiguous(), tol=1e-8) for j in range(16)]
     variants = [(1, 256)] + ([(lpr, 256), (lpr, 512)] if lpr > 1 else [])
