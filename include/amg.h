@@ -187,6 +187,21 @@ amg_status amg_setup_host(int64_t n, const int64_t *row_ptr, const int32_t *col,
 amg_status amg_match(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
                      const double *w, int positive_only, int32_t *mate);
 
+/* Host check of the device matrix layout (no GPU needed): builds the SELL-C
+ * image (C in {4, 8, 16, 32, 64}) of the n x ncols CSR matrix K the way the
+ * library does -- layout 0: row order and per-entry indices; 1: shared column
+ * offsets where they fit (square matrices only); 2: rows sorted by length
+ * within windows of 4 slices -- and computes y = K x (host arrays, x of length
+ * ncols, y of length n) by walking that image as the matrix-pass kernels do:
+ * groups of 8 entries, columns rebuilt from shared offsets (clamped where the
+ * slice needs it), 16-bit deltas or int32 columns, the slot -> row map.  Every
+ * column the walk would read is checked against [0, ncols): AMG_ERR_STATE if
+ * one is not.  shared_slices, stored (may be NULL): slices with shared offsets,
+ * stored entries with padding.  For tests and inspection. */
+amg_status amg_sell_spmv_host(int64_t n, int64_t ncols, const int64_t *row_ptr, const int32_t *col,
+                              const double *val, int C, int layout, const double *x, double *y,
+                              int64_t *shared_slices, int64_t *stored);
+
 /* Free everything the context holds (host and device).  NULL is a no-op. */
 void amg_destroy(amg_ctx *c);
 

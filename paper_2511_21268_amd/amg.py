@@ -23,7 +23,7 @@ EXPORTS = ["amg_params_default", "amg_setup", "pcg_solve", "pcg_solve_batched", 
            "amg_destroy", "amg_last_error", "amg_set_profiling", "amg_get_profile", "amg_get_format",
            "amg_iga_poisson_size", "amg_iga_poisson", "amg_iga_diffusion", "amg_level_features",
            "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_adam", "amg_set_learned_poly",
-           "amg_get_batched_variant", "amg_set_batched_variant", "amg_set_option"]
+           "amg_get_batched_variant", "amg_set_batched_variant", "amg_set_option", "amg_sell_spmv_host"]
 AMG_OPT_GRAPH, AMG_OPT_FUSE_POST = 1, 2
 MLP_NPARAM, MLP_NFEAT, MLP_NACT, MLP_NDEL = 4996, 8, 128, 132
 
@@ -82,6 +82,8 @@ def lib():
         L.amg_mlp_backward.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp, vp]
         L.amg_mlp_adam.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_float, vp]
         L.amg_set_option.argtypes = [vp, C.c_int, C.c_int]
+        L.amg_sell_spmv_host.argtypes = [C.c_int64, C.c_int64, i64p, i32p, f64p, C.c_int, C.c_int, f64p, f64p,
+                                         i64p, i64p]
         L.amg_get_batched_variant.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.amg_set_batched_variant.argtypes = [vp, C.c_int, C.c_int]
         L.amg_set_learned_poly.argtypes = [vp, C.POINTER(C.c_uint16), C.POINTER(C.c_int), f64p]
@@ -132,6 +134,19 @@ def iga_diffusion(p, n, a, mk, want_F=True):
     _check(lib().amg_iga_diffusion(p, n, len(a_), _p(a_, f64p), _p(m_, i32p), _p(rp, i64p), _p(ci, i32p),
                                    _p(v, f64p), _p(F, f64p) if want_F else None))
     return rp, ci, v, F
+
+
+def sell_spmv_host(indptr, indices, data, x, C_slice=64, layout=1, ncols=None):
+    """y = K x through the host image of the device layout (amg_sell_spmv_host);
+    returns (y, shared_slices, stored)."""
+    rp = np.ascontiguousarray(indptr, np.int64); ci = np.ascontiguousarray(indices, np.int32)
+    v = np.ascontiguousarray(data, np.float64); xx = np.ascontiguousarray(x, np.float64)
+    n = len(rp) - 1
+    y = np.zeros(n)
+    sh = C.c_int64(); st = C.c_int64()
+    _check(lib().amg_sell_spmv_host(n, len(xx) if ncols is None else ncols, _p(rp, i64p), _p(ci, i32p), _p(v, f64p),
+                                    C_slice, layout, _p(xx, f64p), _p(y, f64p), C.byref(sh), C.byref(st)))
+    return y, sh.value, st.value
 
 
 def match(indptr, indices, data, w=None, positive_only=False):

@@ -1262,6 +1262,74 @@ amg_status amg_setup_host(int64_t n, const int64_t *row_ptr, const int32_t *col,
     return setup_common(n, row_ptr, col, val, w, prm, nullptr, 1, out);
 }
 
+amg_status amg_sell_spmv_host(int64_t n, int64_t ncols, const int64_t *row_ptr, const int32_t *col,
+                              const double *val, int C, int layout, const double *x, double *y,
+                              int64_t *shared_slices, int64_t *stored)
+{
+    g_err.clear();
+    if (n <= 0 || ncols <= 0 || !row_ptr || !col || !val || !x || !y || (C != 4 && C != 8 && C != 16 && C != 32 &&
+        C != 64) || layout < 0 || layout > 2 || (layout == 1 && ncols != n)) {
+        set_err("bad size, NULL array, slice height or layout");
+        return AMG_ERR_ARG;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        if (row_ptr[i + 1] < row_ptr[i]) { set_err("row_ptr not ascending"); return AMG_ERR_ARG; }
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; k++)
+            if (col[k] < 0 || col[k] >= ncols || (k > row_ptr[i] && col[k] <= col[k - 1])) {
+                set_err("columns out of range or not ascending");
+                return AMG_ERR_ARG;
+            }
+    }
+    CsrView K{n, row_ptr, col, val};
+    SellHost S;
+    build_sell(K, C, true, false, layout == 1, layout == 2 ? 4 * C : 0, S);
+    const int32_t hi = (int32_t)(ncols - 1);
+    auto bad = [&](int64_t c) { return c < 0 || c > hi; };
+    for (int64_t s = 0; s < S.nslices; s++) {
+        const int64_t base = S.soff[s];
+        const int width = (int)((S.soff[s + 1] - base) / C);
+        const int64_t ib = S.ibase[s];
+        for (int r = 0; r < C; r++) {
+            const int64_t slot = s * C + r;
+            const int64_t row = S.sorted ? (int64_t)S.perm[slot] : (slot < n ? slot : -1);
+            double acc = 0.0;
+            if (ib < 0) {
+                if (S.sorted) { set_err("shared offsets in a sorted image"); return AMG_ERR_STATE; }
+                const int64_t e = -1 - ib;
+                const int32_t *so = S.shoff.data() + (e >> 1);
+                if ((e >> 1) + width > (int64_t)S.shoff.size()) { set_err("offset list past its array"); return AMG_ERR_STATE; }
+                for (int k = 0; k < width; k++) {
+                    int64_t c = slot + so[k];
+                    if (!(e & 1)) c = std::min<int64_t>(std::max<int64_t>(c, 0), hi);
+                    if (bad(c)) { set_err("shared-offset column out of range"); return AMG_ERR_STATE; }
+                    acc = std::fma(S.v64[base + (k / 2) * 2 * C + r * 2 + (k % 2)], x[c], acc);
+                }
+            } else if (S.idx16) {
+                int64_t c = S.col0.empty() ? 0 : S.col0[slot];
+                for (int k = 0; k < width; k++) {
+                    const int64_t q = ib + (k / 8) * 8 * C + r * 8 + (k % 8);
+                    if (q >= (int64_t)S.d16.size()) { set_err("delta stream past its array"); return AMG_ERR_STATE; }
+                    c += S.d16[q];
+                    if (bad(c)) { set_err("delta column out of range"); return AMG_ERR_STATE; }
+                    acc = std::fma(S.v64[base + (k / 2) * 2 * C + r * 2 + (k % 2)], x[c], acc);
+                }
+            } else {
+                for (int k = 0; k < width; k++) {
+                    const int64_t q = ib + (k / 4) * 4 * C + r * 4 + (k % 4);
+                    if (q >= (int64_t)S.c32.size()) { set_err("column stream past its array"); return AMG_ERR_STATE; }
+                    const int64_t c = S.c32[q];
+                    if (bad(c)) { set_err("int32 column out of range"); return AMG_ERR_STATE; }
+                    acc = std::fma(S.v64[base + (k / 2) * 2 * C + r * 2 + (k % 2)], x[c], acc);
+                }
+            }
+            if (row >= 0) y[row] = acc;
+        }
+    }
+    if (shared_slices) *shared_slices = S.nshared;
+    if (stored) *stored = S.stored;
+    return AMG_OK;
+}
+
 amg_status amg_match(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val, const double *w,
                      int positive_only, int32_t *mate)
 {

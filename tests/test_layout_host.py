@@ -1,0 +1,89 @@
+"""The device matrix layout on the host (no GPU): amg_sell_spmv_host builds the
+library's SELL image and walks it as the matrix-pass kernels do.  Every layout
+must give K x (checked against an independent CSR product), read only columns
+in range, and -- since every row is summed in ascending column order and the
+extra entries are exact zeros -- the same bits in every layout."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+
+@pytest.fixture(scope="module")
+def amg():
+    import paper_2511_21268_amd as m
+    m.lib()
+    return m
+
+
+def _cases(oracle):
+    from paper_2511_21268_amd.workloads import kappa_params
+    out = {}
+    out["2d-p2"] = oracle.poisson_kron(2, 2, 32)[:3]
+    out["3d-p3"] = oracle.poisson_kron(3, 3, 12)[:3]
+    a, mk = kappa_params(5)
+    out["3d-kappa-p5"] = oracle.diffusion_quad3d(5, 6, a, mk, factorized=True)[:3]
+    rp, ci, v, _ = oracle.poisson_kron(3, 2, 10)
+    K = sp.csr_matrix((v, ci, rp), shape=(len(rp) - 1,) * 2)
+    perm = np.random.default_rng(3).permutation(K.shape[0])
+    Kp = sp.csr_matrix(K[perm][:, perm]); Kp.sort_indices()
+    out["permuted"] = (Kp.indptr, Kp.indices, Kp.data)
+    # column gaps beyond 16 bits: int32 columns
+    n = 70000
+    A = sp.diags([np.full(n, 4.0), np.full(n - 66000, -1.0), np.full(n - 66000, -1.0)], [0, 66000, -66000], format="csr")
+    A.sort_indices()
+    out["wide-gaps"] = (A.indptr, A.indices, A.data)
+    return out
+
+
+def _ref(rp, ci, v, x, ncols):
+    K = sp.csr_matrix((v, ci, rp), shape=(len(rp) - 1, ncols))
+    return K @ x, abs(K) @ np.abs(x)
+
+
+@pytest.mark.parametrize("C", [64, 16, 4])
+def test_layouts_compute_Kx(oracle, amg, C):
+    for name, (rp, ci, v) in _cases(oracle).items():
+        n = len(rp) - 1
+        x = np.random.default_rng(1).standard_normal(n)
+        ref, scale = _ref(rp, ci, v, x, n)
+        ys = []
+        for layout in (0, 1, 2):
+            y, shared, stored = amg.sell_spmv_host(rp, ci, v, x, C_slice=C, layout=layout)
+            assert np.all(np.abs(y - ref) <= 8 * np.finfo(float).eps * scale + 1e-300), (name, layout)
+            assert stored >= len(v)
+            if layout != 1:
+                assert shared == 0
+            ys.append(y)
+            if layout == 1 and name in ("2d-p2", "3d-p3") and C == 64:
+                assert shared > 0, name
+        assert np.array_equal(ys[0], ys[1]) and np.array_equal(ys[0], ys[2]), name
+
+
+def test_rectangular_KP_image(oracle, amg):
+    """K P (one column per aggregate) in the sorted layout: the columns a lane
+    walks stay inside the coarse range."""
+    rp, ci, v, _ = oracle.poisson_kron(3, 3, 10)
+    h = oracle.Hierarchy(rp, ci, v)
+    agg, pc = h.level_agg(0)[:2]
+    n, nc = len(rp) - 1, int(agg.max()) + 1
+    K = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    P = sp.csr_matrix((pc, (np.arange(n), agg)), shape=(n, nc))
+    KP = (K @ P).tocsr(); KP.sort_indices()
+    e = np.random.default_rng(2).standard_normal(nc)
+    ref, scale = _ref(KP.indptr, KP.indices, KP.data, e, nc)
+    for C in (64, 16, 4):
+        for layout in (0, 2):
+            y, _, _ = amg.sell_spmv_host(KP.indptr, KP.indices, KP.data, e, C_slice=C, layout=layout, ncols=nc)
+            assert np.all(np.abs(y - ref) <= 8 * np.finfo(float).eps * scale + 1e-300), (C, layout)
+    with pytest.raises(amg.AmgError):                   # shared offsets only for square matrices
+        amg.sell_spmv_host(KP.indptr, KP.indices, KP.data, e, C_slice=64, layout=1, ncols=nc)
+
+
+def test_sorted_windows_reduce_padding(oracle, amg):
+    rp, ci, v, _ = oracle.poisson_kron(3, 3, 12)
+    h = oracle.Hierarchy(rp, ci, v)
+    rpl, cil, vl = h.level_matrix(1)
+    x = np.random.default_rng(4).standard_normal(len(rpl) - 1)
+    _, _, plain = amg.sell_spmv_host(rpl, cil, vl, x, C_slice=64, layout=0)
+    _, _, srt = amg.sell_spmv_host(rpl, cil, vl, x, C_slice=64, layout=2)
+    assert srt < plain
