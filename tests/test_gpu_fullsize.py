@@ -5,7 +5,12 @@ oracle's, aggregates of every level bit for bit.
 3D p=3, n=128 (N = 2,146,689; 707M entries, the benchmark workload, same
 kernels and launch shapes as bench.py): properties and sampled outputs the
 oracle computes one by one -- sampled SpMV rows, the greedy characterisation of
-the level-0 matching on every edge, and the FP64 true residual of the solve.
+the level-0 matching on every edge, and the FP64 true residual of the solve;
+the 16-RHS form with the autotuned block kernels, every column's FP64 true
+residual.
+3D p=4, n=96 (640M entries): the FP32 V-cycle inside FP64 FCG against the
+FP64 PCG on the same system.
+3D p=5, n=64, variable kappa: sampled rows, plain and learned solves.
 """
 import numpy as np
 import pytest
@@ -51,11 +56,28 @@ def test_c2_full_solve_parity(oracle, amg):
     assert true <= 1e-8
 
 
+def _sampled_rows(oracle, rp, ci, v, x, y, nsample=4000, seed=4):
+    N = len(rp) - 1
+    rows = np.unique(np.concatenate([np.arange(0, 200), np.arange(N - 200, N),
+                                     np.random.default_rng(seed).integers(0, N, nsample)]))
+    for i in rows:
+        s, e = rp[i], rp[i + 1]
+        ref = oracle.dot(v[s:e], x[ci[s:e]])
+        scale = np.abs(v[s:e]) @ np.abs(x[ci[s:e]])
+        assert abs(y[i] - ref) <= 8 * np.finfo(float).eps * scale, i
+
+
+@pytest.fixture(scope="module")
+def c4_system(oracle):
+    rp, ci, v, _ = oracle.poisson_kron(3, 3, 128, want_F=False)
+    return rp, ci, v
+
+
 @pytest.mark.timeout(900)
-def test_c4_properties(oracle, amg):
+def test_c4_properties(oracle, amg, c4_system):
     print("case c4: 3D p=3 n=128 seed 0", flush=True)
     from paper_2511_21268_amd.workloads import rhs_normal
-    rp, ci, v, _ = oracle.poisson_kron(3, 3, 128, want_F=False)
+    rp, ci, v = c4_system
     N = len(rp) - 1
     print(f"  oracle assembled N={N} nnz={len(v)}", flush=True)
     ctx = amg.Context(rp, ci, v)
@@ -63,13 +85,7 @@ def test_c4_properties(oracle, amg):
     # sampled SpMV rows of the level-0 kernel
     x = np.random.default_rng(3).standard_normal(N)
     y = ctx.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
-    rows = np.unique(np.concatenate([np.arange(0, 200), np.arange(N - 200, N),
-                                     np.random.default_rng(4).integers(0, N, 4000)]))
-    for i in rows:
-        s, e = rp[i], rp[i + 1]
-        ref = oracle.dot(v[s:e], x[ci[s:e]])
-        scale = np.abs(v[s:e]) @ np.abs(x[ci[s:e]])
-        assert abs(y[i] - ref) <= 8 * np.finfo(float).eps * scale
+    _sampled_rows(oracle, rp, ci, v, x, y)
     print("  sampled SpMV rows ok", flush=True)
     # the library's level-0 matching sweep is the greedy matching on every edge
     mate = amg.match(rp, ci, v)
@@ -82,3 +98,90 @@ def test_c4_properties(oracle, amg):
     true = np.linalg.norm(F - oracle.spmv(rp, ci, v, u)) / np.linalg.norm(F)
     print(f"  solve: {out['iters']} iterations, true relres {true:.3e}", flush=True)
     assert out["status"] == 0 and true <= 1e-8
+
+
+@pytest.mark.timeout(900)
+def test_c4_batched_properties(oracle, amg, c4_system):
+    """16 right-hand sides (seeds 0..15), FP32 block V-cycle in FP64 FCG with
+    the autotuned block kernels, as bench.py --mode batched runs it."""
+    print("case c4 x 16: 3D p=3 n=128 seeds 0..15", flush=True)
+    from paper_2511_21268_amd.workloads import rhs_block
+    rp, ci, v = c4_system
+    N = len(rp) - 1
+    ctx = amg.Context(rp, ci, v, vcycle_fp32=1, krylov=1, nrhs=16)
+    print(f"  autotuned block variant {ctx.batched_variant()}", flush=True)
+    Fh = rhs_block(N, range(16))
+    out = ctx.solve_batched(torch.from_numpy(Fh).cuda(), tol=1e-8)
+    U = out["U"].cpu().numpy()
+    assert out["status"] == 0
+    for j in range(16):
+        true = np.linalg.norm(Fh[:, j] - oracle.spmv(rp, ci, v, U[:, j])) / np.linalg.norm(Fh[:, j])
+        assert true <= 1e-8 * 1.0001, (j, true)
+    print(f"  iterations {out['iters']}", flush=True)
+
+
+@pytest.mark.timeout(900)
+def test_c3_fp32_vcycle_properties(oracle, amg):
+    """3D p=4, n=96: FP32 V-cycle in FP64 FCG against FP64 PCG, both to 1e-8 on
+    the FP64 system (oracle SpMV); the change in iterations and the solution
+    difference are reported; both residuals at 1e-8 bound K (u32 - u64)."""
+    print("case c3: 3D p=4 n=96 seed 0", flush=True)
+    from paper_2511_21268_amd.workloads import rhs_normal
+    rp, ci, v, _ = oracle.poisson_kron(3, 4, 96, want_F=False)
+    N = len(rp) - 1
+    F = rhs_normal(N, 0)
+    Ft = torch.from_numpy(F).cuda()
+    res, zs = {}, {}
+    rvec = torch.from_numpy(np.random.default_rng(5).standard_normal(N)).cuda()
+    for name, kw in (("fp64", {}), ("fp32", dict(vcycle_fp32=1, krylov=1))):
+        ctx = amg.Context(rp, ci, v, **kw)
+        zs[name] = ctx.vcycle(rvec).cpu().numpy()
+        out = ctx.solve(Ft, tol=1e-8)
+        u = out["u"].cpu().numpy()
+        r = F - oracle.spmv(rp, ci, v, u)
+        true = np.linalg.norm(r) / np.linalg.norm(F)
+        print(f"  {name}: {out['iters']} iterations, true relres {true:.3e}", flush=True)
+        assert out["status"] == 0 and true <= 1e-8 * 1.0001
+        res[name] = (u, out["iters"], r)
+        if name == "fp64":
+            x = np.random.default_rng(3).standard_normal(N)
+            _sampled_rows(oracle, rp, ci, v, x, ctx.spmv(torch.from_numpy(x).cuda()).cpu().numpy(), nsample=2000)
+        del ctx
+    # the FP32 V-cycle is the one in use: it differs from the FP64 V-cycle at FP32 level
+    dz = np.linalg.norm(zs["fp32"] - zs["fp64"]) / np.linalg.norm(zs["fp64"])
+    print(f"  V-cycle FP32 vs FP64: {dz:.2e}", flush=True)
+    assert 1e-9 < dz < 1e-4
+    u64, u32 = res["fp64"][0], res["fp32"][0]
+    err = np.linalg.norm(u32 - u64) / np.linalg.norm(u64)
+    print(f"  iterations fp32 - fp64: {res['fp32'][1] - res['fp64'][1]}, solution difference {err:.2e}", flush=True)
+    assert np.linalg.norm(res["fp64"][2] - res["fp32"][2]) <= 2.0001e-8 * np.linalg.norm(F)
+
+
+@pytest.mark.timeout(900)
+def test_c5_plain_and_learned(oracle, amg):
+    """3D p=5, n=64, variable kappa (seed 0), f = 1: sampled SpMV rows; the
+    plain l1 form and the learned smoother both reach 1e-8 on the FP64 system,
+    the learned one in fewer iterations."""
+    print("case c5: 3D p=5 n=64 kappa seed 0", flush=True)
+    from paper_2511_21268_amd import learned
+    from paper_2511_21268_amd.workloads import kappa_params
+    rp, ci, v, F = amg.iga_diffusion(5, 64, *kappa_params(0))
+    N = len(rp) - 1
+    Ft = torch.from_numpy(F).cuda()
+    its = {}
+    for name in ("l1", "learned"):
+        ctx = amg.Context(rp, ci, v, smoother=1 if name == "learned" else 0, itmax=6000)
+        if name == "learned":
+            acc, _ = learned.apply_learned(ctx)
+            print(f"  accepted levels {acc}", flush=True)
+        else:
+            x = np.random.default_rng(3).standard_normal(N)
+            _sampled_rows(oracle, rp, ci, v, x, ctx.spmv(torch.from_numpy(x).cuda()).cpu().numpy(), nsample=1000)
+        out = ctx.solve(Ft, tol=1e-8)
+        u = out["u"].cpu().numpy()
+        true = np.linalg.norm(F - oracle.spmv(rp, ci, v, u)) / np.linalg.norm(F)
+        print(f"  {name}: {out['iters']} iterations, true relres {true:.3e}", flush=True)
+        assert out["status"] == 0 and true <= 1e-8 * 1.0001
+        its[name] = out["iters"]
+        del ctx
+    assert its["learned"] < its["l1"]
