@@ -71,14 +71,17 @@ def cpu_baseline(cfg, seed, tol, iters_gpu, sample_iters):
     from paper_2511_21268_amd.workloads import rhs_normal
 
     t = time.time()
-    rp, ci, v, _ = oracle.poisson_kron(cfg["d"], cfg["p"], cfg["n"], want_F=False)
+    if cfg["kind"] == "cube":
+        rp, ci, v, Fcube, _ = oracle.cube_system(cfg["p"], cfg["n"])
+    else:
+        rp, ci, v, _ = oracle.poisson_kron(cfg["d"], cfg["p"], cfg["n"], want_F=False)
     log(f"oracle: assembled K ({len(v)} entries) in {time.time() - t:.1f} s")
     t = time.time()
     oracle.set_verbose(1)
     h = oracle.Hierarchy(rp, ci, v)
     oracle.set_verbose(0)
     log(f"oracle: hierarchy of {h.nlevels} levels in {time.time() - t:.1f} s")
-    F = rhs_normal(len(rp) - 1, seed)
+    F = Fcube if cfg["kind"] == "cube" else rhs_normal(len(rp) - 1, seed)
     t = time.time()
     res = h.solve(F, tol=tol, itmax=sample_iters)
     dt = time.time() - t
@@ -138,6 +141,8 @@ def main():
     if cfg["kind"] == "diffusion":
         from paper_2511_21268_amd.workloads import kappa_params
         rp, ci, v, Fload = amg.iga_diffusion(cfg["p"], cfg["n"], *kappa_params(args.seed))
+    elif cfg["kind"] == "cube":
+        rp, ci, v, Fload = amg.iga_cube(cfg["p"], cfg["n"])
     else:
         rp, ci, v, _ = amg.iga_poisson(cfg["d"], cfg["p"], cfg["n"], want_F=False)
         Fload = None
@@ -224,15 +229,19 @@ def main():
     roofline["frac_of_copy"] = round(achieved / roofline["copy_gbs"], 4) if roofline["copy_gbs"] > 0 else None
 
     cpu = None
-    if not args.no_cpu_baseline and args.mode == "fp64":
+    if not args.no_cpu_baseline and args.mode == "fp64" and cfg["kind"] in ("poisson", "cube"):
         cpu = cpu_baseline(cfg, args.seed, args.tol, iters[-1], args.cpu_sample_iters)
 
     form = {"fp64": "FP64 PCG", "fp32": "FP32 V-cycle in FP64 FCG",
             "batched": "16 RHS, FP32 block V-cycle in FP64 FCG",
             "learned": "FP64 PCG, learned degree-4 polynomial smoothers"}[args.mode]
     smoother = "learned POLY4" if args.mode == "learned" else "l1-Jacobi 1/1"
-    problem = ("-div(kappa grad u) = 1, kappa from seed " + str(args.seed)) if cfg["kind"] == "diffusion" \
-        else f"Poisson, F~N(0,1) seed {args.seed}{'..' + str(args.seed + nrhs - 1) if nrhs > 1 else ''}"
+    if cfg["kind"] == "diffusion":
+        problem = "-div(kappa grad u) = 1, kappa from seed " + str(args.seed)
+    elif cfg["kind"] == "cube":
+        problem = "cube of Sec. 5.1 (u = exp(x+z) sin y, Dirichlet x=0,1 y=0, Neumann y=1 z=0,1)"
+    else:
+        problem = f"Poisson, F~N(0,1) seed {args.seed}{'..' + str(args.seed + nrhs - 1) if nrhs > 1 else ''}"
     rec = {"metric": METRIC, "value": round(ms / 1e3, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "strong",
            "vs_baseline": None, "dtype": "f64" if args.mode == "fp64" else "f32/f64", "data": "synthetic",

@@ -254,6 +254,21 @@ amg_status amg_iga_poisson_size(int d, int p, int n, int64_t *N, int64_t *nnz);
 amg_status amg_iga_poisson(int d, int p, int n, int64_t *row_ptr, int32_t *col, double *val,
                            double *F);
 
+/*
+ * The paper's cube benchmark (Sec. 5.1, "Cube"): -Lap u = f on [0,1]^3 with
+ * u = exp(x+z) sin(y), f = -exp(x+z) sin(y), Dirichlet data g_D = u on sides
+ * 1-3 (x = 0, x = 1, y = 0) and Neumann data g_N = du/dn on sides 4-6 (y = 1,
+ * z = 0, z = 1), tensor B-splines of degree p with n elements per direction.
+ * The Dirichlet functions (first and last in x, first in y) are removed; F is
+ * the interior load vector: source and Neumann integrals (Sec. 2.2, f_i) minus
+ * K times the lifting, whose coefficients are those of the L2 projection of
+ * g_D onto the spline space.  N = (n+p-2)(n+p-1)(n+p) (Table 1(b)); ordering
+ * lexicographic, x fastest.  Host arrays sized by amg_iga_cube_size; F may be
+ * NULL.  1 <= p <= 10.
+ */
+amg_status amg_iga_cube_size(int p, int n, int64_t *N, int64_t *nnz);
+amg_status amg_iga_cube(int p, int n, int64_t *row_ptr, int32_t *col, double *val, double *F);
+
 /* ------------------------------------------------------------------------
  * Learned polynomial smoother: a small MLP (8 -> 64 -> 64 -> 4, tanh) maps the
  * features of a level to the coefficients of its degree-4 polynomial smoother

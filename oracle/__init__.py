@@ -15,7 +15,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "liboracle.so")
-_SRC = ["iga.c", "amg.c", "krylov.c", "mlp.c"]
+_SRC = ["iga.c", "cube.c", "amg.c", "krylov.c", "mlp.c"]
 
 
 def build(force=True):
@@ -61,6 +61,10 @@ def lib():
         L.or_poisson_kron_bc.argtypes = [C.c_int, C.c_int, C.c_int, i32p, i64p, i32p, f64p, f64p]
         L.or_greedy_edges.argtypes = [C.c_int64, C.c_int64, f64p, i32p, i32p, C.c_int, i32p]
         L.or_diffusion_quad3d.argtypes = [C.c_int, C.c_int, C.c_int, f64p, i32p, i64p, i32p, f64p, f64p]
+        L.or_cube_size.argtypes = [C.c_int, C.c_int, i64p, i64p]
+        L.or_cube_system.argtypes = [C.c_int, C.c_int, i64p, i32p, f64p, f64p, f64p]
+        L.or_cube_embed.argtypes = [C.c_int, C.c_int, f64p, f64p, f64p]
+        L.or_cube_error.argtypes = [C.c_int, C.c_int, f64p, f64p, f64p]
         L.or_diffusion_sf3d.argtypes = [C.c_int, C.c_int, C.c_int, f64p, i32p, i64p, i32p, f64p, f64p]
         L.or_cij.argtypes = [C.c_double] * 5
         L.or_cij.restype = C.c_double
@@ -178,6 +182,36 @@ def poisson_kron_bc(d, p, n, dirichlet):
     if rc:
         raise ValueError("or_poisson_kron_bc failed")
     return rp, ci, v, F
+
+
+# ---------------------------------------------------------------- Sec. 5.1 cube
+def cube_size(p, n):
+    N = C.c_int64(); nz = C.c_int64()
+    lib().or_cube_size(p, n, C.byref(N), C.byref(nz))
+    return N.value, nz.value
+
+
+def cube_system(p, n):
+    """The paper's cube problem: (rp, ci, v, F, lift), lift in full-space order."""
+    N, nz = cube_size(p, n)
+    m = n + p
+    rp = np.zeros(N + 1, np.int64); ci = np.zeros(nz, np.int32); v = np.zeros(nz); F = np.zeros(N)
+    lift = np.zeros(m ** 3)
+    rc = lib().or_cube_system(p, n, _p(rp, i64p), _p(ci, i32p), _p(v, f64p), _p(F, f64p), _p(lift, f64p))
+    if rc:
+        raise ValueError("or_cube_system failed")
+    return rp, ci, v, F, lift
+
+
+def cube_error(p, n, u0, lift):
+    """(||u_h - u||_L2, ||u||_L2) for the interior solution u0."""
+    m = n + p
+    uf = np.zeros(m ** 3)
+    u0 = _f64(u0); lift = _f64(lift)
+    lib().or_cube_embed(p, n, _p(u0, f64p), _p(lift, f64p), _p(uf, f64p))
+    e = C.c_double(); nr = C.c_double()
+    lib().or_cube_error(p, n, _p(uf, f64p), C.byref(e), C.byref(nr))
+    return e.value, nr.value
 
 
 def diffusion_quad3d(p, n, a=None, mk=None, factorized=False):

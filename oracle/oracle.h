@@ -65,6 +65,20 @@ int  or_diffusion_quad3d(int p, int n, int nk, const double *a, const int32_t *m
 int  or_diffusion_sf3d(int p, int n, int nk, const double *a, const int32_t *mk,
                        int64_t *rp, int32_t *ci, double *v, double *F);
 
+/* ---------------- cube.c : the paper's cube benchmark (Sec. 5.1) ---------------- */
+
+/* Size of the cube system: Dirichlet on x = 0, x = 1, y = 0 (Table 1(b)). */
+void or_cube_size(int p, int n, int64_t *N, int64_t *nnz);
+/* Interior system K u0 = F of -Lap u = f with u = exp(x+z) sin(y): K in CSR
+ * (or_poisson_kron_bc pattern), F with the source, the Neumann integrals of
+ * sides 4-6 and minus the lifting; lift (length (n+p)^3, full-space order)
+ * holds the Dirichlet coefficients (L2 projection of g_D), zero elsewhere. */
+int  or_cube_system(int p, int n, int64_t *rp, int32_t *ci, double *v, double *F, double *lift);
+/* Full-space coefficients u_h = lift + u0 on the interior functions. */
+void or_cube_embed(int p, int n, const double *u0, const double *lift, double *ufull);
+/* L2 norm of u_h - u and of u over the cube by (p+4)^3 Gauss points per element. */
+int  or_cube_error(int p, int n, const double *ufull, double *err, double *norm);
+
 /* ---------------- amg.c : hierarchy (Sec. 3, 3.1) ---------------- */
 
 typedef struct {

@@ -23,7 +23,8 @@ EXPORTS = ["amg_params_default", "amg_setup", "pcg_solve", "pcg_solve_batched", 
            "amg_destroy", "amg_last_error", "amg_set_profiling", "amg_get_profile", "amg_get_format",
            "amg_iga_poisson_size", "amg_iga_poisson", "amg_iga_diffusion", "amg_level_features",
            "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_adam", "amg_set_learned_poly",
-           "amg_get_batched_variant", "amg_set_batched_variant", "amg_set_option", "amg_sell_spmv_host"]
+           "amg_get_batched_variant", "amg_set_batched_variant", "amg_set_option", "amg_sell_spmv_host",
+           "amg_iga_cube_size", "amg_iga_cube"]
 AMG_OPT_GRAPH, AMG_OPT_FUSE_POST = 1, 2
 MLP_NPARAM, MLP_NFEAT, MLP_NACT, MLP_NDEL = 4996, 8, 128, 132
 
@@ -76,6 +77,8 @@ def lib():
         L.amg_get_format.argtypes = [vp, C.c_int, C.POINTER(C.c_int), i64p, C.POINTER(C.c_int), i64p]
         L.amg_iga_poisson_size.argtypes = [C.c_int, C.c_int, C.c_int, i64p, i64p]
         L.amg_iga_poisson.argtypes = [C.c_int, C.c_int, C.c_int, i64p, i32p, f64p, f64p]
+        L.amg_iga_cube_size.argtypes = [C.c_int, C.c_int, i64p, i64p]
+        L.amg_iga_cube.argtypes = [C.c_int, C.c_int, i64p, i32p, f64p, f64p]
         L.amg_iga_diffusion.argtypes = [C.c_int, C.c_int, C.c_int, f64p, i32p, i64p, i32p, f64p, f64p]
         L.amg_level_features.argtypes = [vp, C.c_int, C.POINTER(C.c_float)]
         L.amg_mlp_forward.argtypes = [vp, vp, C.c_int, vp, vp, vp]
@@ -120,6 +123,16 @@ def iga_poisson(d, p, n, want_F=True):
     F = np.empty(N.value) if want_F else None
     _check(lib().amg_iga_poisson(d, p, n, _p(rp, i64p), _p(ci, i32p), _p(v, f64p),
                                  _p(F, f64p) if want_F else None))
+    return rp, ci, v, F
+
+
+def iga_cube(p, n, want_F=True):
+    """Host CSR and load vector of the paper's cube problem (library's generator)."""
+    N = C.c_int64(); nz = C.c_int64()
+    _check(lib().amg_iga_cube_size(p, n, C.byref(N), C.byref(nz)))
+    rp = np.empty(N.value + 1, np.int64); ci = np.empty(nz.value, np.int32); v = np.empty(nz.value)
+    F = np.empty(N.value) if want_F else None
+    _check(lib().amg_iga_cube(p, n, _p(rp, i64p), _p(ci, i32p), _p(v, f64p), _p(F, f64p) if want_F else None))
     return rp, ci, v, F
 
 

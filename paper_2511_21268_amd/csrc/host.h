@@ -75,6 +75,8 @@ void suitor_match(const CsrView &K, const double *w, int positive_only, int32_t 
 // Workload generator.
 void iga_size(int d, int p, int n, int64_t *N, int64_t *nnz);
 int iga_poisson(int d, int p, int n, int64_t *rp, int32_t *ci, double *v, double *F);
+void iga_cube_size(int p, int n, int64_t *N, int64_t *nnz);
+int iga_cube(int p, int n, int64_t *rp, int32_t *ci, double *v, double *F);
 int iga_diffusion(int p, int n, int nk, const double *a, const int32_t *mk, int64_t *rp, int32_t *ci, double *v,
                   double *F);
 

@@ -594,6 +594,152 @@ int iga_poisson(int d, int p, int n, int64_t *rp, int32_t *ci, double *v, double
 }
 
 
+// The paper's cube problem (Sec. 5.1): -Lap u = f on [0,1]^3, u = e^{x+z} sin y,
+// Dirichlet on x = 0, x = 1, y = 0 (rows and columns of the functions with a
+// nonzero trace there removed: the first and last in x, the first in y),
+// Neumann data g_N = du/dn on y = 1, z = 0, z = 1 through boundary integrals.
+// Dirichlet data by a lifting with the L2-projection coefficients of g_D.
+// Every term is separable: integrals of e^x, sin y, e^z against the 1D basis,
+// and the lifting, a tensor product restricted to the Dirichlet functions, is
+// split by inclusion-exclusion into three tensor products whose images under
+// K = K1 x M1 x M1 + M1 x K1 x M1 + M1 x M1 x K1 are products of 1D vectors.
+
+// int_0^1 g(x) N_i(x) dx, (p+4)-point Gauss per element
+template <typename G> static void load_1d(int p, int n, G g, std::vector<double> &out)
+{
+    const int m = n + p, q = p + 4;
+    std::vector<double> t(n + 2 * p + 1);
+    for (int i = 0; i <= p; i++) { t[i] = 0.0; t[n + p + i] = 1.0; }
+    for (int k = 1; k < n; k++) t[p + k] = (double)k / (double)n;
+    double xg[32], wg[32];
+    gauss_nodes(q, xg, wg);
+    out.assign(m, 0.0);
+    for (int e = 0; e < n; e++) {
+        const int s = p + e;
+        const double a = t[s], h = t[s + 1] - t[s];
+        for (int k = 0; k < q; k++) {
+            const double x = a + 0.5 * (xg[k] + 1.0) * h, w = 0.5 * wg[k] * h;
+            double N[16], D[16];
+            span_basis(t, s, p, x, N, D);
+            const double gx = g(x);
+            for (int l = 0; l <= p; l++) out[s - p + l] += w * (gx * N[l]);
+        }
+    }
+}
+
+// solve the banded SPD system A x = b (m x m dense storage, bandwidth p) by LDL^T
+static void band_spd_solve(int m, int p, const std::vector<double> &A, const std::vector<double> &b,
+                           std::vector<double> &x)
+{
+    std::vector<double> L((size_t)m * m, 0.0), D(m, 0.0);
+    for (int i = 0; i < m; i++) {
+        for (int j = std::max(0, i - p); j < i; j++) {
+            double s = A[(size_t)i * m + j];
+            for (int k = std::max(0, i - p); k < j; k++) s -= L[(size_t)i * m + k] * L[(size_t)j * m + k] * D[k];
+            L[(size_t)i * m + j] = s / D[j];
+        }
+        double s = A[(size_t)i * m + i];
+        for (int k = std::max(0, i - p); k < i; k++) s -= L[(size_t)i * m + k] * L[(size_t)i * m + k] * D[k];
+        D[i] = s;
+    }
+    x = b;
+    for (int i = 0; i < m; i++)
+        for (int k = std::max(0, i - p); k < i; k++) x[i] -= L[(size_t)i * m + k] * x[k];
+    for (int i = 0; i < m; i++) x[i] /= D[i];
+    for (int i = m - 1; i >= 0; i--)
+        for (int k = i + 1; k < std::min(m, i + p + 1); k++) x[i] -= L[(size_t)k * m + i] * x[k];
+}
+
+void iga_cube_size(int p, int n, int64_t *N, int64_t *nnz)
+{
+    const int m = n + p, md[3] = {m - 2, m - 1, m};
+    int64_t nn = 1, nz = 1;
+    for (int d = 0; d < 3; d++) {
+        int64_t b = 0;
+        for (int i = 0; i < md[d]; i++) b += std::min(md[d] - 1, i + p) - std::max(0, i - p) + 1;
+        nn *= md[d];
+        nz *= b;
+    }
+    *N = nn;
+    *nnz = nz;
+}
+
+int iga_cube(int p, int n, int64_t *rp, int32_t *ci, double *v, double *F)
+{
+    if (p < 1 || p > 10 || n < 1 || n + p < 3) return -1;
+    const int m = n + p;
+    const int mx = m - 2, my = m - 1, mz = m, ox = 1, oy = 1, oz = 0;   // kept functions, first kept index
+    std::vector<double> M, K, Fi;
+    matrices_1d(p, n, M, K, Fi);
+    auto M1 = [&](int a, int b) { return M[(size_t)a * m + b]; };
+    auto K1 = [&](int a, int b) { return K[(size_t)a * m + b]; };
+    auto band = [&](int i, int md, int &lo, int &hi) { lo = std::max(0, i - p); hi = std::min(md - 1, i + p); };
+    const int64_t N = (int64_t)mx * my * mz;
+    rp[0] = 0;
+    for (int64_t g = 0; g < N; g++) {
+        const int ix = (int)(g % mx), iy = (int)((g / mx) % my), iz = (int)(g / ((int64_t)mx * my));
+        int a0, a1, b0, b1, c0, c1;
+        band(ix, mx, a0, a1); band(iy, my, b0, b1); band(iz, mz, c0, c1);
+        rp[g + 1] = rp[g] + (int64_t)(a1 - a0 + 1) * (b1 - b0 + 1) * (c1 - c0 + 1);
+    }
+    // load vectors and lifting coefficients
+    std::vector<double> E, S, ax, ay;
+    load_1d(p, n, [](double x) { return std::exp(x); }, E);
+    load_1d(p, n, [](double y) { return std::sin(y); }, S);
+    band_spd_solve(m, p, M, E, ax);
+    band_spd_solve(m, p, M, S, ay);
+    // lifting l = (ax x ay x ax) restricted to {i in {0, m-1}} u {j = 0}
+    //   = (ax_X) x ay x ax + ax x (ay_0) x ax - (ax_X) x (ay_0) x ax,
+    // ax_X: ax on i in {0, m-1} only; ay_0: ay on j = 0 only.
+    std::vector<double> axX(m, 0.0), ay0(m, 0.0);
+    axX[0] = ax[0]; axX[m - 1] = ax[m - 1]; ay0[0] = ay[0];
+    auto mul = [&](const std::vector<double> &A, const std::vector<double> &u, std::vector<double> &r) {
+        r.assign(m, 0.0);
+        for (int i = 0; i < m; i++)
+            for (int j = std::max(0, i - p); j <= std::min(m - 1, i + p); j++) r[i] += A[(size_t)i * m + j] * u[j];
+    };
+    std::vector<double> Mx_, Kx_, MxX, KxX, My_, Ky_, My0, Ky0, Mz_, Kz_;
+    mul(M, ax, Mx_); mul(K, ax, Kx_); mul(M, axX, MxX); mul(K, axX, KxX);
+    mul(M, ay, My_); mul(K, ay, Ky_); mul(M, ay0, My0); mul(K, ay0, Ky0);
+    Mz_ = Mx_; Kz_ = Kx_;                               // z uses ax as well (e^z)
+    // (K u x v x w)_(i,j,k) for the tensor term u x v x w, by its 1D images
+    auto kterm = [&](const std::vector<double> &Mu, const std::vector<double> &Ku, const std::vector<double> &Mv,
+                     const std::vector<double> &Kv, int i, int j, int k) {
+        return (Kz_[k] * Mv[j]) * Mu[i] + (Mz_[k] * Kv[j]) * Mu[i] + (Mz_[k] * Mv[j]) * Ku[i];
+    };
+    const double exp1 = std::exp(1.0), cos1 = std::cos(1.0);
+    parallel_for(N, [&](int64_t b, int64_t e) {
+        for (int64_t g = b; g < e; g++) {
+            const int ix = (int)(g % mx), iy = (int)((g / mx) % my), iz = (int)(g / ((int64_t)mx * my));
+            const int i = ix + ox, j = iy + oy, k = iz + oz;   // full-space indices
+            int a0, a1, b0, b1, c0, c1;
+            band(ix, mx, a0, a1); band(iy, my, b0, b1); band(iz, mz, c0, c1);
+            int64_t pos = rp[g];
+            for (int jz = c0; jz <= c1; jz++)
+                for (int jy = b0; jy <= b1; jy++)
+                    for (int jx = a0; jx <= a1; jx++) {
+                        const int ii = jx + ox, jj = jy + oy, kk = jz + oz;
+                        const double t1 = (K1(k, kk) * M1(j, jj)) * M1(i, ii);
+                        const double t2 = (M1(k, kk) * K1(j, jj)) * M1(i, ii);
+                        const double t3 = (M1(k, kk) * M1(j, jj)) * K1(i, ii);
+                        ci[pos] = (int32_t)(jx + (int64_t)mx * (jy + (int64_t)my * jz));
+                        v[pos] = (t1 + t2) + t3;
+                        pos++;
+                    }
+            if (F) {
+                double f = -(E[i] * S[j]) * E[k];               // source -e^x sin y e^z
+                if (j == m - 1) f += cos1 * (E[i] * E[k]);        // y = 1: e^{x+z} cos 1
+                if (k == 0) f -= E[i] * S[j];                   // z = 0: -e^x sin y
+                if (k == m - 1) f += exp1 * (E[i] * S[j]);        // z = 1: e^{x+1} sin y
+                const double lift = kterm(MxX, KxX, My_, Ky_, i, j, k) + kterm(Mx_, Kx_, My0, Ky0, i, j, k) -
+                                    kterm(MxX, KxX, My0, Ky0, i, j, k);
+                F[g] = f - lift;
+            }
+        }
+    });
+    return 0;
+}
+
 // Variable-coefficient stiffness -div(kappa grad u) on the unit cube, kappa by
 // its parameters (kappa = exp(0.5 sum_k a_k cos(2 pi m_k . x))), (p+1)^3 Gauss
 // points per element, sum factorization per element (contracting x, then y,

@@ -1759,6 +1759,20 @@ amg_status amg_iga_poisson(int d, int p, int n, int64_t *row_ptr, int32_t *col, 
     return AMG_OK;
 }
 
+amg_status amg_iga_cube_size(int p, int n, int64_t *N, int64_t *nnz)
+{
+    if (p < 1 || p > 10 || n < 1 || n + p < 3 || !N || !nnz) { set_err("need 1 <= p <= 10, n >= 1, n + p >= 3"); return AMG_ERR_ARG; }
+    amgiga::iga_cube_size(p, n, N, nnz);
+    return AMG_OK;
+}
+
+amg_status amg_iga_cube(int p, int n, int64_t *row_ptr, int32_t *col, double *val, double *F)
+{
+    if (!row_ptr || !col || !val) { set_err("NULL output"); return AMG_ERR_ARG; }
+    if (amgiga::iga_cube(p, n, row_ptr, col, val, F)) { set_err("bad p or n"); return AMG_ERR_ARG; }
+    return AMG_OK;
+}
+
 amg_status amg_level_features(const amg_ctx *c, int level, float *feat)
 {
     if (!c || !feat || level < 0 || level >= c->nlev) { set_err("bad level or NULL"); return AMG_ERR_ARG; }

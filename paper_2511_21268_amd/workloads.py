@@ -15,6 +15,8 @@ CONFIGS = {
     "c3": dict(d=3, p=4, n=96, kind="poisson"),     # N = 98^3   = 941,192
     "c4": dict(d=3, p=3, n=128, kind="poisson"),    # N = 129^3  = 2,146,689
     "c5": dict(d=3, p=5, n=64, kind="diffusion", itmax=6000),   # N = 67^3 = 300,763; plain l1: ~3000 iterations
+    # the paper's cube benchmark (Sec. 5.1), its largest p = 3 case of Table 1(b)
+    "cube": dict(d=3, p=3, n=96, kind="cube"),     # N = 95*96*97 = 941,094
 }
 
 
