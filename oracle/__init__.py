@@ -39,7 +39,9 @@ f64p = C.POINTER(C.c_double)
 class Params(C.Structure):
     _fields_ = [("sweeps_per_level", C.c_int), ("max_coarse", C.c_int), ("max_levels", C.c_int),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("match_positive_only", C.c_int),
-                ("smoother", C.c_int)]
+                ("smoother", C.c_int), ("smooth_prolong", C.c_int), ("cheb_degree", C.c_int),
+                ("coarse_solver", C.c_int), ("coarse_itmax", C.c_int), ("omega", C.c_double),
+                ("coarse_tol", C.c_double)]
 
 
 def lib():
@@ -86,6 +88,11 @@ def lib():
         L.or_level_agg.argtypes = [C.c_void_p, C.c_int, i32p, f64p, f64p, f64p]
         L.or_coarse_factor.argtypes = [C.c_void_p, f64p]
         L.or_set_poly.argtypes = [C.c_void_p, C.c_int, f64p]
+        L.or_level_pnnz.argtypes = [C.c_void_p, C.c_int]
+        L.or_level_pnnz.restype = C.c_int64
+        L.or_level_prolongator.argtypes = [C.c_void_p, C.c_int, i64p, i32p, f64p]
+        L.or_cheb4.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, f64p, f64p, C.c_int, C.c_int]
+        L.or_cg_jacobi.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, f64p, C.c_double, C.c_int]
         L.or_spmv.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, f64p]
         L.or_dot.argtypes = [C.c_int64, f64p, f64p]
         L.or_dot.restype = C.c_double
@@ -348,7 +355,7 @@ class Hierarchy:
         prm = Params()
         lib().or_params_default(C.byref(prm))
         for k, val in kw.items():
-            setattr(prm, k, int(val))
+            setattr(prm, k, float(val) if k in ("omega", "coarse_tol") else int(val))
         self._keep = (_i64(rp), _i32(ci), _f64(v))
         rp, ci, v = self._keep
         n = len(rp) - 1
@@ -397,6 +404,16 @@ class Hierarchy:
         c = _f64(coef)
         return lib().or_set_poly(self.h, l, _p(c, f64p))
 
+    def prolongator(self, l):
+        """The smoothed prolongator of level l as CSR (None without smoothing)."""
+        nz = lib().or_level_pnnz(self.h, l)
+        if nz == 0:
+            return None
+        n, _ = self.level_info(l)
+        rp = np.zeros(n + 1, np.int64); ci = np.zeros(nz, np.int32); v = np.zeros(nz)
+        lib().or_level_prolongator(self.h, l, _p(rp, i64p), _p(ci, i32p), _p(v, f64p))
+        return rp, ci, v
+
     def opc(self):
         nz0 = self.level_info(0)[1]
         return sum(self.level_info(l)[1] for l in range(self.nlevels)) / nz0
@@ -413,3 +430,21 @@ class Hierarchy:
         rc = lib().or_pcg(self.h, _p(F, f64p), _p(u, f64p), tol, itmax, int(flexible),
                           C.byref(it), C.byref(rel), _p(hist, f64p))
         return dict(rc=rc, u=u, iters=it.value, relres=rel.value, hist=hist[: it.value + 1].copy())
+
+
+def cheb4(rp, ci, v, invd, f, x0=None, degree=8):
+    """Fourth-kind Chebyshev smoother of the given degree (x0 None: from zero)."""
+    rp, ci, v, invd, f = _i64(rp), _i32(ci), _f64(v), _f64(invd), _f64(f)
+    x = np.zeros_like(f) if x0 is None else _f64(np.array(x0, copy=True))
+    lib().or_cheb4(len(f), _p(rp, i64p), _p(ci, i32p), _p(v, f64p), _p(invd, f64p), _p(f, f64p),
+                   _p(x, f64p), int(x0 is None), int(degree))
+    return x
+
+
+def cg_jacobi(rp, ci, v, b, tol=1e-4, itmax=30):
+    """Jacobi-preconditioned CG from zero; returns (x, iterations)."""
+    rp, ci, v, b = _i64(rp), _i32(ci), _f64(v), _f64(b)
+    x = np.zeros_like(b)
+    it = lib().or_cg_jacobi(len(b), _p(rp, i64p), _p(ci, i32p), _p(v, f64p), _p(b, f64p), _p(x, f64p),
+                            float(tol), int(itmax))
+    return x, it

@@ -26,7 +26,18 @@
  *    hierarchy stops when a level has at most max_coarse rows (dense Cholesky
  *    there); if a level shrinks by less than 10% the previous level becomes the
  *    coarsest when it has at most 2000 rows, otherwise the setup fails;
- *  - l1 diagonal: d_i = k_ii, then + |k_ij| for j ascending, j != i.
+ *  - l1 diagonal: d_i = k_ii, then + |k_ij| for j ascending, j != i;
+ *  - smoothed prolongator (Sec. 3.1, "Variants and efficiency"), on request:
+ *    P' = (I - omega D^{-1} K) P with the tentative P of the m composed sweeps,
+ *    D the l1 diagonal (the paper's only D; lambda(D^{-1}K) <= 1, so
+ *    omega = 4/3 needs no spectral estimate).  Entry by entry:
+ *    T_iJ = sum over row i's stored j with agg(j) = J, ascending j, of k_ij pc_j
+ *    from +0.0; P'_iJ = [J = agg(i)] pc_i - (omega invd_i) T_iJ on the pattern
+ *    of T (exact zeros kept).  The coarse matrix is then (P'^T K) P':
+ *    B_Ij = sum over i ascending of P'_iI k_ij, then
+ *    K_c,IJ = sum over j ascending of B_Ij P'_jJ, each from +0.0; the
+ *    unsmoothed product of the last sweep is not used.  The test vector of the
+ *    next level is still the pairwise restriction.
  */
 #include "oracle.h"
 #include <math.h>
@@ -46,6 +57,12 @@ void or_params_default(or_params *p)
     p->nu_post = 1;
     p->match_positive_only = 0;
     p->smoother = 0;
+    p->smooth_prolong = 0;
+    p->cheb_degree = 8;
+    p->coarse_solver = 0;
+    p->coarse_itmax = 30;
+    p->omega = 4.0 / 3.0;
+    p->coarse_tol = 1e-4;
 }
 
 double or_cij(double kij, double kii, double kjj, double wi, double wj)
@@ -276,6 +293,116 @@ static csr_t galerkin(const csr_t *K, int64_t nc, const int32_t *agg, const doub
     return C;
 }
 
+/* P' = (I - omega D^{-1} K) P for the one-entry-per-row tentative P. */
+static csr_t smooth_p(const csr_t *K, const double *invd, int64_t nc, const int32_t *agg, const double *pc,
+                      double omega)
+{
+    csr_t P;
+    P.n = K->n;
+    P.rp = malloc(sizeof(int64_t) * (K->n + 1));
+    P.ci = malloc(sizeof(int32_t) * (K->nnz > 0 ? K->nnz : 1));
+    P.v = malloc(sizeof(double) * (K->nnz > 0 ? K->nnz : 1));
+    double *acc = malloc(sizeof(double) * nc);
+    char *mark = calloc(nc, 1);
+    int32_t *cols = malloc(sizeof(int32_t) * (nc > 0 ? nc : 1));
+    int64_t pos = 0;
+    P.rp[0] = 0;
+    for (int64_t i = 0; i < K->n; i++) {
+        int64_t nt = 0;
+        for (int64_t e = K->rp[i]; e < K->rp[i + 1]; e++) {
+            int32_t J = agg[K->ci[e]];
+            if (!mark[J]) { mark[J] = 1; acc[J] = 0.0; cols[nt++] = J; }
+            acc[J] = acc[J] + K->v[e] * pc[K->ci[e]];
+        }
+        qsort(cols, nt, sizeof(int32_t), cmp_i32);
+        const double s = omega * invd[i];
+        for (int64_t k = 0; k < nt; k++) {
+            int32_t J = cols[k];
+            double tent = (J == agg[i]) ? pc[i] : 0.0;
+            P.ci[pos] = J;
+            P.v[pos] = tent - s * acc[J];
+            mark[J] = 0;
+            pos++;
+        }
+        P.rp[i + 1] = pos;
+    }
+    P.nnz = pos;
+    free(acc); free(mark); free(cols);
+    return P;
+}
+
+/* K_c = (P^T K) P for a general sparse P (n x nc). */
+static csr_t galerkin_general(const csr_t *K, const csr_t *P, int64_t nc)
+{
+    const int64_t n = K->n;
+    /* columns of P: for coarse J the rows i (ascending) with their values */
+    int64_t *tp = calloc(nc + 1, sizeof(int64_t));
+    for (int64_t e = 0; e < P->nnz; e++) tp[P->ci[e] + 1]++;
+    for (int64_t J = 0; J < nc; J++) tp[J + 1] += tp[J];
+    int64_t *ti = malloc(sizeof(int64_t) * (P->nnz > 0 ? P->nnz : 1));
+    double *tv = malloc(sizeof(double) * (P->nnz > 0 ? P->nnz : 1));
+    int64_t *fill = malloc(sizeof(int64_t) * (nc > 0 ? nc : 1));
+    for (int64_t J = 0; J < nc; J++) fill[J] = tp[J];
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t e = P->rp[i]; e < P->rp[i + 1]; e++) {
+            int64_t q = fill[P->ci[e]]++;
+            ti[q] = i;
+            tv[q] = P->v[e];
+        }
+    free(fill);
+    double *accB = malloc(sizeof(double) * n), *accC = malloc(sizeof(double) * nc);
+    char *markB = calloc(n, 1), *markC = calloc(nc, 1);
+    int32_t *colB = malloc(sizeof(int32_t) * n), *colC = malloc(sizeof(int32_t) * (nc > 0 ? nc : 1));
+    csr_t C;
+    C.n = nc;
+    int64_t cap = K->nnz > 16 ? K->nnz : 16;
+    C.rp = malloc(sizeof(int64_t) * (nc + 1));
+    C.ci = malloc(sizeof(int32_t) * cap);
+    C.v = malloc(sizeof(double) * cap);
+    C.rp[0] = 0;
+    int64_t pos = 0;
+    for (int64_t I = 0; I < nc; I++) {
+        /* B_I = sum_i P_iI K_i, i ascending */
+        int64_t nb = 0;
+        for (int64_t q = tp[I]; q < tp[I + 1]; q++) {
+            int64_t i = ti[q];
+            for (int64_t e = K->rp[i]; e < K->rp[i + 1]; e++) {
+                int32_t j = K->ci[e];
+                if (!markB[j]) { markB[j] = 1; accB[j] = 0.0; colB[nb++] = j; }
+                accB[j] = accB[j] + tv[q] * K->v[e];
+            }
+        }
+        qsort(colB, nb, sizeof(int32_t), cmp_i32);
+        /* C_I = sum_j B_Ij P_j, j ascending */
+        int64_t ncol = 0;
+        for (int64_t k = 0; k < nb; k++) {
+            int32_t j = colB[k];
+            for (int64_t e = P->rp[j]; e < P->rp[j + 1]; e++) {
+                int32_t J = P->ci[e];
+                if (!markC[J]) { markC[J] = 1; accC[J] = 0.0; colC[ncol++] = J; }
+                accC[J] = accC[J] + accB[j] * P->v[e];
+            }
+            markB[j] = 0;
+        }
+        qsort(colC, ncol, sizeof(int32_t), cmp_i32);
+        if (pos + ncol > cap) {
+            while (pos + ncol > cap) cap *= 2;
+            C.ci = realloc(C.ci, sizeof(int32_t) * cap);
+            C.v = realloc(C.v, sizeof(double) * cap);
+        }
+        for (int64_t k = 0; k < ncol; k++) {
+            C.ci[pos] = colC[k];
+            C.v[pos] = accC[colC[k]];
+            markC[colC[k]] = 0;
+            pos++;
+        }
+        C.rp[I + 1] = pos;
+    }
+    C.nnz = pos;
+    free(tp); free(ti); free(tv); free(accB); free(accC); free(markB); free(markC); free(colB); free(colC);
+    return C;
+}
+
 void or_l1_invdiag(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, double *invd)
 {
     for (int64_t i = 0; i < n; i++) {
@@ -354,6 +481,7 @@ static int factor_level(or_hier *h, int l)
 {
     or_level *L = &h->lev[l];
     int nl = (int)L->n;
+    if (h->prm.coarse_solver == 1) { h->nlev = l + 1; return 0; }
     h->chol = calloc((size_t)nl * nl, sizeof(double));
     for (int i = 0; i < nl; i++)
         for (int64_t e = L->rp[i]; e < L->rp[i + 1]; e++)
@@ -421,6 +549,13 @@ int or_setup(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
         }
         L->agg = agg;
         L->pc = pc;
+        if (h->prm.smooth_prolong) {
+            csr_t Kl = { L->n, L->nnz, L->rp, L->ci, L->v };
+            csr_t P = smooth_p(&Kl, L->invd, nc, agg, pc, h->prm.omega);
+            free(cur.rp); free(cur.ci); free(cur.v);
+            cur = galerkin_general(&Kl, &P, nc);
+            L->prp = P.rp; L->pci = P.ci; L->pv = P.v; L->pnnz = P.nnz;
+        }
         level_from(&h->lev[l + 1], cur, cw);
         if (verbose) {
             fprintf(stderr, "oracle setup: level %d done: n=%lld nnz=%lld\n", l + 1, (long long)cur.n,
@@ -440,6 +575,7 @@ void or_free(or_hier *h)
         or_level *L = &h->lev[l];
         free(L->rp); free(L->ci); free(L->v); free(L->invd); free(L->w);
         free(L->agg); free(L->pc);
+        free(L->prp); free(L->pci); free(L->pv);
     }
     free(h->lev);
     free(h->chol);
@@ -475,4 +611,15 @@ void or_coarse_factor(const or_hier *h, double *L)
 {
     int nl = (int)h->lev[h->nlev - 1].n;
     memcpy(L, h->chol, sizeof(double) * nl * nl);
+}
+
+int64_t or_level_pnnz(const or_hier *h, int l) { return h->lev[l].prp ? h->lev[l].pnnz : 0; }
+
+void or_level_prolongator(const or_hier *h, int l, int64_t *rp, int32_t *ci, double *v)
+{
+    const or_level *L = &h->lev[l];
+    if (!L->prp) return;
+    memcpy(rp, L->prp, sizeof(int64_t) * (L->n + 1));
+    memcpy(ci, L->pci, sizeof(int32_t) * L->pnnz);
+    memcpy(v, L->pv, sizeof(double) * L->pnnz);
 }

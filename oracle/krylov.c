@@ -13,6 +13,24 @@
  *  - degree-4 polynomial smoother: u <- u + sum_{k=0..3} a_k (D^{-1}K)^k D^{-1} r
  *    with r = f - K u, evaluated by Horner's rule; its error polynomial is
  *    e(t) = 1 - sum_k a_k t^{k+1} on the spectrum t of D^{-1}K, in (0, 1];
+ *  - fourth-kind Chebyshev smoother (Sec. 3.2: Chebyshev acceleration of
+ *    l1-Jacobi without spectral estimates, after Lottes' fourth-kind
+ *    polynomials; the paper's optimized coefficients are not given, the
+ *    unoptimized fourth-kind polynomial is taken): k sweeps leave the error
+ *    e_k = W_k(I - 2 D^{-1}K) e_0 / (2k+1), W_k the fourth-kind Chebyshev
+ *    polynomial, W_k(cos t) = sin((k + 1/2) t) / sin(t/2), on the spectrum of
+ *    D^{-1}K in (0, 1].  Written as the three-term recurrence of W_k on the
+ *    iterates with the true residual r_j = f - K x_j:
+ *      x_1 = x_0 + (4/3) D^{-1} r_0,
+ *      (2j+3) x_{j+1} = 2(2j+1) x_j + 4(2j+1) D^{-1} r_j - (2j-1) x_{j-1};
+ *    nu_pre / nu_post count such smoothers; the same polynomial before and
+ *    after keeps the V-cycle symmetric;
+ *  - coarsest level (coarse_solver 1, Sec. 5.1): CG preconditioned by one
+ *    Jacobi sweep z = diag(K)^{-1} r from x = 0 (a Jacobi weight cancels in
+ *    CG), to ||r|| <= coarse_tol ||f|| or coarse_itmax iterations; the
+ *    V-cycle is then a variable preconditioner (use FCG);
+ *  - restriction and prolongation with a smoothed prolongator: f_c = P'^T r
+ *    summed over the rows i ascending, u_i += sum_J P'_iJ e_J ascending J;
  *  - CG: Hestenes-Stiefel PCG; FCG(1): alpha = (p,r)/(p,q),
  *    beta = -(z_{k+1}, q_k)/(p_k, q_k);
  *  - stop when ||r_k||_2 <= tol ||F||_2 on the recursive residual; iters counts
@@ -72,19 +90,97 @@ static void sweep(const or_level *L, int poly, const double *f, double *u,
     for (int64_t i = 0; i < L->n; i++) u[i] = u[i] + c[i];
 }
 
+void or_cheb4(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *invd,
+              const double *f, double *x, int x0_zero, int degree)
+{
+    double *xp = malloc(sizeof(double) * n), *r = malloc(sizeof(double) * n);
+    double *xn = malloc(sizeof(double) * n);
+    if (x0_zero)
+        for (int64_t i = 0; i < n; i++) x[i] = 0.0;
+    for (int j = 0; j < degree; j++) {
+        or_spmv(n, rp, ci, v, x, r);
+        for (int64_t i = 0; i < n; i++) r[i] = f[i] - r[i];
+        if (j == 0) {
+            for (int64_t i = 0; i < n; i++) {
+                xp[i] = x[i];
+                x[i] = x[i] + (4.0 / 3.0) * (invd[i] * r[i]);
+            }
+            continue;
+        }
+        const double a = 2.0 * (2 * j + 1), b = 4.0 * (2 * j + 1), c = (double)(2 * j - 1), d = (double)(2 * j + 3);
+        for (int64_t i = 0; i < n; i++) xn[i] = (a * x[i] + b * (invd[i] * r[i]) - c * xp[i]) / d;
+        for (int64_t i = 0; i < n; i++) { xp[i] = x[i]; x[i] = xn[i]; }
+    }
+    free(xp); free(r); free(xn);
+}
+
+int or_cg_jacobi(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *b,
+                 double *x, double tol, int itmax)
+{
+    double *r = malloc(sizeof(double) * n), *z = malloc(sizeof(double) * n);
+    double *p = malloc(sizeof(double) * n), *q = malloc(sizeof(double) * n);
+    double *dj = malloc(sizeof(double) * n);
+    for (int64_t i = 0; i < n; i++) {
+        double kii = 0.0;
+        for (int64_t e = rp[i]; e < rp[i + 1]; e++)
+            if (ci[e] == i) kii = v[e];
+        dj[i] = 1.0 / kii;
+        x[i] = 0.0;
+        r[i] = b[i];
+    }
+    int it = 0;
+    const double nb = sqrt(or_dot(n, b, b));
+    if (nb > 0.0) {
+        for (int64_t i = 0; i < n; i++) { z[i] = dj[i] * r[i]; p[i] = z[i]; }
+        double rz = or_dot(n, r, z);
+        while (it < itmax) {
+            or_spmv(n, rp, ci, v, p, q);
+            double pq = or_dot(n, p, q);
+            if (!(pq > 0.0)) break;
+            double alpha = rz / pq;
+            for (int64_t i = 0; i < n; i++) {
+                x[i] = x[i] + alpha * p[i];
+                r[i] = r[i] - alpha * q[i];
+            }
+            it++;
+            if (sqrt(or_dot(n, r, r)) <= tol * nb) break;
+            for (int64_t i = 0; i < n; i++) z[i] = dj[i] * r[i];
+            double rzn = or_dot(n, r, z);
+            double beta = rzn / rz;
+            rz = rzn;
+            for (int64_t i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
+        }
+    }
+    free(r); free(z); free(p); free(q); free(dj);
+    return it;
+}
+
+static void coarsest_solve(const or_hier *h, const or_level *L, const double *f, double *u)
+{
+    if (h->prm.coarse_solver == 1)
+        or_cg_jacobi(L->n, L->rp, L->ci, L->v, f, u, h->prm.coarse_tol, h->prm.coarse_itmax);
+    else
+        or_chol_solve((int)L->n, h->chol, f, u);
+}
+
 void or_vcycle(const or_hier *h, int l, const double *f, double *u)
 {
     const or_level *L = &h->lev[l];
     int64_t n = L->n;
     if (l == h->nlev - 1) {
-        or_chol_solve((int)n, h->chol, f, u);
+        coarsest_solve(h, L, f, u);
         return;
     }
-    int poly = h->prm.smoother == 1;
+    int poly = h->prm.smoother == 1, cheb = h->prm.smoother == 2;
     double *r = malloc(sizeof(double) * n), *c = malloc(sizeof(double) * n);
     double *tmp = malloc(sizeof(double) * n);
     /* 1. pre-smoothing from u = 0 */
-    if (h->prm.nu_pre > 0) {
+    if (cheb) {
+        for (int s = 0; s < h->prm.nu_pre; s++)
+            or_cheb4(n, L->rp, L->ci, L->v, L->invd, f, u, s == 0, h->prm.cheb_degree);
+        if (h->prm.nu_pre <= 0)
+            for (int64_t i = 0; i < n; i++) u[i] = 0.0;
+    } else if (h->prm.nu_pre > 0) {
         smoother_apply(L, poly, f, u, tmp);
         for (int s = 1; s < h->prm.nu_pre; s++) sweep(L, poly, f, u, r, c, tmp);
     } else {
@@ -95,13 +191,30 @@ void or_vcycle(const or_hier *h, int l, const double *f, double *u)
     for (int64_t i = 0; i < n; i++) r[i] = f[i] - r[i];
     int64_t nc = h->lev[l + 1].n;
     double *fc = calloc(nc, sizeof(double)), *ec = malloc(sizeof(double) * nc);
-    for (int64_t i = 0; i < n; i++) fc[L->agg[i]] = fc[L->agg[i]] + L->pc[i] * r[i];
+    if (L->prp) {
+        for (int64_t i = 0; i < n; i++)
+            for (int64_t e = L->prp[i]; e < L->prp[i + 1]; e++)
+                fc[L->pci[e]] = fc[L->pci[e]] + L->pv[e] * r[i];
+    } else {
+        for (int64_t i = 0; i < n; i++) fc[L->agg[i]] = fc[L->agg[i]] + L->pc[i] * r[i];
+    }
     /* 3. coarse solve */
     or_vcycle(h, l + 1, fc, ec);
     /* 4. prolongate and correct */
-    for (int64_t i = 0; i < n; i++) u[i] = u[i] + L->pc[i] * ec[L->agg[i]];
+    if (L->prp) {
+        for (int64_t i = 0; i < n; i++) {
+            double s = 0.0;
+            for (int64_t e = L->prp[i]; e < L->prp[i + 1]; e++) s = s + L->pv[e] * ec[L->pci[e]];
+            u[i] = u[i] + s;
+        }
+    } else {
+        for (int64_t i = 0; i < n; i++) u[i] = u[i] + L->pc[i] * ec[L->agg[i]];
+    }
     /* 5. post-smoothing */
-    for (int s = 0; s < h->prm.nu_post; s++) sweep(L, poly, f, u, r, c, tmp);
+    for (int s = 0; s < h->prm.nu_post; s++) {
+        if (cheb) or_cheb4(n, L->rp, L->ci, L->v, L->invd, f, u, 0, h->prm.cheb_degree);
+        else sweep(L, poly, f, u, r, c, tmp);
+    }
     free(r); free(c); free(tmp); free(fc); free(ec);
 }
 

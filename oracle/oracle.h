@@ -87,7 +87,14 @@ typedef struct {
     int max_levels;
     int nu_pre, nu_post;    /* l1-Jacobi sweeps                                 */
     int match_positive_only;/* 1: only edges with c > 1 are eligible           */
-    int smoother;           /* 0: l1-Jacobi, 1: degree-4 polynomial            */
+    int smoother;           /* 0: l1-Jacobi, 1: degree-4 polynomial,
+                               2: fourth-kind Chebyshev of degree cheb_degree */
+    int smooth_prolong;     /* 1: smoothed prolongator (I - omega D^{-1} K) P  */
+    int cheb_degree;        /* smoother 2: degree = matrix products per sweep */
+    int coarse_solver;      /* 0: dense Cholesky; 1: CG with Jacobi            */
+    int coarse_itmax;       /* coarse_solver 1: iteration limit (30)          */
+    double omega;           /* prolongator damping (4/3)                      */
+    double coarse_tol;      /* coarse_solver 1: relative residual (1e-4)      */
 } or_params;
 
 void or_params_default(or_params *p);
@@ -100,6 +107,9 @@ typedef struct {
     int32_t *agg;           /* aggregate (coarse index) of each row; ell < L  */
     double *pc;             /* prolongator coefficient of each row; ell < L   */
     double poly[4];         /* polynomial smoother coefficients (smoother 1)  */
+    int64_t *prp; int32_t *pci; double *pv;   /* smoothed prolongator, n x n_c
+                               CSR (smooth_prolong; NULL otherwise)           */
+    int64_t pnnz;
 } or_level;
 
 typedef struct {
@@ -147,6 +157,9 @@ void or_level_matrix(const or_hier *h, int l, int64_t *rp, int32_t *ci, double *
 void or_level_agg(const or_hier *h, int l, int32_t *agg, double *pc, double *invd, double *w);
 void or_coarse_factor(const or_hier *h, double *L);
 int  or_set_poly(or_hier *h, int l, const double *coef);
+/* Size and copy of the smoothed prolongator of level l (nnz 0: none). */
+int64_t or_level_pnnz(const or_hier *h, int l);
+void or_level_prolongator(const or_hier *h, int l, int64_t *rp, int32_t *ci, double *v);
 
 /* ---------------- krylov.c : V-cycle and CG (Sec. 3, 4) ---------------- */
 
@@ -160,6 +173,16 @@ void or_vcycle(const or_hier *h, int l, const double *r, double *z);
  * -5 breakdown.  hist (may be NULL) receives ||r_k||/||F|| for k = 0..iters. */
 int  or_pcg(const or_hier *h, const double *F, double *u, double tol, int itmax,
             int flexible, int *iters, double *relres, double *hist);
+/* Fourth-kind Chebyshev smoother of the given degree for K x = f with the
+ * l1 diagonal (invd = 1/d): x in: initial guess (ignored, taken as 0, when
+ * x0_zero), out: the smoothed iterate. */
+void or_cheb4(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *invd,
+              const double *f, double *x, int x0_zero, int degree);
+/* CG with the Jacobi preconditioner diag(K)^{-1} from x = 0: stops when
+ * ||r|| <= tol ||b|| (recursive residual) or after itmax iterations.
+ * Returns the iteration count. */
+int  or_cg_jacobi(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *b,
+                  double *x, double tol, int itmax);
 /* l1-Jacobi-preconditioned polynomial smoother error polynomial check. */
 int  or_poly_accept(const double *coef);
 
