@@ -56,7 +56,9 @@ typedef struct {
     int vcycle_fp32;        /* 0: V-cycle in FP64; 1: V-cycle in FP32 (outer
                                residual, dots, coarse Cholesky stay FP64)       */
     int smoother;           /* 0: l1-Jacobi (Sec. 3.2); 1: degree-4 polynomial
-                               in D^{-1}K (coefficients by amg_set_poly_coeffs) */
+                               in D^{-1}K (coefficients by amg_set_poly_coeffs);
+                               2: Chebyshev acceleration of l1-Jacobi (Sec. 3.2,
+                               Sec. 5.1), fourth kind, degree cheb_degree      */
     int krylov;             /* 0: CG; 1: flexible CG, FCG(1) (Sec. 3.1 end)     */
     int match_positive_only;/* 0: every edge eligible (default);
                                1: only edges with c_ij > 1 (log c_ij > 0)       */
@@ -70,6 +72,25 @@ typedef struct {
                                than its longest row stores that list once
                                instead of per-entry indices (stencil matrices);
                                0: per-entry indices in every slice              */
+    /* The paper's default preconditioner (Sec. 3.1 "Variants and efficiency",
+     * Sec. 5.1) is sweeps_per_level = 3, smooth_prolong = 1, smoother = 2 with
+     * cheb_degree 8 / 12 / 14 / 16 for p = 3 / 4 / 5 / 6, coarse_solver = 1 and
+     * krylov = 1.  Any of smoother 2, smooth_prolong 1 or coarse_solver 1 takes
+     * the FP64 single-vector V-cycle: vcycle_fp32 = 0, nrhs = 1, and with
+     * smoother 2 nu_pre = nu_post = 1.                                         */
+    int smooth_prolong;     /* 0 (default): tentative prolongator P;
+                               1: P' = (I - omega D^{-1} K) P, D the l1 diagonal,
+                               coarse matrix (P'^T K) P'                        */
+    int cheb_degree;        /* smoother 2: matrix products per smoothing step,
+                               1..64; default 8                                 */
+    int coarse_solver;      /* 0 (default): dense Cholesky of the coarsest level;
+                               1: CG preconditioned by one Jacobi sweep, to
+                               coarse_tol or coarse_itmax iterations (Sec. 5.1;
+                               a variable preconditioner: use krylov = 1)       */
+    int coarse_itmax;       /* coarse_solver 1: 1..1000; default 30            */
+    double omega;           /* smooth_prolong: damping, (0, 2]; default 4/3     */
+    double coarse_tol;      /* coarse_solver 1: relative residual, >= 0;
+                               default 1e-4                                     */
 } amg_params;
 
 /* Fill p with the defaults above.  p must not be NULL. */
@@ -172,6 +193,14 @@ amg_status amg_get_aggregates(const amg_ctx *c, int level, int32_t *agg, double 
  * amg_get_level_info).  Any output may be NULL. */
 amg_status amg_get_coarse_matrix(const amg_ctx *c, int level, int64_t *row_ptr, int32_t *col,
                                  double *val);
+
+/* Host CSR copy of the smoothed prolongator (I - omega D^{-1} K) P of level
+ * `level` (0 .. levels-2; rows n_level, columns n_{level+1}; Sec. 3.1
+ * "Variants and efficiency").  *nnz receives its stored entries (0 when the
+ * context was built without smooth_prolong); row_ptr (n_level + 1), col and val
+ * may each be NULL, e.g. to query the size first. */
+amg_status amg_get_prolongator(const amg_ctx *c, int level, int64_t *nnz, int64_t *row_ptr, int32_t *col,
+                               double *val);
 
 /* Host-only build of the same hierarchy (no device memory, no HIP call): for
  * inspecting aggregates, coarse matrices and operator complexity on a machine

@@ -6,7 +6,9 @@ compatible weighted matching, and a solve phase made of hand-written HIP
 kernels.  This package is its thin binding; `workloads` holds the seeded
 synthetic inputs.
 """
-from .amg import (AmgError, Context, iga_cube, iga_diffusion, iga_poisson, lib, match, params_default,  # noqa: F401
+from .amg import (AmgError, Context, iga_cube, iga_diffusion, iga_poisson, lib, match, paper_default,  # noqa: F401
+                  params_default,
                   sell_spmv_host)
 
-__all__ = ["AmgError", "Context", "iga_cube", "iga_diffusion", "iga_poisson", "lib", "match", "params_default", "sell_spmv_host"]
+__all__ = ["AmgError", "Context", "iga_cube", "iga_diffusion", "iga_poisson", "lib", "match", "paper_default",
+           "params_default", "sell_spmv_host"]

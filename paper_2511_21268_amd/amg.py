@@ -24,7 +24,7 @@ EXPORTS = ["amg_params_default", "amg_setup", "pcg_solve", "pcg_solve_batched", 
            "amg_iga_poisson_size", "amg_iga_poisson", "amg_iga_diffusion", "amg_level_features",
            "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_adam", "amg_set_learned_poly",
            "amg_get_batched_variant", "amg_set_batched_variant", "amg_set_option", "amg_sell_spmv_host",
-           "amg_iga_cube_size", "amg_iga_cube"]
+           "amg_iga_cube_size", "amg_iga_cube", "amg_get_prolongator"]
 AMG_OPT_GRAPH, AMG_OPT_FUSE_POST = 1, 2
 MLP_NPARAM, MLP_NFEAT, MLP_NACT, MLP_NDEL = 4996, 8, 128, 132
 
@@ -39,7 +39,20 @@ class Params(C.Structure):
     _fields_ = [("sweeps_per_level", C.c_int), ("max_coarse", C.c_int), ("max_levels", C.c_int),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("vcycle_fp32", C.c_int), ("smoother", C.c_int),
                 ("krylov", C.c_int), ("match_positive_only", C.c_int), ("itmax", C.c_int), ("nrhs", C.c_int),
-                ("slice_offsets", C.c_int)]
+                ("slice_offsets", C.c_int), ("smooth_prolong", C.c_int), ("cheb_degree", C.c_int),
+                ("coarse_solver", C.c_int), ("coarse_itmax", C.c_int), ("omega", C.c_double),
+                ("coarse_tol", C.c_double)]
+
+# The paper's default preconditioner (Sec. 3.1 variants, Sec. 5.1): aggregates
+# of 8, smoothed prolongator, Chebyshev-accelerated l1-Jacobi of degree
+# 8 / 12 / 14 / 16 for p = 3..6, CG coarse solver, flexible CG outside.
+CHEB_DEGREE = {3: 8, 4: 12, 5: 14, 6: 16}
+
+
+def paper_default(p):
+    """amg_params of the paper's default preconditioner for spline degree p."""
+    return dict(sweeps_per_level=3, smooth_prolong=1, smoother=2, cheb_degree=CHEB_DEGREE.get(p, 8),
+                coarse_solver=1, krylov=1)
 
 
 i64p = C.POINTER(C.c_int64)
@@ -69,6 +82,7 @@ def lib():
         L.amg_get_level_info.argtypes = [vp, C.c_int, i64p, i64p]
         L.amg_get_aggregates.argtypes = [vp, C.c_int, i32p, f64p]
         L.amg_get_coarse_matrix.argtypes = [vp, C.c_int, i64p, i32p, f64p]
+        L.amg_get_prolongator.argtypes = [vp, C.c_int, i64p, i64p, i32p, f64p]
         L.amg_destroy.argtypes = [vp]
         L.amg_destroy.restype = None
         L.amg_last_error.restype = C.c_char_p
@@ -110,7 +124,7 @@ def params_default(**kw):
     for k, v in kw.items():
         if not hasattr(prm, k):
             raise TypeError(f"unknown parameter {k}")
-        setattr(prm, k, int(v))
+        setattr(prm, k, float(v) if k in ("omega", "coarse_tol") else int(v))
     return prm
 
 
@@ -236,6 +250,17 @@ class Context:
         n, nz = self.level_info(level)
         rp = np.empty(n + 1, np.int64); ci = np.empty(nz, np.int32); v = np.empty(nz)
         _check(lib().amg_get_coarse_matrix(self.h, level, _p(rp, i64p), _p(ci, i32p), _p(v, f64p)))
+        return rp, ci, v
+
+    def prolongator(self, level):
+        """The smoothed prolongator of `level` as CSR (None when not built)."""
+        nz = C.c_int64()
+        _check(lib().amg_get_prolongator(self.h, level, C.byref(nz), None, None, None))
+        if nz.value == 0:
+            return None
+        n, _ = self.level_info(level)
+        rp = np.empty(n + 1, np.int64); ci = np.empty(nz.value, np.int32); v = np.empty(nz.value)
+        _check(lib().amg_get_prolongator(self.h, level, C.byref(nz), _p(rp, i64p), _p(ci, i32p), _p(v, f64p)))
         return rp, ci, v
 
     def format(self, level=0):

@@ -33,6 +33,9 @@ struct SetupParams {
     int max_coarse = 200;
     int max_levels = 40;
     int positive_only = 0;
+    int smooth = 0;              // smoothed prolongator (I - omega D^{-1} K) P
+    double omega = 4.0 / 3.0;
+    int coarse_dense = 1;        // dense lower triangle of the coarsest matrix
 };
 
 struct HostLevel {
@@ -42,6 +45,7 @@ struct HostLevel {
     std::vector<double> w;       // test vector of this level
     std::vector<int32_t> agg;    // coarse index of each row (not on coarsest)
     std::vector<double> pc;      // prolongator coefficient of each row
+    Csr P, PT;                   // smoothed prolongator (n x nc) and its transpose, if built
     int max_members = 0;         // largest aggregate size into the next level
     float feat[6] = {0, 0, 0, 0, 0, 0};  // level features independent of the depth
 };
@@ -67,6 +71,15 @@ void level_features(const CsrView &K, const std::vector<double> &invd, float out
 // accumulated in ascending j, columns ascending.  Used by the fused
 // prolongation + post-smoothing pass: f - K (u + P e) = r - (K P) e.
 Csr kp_product(const CsrView &K, int64_t nc, const int32_t *agg, const double *pc);
+
+// Smoothed prolongator P' = (I - omega D^{-1} K) P on the pattern of K P:
+// P'_iJ = [J = agg(i)] pc_i - (omega invd_i) (K P)_iJ, and its Galerkin
+// product (P'^T K) P': B_Ij = sum over i ascending of P'_iI k_ij, then
+// K_c,IJ = sum over j ascending of B_Ij P'_jJ (parallel over coarse rows).
+Csr smooth_prolongator(const CsrView &K, const std::vector<double> &invd, int64_t nc, const int32_t *agg,
+                       const double *pc, double omega);
+Csr transpose(const Csr &P, int64_t ncols);
+Csr galerkin_general(const CsrView &K, const Csr &P, const Csr &PT);
 
 // Pieces exposed for the unit tests of the library's own setup.
 double cij(double kij, double kii, double kjj, double wi, double wj);

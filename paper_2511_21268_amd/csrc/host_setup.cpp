@@ -17,6 +17,7 @@
 // file is compiled without FMA contraction, so that two implementations of the
 // same readings agree to the bit.
 #include "host.h"
+#include <atomic>
 
 #include <algorithm>
 #include <cmath>
@@ -319,6 +320,106 @@ Csr kp_product(const CsrView &K, int64_t nc, const int32_t *agg, const double *p
     return C;
 }
 
+Csr smooth_prolongator(const CsrView &K, const std::vector<double> &invd, int64_t nc, const int32_t *agg,
+                       const double *pc, double omega)
+{
+    Csr P = kp_product(K, nc, agg, pc);
+    parallel_for(K.n, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; i++) {
+            const double s = omega * invd[i];
+            for (int64_t k = P.rp[i]; k < P.rp[i + 1]; k++) {
+                const double tent = (P.ci[k] == agg[i]) ? pc[i] : 0.0;
+                P.v[k] = tent - s * P.v[k];
+            }
+        }
+    });
+    return P;
+}
+
+Csr transpose(const Csr &P, int64_t ncols)
+{
+    Csr T;
+    T.n = ncols;
+    T.rp.assign(ncols + 1, 0);
+    for (int64_t k = 0; k < P.nnz(); k++) T.rp[P.ci[k] + 1]++;
+    for (int64_t J = 0; J < ncols; J++) T.rp[J + 1] += T.rp[J];
+    T.ci.resize(P.nnz());
+    T.v.resize(P.nnz());
+    std::vector<int64_t> fill(T.rp.begin(), T.rp.end() - 1);
+    for (int64_t i = 0; i < P.n; i++)
+        for (int64_t k = P.rp[i]; k < P.rp[i + 1]; k++) {
+            int64_t q = fill[P.ci[k]]++;
+            T.ci[q] = (int32_t)i;
+            T.v[q] = P.v[k];
+        }
+    return T;
+}
+
+Csr galerkin_general(const CsrView &K, const Csr &P, const Csr &PT)
+{
+    const int64_t n = K.n, nc = PT.n;
+    const int nt = std::max(1, host_threads());
+    // coarse rows in chunks handed out in order; each chunk keeps its rows
+    const int64_t nchunk = std::min<int64_t>(nc, (int64_t)nt * 16);
+    std::vector<std::vector<int32_t>> cci(nchunk);
+    std::vector<std::vector<double>> cv(nchunk);
+    std::vector<int64_t> rowlen(nc, 0);
+    std::atomic<int64_t> next(0);
+    auto work = [&]() {
+        std::vector<double> accB(n), accC(nc);
+        std::vector<int64_t> stampB(n, -1), stampC(nc, -1);
+        std::vector<int32_t> colB, colC;
+        for (;;) {
+            const int64_t ch = next.fetch_add(1);
+            if (ch >= nchunk) break;
+            const int64_t I0 = nc * ch / nchunk, I1 = nc * (ch + 1) / nchunk;
+            for (int64_t I = I0; I < I1; I++) {
+                colB.clear();
+                for (int64_t q = PT.rp[I]; q < PT.rp[I + 1]; q++) {
+                    const int64_t i = PT.ci[q];
+                    const double pv = PT.v[q];
+                    for (int64_t k = K.rp[i]; k < K.rp[i + 1]; k++) {
+                        const int32_t j = K.ci[k];
+                        if (stampB[j] != I) { stampB[j] = I; accB[j] = 0.0; colB.push_back(j); }
+                        accB[j] = accB[j] + pv * K.v[k];
+                    }
+                }
+                std::sort(colB.begin(), colB.end());
+                colC.clear();
+                for (int32_t j : colB) {
+                    const double bj = accB[j];
+                    for (int64_t k = P.rp[j]; k < P.rp[j + 1]; k++) {
+                        const int32_t J = P.ci[k];
+                        if (stampC[J] != I) { stampC[J] = I; accC[J] = 0.0; colC.push_back(J); }
+                        accC[J] = accC[J] + bj * P.v[k];
+                    }
+                }
+                std::sort(colC.begin(), colC.end());
+                rowlen[I] = (int64_t)colC.size();
+                for (int32_t J : colC) { cci[ch].push_back(J); cv[ch].push_back(accC[J]); }
+            }
+        }
+    };
+    {
+        std::vector<std::thread> th;
+        for (int t = 1; t < nt; t++) th.emplace_back(work);
+        work();
+        for (auto &x : th) x.join();
+    }
+    Csr C;
+    C.n = nc;
+    C.rp.assign(nc + 1, 0);
+    for (int64_t I = 0; I < nc; I++) C.rp[I + 1] = C.rp[I] + rowlen[I];
+    C.ci.resize(C.rp[nc]);
+    C.v.resize(C.rp[nc]);
+    for (int64_t ch = 0; ch < nchunk; ch++) {
+        const int64_t I0 = nc * ch / nchunk;
+        std::copy(cci[ch].begin(), cci[ch].end(), C.ci.begin() + C.rp[I0]);
+        std::copy(cv[ch].begin(), cv[ch].end(), C.v.begin() + C.rp[I0]);
+    }
+    return C;
+}
+
 static void l1_invdiag(const CsrView &K, std::vector<double> &invd)
 {
     invd.resize(K.n);
@@ -364,9 +465,10 @@ void level_features(const CsrView &K, const std::vector<double> &invd, float out
     out[5] = (float)(noff ? (double)npos / (double)noff : 0.0);
 }
 
-static void make_coarsest(HostHierarchy &H, const CsrView &K)
+static void make_coarsest(HostHierarchy &H, const CsrView &K, int dense = 1)
 {
     int64_t n = K.n;
+    if (!dense) { H.coarse_lower.clear(); return; }
     H.coarse_lower.assign((size_t)(n * n), 0.0);
     for (int64_t i = 0; i < n; i++)
         for (int64_t k = K.rp[i]; k < K.rp[i + 1]; k++)
@@ -391,9 +493,9 @@ int build_hierarchy(const CsrView &K0, const double *w, const SetupParams &prm,
     for (int l = 0;; l++) {
         CsrView K = l == 0 ? K0 : view(H.lev[l].K);
         int64_t nl = H.lev[l].n;
-        if (nl <= prm.max_coarse) { make_coarsest(H, K); return 0; }
+        if (nl <= prm.max_coarse) { make_coarsest(H, K, prm.coarse_dense); return 0; }
         if (l == maxl - 1) {
-            if (nl <= 2000) { make_coarsest(H, K); return 0; }
+            if (nl <= 2000) { make_coarsest(H, K, prm.coarse_dense); return 0; }
             err = "coarsening reached max_levels above 2000 unknowns";
             return -6;
         }
@@ -411,7 +513,8 @@ int build_hierarchy(const CsrView &K0, const double *w, const SetupParams &prm,
             std::vector<int32_t> ag;
             std::vector<double> pcs, wc;
             nc = pairwise(kv.n, mate.data(), ww, ag, pcs, wc);
-            Csr C = galerkin(kv, nc, ag, pcs);
+            // with smoothing, the last sweep's unsmoothed product is not needed
+            Csr C = (prm.smooth && s == prm.sweeps - 1) ? Csr() : galerkin(kv, nc, ag, pcs);
             if (s == 0) {
                 agg = ag;
                 pc = pcs;
@@ -425,13 +528,18 @@ int build_hierarchy(const CsrView &K0, const double *w, const SetupParams &prm,
             cw = std::move(wc);
         }
         if ((double)nc > 0.9 * (double)nl) {
-            if (nl <= 2000) { make_coarsest(H, K); return 0; }
+            if (nl <= 2000) { make_coarsest(H, K, prm.coarse_dense); return 0; }
             err = "coarsening stalled above 2000 unknowns";
             return -6;
         }
         HostLevel &L = H.lev[l];
         L.agg = std::move(agg);
         L.pc = std::move(pc);
+        if (prm.smooth) {
+            L.P = smooth_prolongator(K, L.invd, nc, L.agg.data(), L.pc.data(), prm.omega);
+            L.PT = transpose(L.P, nc);
+            cur = galerkin_general(K, L.P, L.PT);
+        }
         {
             std::vector<int> cnt(nc, 0);
             for (int64_t i = 0; i < nl; i++) cnt[L.agg[i]]++;

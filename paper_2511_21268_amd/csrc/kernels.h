@@ -45,7 +45,7 @@ constexpr int SLICE = 64;
 constexpr int SELL_WAVES = 4;          // slices (wavefronts) per 256-thread block
 constexpr int RED_THREADS = 256;
 
-enum Epi { EPI_SPMV = 0, EPI_RESID = 1, EPI_SMOOTH = 2, EPI_POLY = 3 };
+enum Epi { EPI_SPMV = 0, EPI_RESID = 1, EPI_SMOOTH = 2, EPI_POLY = 3, EPI_ADD = 4 };
 
 // scalar slots of the solver's device scalar array
 enum Slot { S_RZ = 0, S_PQ, S_RR, S_ALPHA, S_BETA, S_PR, S_ZQ, S_FF, S_FLAG, S_TMP, S_NSLOTS = 16 };
@@ -246,6 +246,8 @@ __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)(th
 //   EPI_SMOOTH: y = x + invd (f - acc);    dots: (y, g0), (y, g1)
 //   EPI_POLY  : y = a invd f + invd acc    (a = coef; one Horner step of the
 //               polynomial smoother: c <- a D^{-1} r + D^{-1} K c)
+//   EPI_ADD   : y = f + acc                (prolongation u + P e with the
+//               smoothed prolongator; x is the coarse vector)
 // VT: matrix, x and invd type; FT: type of f; OT: type of y; IT: index stream
 // (uint16_t deltas or int32_t columns).  NDOT dots are accumulated in FP64 and
 // written as one partial per block to partial[blockIdx.x * 2 + d].
@@ -282,6 +284,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
                 y[row] = (OT)out;
                 if (NDOT >= 1) d0 = (double)out * g0[row];
                 if (NDOT >= 2) d1 = (double)out * g1[row];
+            } else if (EPI == EPI_ADD) {
+                y[row] = (OT)((VT)f[row] + acc);
             } else {
                 VT di = invd[row];
                 y[row] = (OT)(coef * (di * (VT)f[row]) + di * acc);

@@ -3,6 +3,7 @@
 // kernels.h / coarse.h on the context's stream; the host only enqueues them and
 // reads one small scalar block per iteration to test convergence.
 #include "amg.h"
+#include "cheb.h"
 #include "coarse.h"
 #include "host.h"
 #include "kernels.h"
@@ -285,6 +286,8 @@ struct Level {
     DevMat Ab;    // SELL-(64/LPR) image of the block kernels (batched solves), if built
     DevMat KP;    // SELL-64 image of K P (fused prolongation + post-smoothing), ell < L
     DevMat KPb;   // SELL-(64/LPR) image of K P for the block kernels, if built
+    DevMat Pm;    // SELL-64 image of the smoothed prolongator (rows n, columns n_c), if built
+    DevMat Rm;    // SELL-64 image of its transpose (rows n_c, columns n), if built
     double *invd64 = nullptr;
     float *invd32 = nullptr;
     // transfer to the next level
@@ -317,6 +320,9 @@ struct amg_ctx {
     int nlev = 0;
     int nL = 0, ldL = 0;
     double *Linv = nullptr, *LinvT = nullptr;
+    // coarsest level for the CG coarse solver: CSR (int32) and 1 / k_ii
+    int32_t *cg_rp = nullptr, *cg_ci = nullptr;
+    double *cg_v = nullptr, *cg_dj = nullptr;
     int64_t n = 0;
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
     double *partial = nullptr;
@@ -800,11 +806,154 @@ struct amg_ctx {
         return u;
     }
 
+    // ---- the smoothed-aggregation form (Sec. 3.1 variants, Sec. 3.2, Sec. 5.1) --
+    // Any of: fourth-kind Chebyshev smoother, smoothed prolongator, CG coarse
+    // solver.  FP64, single vector.
+    bool general_vcycle() const { return prm.smoother == 2 || prm.smooth_prolong || prm.coarse_solver == 1; }
+
+    void coarsest_solve(const double *f, double *e)
+    {
+        if (prm.coarse_solver == 1)
+            hipLaunchKernelGGL(k_coarse_cg, dim3(1), dim3(CG_THREADS), 0, stream, nL, cg_rp, cg_ci, cg_v, cg_dj, f,
+                               e, prm.coarse_tol, prm.coarse_itmax);
+        else
+            hipLaunchKernelGGL((k_coarse_solve<double>), dim3(1), dim3(256), 0, stream, nL, ldL, Linv, LinvT, f, e);
+        HIPCHK(hipGetLastError());
+    }
+
+    // One Chebyshev matrix pass over K_l (modes of k_sell_cheb).
+    template <int MODE>
+    void cheb(int l, const double *x, const double *f, double *r, double *u, double *dn, double a, double b,
+              int first)
+    {
+        const Level &L = lev[l];
+        const DevMat &A = L.A;
+        unsigned nb = (unsigned)((A.nslices + SELL_WAVES - 1) / SELL_WAVES);
+        if (l == 0) prof_begin();
+        if (A.idx16)
+            hipLaunchKernelGGL((k_sell_cheb<uint16_t, MODE>), dim3(nb), dim3(256), 0, stream,
+                               A.sv<double, uint16_t>(), x, f, r, L.invd64, u, dn, a, b, first);
+        else
+            hipLaunchKernelGGL((k_sell_cheb<int32_t, MODE>), dim3(nb), dim3(256), 0, stream,
+                               A.sv<double, int32_t>(), x, f, r, L.invd64, u, dn, a, b, first);
+        HIPCHK(hipGetLastError());
+        if (l == 0) {
+            // vectors: MODE 0 reads x (gathered once), f, invd and writes r, dn;
+            // MODES 1/2 read x, r or f, u unless first, and write u, r; MODE 1
+            // also reads invd and writes dn
+            const int nvec = MODE == 0 ? 5 : (first ? 4 : 5) + (MODE == 1 ? 2 : 0);
+            prof_end(pass_bytes(8, nvec));
+        }
+    }
+
+    // Level l of the V-cycle in this form; returns where the result lives
+    // (level 0 writes zout with the dot partials instead).
+    double *vgen(int l, const double *f, double *zout, int ndot, const double *g0, const double *g1)
+    {
+        Level &L = lev[l];
+        double *u = (double *)L.u, *u2 = (double *)L.u2, *d = (double *)L.c, *d2 = (double *)L.c2;
+        double *r = (double *)L.r;
+        const bool ch = prm.smoother == 2;
+        const int k = prm.cheb_degree;
+        const unsigned g = nblocks(L.n);
+        // 1. pre-smoothing from the zero guess, leaving r = f - K u
+        if (ch) {
+            hipLaunchKernelGGL((k_scale_coef<double, double>), dim3(g), dim3(256), 0, stream, L.n, L.invd64, f, d,
+                               4.0 / 3.0);
+            HIPCHK(hipGetLastError());
+            for (int j = 1; j < k; j++) {
+                cheb<1>(l, d, f, r, u, d2, (2.0 * j - 1.0) / (2.0 * j + 3.0), (8.0 * j + 4.0) / (2.0 * j + 3.0),
+                        j == 1);
+                std::swap(d, d2);
+            }
+            cheb<2>(l, d, f, r, u, nullptr, 0.0, 0.0, k == 1);
+        } else {
+            hipLaunchKernelGGL((k_scale<double, double>), dim3(g), dim3(256), 0, stream, L.n, L.invd64, f, u);
+            HIPCHK(hipGetLastError());
+            for (int s = 1; s < prm.nu_pre; s++) {
+                sweep<double, double, double>(l, f, u, u2, 0, nullptr, nullptr);
+                std::swap(u, u2);
+            }
+            sell<double, double, double, EPI_RESID, 0>(l, u, f, L.invd64, r, nullptr, nullptr);
+        }
+        // 2. restriction f_c = P^T r
+        Level &C = lev[l + 1];
+        const bool coarsest = (l + 1 == nlev - 1);
+        if (L.Rm.soff) {
+            launch_sell<double, double, double, EPI_SPMV, 0>(L.Rm, (unsigned)((L.Rm.nslices + SELL_WAVES - 1) /
+                                                                              SELL_WAVES),
+                                                             r, nullptr, nullptr, (double *)C.f, nullptr, nullptr,
+                                                             1.0);
+        } else {
+            hipLaunchKernelGGL((k_restrict<double>), dim3(nblocks(C.n)), dim3(256), 0, stream, C.n, L.mw,
+                               L.members, L.pc64, (const double *)r, (double *)C.f, nullptr, nullptr, 1.0);
+            HIPCHK(hipGetLastError());
+        }
+        // 3. coarse correction
+        double *e;
+        if (coarsest) {
+            e = (double *)C.u;
+            coarsest_solve((const double *)C.f, e);
+        } else {
+            e = vgen(l + 1, (const double *)C.f, nullptr, 0, nullptr, nullptr);
+        }
+        // 4. prolongation u += P e
+        if (L.Pm.soff) {
+            launch_sell<double, double, double, EPI_ADD, 0>(L.Pm, (unsigned)((L.Pm.nslices + SELL_WAVES - 1) /
+                                                                             SELL_WAVES),
+                                                            e, u, nullptr, u2, nullptr, nullptr, 1.0);
+            std::swap(u, u2);
+        } else {
+            hipLaunchKernelGGL((k_prolong<double>), dim3(g), dim3(256), 0, stream, L.n, L.agg, L.pc64, e, u);
+            HIPCHK(hipGetLastError());
+        }
+        // 5. post-smoothing
+        if (ch) {
+            cheb<0>(l, u, f, r, nullptr, d, 0.0, 4.0 / 3.0, 0);
+            for (int j = 1; j < k; j++) {
+                cheb<1>(l, d, f, r, u, d2, (2.0 * j - 1.0) / (2.0 * j + 3.0), (8.0 * j + 4.0) / (2.0 * j + 3.0), 0);
+                std::swap(d, d2);
+            }
+            if (zout) {
+                hipLaunchKernelGGL((k_add<double, double>), dim3(g), dim3(256), 0, stream, L.n, u, d, zout);
+                HIPCHK(hipGetLastError());
+                if (ndot) vc_nb = dot_partials(L.n, zout, g0, g1);
+                return nullptr;
+            }
+            hipLaunchKernelGGL((k_add<double, double>), dim3(g), dim3(256), 0, stream, L.n, u, d, u2);
+            HIPCHK(hipGetLastError());
+            return u2;
+        }
+        for (int s = 1; s <= prm.nu_post; s++) {
+            if (zout && s == prm.nu_post) {
+                sweep<double, double, double>(l, f, u, zout, ndot, g0, g1);
+                return nullptr;
+            }
+            sweep<double, double, double>(l, f, u, u2, 0, nullptr, nullptr);
+            std::swap(u, u2);
+        }
+        if (zout) {
+            copy<double, double>(L.n, u, zout);
+            if (ndot) vc_nb = dot_partials(L.n, zout, g0, g1);
+            return nullptr;
+        }
+        return u;
+    }
+
     // z = B r; when ndot > 0 the partials of (z, g0) [and (z, g1)] are left in
     // `partial` and the number of blocks to finalize is returned.
     unsigned vcycle(const double *rin, double *zout, int ndot, const double *g0, const double *g1)
     {
         vc_nb = 0;
+        if (general_vcycle()) {
+            if (nlev == 1) {
+                coarsest_solve(rin, zout);
+                if (ndot) vc_nb = dot_partials(n, zout, g0, g1);
+            } else {
+                vgen(0, rin, zout, ndot, g0, g1);
+            }
+            return vc_nb;
+        }
         if (nlev == 1) {
             hipLaunchKernelGGL((k_coarse_solve<double>), dim3(1), dim3(256), 0, stream, nL, ldL, Linv, LinvT, rin,
                                zout);
@@ -1097,7 +1246,12 @@ static amg_status build_device(amg_ctx *c, const CsrView &K0)
             L.invd32 = c->upload(t);
         }
         if (!coarsest) {
-            {
+            if (c->general_vcycle()) {
+                if (!hl.P.rp.empty()) {
+                    L.Pm = c->upload_sell(amgiga::view(hl.P), SLICE, true, false, H.lev[l + 1].n);
+                    L.Rm = c->upload_sell(amgiga::view(hl.PT), SLICE, true, false, hl.n);
+                }
+            } else {
                 CsrView K = l == 0 ? K0 : amgiga::view(hl.K);
                 amgiga::Csr kp = amgiga::kp_product(K, H.lev[l + 1].n, hl.agg.data(), hl.pc.data());
                 L.KP = c->upload_sell(amgiga::view(kp), SLICE, !fp32, fp32, H.lev[l + 1].n);
@@ -1126,8 +1280,28 @@ static amg_status build_device(amg_ctx *c, const CsrView &K0)
         L.c = c->alloc<char>(nn * vsz);
         L.c2 = c->alloc<char>(nn * vsz);
     }
-    // coarsest level: dense Cholesky on the device, then the inverse factor
-    {
+    // coarsest level: CSR and 1 / k_ii for the CG coarse solver, or the dense
+    // Cholesky factor on the device, then the inverse factor
+    if (c->prm.coarse_solver == 1) {
+        auto &hl = H.lev.back();
+        CsrView K = c->nlev == 1 ? K0 : amgiga::view(hl.K);
+        if (K.n > CG_MAXN || K.nnz() >= (int64_t(1) << 31)) {
+            set_err("coarsest level too large for the CG coarse solver");
+            return AMG_ERR_ARG;
+        }
+        std::vector<int32_t> rp32(K.n + 1);
+        std::vector<double> dj(K.n, 0.0);
+        for (int64_t i = 0; i <= K.n; i++) rp32[i] = (int32_t)K.rp[i];
+        for (int64_t i = 0; i < K.n; i++)
+            for (int64_t k = K.rp[i]; k < K.rp[i + 1]; k++)
+                if (K.ci[k] == i) dj[i] = 1.0 / K.v[k];
+        c->cg_rp = c->upload(rp32);
+        c->cg_ci = c->upload(std::vector<int32_t>(K.ci, K.ci + K.nnz()));
+        c->cg_v = c->upload(std::vector<double>(K.v, K.v + K.nnz()));
+        c->cg_dj = c->upload(dj);
+        c->nL = (int)K.n;
+        c->ldL = 0;
+    } else {
         auto &hl = H.lev.back();
         int nl = (int)hl.n;
         int npad = (nl + 15) / 16 * 16;
@@ -1187,6 +1361,12 @@ amg_status amg_params_default(amg_params *p)
     p->itmax = 1000;
     p->nrhs = 1;
     p->slice_offsets = 1;
+    p->smooth_prolong = 0;
+    p->cheb_degree = 8;
+    p->coarse_solver = 0;
+    p->coarse_itmax = 30;
+    p->omega = 4.0 / 3.0;
+    p->coarse_tol = 1e-4;
     return AMG_OK;
 }
 
@@ -1205,9 +1385,19 @@ static amg_status setup_common(int64_t n, const int64_t *row_ptr, const int32_t 
     if (P.sweeps_per_level < 1 || P.sweeps_per_level > 3 || P.max_coarse < 1 || P.max_coarse > 2000 ||
         P.max_levels < 1 || P.nu_pre < 1 || P.nu_post < 0 || P.itmax < 1 || P.krylov < 0 || P.krylov > 1 ||
         P.nrhs < 1 || P.nrhs > NB ||
-        P.smoother < 0 || P.smoother > 1 || P.slice_offsets < 0 || P.slice_offsets > 1) {
+        P.smoother < 0 || P.smoother > 2 || P.slice_offsets < 0 || P.slice_offsets > 1 ||
+        P.smooth_prolong < 0 || P.smooth_prolong > 1 || P.cheb_degree < 1 || P.cheb_degree > 64 ||
+        P.coarse_solver < 0 || P.coarse_solver > 1 || P.coarse_itmax < 1 || P.coarse_itmax > 1000 ||
+        !(P.omega > 0.0 && P.omega <= 2.0) || !(P.coarse_tol >= 0.0 && std::isfinite(P.coarse_tol))) {
         set_err("parameter out of range");
         return AMG_ERR_ARG;
+    }
+    if (P.smoother == 2 || P.smooth_prolong || P.coarse_solver == 1) {
+        if (P.vcycle_fp32 || P.nrhs != 1 || P.smoother == 1 || (P.smoother == 2 && (P.nu_pre != 1 || P.nu_post != 1))) {
+            set_err("smoother 2, smooth_prolong and coarse_solver 1 take the FP64 single-vector V-cycle "
+                    "(vcycle_fp32 0, nrhs 1, smoother 0 or 2, one Chebyshev step before and after)");
+            return AMG_ERR_ARG;
+        }
     }
     if (n <= 0 || !row_ptr || !col || !val) { set_err("n <= 0 or NULL CSR array"); return AMG_ERR_ARG; }
     if (!host_only && n >= (int64_t(1) << 29)) {
@@ -1232,6 +1422,9 @@ static amg_status setup_common(int64_t n, const int64_t *row_ptr, const int32_t 
         sp.max_coarse = P.max_coarse;
         sp.max_levels = P.max_levels;
         sp.positive_only = P.match_positive_only;
+        sp.smooth = P.smooth_prolong;
+        sp.omega = P.omega;
+        sp.coarse_dense = P.coarse_solver == 0;
         int rc = amgiga::build_hierarchy(K0, w, sp, c->host, err);
         if (rc) { set_err(err); return (amg_status)rc; }
         c->nlev = (int)c->host.lev.size();
@@ -1568,6 +1761,10 @@ amg_status pcg_solve_batched(amg_ctx *c, int nrhs, const double *F, double *U, d
         return AMG_ERR_ARG;
     }
     if (c->host_only) { set_err("context was built by amg_setup_host"); return AMG_ERR_STATE; }
+    if (c->general_vcycle()) {
+        set_err("the batched solve takes the l1-Jacobi / polynomial forms with the tentative prolongator");
+        return AMG_ERR_STATE;
+    }
     try {
         return solve_batched_impl(c, nrhs, F, U, tol, iters, relres);
     } catch (Fail &f) {
@@ -1705,6 +1902,19 @@ amg_status amg_get_coarse_matrix(const amg_ctx *c, int level, int64_t *row_ptr, 
     if (row_ptr) std::memcpy(row_ptr, K.rp.data(), K.rp.size() * sizeof(int64_t));
     if (col) std::memcpy(col, K.ci.data(), K.ci.size() * sizeof(int32_t));
     if (val) std::memcpy(val, K.v.data(), K.v.size() * sizeof(double));
+    return AMG_OK;
+}
+
+amg_status amg_get_prolongator(const amg_ctx *c, int level, int64_t *nnz, int64_t *row_ptr, int32_t *col,
+                               double *val)
+{
+    if (!c || level < 0 || level >= c->nlev - 1) { set_err("level must be 0 .. levels-2"); return AMG_ERR_ARG; }
+    auto &P = c->host.lev[level].P;
+    if (nnz) *nnz = P.rp.empty() ? 0 : P.nnz();
+    if (P.rp.empty()) return AMG_OK;
+    if (row_ptr) std::memcpy(row_ptr, P.rp.data(), P.rp.size() * sizeof(int64_t));
+    if (col) std::memcpy(col, P.ci.data(), P.ci.size() * sizeof(int32_t));
+    if (val) std::memcpy(val, P.v.data(), P.v.size() * sizeof(double));
     return AMG_OK;
 }
 

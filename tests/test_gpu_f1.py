@@ -1,0 +1,130 @@
+"""GPU: the paper's default preconditioner (Sec. 3.1 "Variants and
+efficiency", Sec. 3.2, Sec. 5.1) against the oracle: V-cycle outputs (fourth-
+kind Chebyshev smoother, smoothed prolongator, Cholesky or CG coarse solver,
+and each piece alone), and FCG solves of the cube problem at the Table 1(b)
+sizes (iterations by the parity rule of the other FP64 tests, iterates to 1% of
+the algebraic error the solve leaves).  Iteration counts and operator
+complexities are printed beside Table 1(a)/(c), which come from the paper's
+own implementation: context, not a pin."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TABLE_1A = {12: {3: 10, 4: 22, 5: 27, 6: 25}, 24: {3: 11, 4: 23, 5: 29, 6: 32}, 48: {3: 11, 4: 22, 5: 27, 6: 34},
+            96: {3: 11, 4: 21}}
+DEG = {2: 6, 3: 8, 4: 12, 5: 14, 6: 16}
+
+
+@pytest.fixture(scope="module")
+def amg():
+    import paper_2511_21268_amd as m
+    assert torch.cuda.is_available()
+    m.lib()
+    return m
+
+
+def _opc_table():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table1c_cube_opc.json")) as f:
+        return json.load(f)["opc"]
+
+
+def _system(oracle, name):
+    if name == "cube p3 k6":
+        rp, ci, v, _, _ = oracle.cube_system(3, 6)
+    elif name == "cube p4 k12":
+        rp, ci, v, _, _ = oracle.cube_system(4, 12)
+    elif name == "poisson p2 n14":
+        rp, ci, v, _ = oracle.poisson_kron(3, 2, 14)
+    else:
+        raise KeyError(name)
+    return rp, ci, v
+
+
+VCYCLE_CASES = [
+    # (system, params, tolerance on the relative V-cycle difference)
+    ("cube p3 k6", dict(sweeps_per_level=3, smooth_prolong=1, smoother=2, cheb_degree=8, coarse_solver=0), 1e-12),
+    ("cube p3 k6", dict(sweeps_per_level=3, smooth_prolong=1, smoother=2, cheb_degree=8, coarse_solver=1), 1e-10),
+    ("cube p3 k6", dict(sweeps_per_level=3, smooth_prolong=1, smoother=2, cheb_degree=1, coarse_solver=0), 1e-12),
+    ("cube p4 k12", dict(sweeps_per_level=3, smooth_prolong=1, smoother=2, cheb_degree=12, coarse_solver=1), 1e-10),
+    ("poisson p2 n14", dict(sweeps_per_level=3, smooth_prolong=1, smoother=2, cheb_degree=3, coarse_solver=0,
+                            max_coarse=20), 1e-12),
+    # each piece alone
+    ("poisson p2 n14", dict(smoother=2, cheb_degree=5), 1e-12),
+    ("poisson p2 n14", dict(smooth_prolong=1), 1e-12),
+    ("poisson p2 n14", dict(coarse_solver=1), 1e-10),
+    ("cube p3 k6", dict(smooth_prolong=1, nu_pre=2, nu_post=2), 1e-12),
+]
+
+
+@pytest.mark.parametrize("ci_", range(len(VCYCLE_CASES)))
+def test_f1_vcycle_parity(oracle, amg, ci_):
+    name, prm, tol = VCYCLE_CASES[ci_]
+    print(f"case {name} {prm}", flush=True)
+    rp, ci, v = _system(oracle, name)
+    h = oracle.Hierarchy(rp, ci, v, **prm)
+    ctx = amg.Context(rp, ci, v, krylov=1, **prm)
+    assert ctx.nlevels == h.nlevels >= 2
+    rng = np.random.default_rng(ci_)
+    for _ in range(3):
+        r = rng.standard_normal(h.n)
+        z = ctx.vcycle(torch.from_numpy(r).cuda()).cpu().numpy()
+        zo = h.vcycle(r)
+        err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+        assert err <= tol, err
+    # the same input twice gives the same bits
+    rt = torch.from_numpy(r).cuda()
+    assert torch.equal(ctx.vcycle(rt), ctx.vcycle(rt))
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("k,p", [(12, 3), (12, 4), (12, 5), (12, 6), (24, 3), (24, 4), (24, 5)])
+def test_f1_cube_solve_parity(oracle, amg, iters_match, oracle_iterate, k, p):
+    print(f"case cube k={k} p={p} paper default", flush=True)
+    rp, ci, v, F, lift = oracle.cube_system(p, k)
+    prm = amg.paper_default(p)
+    h = oracle.Hierarchy(rp, ci, v, **{a: b for a, b in prm.items() if a != "krylov"})
+    ctx = amg.Context(rp, ci, v, **prm)
+    assert ctx.nlevels == h.nlevels
+    for l in range(h.nlevels - 1):
+        a, pc = ctx.aggregates(l)
+        ao, pco, _, _ = h.level_agg(l)
+        assert np.array_equal(a, ao) and np.array_equal(pc, pco), l
+    for tol in (1e-6, 1e-8):
+        ref = h.solve(F, tol=tol, itmax=1000, flexible=True)
+        out = ctx.solve(torch.from_numpy(F).cuda(), tol=tol)
+        assert out["status"] == 0 and iters_match(out["iters"], ref, tol)
+        u = out["u"].cpu().numpy()
+        uo = oracle_iterate(h, F, ref, out["iters"], flexible=True)
+        ex = h.solve(F, tol=1e-13, itmax=2000, flexible=True)["u"]
+        alg = np.linalg.norm(uo - ex) / np.linalg.norm(ex)
+        err = np.linalg.norm(u - uo) / np.linalg.norm(uo)
+        print(f"  tol {tol:g}: {out['iters']} iterations (oracle {ref['iters']}, Table 1(a) {TABLE_1A[k][p]}), "
+              f"OPC {ctx.opc():.3f} (Table 1(c) {_opc_table()[str(k)][str(p)]}), iterate difference {err:.2e} "
+              f"(algebraic error {alg:.2e})", flush=True)
+        assert err <= 1e-2 * alg
+        assert out["relres_true"] <= tol * 1.0001
+    e, nr = oracle.cube_error(p, k, u, lift)
+    assert e / nr < 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_f1_table1_library_generator(amg):
+    """Table 1's cube cases with the library's generator and the paper's
+    default preconditioner at the paper's tolerance 1e-6 (k = 96 at p = 3)."""
+    opc = _opc_table()
+    for k, p in [(12, 3), (12, 6), (24, 4), (24, 6), (48, 3), (48, 5), (96, 3)]:
+        rp, ci, v, F = amg.iga_cube(p, k)
+        ctx = amg.Context(rp, ci, v, **amg.paper_default(p))
+        out = ctx.solve(torch.from_numpy(F).cuda(), tol=1e-6)
+        print(f"  k={k} p={p} N={len(F)}: {out['iters']} iterations (Table 1(a) {TABLE_1A[k][p]}), OPC "
+              f"{ctx.opc():.3f} (Table 1(c) {opc[str(k)][str(p)]}), true relres {out['relres_true']:.2e}",
+              flush=True)
+        assert out["status"] == 0 and out["relres_true"] <= 1e-6 * 1.0001
+        assert out["iters"] <= 3 * TABLE_1A[k][p]
+        del ctx
