@@ -100,10 +100,12 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c4")
-    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32", "batched", "learned"],
+    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32", "batched", "learned", "paper"],
                     help="fp64: FP64 PCG (default); fp32: FP32 V-cycle inside FP64 FCG; "
                          "batched: 16 right-hand sides, FP32 block V-cycle inside FP64 FCG; "
-                         "learned: FP64 PCG with the MLP-predicted degree-4 polynomial smoothers")
+                         "learned: FP64 PCG with the MLP-predicted degree-4 polynomial smoothers; "
+                         "paper: FP64 FCG with the paper's default preconditioner (aggregates of 8, "
+                         "smoothed prolongator, Chebyshev l1-Jacobi, CG coarse solve)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--itmax", type=int, default=0, help="iteration limit (0: the workload's, else 1000)")
@@ -158,7 +160,8 @@ def main():
         F = torch.from_numpy(rhs_block(N, range(args.seed, args.seed + nrhs))).cuda()
     torch.cuda.synchronize()
     t = time.time()
-    kw = dict({"fp64": {}, "learned": {"smoother": 1}}.get(args.mode, {"vcycle_fp32": 1, "krylov": 1}))
+    kw = dict({"fp64": {}, "learned": {"smoother": 1}, "paper": amg.paper_default(cfg["p"])}.get(
+        args.mode, {"vcycle_fp32": 1, "krylov": 1}))
     kw["itmax"] = args.itmax or cfg.get("itmax", 1000)
     if nrhs > 1:
         kw["nrhs"] = nrhs
@@ -218,8 +221,9 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": MEASURED_TRAFFIC.get((args.workload, kernel_source_sha())) if args.mode == "fp64" else None,
-                "kernel": "k_sell (level-0 SpMV / residual / smoother pass)" if nrhs == 1 else
-                          "k_sell_blk (level-0 16-column SpMV / residual / smoother pass)",
+                "kernel": ("k_sell_cheb + k_sell (level-0 Chebyshev / SpMV / residual passes)"
+                           if args.mode == "paper" else "k_sell (level-0 SpMV / residual / smoother pass)")
+                          if nrhs == 1 else "k_sell_blk (level-0 16-column SpMV / residual / smoother pass)",
                 "launches": prof["launches"], "avg_launch_ms": round(kernel_ms, 4),
                 "bytes_per_launch": round(prof["bytes"] / max(prof["launches"], 1))}
 
@@ -234,8 +238,12 @@ def main():
 
     form = {"fp64": "FP64 PCG", "fp32": "FP32 V-cycle in FP64 FCG",
             "batched": "16 RHS, FP32 block V-cycle in FP64 FCG",
-            "learned": "FP64 PCG, learned degree-4 polynomial smoothers"}[args.mode]
+            "learned": "FP64 PCG, learned degree-4 polynomial smoothers", "paper": "FP64 FCG"}[args.mode]
     smoother = "learned POLY4" if args.mode == "learned" else "l1-Jacobi 1/1"
+    amg_desc = f"m=2, {smoother}, Cholesky <= 200"
+    if args.mode == "paper":
+        amg_desc = (f"m=3 smoothed (omega 4/3), fourth-kind Chebyshev l1-Jacobi degree {kw['cheb_degree']}, "
+                    f"CG-Jacobi coarse solve 1e-4 / 30 at <= 200")
     if cfg["kind"] == "diffusion":
         problem = "-div(kappa grad u) = 1, kappa from seed " + str(args.seed)
     elif cfg["kind"] == "cube":
@@ -244,10 +252,11 @@ def main():
         problem = f"Poisson, F~N(0,1) seed {args.seed}{'..' + str(args.seed + nrhs - 1) if nrhs > 1 else ''}"
     rec = {"metric": METRIC, "value": round(ms / 1e3, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "strong",
-           "vs_baseline": None, "dtype": "f64" if args.mode == "fp64" else "f32/f64", "data": "synthetic",
+           "vs_baseline": None, "dtype": "f64" if args.mode in ("fp64", "paper") else "f32/f64",
+           "data": "synthetic",
            "config": {"workload": f"{args.workload}: {cfg['d']}D {problem}, B-splines p={cfg['p']}, "
                                   f"n={cfg['n']}, N={N}, nnz={nnz}, {form} + "
-                                  f"matching AMG V-cycle (m=2, {smoother}, Cholesky <= 200), tol {args.tol}",
+                                  f"matching AMG V-cycle ({amg_desc}), tol {args.tol}",
                       "mode": args.mode, "nrhs": nrhs, "converged": converged,
                       "iters": iters[-1], "relres_true": relres_true, "levels": len(levels),
                       "opc": round(ctx.opc(), 4), "setup_s": round(setup_s, 2),

@@ -265,7 +265,9 @@ amg_status amg_get_profile(amg_ctx *c, int64_t *launches, double *ms, double *by
 /* Description of a level's single-vector layout: slice height, stored
  * entries with padding, index bytes per entry in slices with per-entry
  * indices (2 or 4), and the number of slices (of ceil(n / slice)) that store
- * shared column offsets instead.  Any output may be NULL. */
+ * shared column offsets instead.  A coarse level of the Chebyshev form held as
+ * CSR with L lanes per row (long or few rows) reports slice = -L and 4 index
+ * bytes.  Any output may be NULL. */
 amg_status amg_get_format(const amg_ctx *c, int level, int *slice, int64_t *stored,
                           int *index_bytes, int64_t *shared_slices);
 

@@ -56,6 +56,84 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     }
 }
 
+// ---- CSR with LPR lanes per row ---------------------------------------------
+//
+// The coarse matrices and transfer operators of the smoothed hierarchy have few
+// rows of hundreds to thousands of entries: one lane per row leaves the GPU
+// nearly empty and each lane walks its row serially.  Here LPR consecutive lanes
+// (8..64) share a row, stride through its entries (coalesced loads of values and
+// int32 columns), and reduce by a butterfly within the group; the group's first
+// lane writes, so the result does not depend on which lane is asked.
+template <int LPR>
+__device__ inline double csr_row(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                 const double *__restrict__ v, const double *__restrict__ x, int64_t row, int sub)
+{
+    // four independent chains (column load -> gather -> fma) per lane, summed
+    // in a fixed order at the end
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const int64_t e1 = rp[row + 1];
+    int64_t e = rp[row] + sub;
+    for (; e + 3 * LPR < e1; e += 4 * LPR) {
+        const int32_t c0 = __builtin_nontemporal_load(ci + e), c1 = __builtin_nontemporal_load(ci + e + LPR);
+        const int32_t c2 = __builtin_nontemporal_load(ci + e + 2 * LPR), c3 = __builtin_nontemporal_load(ci + e + 3 * LPR);
+        a0 = fma(__builtin_nontemporal_load(v + e), x[c0], a0);
+        a1 = fma(__builtin_nontemporal_load(v + e + LPR), x[c1], a1);
+        a2 = fma(__builtin_nontemporal_load(v + e + 2 * LPR), x[c2], a2);
+        a3 = fma(__builtin_nontemporal_load(v + e + 3 * LPR), x[c3], a3);
+    }
+    for (; e < e1; e += LPR) a0 = fma(__builtin_nontemporal_load(v + e), x[__builtin_nontemporal_load(ci + e)], a0);
+    double acc = (a0 + a1) + (a2 + a3);
+#pragma unroll
+    for (int o = LPR / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    return acc;
+}
+
+// Chebyshev pass (modes of k_sell_cheb) over a CSR image.
+template <int LPR, int MODE>
+__global__ __launch_bounds__(256) void k_csr_cheb(int64_t nrows, const int64_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                  const double *__restrict__ x, const double *__restrict__ f,
+                                                  double *__restrict__ r, const double *__restrict__ invd,
+                                                  double *__restrict__ u, double *__restrict__ dn, double a, double b,
+                                                  int first)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t row = t / LPR;
+    const int sub = (int)(t % LPR);
+    if (row >= nrows) return;   // whole groups leave together
+    const double acc = csr_row<LPR>(rp, ci, v, x, row, sub);
+    if (sub != 0) return;
+    if (MODE == 0) {
+        const double rr = f[row] - acc;
+        r[row] = rr;
+        dn[row] = b * (invd[row] * rr);
+    } else {
+        const double dold = x[row];
+        u[row] = first ? dold : u[row] + dold;
+        const double rr = (first ? f[row] : r[row]) - acc;
+        r[row] = rr;
+        if (MODE == 1) dn[row] = a * dold + b * (invd[row] * rr);
+    }
+}
+
+// y = acc (EPI_SPMV), f + acc (EPI_ADD) or f - acc (EPI_RESID) over a CSR image.
+template <int LPR, int EPI>
+__global__ __launch_bounds__(256) void k_csr_apply(int64_t nrows, const int64_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                   const double *__restrict__ x, const double *__restrict__ f,
+                                                   double *__restrict__ y)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t row = t / LPR;
+    const int sub = (int)(t % LPR);
+    if (row >= nrows) return;
+    const double acc = csr_row<LPR>(rp, ci, v, x, row, sub);
+    if (sub != 0) return;
+    if (EPI == EPI_ADD) y[row] = f[row] + acc;
+    else if (EPI == EPI_RESID) y[row] = f[row] - acc;
+    else y[row] = acc;
+}
+
 constexpr int CG_THREADS = 1024;
 constexpr int CG_WAVES = CG_THREADS / 64;
 constexpr int CG_MAXN = 2000;   // the coarsest level never exceeds 2000 rows

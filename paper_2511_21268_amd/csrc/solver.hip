@@ -268,6 +268,13 @@ struct DevMat {
     uint16_t *d16 = nullptr;
     double *v64 = nullptr;
     float *v32 = nullptr;
+    // CSR image with `lpr` lanes per row (lpr > 0; FP64, int32 columns) instead
+    // of SELL: long or few rows of the smoothed hierarchy
+    int lpr = 0;
+    int64_t *crp = nullptr;
+    int32_t *cci = nullptr;
+    double *cv = nullptr;
+    bool built() const { return soff || crp; }
     template <typename VT> const VT *val() const;
     template <typename IT> const IT *idx() const;
     template <typename VT, typename IT> Sell<VT, IT> sv() const
@@ -426,7 +433,47 @@ struct amg_ctx {
         release(M.soff); release(M.ibase); release(M.shoff); release(M.perm); release(M.col0); release(M.c32);
         release(M.d16);
         release(M.v64); release(M.v32);
+        release(M.crp); release(M.cci); release(M.cv);
         M = DevMat();
+    }
+    // Image of a matrix of the smoothed-aggregation V-cycle: SELL-64 (stencil
+    // matrices, and short rows in numbers that fill the GPU), else CSR with
+    // 8..64 lanes per row by the mean row length.
+    DevMat upload_image(const CsrView &K, int64_t ncols = 0)
+    {
+        const bool square = ncols <= 0;
+        const int64_t ns = (K.n + SLICE - 1) / SLICE;
+        const double mean = (double)K.nnz() / (double)std::max<int64_t>(K.n, 1);
+        const bool stencil = square && prm.slice_offsets && 2 * count_shared(K, SLICE) >= ns;
+        if (stencil || !(mean >= 256.0 || (mean >= 32.0 && ns < 2048))) return upload_sell(K, SLICE, true, false, ncols);
+        DevMat A;
+        A.n = K.n; A.ncols = square ? K.n : ncols; A.nnz = K.nnz(); A.stored = K.nnz(); A.C = 0;
+        A.index_bytes = 4.0 * (double)K.nnz() + 8.0 * (double)(K.n + 1);
+        A.lpr = mean >= 512.0 ? 64 : mean >= 256.0 ? 32 : mean >= 64.0 ? 16 : 8;
+        A.crp = dupload(K.rp, (size_t)K.n + 1); allocs.push_back(A.crp);
+        A.cci = dupload(K.ci, (size_t)K.nnz()); allocs.push_back(A.cci);
+        A.cv = dupload(K.v, (size_t)K.nnz()); allocs.push_back(A.cv);
+        return A;
+    }
+    // y = acc, f + acc or f - acc over an image (SELL or CSR), FP64, no dots.
+    template <int EPI> void apply(const DevMat &M, const double *x, const double *f, double *y)
+    {
+        if (M.lpr) {
+            const unsigned g = (unsigned)((M.n * M.lpr + 255) / 256);
+#define CSR_APPLY(L) hipLaunchKernelGGL((k_csr_apply<L, EPI>), dim3(g), dim3(256), 0, stream, M.n, M.crp, M.cci, \
+                                        M.cv, x, f, y)
+            switch (M.lpr) {
+            case 8: CSR_APPLY(8); break;
+            case 16: CSR_APPLY(16); break;
+            case 32: CSR_APPLY(32); break;
+            default: CSR_APPLY(64); break;
+            }
+#undef CSR_APPLY
+            HIPCHK(hipGetLastError());
+            return;
+        }
+        launch_sell<double, double, double, EPI, 0>(M, (unsigned)((M.nslices + SELL_WAVES - 1) / SELL_WAVES), x, f,
+                                                    nullptr, y, nullptr, nullptr, 1.0);
     }
     // SELL-C image of a square level matrix, or with ncols > 0 of a
     // rectangular one (K P).  With prm.slice_offsets: a square matrix whose
@@ -828,6 +875,20 @@ struct amg_ctx {
     {
         const Level &L = lev[l];
         const DevMat &A = L.A;
+        if (A.lpr) {
+            const unsigned g = (unsigned)((A.n * A.lpr + 255) / 256);
+#define CSR_CHEB(LP) hipLaunchKernelGGL((k_csr_cheb<LP, MODE>), dim3(g), dim3(256), 0, stream, A.n, A.crp, A.cci, \
+                                        A.cv, x, f, r, L.invd64, u, dn, a, b, first)
+            switch (A.lpr) {
+            case 8: CSR_CHEB(8); break;
+            case 16: CSR_CHEB(16); break;
+            case 32: CSR_CHEB(32); break;
+            default: CSR_CHEB(64); break;
+            }
+#undef CSR_CHEB
+            HIPCHK(hipGetLastError());
+            return;
+        }
         unsigned nb = (unsigned)((A.nslices + SELL_WAVES - 1) / SELL_WAVES);
         if (l == 0) prof_begin();
         if (A.idx16)
@@ -879,11 +940,8 @@ struct amg_ctx {
         // 2. restriction f_c = P^T r
         Level &C = lev[l + 1];
         const bool coarsest = (l + 1 == nlev - 1);
-        if (L.Rm.soff) {
-            launch_sell<double, double, double, EPI_SPMV, 0>(L.Rm, (unsigned)((L.Rm.nslices + SELL_WAVES - 1) /
-                                                                              SELL_WAVES),
-                                                             r, nullptr, nullptr, (double *)C.f, nullptr, nullptr,
-                                                             1.0);
+        if (L.Rm.built()) {
+            apply<EPI_SPMV>(L.Rm, r, nullptr, (double *)C.f);
         } else {
             hipLaunchKernelGGL((k_restrict<double>), dim3(nblocks(C.n)), dim3(256), 0, stream, C.n, L.mw,
                                L.members, L.pc64, (const double *)r, (double *)C.f, nullptr, nullptr, 1.0);
@@ -898,10 +956,8 @@ struct amg_ctx {
             e = vgen(l + 1, (const double *)C.f, nullptr, 0, nullptr, nullptr);
         }
         // 4. prolongation u += P e
-        if (L.Pm.soff) {
-            launch_sell<double, double, double, EPI_ADD, 0>(L.Pm, (unsigned)((L.Pm.nslices + SELL_WAVES - 1) /
-                                                                             SELL_WAVES),
-                                                            e, u, nullptr, u2, nullptr, nullptr, 1.0);
+        if (L.Pm.built()) {
+            apply<EPI_ADD>(L.Pm, e, u, u2);
             std::swap(u, u2);
         } else {
             hipLaunchKernelGGL((k_prolong<double>), dim3(g), dim3(256), 0, stream, L.n, L.agg, L.pc64, e, u);
@@ -1235,10 +1291,10 @@ static amg_status build_device(amg_ctx *c, const CsrView &K0)
         L.nnz = hl.nnz;
         const bool coarsest = (l == c->nlev - 1);
         if (!coarsest || l == 0) {
-            {
-                CsrView K = l == 0 ? K0 : amgiga::view(hl.K);
-                L.A = c->upload_sell(K, SLICE, (l == 0) || !fp32, fp32);
-            }
+            CsrView K = l == 0 ? K0 : amgiga::view(hl.K);
+            // the Chebyshev passes of coarse levels may take the CSR image
+            if (c->prm.smoother == 2 && l > 0) L.A = c->upload_image(K);
+            else L.A = c->upload_sell(K, SLICE, (l == 0) || !fp32, fp32);
         }
         L.invd64 = c->upload(hl.invd);
         if (fp32) {
@@ -1248,8 +1304,8 @@ static amg_status build_device(amg_ctx *c, const CsrView &K0)
         if (!coarsest) {
             if (c->general_vcycle()) {
                 if (!hl.P.rp.empty()) {
-                    L.Pm = c->upload_sell(amgiga::view(hl.P), SLICE, true, false, H.lev[l + 1].n);
-                    L.Rm = c->upload_sell(amgiga::view(hl.PT), SLICE, true, false, hl.n);
+                    L.Pm = c->upload_image(amgiga::view(hl.P), H.lev[l + 1].n);
+                    L.Rm = c->upload_image(amgiga::view(hl.PT), hl.n);
                 }
             } else {
                 CsrView K = l == 0 ? K0 : amgiga::view(hl.K);
@@ -1795,11 +1851,13 @@ amg_status amg_spmv(amg_ctx *c, int level, const double *x, double *y)
         set_err("level has no sparse device matrix");
         return AMG_ERR_ARG;
     }
-    if (!c->lev[level].A.v64) { set_err("level is held in FP32 only (vcycle_fp32)"); return AMG_ERR_ARG; }
+    const DevMat &A = c->lev[level].A;
+    if (!A.v64 && !A.cv) { set_err("level is held in FP32 only (vcycle_fp32)"); return AMG_ERR_ARG; }
     try {
         int saved = c->prof;
         c->prof = 0;
-        c->sell<double, double, double, EPI_SPMV, 0>(level, x, nullptr, nullptr, y, nullptr, nullptr);
+        if (A.lpr) c->apply<EPI_SPMV>(A, x, nullptr, y);
+        else c->sell<double, double, double, EPI_SPMV, 0>(level, x, nullptr, nullptr, y, nullptr, nullptr);
         c->prof = saved;
         HIPCHK(hipStreamSynchronize(c->stream));
     } catch (Fail &f) {
@@ -1945,9 +2003,9 @@ amg_status amg_get_format(const amg_ctx *c, int level, int *slice, int64_t *stor
         return AMG_ERR_ARG;
     }
     const DevMat &A = c->lev[level].A;
-    if (slice) *slice = SLICE;
+    if (slice) *slice = A.lpr ? -A.lpr : SLICE;
     if (stored) *stored = A.stored;
-    if (index_bytes) *index_bytes = A.idx16 ? 2 : 4;
+    if (index_bytes) *index_bytes = (A.idx16 && !A.lpr) ? 2 : 4;
     if (shared_slices) *shared_slices = A.nshared;
     return AMG_OK;
 }
