@@ -92,6 +92,7 @@ def lib():
         L.or_level_pnnz.restype = C.c_int64
         L.or_level_prolongator.argtypes = [C.c_void_p, C.c_int, i64p, i32p, f64p]
         L.or_cheb4.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, f64p, f64p, C.c_int, C.c_int]
+        L.or_bootstrap_w.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, C.c_int, f64p]
         L.or_cg_jacobi.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, f64p, C.c_double, C.c_int]
         L.or_spmv.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, f64p]
         L.or_dot.argtypes = [C.c_int64, f64p, f64p]
@@ -448,3 +449,11 @@ def cg_jacobi(rp, ci, v, b, tol=1e-4, itmax=30):
     it = lib().or_cg_jacobi(len(b), _p(rp, i64p), _p(ci, i32p), _p(v, f64p), _p(b, f64p), _p(x, f64p),
                             float(tol), int(itmax))
     return x, it
+
+
+def bootstrap_w(rp, ci, v, w0, sweeps):
+    """Test vector: `sweeps` l1-Jacobi sweeps on K w = 0 from w0."""
+    rp, ci, v, w0 = _i64(rp), _i32(ci), _f64(v), _f64(w0)
+    w = np.zeros_like(w0)
+    lib().or_bootstrap_w(len(w0), _p(rp, i64p), _p(ci, i32p), _p(v, f64p), _p(w0, f64p), int(sweeps), _p(w, f64p))
+    return w

@@ -29,6 +29,9 @@
  *    Jacobi sweep z = diag(K)^{-1} r from x = 0 (a Jacobi weight cancels in
  *    CG), to ||r|| <= coarse_tol ||f|| or coarse_itmax iterations; the
  *    V-cycle is then a variable preconditioner (use FCG);
+ *  - test vector (Sec. 3.1): a few l1-Jacobi sweeps on K w = 0 from a random
+ *    start that the caller draws (the relaxation named by the paper is damped
+ *    Jacobi or Gauss-Seidel; l1-Jacobi is the path's own damped Jacobi);
  *  - restriction and prolongation with a smoothed prolongator: f_c = P'^T r
  *    summed over the rows i ascending, u_i += sum_J P'_iJ e_J ascending J;
  *  - CG: Hestenes-Stiefel PCG; FCG(1): alpha = (p,r)/(p,q),
@@ -88,6 +91,19 @@ static void sweep(const or_level *L, int poly, const double *f, double *u,
     for (int64_t i = 0; i < L->n; i++) r[i] = f[i] - r[i];
     smoother_apply(L, poly, r, c, tmp);
     for (int64_t i = 0; i < L->n; i++) u[i] = u[i] + c[i];
+}
+
+void or_bootstrap_w(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *w0,
+                    int sweeps, double *w)
+{
+    double *invd = malloc(sizeof(double) * n), *s = malloc(sizeof(double) * n);
+    or_l1_invdiag(n, rp, ci, v, invd);
+    memcpy(w, w0, sizeof(double) * n);
+    for (int k = 0; k < sweeps; k++) {
+        or_spmv(n, rp, ci, v, w, s);
+        for (int64_t i = 0; i < n; i++) w[i] = w[i] - invd[i] * s[i];
+    }
+    free(invd); free(s);
 }
 
 void or_cheb4(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *invd,

@@ -173,6 +173,11 @@ void or_vcycle(const or_hier *h, int l, const double *r, double *z);
  * -5 breakdown.  hist (may be NULL) receives ||r_k||/||F|| for k = 0..iters. */
 int  or_pcg(const or_hier *h, const double *F, double *u, double tol, int itmax,
             int flexible, int *iters, double *relres, double *hist);
+/* Test vector by relaxation on K w = 0 (Sec. 3.1, "Edge weights and projection
+ * onto the fine subspace"): `sweeps` l1-Jacobi sweeps w <- w - D^{-1} (K w) from
+ * the given random start w0 (row sums ascending from +0.0, no contraction). */
+void or_bootstrap_w(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *w0,
+                    int sweeps, double *w);
 /* Fourth-kind Chebyshev smoother of the given degree for K x = f with the
  * l1 diagonal (invd = 1/d): x in: initial guess (ignored, taken as 0, when
  * x0_zero), out: the smoothed iterate. */

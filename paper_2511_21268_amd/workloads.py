@@ -35,6 +35,11 @@ def rhs_block(N, seeds):
     return np.stack([rhs_normal(N, s) for s in seeds], axis=1)
 
 
+def random_start(N, seed):
+    """Random start of the test-vector relaxation: uniform on [0, 1), float64."""
+    return np.random.default_rng(seed).random(N)
+
+
 def kappa_params(seed, nterms=8):
     """Parameters of kappa(x) = exp(0.5 sum_k a_k cos(2 pi m_k . x)):
     a_k ~ N(0,1) then m_k in {0..3}^3, drawn in that order from one generator."""

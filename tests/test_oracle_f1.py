@@ -220,3 +220,26 @@ def test_table1c_operator_complexity_k12():
         h = oracle.Hierarchy(rp, ci, v, sweeps_per_level=3, smooth_prolong=1, smoother=2, cheb_degree=deg[p],
                              coarse_solver=1)
         assert abs(h.opc() - opc[str(p)]) <= 0.02, (p, h.opc())
+
+
+@pytest.mark.parametrize("sweeps", [1, 3, 10])
+def test_bootstrap_w(sweeps):
+    from paper_2511_21268_amd.workloads import random_start
+    rp, ci, v, K, invd = _small_system()
+    n = K.shape[0]
+    w0 = random_start(n, sweeps)
+    w = oracle.bootstrap_w(rp, ci, v, w0, sweeps)
+    # the iteration (I - D^{-1} K)^s w0 by dense matrix powers
+    E = np.eye(n) - invd[:, None] * K
+    ref = np.linalg.matrix_power(E, sweeps) @ w0
+    assert np.linalg.norm(w - ref) <= 1e-13 * np.linalg.norm(ref)
+    # each sweep lowers the energy (spectrum of I - D^{-1}K in [0, 1)) and the
+    # Rayleigh quotient (w is smoother than the random start)
+    prev = w0
+    for s in range(1, sweeps + 1):
+        cur = oracle.bootstrap_w(rp, ci, v, w0, s)
+        assert cur @ K @ cur < prev @ K @ prev
+        prev = cur
+    d = 1.0 / invd
+    assert (w @ K @ w) / (w @ (d * w)) < (w0 @ K @ w0) / (w0 @ (d * w0))
+    assert np.array_equal(oracle.bootstrap_w(rp, ci, v, w0, 0), w0)
