@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--itmax", type=int, default=0, help="iteration limit (0: the workload's, else 1000)")
+    ap.add_argument("--setup-device", action="store_true",
+                    help="build the hierarchy (matching, Galerkin products) on the device")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -165,6 +167,8 @@ def main():
     kw["itmax"] = args.itmax or cfg.get("itmax", 1000)
     if nrhs > 1:
         kw["nrhs"] = nrhs
+    if args.setup_device:
+        kw["setup_device"] = 1
     ctx = amg.Context(rp, ci, v, **kw)
     if args.mode == "learned":
         from paper_2511_21268_amd import learned
@@ -260,6 +264,7 @@ def main():
                       "mode": args.mode, "nrhs": nrhs, "converged": converged,
                       "iters": iters[-1], "relres_true": relres_true, "levels": len(levels),
                       "opc": round(ctx.opc(), 4), "setup_s": round(setup_s, 2),
+                      "setup_on_device": bool(args.setup_device),
                       "spmv_gbs": round(achieved, 1),
                       "block_variant": list(ctx.batched_variant()) if nrhs > 1 else None},
            "roofline": roofline, "cpu_baseline": cpu}

@@ -91,6 +91,16 @@ typedef struct {
     double omega;           /* smooth_prolong: damping, (0, 2]; default 4/3     */
     double coarse_tol;      /* coarse_solver 1: relative residual, >= 0;
                                default 1e-4                                     */
+    int setup_device;       /* 0 (default): matching and Galerkin products on
+                               the host; 1: on the device (rounds of locally
+                               dominant edges, sort-based Galerkin), the same
+                               hierarchy bit for bit; needs a structurally
+                               symmetric K with fewer than 2^31 entries and
+                               smooth_prolong = 0 (not with amg_setup_host)     */
+    int bootstrap_sweeps;   /* 0 (default): the test vector is w (ones if NULL);
+                               s > 0: w is the random start of s l1-Jacobi
+                               sweeps on K w = 0 (Sec. 3.1) and must be given;
+                               at most 1000                                     */
 } amg_params;
 
 /* Fill p with the defaults above.  p must not be NULL. */
@@ -193,6 +203,11 @@ amg_status amg_get_aggregates(const amg_ctx *c, int level, int32_t *agg, double 
  * amg_get_level_info).  Any output may be NULL. */
 amg_status amg_get_coarse_matrix(const amg_ctx *c, int level, int64_t *row_ptr, int32_t *col,
                                  double *val);
+
+/* Rounds of the device matching (setup_device = 1): matching sweeps run, rounds
+ * of locally dominant edges summed over them, and the most in one sweep; zeros
+ * for a host set-up.  Any output may be NULL. */
+amg_status amg_get_setup_rounds(const amg_ctx *c, int *sweeps, int *rounds_total, int *rounds_max);
 
 /* Host CSR copy of the smoothed prolongator (I - omega D^{-1} K) P of level
  * `level` (0 .. levels-2; rows n_level, columns n_{level+1}; Sec. 3.1

@@ -24,7 +24,7 @@ EXPORTS = ["amg_params_default", "amg_setup", "pcg_solve", "pcg_solve_batched", 
            "amg_iga_poisson_size", "amg_iga_poisson", "amg_iga_diffusion", "amg_level_features",
            "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_adam", "amg_set_learned_poly",
            "amg_get_batched_variant", "amg_set_batched_variant", "amg_set_option", "amg_sell_spmv_host",
-           "amg_iga_cube_size", "amg_iga_cube", "amg_get_prolongator"]
+           "amg_iga_cube_size", "amg_iga_cube", "amg_get_prolongator", "amg_get_setup_rounds"]
 AMG_OPT_GRAPH, AMG_OPT_FUSE_POST = 1, 2
 MLP_NPARAM, MLP_NFEAT, MLP_NACT, MLP_NDEL = 4996, 8, 128, 132
 
@@ -41,7 +41,7 @@ class Params(C.Structure):
                 ("krylov", C.c_int), ("match_positive_only", C.c_int), ("itmax", C.c_int), ("nrhs", C.c_int),
                 ("slice_offsets", C.c_int), ("smooth_prolong", C.c_int), ("cheb_degree", C.c_int),
                 ("coarse_solver", C.c_int), ("coarse_itmax", C.c_int), ("omega", C.c_double),
-                ("coarse_tol", C.c_double)]
+                ("coarse_tol", C.c_double), ("setup_device", C.c_int), ("bootstrap_sweeps", C.c_int)]
 
 # The paper's default preconditioner (Sec. 3.1 variants, Sec. 5.1): aggregates
 # of 8, smoothed prolongator, Chebyshev-accelerated l1-Jacobi of degree
@@ -83,6 +83,7 @@ def lib():
         L.amg_get_aggregates.argtypes = [vp, C.c_int, i32p, f64p]
         L.amg_get_coarse_matrix.argtypes = [vp, C.c_int, i64p, i32p, f64p]
         L.amg_get_prolongator.argtypes = [vp, C.c_int, i64p, i64p, i32p, f64p]
+        L.amg_get_setup_rounds.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.amg_destroy.argtypes = [vp]
         L.amg_destroy.restype = None
         L.amg_last_error.restype = C.c_char_p
@@ -262,6 +263,12 @@ class Context:
         rp = np.empty(n + 1, np.int64); ci = np.empty(nz.value, np.int32); v = np.empty(nz.value)
         _check(lib().amg_get_prolongator(self.h, level, C.byref(nz), _p(rp, i64p), _p(ci, i32p), _p(v, f64p)))
         return rp, ci, v
+
+    def setup_rounds(self):
+        """(matching sweeps, rounds summed, most rounds in a sweep) of a device set-up."""
+        a = C.c_int(); b = C.c_int(); d = C.c_int()
+        _check(lib().amg_get_setup_rounds(self.h, C.byref(a), C.byref(b), C.byref(d)))
+        return a.value, b.value, d.value
 
     def format(self, level=0):
         sl = C.c_int(); stored = C.c_int64(); ib = C.c_int(); sh = C.c_int64()

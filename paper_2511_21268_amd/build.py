@@ -30,8 +30,13 @@ def build(verbose=False):
     _run([HIPCC, "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
          + inc + ["-c", os.path.join(CSRC, "solver.hip"), "-o", dev_o])
+    # device set-up: no FMA contraction (its bits must equal the host set-up's)
+    sdev_o = os.path.join(bdir, "setup_dev.o")
+    _run([HIPCC, "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-ffp-contract=off",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
+         + inc + ["-c", os.path.join(CSRC, "setup_dev.hip"), "-o", sdev_o])
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, dev_o, host_o, "-pthread"])
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, dev_o, sdev_o, host_o, "-pthread"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -36,6 +36,7 @@ struct SetupParams {
     int smooth = 0;              // smoothed prolongator (I - omega D^{-1} K) P
     double omega = 4.0 / 3.0;
     int coarse_dense = 1;        // dense lower triangle of the coarsest matrix
+    int bootstrap = 0;           // > 0: w from this many relaxation sweeps on K w = 0
 };
 
 struct HostLevel {
@@ -55,10 +56,32 @@ struct HostHierarchy {
     std::vector<double> coarse_lower;  // dense n_L x n_L, lower triangle of K_L
 };
 
+// One level's coarsening: m composed pairwise sweeps (matching, pairwise
+// prolongator, Galerkin product) from (K, w) to the coarse matrix and test
+// vector, with the composed aggregate map and coefficients.
+struct CoarsenResult {
+    int64_t nc = 0;
+    std::vector<int32_t> agg;
+    std::vector<double> pc, wc;
+    Csr C;
+};
+
+// Alternative executor of the set-up steps (the device one); results must be
+// the host's bits.
+struct Coarsener {
+    virtual ~Coarsener() {}
+    // w = `sweeps` l1-Jacobi sweeps on K w = 0 from w0
+    virtual void bootstrap(const CsrView &K0, const double *w0, int sweeps, std::vector<double> &w) = 0;
+    virtual void coarsen(int level, const CsrView &K, const double *w, const SetupParams &prm, CoarsenResult &out) = 0;
+};
+
 // Status codes follow amg_status.
 int validate_csr(const CsrView &K, std::string &err);
 int build_hierarchy(const CsrView &K0, const double *w, const SetupParams &prm,
-                    HostHierarchy &H, std::string &err);
+                    HostHierarchy &H, std::string &err, Coarsener *dev = nullptr);
+// Test vector on the host: `sweeps` l1-Jacobi sweeps on K w = 0 from w0, each
+// row sum ascending from +0.0, w_i <- w_i - invd_i s_i.
+void bootstrap_w(const CsrView &K, const double *w0, int sweeps, std::vector<double> &w);
 
 // Features of a level for the learned smoother (the first six of eight; the
 // relative depth and the coarsening ratio are added once the hierarchy is known):

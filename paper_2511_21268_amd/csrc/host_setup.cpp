@@ -475,8 +475,25 @@ static void make_coarsest(HostHierarchy &H, const CsrView &K, int dense = 1)
             if (K.ci[k] <= i) H.coarse_lower[(size_t)(i * n + K.ci[k])] = K.v[k];
 }
 
+void bootstrap_w(const CsrView &K, const double *w0, int sweeps, std::vector<double> &w)
+{
+    std::vector<double> invd, s(K.n);
+    l1_invdiag(K, invd);
+    w.assign(w0, w0 + K.n);
+    for (int k = 0; k < sweeps; k++) {
+        parallel_for(K.n, [&](int64_t b, int64_t e) {
+            for (int64_t i = b; i < e; i++) {
+                double t = 0.0;
+                for (int64_t q = K.rp[i]; q < K.rp[i + 1]; q++) t = t + K.v[q] * w[K.ci[q]];
+                s[i] = t;
+            }
+        });
+        for (int64_t i = 0; i < K.n; i++) w[i] = w[i] - invd[i] * s[i];
+    }
+}
+
 int build_hierarchy(const CsrView &K0, const double *w, const SetupParams &prm,
-                    HostHierarchy &H, std::string &err)
+                    HostHierarchy &H, std::string &err, Coarsener *dev)
 {
     int maxl = prm.max_levels > 0 ? prm.max_levels : 1;
     H.lev.clear();
@@ -485,8 +502,13 @@ int build_hierarchy(const CsrView &K0, const double *w, const SetupParams &prm,
         HostLevel &L0 = H.lev[0];
         L0.n = K0.n;
         L0.nnz = K0.nnz();
-        L0.w.resize(K0.n);
-        for (int64_t i = 0; i < K0.n; i++) L0.w[i] = w ? w[i] : 1.0;
+        if (prm.bootstrap > 0) {
+            if (dev) dev->bootstrap(K0, w, prm.bootstrap, L0.w);
+            else bootstrap_w(K0, w, prm.bootstrap, L0.w);
+        } else {
+            L0.w.resize(K0.n);
+            for (int64_t i = 0; i < K0.n; i++) L0.w[i] = w ? w[i] : 1.0;
+        }
         l1_invdiag(K0, L0.invd);
         level_features(K0, L0.invd, L0.feat);
     }
@@ -505,7 +527,16 @@ int build_hierarchy(const CsrView &K0, const double *w, const SetupParams &prm,
         std::vector<double> cw;
         const double *wl = H.lev[l].w.data();
         int64_t nc = nl;
-        for (int s = 0; s < prm.sweeps; s++) {
+        if (dev) {
+            CoarsenResult res;
+            dev->coarsen(l, K, wl, prm, res);
+            nc = res.nc;
+            agg = std::move(res.agg);
+            pc = std::move(res.pc);
+            cur = std::move(res.C);
+            cw = std::move(res.wc);
+        }
+        for (int s = 0; s < (dev ? 0 : prm.sweeps); s++) {
             CsrView kv = s == 0 ? K : view(cur);
             const double *ww = s == 0 ? wl : cw.data();
             std::vector<int32_t> mate(kv.n);

@@ -9,6 +9,7 @@
 #include "kernels.h"
 #include "kernels_blk.h"
 #include "mlp.h"
+#include "setup_dev.h"
 
 #include <hip/hip_runtime.h>
 
@@ -397,6 +398,7 @@ struct amg_ctx {
         }
     };
     std::vector<std::pair<std::string, double>> tune_log;
+    amgiga::DevSetupInfo setup_info;
     double *sc = nullptr;
     double *hsc = nullptr;     // pinned host copy of the scalar block
     hipEvent_t ev_iter = nullptr;
@@ -1423,6 +1425,8 @@ amg_status amg_params_default(amg_params *p)
     p->coarse_itmax = 30;
     p->omega = 4.0 / 3.0;
     p->coarse_tol = 1e-4;
+    p->setup_device = 0;
+    p->bootstrap_sweeps = 0;
     return AMG_OK;
 }
 
@@ -1444,7 +1448,8 @@ static amg_status setup_common(int64_t n, const int64_t *row_ptr, const int32_t 
         P.smoother < 0 || P.smoother > 2 || P.slice_offsets < 0 || P.slice_offsets > 1 ||
         P.smooth_prolong < 0 || P.smooth_prolong > 1 || P.cheb_degree < 1 || P.cheb_degree > 64 ||
         P.coarse_solver < 0 || P.coarse_solver > 1 || P.coarse_itmax < 1 || P.coarse_itmax > 1000 ||
-        !(P.omega > 0.0 && P.omega <= 2.0) || !(P.coarse_tol >= 0.0 && std::isfinite(P.coarse_tol))) {
+        !(P.omega > 0.0 && P.omega <= 2.0) || !(P.coarse_tol >= 0.0 && std::isfinite(P.coarse_tol)) ||
+        P.setup_device < 0 || P.setup_device > 1 || P.bootstrap_sweeps < 0 || P.bootstrap_sweeps > 1000) {
         set_err("parameter out of range");
         return AMG_ERR_ARG;
     }
@@ -1456,6 +1461,11 @@ static amg_status setup_common(int64_t n, const int64_t *row_ptr, const int32_t 
         }
     }
     if (n <= 0 || !row_ptr || !col || !val) { set_err("n <= 0 or NULL CSR array"); return AMG_ERR_ARG; }
+    if (P.bootstrap_sweeps > 0 && !w) { set_err("bootstrap_sweeps needs the random start in w"); return AMG_ERR_ARG; }
+    if (P.setup_device && (host_only || P.smooth_prolong)) {
+        set_err("setup_device needs a device context and the tentative prolongator (smooth_prolong 0)");
+        return AMG_ERR_ARG;
+    }
     if (!host_only && n >= (int64_t(1) << 29)) {
         // vector gathers use 32-bit byte offsets
         set_err("the device path takes at most 2^29 - 1 rows");
@@ -1481,7 +1491,14 @@ static amg_status setup_common(int64_t n, const int64_t *row_ptr, const int32_t 
         sp.smooth = P.smooth_prolong;
         sp.omega = P.omega;
         sp.coarse_dense = P.coarse_solver == 0;
-        int rc = amgiga::build_hierarchy(K0, w, sp, c->host, err);
+        sp.bootstrap = P.bootstrap_sweeps;
+        int rc;
+        if (P.setup_device) {
+            HIPCHK(hipGetDevice(&c->device));
+            rc = amgiga::build_hierarchy_on_device(K0, w, sp, c->host, err, (void *)c->stream, &c->setup_info);
+        } else {
+            rc = amgiga::build_hierarchy(K0, w, sp, c->host, err);
+        }
         if (rc) { set_err(err); return (amg_status)rc; }
         c->nlev = (int)c->host.lev.size();
         if (!host_only) {
@@ -1960,6 +1977,15 @@ amg_status amg_get_coarse_matrix(const amg_ctx *c, int level, int64_t *row_ptr, 
     if (row_ptr) std::memcpy(row_ptr, K.rp.data(), K.rp.size() * sizeof(int64_t));
     if (col) std::memcpy(col, K.ci.data(), K.ci.size() * sizeof(int32_t));
     if (val) std::memcpy(val, K.v.data(), K.v.size() * sizeof(double));
+    return AMG_OK;
+}
+
+amg_status amg_get_setup_rounds(const amg_ctx *c, int *sweeps, int *rounds_total, int *rounds_max)
+{
+    if (!c) { set_err("NULL context"); return AMG_ERR_ARG; }
+    if (sweeps) *sweeps = c->setup_info.sweeps;
+    if (rounds_total) *rounds_total = c->setup_info.rounds_total;
+    if (rounds_max) *rounds_max = c->setup_info.rounds_max;
     return AMG_OK;
 }
 
