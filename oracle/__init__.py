@@ -92,6 +92,7 @@ def lib():
         L.or_level_pnnz.restype = C.c_int64
         L.or_level_prolongator.argtypes = [C.c_void_p, C.c_int, i64p, i32p, f64p]
         L.or_cheb4.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, f64p, f64p, C.c_int, C.c_int]
+        L.or_block_fcg.argtypes = [C.c_void_p, C.c_int, f64p, f64p, C.c_double, C.c_int, C.POINTER(C.c_int), f64p]
         L.or_bootstrap_w.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, C.c_int, f64p]
         L.or_cg_jacobi.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, f64p, C.c_double, C.c_int]
         L.or_spmv.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, f64p]
@@ -423,6 +424,16 @@ class Hierarchy:
         r = _f64(r); z = np.zeros_like(r)
         lib().or_vcycle(self.h, level, _p(r, f64p), _p(z, f64p))
         return z
+
+    def block_solve(self, F, U0=None, tol=1e-8, itmax=1000):
+        """Block flexible CG for the columns of F (n x s)."""
+        F = np.asarray(F, np.float64)
+        n, s = F.shape
+        Fc = np.ascontiguousarray(F.T)
+        U = np.zeros_like(Fc) if U0 is None else np.ascontiguousarray(np.asarray(U0, np.float64).T)
+        it = (C.c_int * s)(); rel = np.zeros(s)
+        rc = lib().or_block_fcg(self.h, s, _p(Fc, f64p), _p(U, f64p), tol, itmax, it, _p(rel, f64p))
+        return dict(rc=rc, U=U.T.copy(), iters=np.array(list(it)), relres=rel)
 
     def solve(self, F, u0=None, tol=1e-8, itmax=1000, flexible=False):
         F = _f64(F)

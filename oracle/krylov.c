@@ -34,6 +34,13 @@
  *    Jacobi or Gauss-Seidel; l1-Jacobi is the path's own damped Jacobi);
  *  - restriction and prolongation with a smoothed prolongator: f_c = P'^T r
  *    summed over the rows i ascending, u_i += sum_J P'_iJ e_J ascending J;
+ *  - block flexible CG for s right-hand sides (O'Leary's block CG, with the
+ *    coefficients of FCG(1) so that a variable preconditioner is allowed):
+ *    Q = K P, G = P^T Q, alpha = G^{-1} P^T R, X += P alpha, R -= Q alpha,
+ *    Z = B R, beta = -G^{-1} Q^T Z, P = Z + P beta, all over the active
+ *    columns (G^{-1} by Cholesky of the active block); a column whose
+ *    residual reaches tol ||F_j|| leaves the block (its X and R freeze), and
+ *    beta is formed over the columns still active after that test;
  *  - CG: Hestenes-Stiefel PCG; FCG(1): alpha = (p,r)/(p,q),
  *    beta = -(z_{k+1}, q_k)/(p_k, q_k);
  *  - stop when ||r_k||_2 <= tol ||F||_2 on the recursive residual; iters counts
@@ -313,4 +320,132 @@ int or_set_poly(or_hier *h, int l, const double *coef)
     if (!or_poly_accept(coef)) return 1;
     for (int k = 0; k < 4; k++) h->lev[l].poly[k] = coef[k];
     return 0;
+}
+
+/* Cholesky of the s x s SPD block G (row-major, leading dimension ld) into L;
+ * returns -1 on a non-positive pivot. */
+static int small_chol(int s, const double *G, int ld, double *L)
+{
+    for (int i = 0; i < s; i++)
+        for (int j = 0; j <= i; j++) {
+            double t = G[i * ld + j];
+            for (int k = 0; k < j; k++) t -= L[i * s + k] * L[j * s + k];
+            if (i == j) {
+                if (!(t > 0.0) || !isfinite(t)) return -1;
+                L[i * s + i] = sqrt(t);
+            } else {
+                L[i * s + j] = t / L[j * s + j];
+            }
+        }
+    return 0;
+}
+
+/* Y = G^{-1} B for the s x m right side B (row-major s x m), with L from small_chol. */
+static void small_solve(int s, const double *L, int m, double *B)
+{
+    for (int c = 0; c < m; c++) {
+        for (int i = 0; i < s; i++) {
+            double t = B[i * m + c];
+            for (int k = 0; k < i; k++) t -= L[i * s + k] * B[k * m + c];
+            B[i * m + c] = t / L[i * s + i];
+        }
+        for (int i = s - 1; i >= 0; i--) {
+            double t = B[i * m + c];
+            for (int k = i + 1; k < s; k++) t -= L[k * s + i] * B[k * m + c];
+            B[i * m + c] = t / L[i * s + i];
+        }
+    }
+}
+
+int or_block_fcg(const or_hier *h, int s, const double *F, double *U, double tol, int itmax, int *iters,
+                 double *relres)
+{
+    const or_level *L0 = &h->lev[0];
+    const int64_t n = L0->n;
+    double *R = malloc(sizeof(double) * n * s), *Z = malloc(sizeof(double) * n * s);
+    double *P = malloc(sizeof(double) * n * s), *Q = malloc(sizeof(double) * n * s);
+    double *G = malloc(sizeof(double) * s * s), *Lc = malloc(sizeof(double) * s * s);
+    double *A = malloc(sizeof(double) * s * s), *nf = malloc(sizeof(double) * s), *rr = malloc(sizeof(double) * s);
+    int *act = malloc(sizeof(int) * s), *idx = malloc(sizeof(int) * s);
+    int rc = 1;
+    for (int j = 0; j < s; j++) {
+        const double *f = F + (int64_t)j * n;
+        double *r = R + (int64_t)j * n;
+        or_spmv(n, L0->rp, L0->ci, L0->v, U + (int64_t)j * n, r);
+        for (int64_t i = 0; i < n; i++) r[i] = f[i] - r[i];
+        nf[j] = sqrt(or_dot(n, f, f));
+        rr[j] = or_dot(n, r, r);
+        iters[j] = 0;
+        act[j] = !(nf[j] == 0.0 || sqrt(rr[j]) <= tol * nf[j]);
+    }
+    int na = 0;
+    for (int j = 0; j < s; j++) na += act[j];
+    if (na == 0) { rc = 0; goto done; }
+    for (int j = 0; j < s; j++)
+        if (act[j]) {
+            or_vcycle(h, 0, R + (int64_t)j * n, Z + (int64_t)j * n);
+            memcpy(P + (int64_t)j * n, Z + (int64_t)j * n, sizeof(double) * n);
+        }
+    for (int k = 1; k <= itmax; k++) {
+        int m = 0;
+        for (int j = 0; j < s; j++) if (act[j]) idx[m++] = j;
+        for (int a = 0; a < m; a++)
+            or_spmv(n, L0->rp, L0->ci, L0->v, P + (int64_t)idx[a] * n, Q + (int64_t)idx[a] * n);
+        /* G = P^T Q and A = P^T R over the active columns */
+        for (int a = 0; a < m; a++)
+            for (int b = 0; b < m; b++) {
+                G[a * m + b] = or_dot(n, P + (int64_t)idx[a] * n, Q + (int64_t)idx[b] * n);
+                A[a * m + b] = or_dot(n, P + (int64_t)idx[a] * n, R + (int64_t)idx[b] * n);
+            }
+        if (small_chol(m, G, m, Lc)) { rc = -5; goto done; }
+        small_solve(m, Lc, m, A);            /* alpha = G^{-1} P^T R */
+        for (int b = 0; b < m; b++) {
+            double *x = U + (int64_t)idx[b] * n, *r = R + (int64_t)idx[b] * n;
+            for (int64_t i = 0; i < n; i++) {
+                double dx = 0.0, dr = 0.0;
+                for (int a = 0; a < m; a++) {
+                    dx = dx + P[(int64_t)idx[a] * n + i] * A[a * m + b];
+                    dr = dr + Q[(int64_t)idx[a] * n + i] * A[a * m + b];
+                }
+                x[i] = x[i] + dx;
+                r[i] = r[i] - dr;
+            }
+            const int j = idx[b];
+            rr[j] = or_dot(n, r, r);
+            iters[j] = k;
+            if (sqrt(rr[j]) <= tol * nf[j]) act[j] = 0;
+        }
+        na = 0;
+        for (int j = 0; j < s; j++) na += act[j];
+        if (na == 0) { rc = 0; break; }
+        if (k == itmax) break;
+        /* beta over the columns still active: -G'^{-1} Q'^T Z' */
+        int m2 = 0;
+        int *pos = malloc(sizeof(int) * m);
+        for (int a = 0; a < m; a++) if (act[idx[a]]) pos[m2++] = a;
+        for (int a = 0; a < m2; a++)
+            or_vcycle(h, 0, R + (int64_t)idx[pos[a]] * n, Z + (int64_t)idx[pos[a]] * n);
+        double *G2 = malloc(sizeof(double) * m2 * m2), *B = malloc(sizeof(double) * m2 * m2);
+        for (int a = 0; a < m2; a++)
+            for (int b = 0; b < m2; b++) {
+                G2[a * m2 + b] = G[pos[a] * m + pos[b]];
+                B[a * m2 + b] = -or_dot(n, Q + (int64_t)idx[pos[a]] * n, Z + (int64_t)idx[pos[b]] * n);
+            }
+        if (small_chol(m2, G2, m2, Lc)) { free(pos); free(G2); free(B); rc = -5; goto done; }
+        small_solve(m2, Lc, m2, B);
+        /* P_j = Z_j + sum_a P_a beta_aj, written after all reads of the old P */
+        double *Pn = malloc(sizeof(double) * n * m2);
+        for (int b = 0; b < m2; b++)
+            for (int64_t i = 0; i < n; i++) {
+                double t = 0.0;
+                for (int a = 0; a < m2; a++) t = t + P[(int64_t)idx[pos[a]] * n + i] * B[a * m2 + b];
+                Pn[(int64_t)b * n + i] = Z[(int64_t)idx[pos[b]] * n + i] + t;
+            }
+        for (int b = 0; b < m2; b++) memcpy(P + (int64_t)idx[pos[b]] * n, Pn + (int64_t)b * n, sizeof(double) * n);
+        free(Pn); free(pos); free(G2); free(B);
+    }
+done:
+    for (int j = 0; j < s; j++) relres[j] = nf[j] > 0.0 ? sqrt(rr[j]) / nf[j] : 0.0;
+    free(R); free(Z); free(P); free(Q); free(G); free(Lc); free(A); free(nf); free(rr); free(act); free(idx);
+    return rc;
 }

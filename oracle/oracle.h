@@ -188,6 +188,14 @@ void or_cheb4(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, 
  * Returns the iteration count. */
 int  or_cg_jacobi(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, const double *b,
                   double *x, double tol, int itmax);
+/* Block flexible CG (O'Leary's block CG with the flexible coefficients) for s
+ * right-hand sides F (n x s, column j at F + j n), preconditioned by the
+ * V-cycle; U in: initial guesses, out: solutions.  Columns whose residual
+ * reaches tol ||F_j|| leave the block.  iters[j], relres[j] per column.
+ * Returns 0 all converged, 1 not converged, -5 breakdown (Gram matrix not
+ * positive definite). */
+int  or_block_fcg(const or_hier *h, int s, const double *F, double *U, double tol, int itmax, int *iters,
+                  double *relres);
 /* l1-Jacobi-preconditioned polynomial smoother error polynomial check. */
 int  or_poly_accept(const double *coef);
 
