@@ -100,9 +100,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c4")
-    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32", "batched", "learned", "paper"],
+    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32", "batched", "blockcg", "learned", "paper"],
                     help="fp64: FP64 PCG (default); fp32: FP32 V-cycle inside FP64 FCG; "
                          "batched: 16 right-hand sides, FP32 block V-cycle inside FP64 FCG; "
+                         "blockcg: the same 16 right-hand sides by block flexible CG; "
                          "learned: FP64 PCG with the MLP-predicted degree-4 polynomial smoothers; "
                          "paper: FP64 FCG with the paper's default preconditioner (aggregates of 8, "
                          "smoothed prolongator, Chebyshev l1-Jacobi, CG coarse solve)")
@@ -152,7 +153,7 @@ def main():
         Fload = None
     N, nnz = len(rp) - 1, len(v)
     log(f"generated K: N={N} nnz={nnz} in {time.time() - t:.1f} s")
-    nrhs = 16 if args.mode == "batched" else 1
+    nrhs = 16 if args.mode in ("batched", "blockcg") else 1
     if Fload is not None:
         F = torch.from_numpy(Fload).cuda()      # f = 1
     elif nrhs == 1:
@@ -162,8 +163,8 @@ def main():
         F = torch.from_numpy(rhs_block(N, range(args.seed, args.seed + nrhs))).cuda()
     torch.cuda.synchronize()
     t = time.time()
-    kw = dict({"fp64": {}, "learned": {"smoother": 1}, "paper": amg.paper_default(cfg["p"])}.get(
-        args.mode, {"vcycle_fp32": 1, "krylov": 1}))
+    kw = dict({"fp64": {}, "learned": {"smoother": 1}, "paper": amg.paper_default(cfg["p"]),
+               "blockcg": {"vcycle_fp32": 1, "krylov": 2}}.get(args.mode, {"vcycle_fp32": 1, "krylov": 1}))
     kw["itmax"] = args.itmax or cfg.get("itmax", 1000)
     if nrhs > 1:
         kw["nrhs"] = nrhs
@@ -242,6 +243,7 @@ def main():
 
     form = {"fp64": "FP64 PCG", "fp32": "FP32 V-cycle in FP64 FCG",
             "batched": "16 RHS, FP32 block V-cycle in FP64 FCG",
+            "blockcg": "16 RHS, FP32 block V-cycle in FP64 block flexible CG",
             "learned": "FP64 PCG, learned degree-4 polynomial smoothers", "paper": "FP64 FCG"}[args.mode]
     smoother = "learned POLY4" if args.mode == "learned" else "l1-Jacobi 1/1"
     amg_desc = f"m=2, {smoother}, Cholesky <= 200"

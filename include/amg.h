@@ -59,7 +59,11 @@ typedef struct {
                                in D^{-1}K (coefficients by amg_set_poly_coeffs);
                                2: Chebyshev acceleration of l1-Jacobi (Sec. 3.2,
                                Sec. 5.1), fourth kind, degree cheb_degree      */
-    int krylov;             /* 0: CG; 1: flexible CG, FCG(1) (Sec. 3.1 end)     */
+    int krylov;             /* 0: CG; 1: flexible CG, FCG(1) (Sec. 3.1 end);
+                               2: in pcg_solve_batched, block flexible CG (one
+                               block Krylov space shared by the columns, 16 x 16
+                               Gram matrices; a converged column leaves the
+                               block), FCG(1) in pcg_solve                      */
     int match_positive_only;/* 0: every edge eligible (default);
                                1: only edges with c_ij > 1 (log c_ij > 0)       */
     int itmax;              /* default 1000                                     */

@@ -8,6 +8,7 @@
 #include "host.h"
 #include "kernels.h"
 #include "kernels_blk.h"
+#include "blockcg.h"
 #include "mlp.h"
 #include "setup_dev.h"
 
@@ -338,6 +339,7 @@ struct amg_ctx {
     // batched solve (allocated on first use)
     double *bR = nullptr, *bZ = nullptr, *bP = nullptr, *bQ = nullptr, *bU = nullptr, *bF = nullptr;
     double *bY = nullptr, *bsc = nullptr, *hbsc = nullptr, *bpartial = nullptr;
+    double *bgram = nullptr, *bcoef = nullptr, *bgsave = nullptr;   // block CG: Gram partials, alpha / beta, G
     int blk_lpr = 1, blk_threads = 256;   // block-kernel variant (autotuned when prm.nrhs > 1)
     // graph replay of the iteration body (single: [0]=CG [1]=FCG; batched likewise)
     int use_graph = 0;
@@ -1041,6 +1043,9 @@ struct amg_ctx {
         bY = alloc<double>((size_t)std::max(nL, 1) * NB);
         bsc = alloc<double>(B_NSLOTS * NB);
         bpartial = alloc<double>((size_t)partial_cap * NB);
+        bgram = alloc<double>((size_t)GRAM_BLOCKS * 512);
+        bcoef = alloc<double>(256);
+        bgsave = alloc<double>(256);
         HIPCHK(hipHostMalloc((void **)&hbsc, B_NSLOTS * NB * sizeof(double), hipHostMallocDefault));
     }
     unsigned blk_grid(const DevMat &B) const
@@ -1443,7 +1448,7 @@ static amg_status setup_common(int64_t n, const int64_t *row_ptr, const int32_t 
     amg_params_default(&P);
     if (prm) P = *prm;
     if (P.sweeps_per_level < 1 || P.sweeps_per_level > 3 || P.max_coarse < 1 || P.max_coarse > 2000 ||
-        P.max_levels < 1 || P.nu_pre < 1 || P.nu_post < 0 || P.itmax < 1 || P.krylov < 0 || P.krylov > 1 ||
+        P.max_levels < 1 || P.nu_pre < 1 || P.nu_post < 0 || P.itmax < 1 || P.krylov < 0 || P.krylov > 2 ||
         P.nrhs < 1 || P.nrhs > NB ||
         P.smoother < 0 || P.smoother > 2 || P.slice_offsets < 0 || P.slice_offsets > 1 ||
         P.smooth_prolong < 0 || P.smooth_prolong > 1 || P.cheb_degree < 1 || P.cheb_degree > 64 ||
@@ -1616,7 +1621,7 @@ static amg_status solve_impl(amg_ctx *c, const double *F, double *u_user, double
                              double *relres_true)
 {
     const int64_t n = c->n;
-    const bool flex = c->prm.krylov == 1;
+    const bool flex = c->prm.krylov >= 1;
     const int itmax = c->prm.itmax;
     const bool graph = c->use_graph && !c->prof;
     amg_ctx::OnGraphStream on(c, graph);
@@ -1734,11 +1739,96 @@ amg_status pcg_solve(amg_ctx *c, const double *F, double *u, double tol, int *it
     }
 }
 
+// Block flexible CG over the batch (krylov = 2): one block of up to 16 columns
+// shares every Krylov step, alpha = G^{-1} P^T R, beta = -G^{-1} Q^T Z with
+// G = P^T Q over the active columns (blockcg.h).
+static amg_status solve_block_impl(amg_ctx *c, int nrhs, const double *F, double *U, double tol, int *iters,
+                                   double *relres)
+{
+    const int64_t n = c->n;
+    const int itmax = c->prm.itmax;
+    hipStream_t st = c->stream;
+    c->blk_alloc();
+    c->evused = 0;
+    c->evbytes.clear();
+    hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(256), 0, st, (int64_t)(B_NSLOTS * NB), 0.0, c->bsc);
+    if (nrhs < NB)
+        hipLaunchKernelGGL((k_fill<double>), dim3(1), dim3(256), 0, st, (int64_t)(NB - nrhs), 1.0,
+                           c->bsc + B_DONE * NB + nrhs);
+    hipLaunchKernelGGL(k_pack_blk, dim3(nblocks(n)), dim3(256), 0, st, n, nrhs, F, c->bF);
+    hipLaunchKernelGGL(k_pack_blk, dim3(nblocks(n)), dim3(256), 0, st, n, nrhs, (const double *)U, c->bU);
+    HIPCHK(hipGetLastError());
+    c->sell_blk<double, double, double, EPI_RESID, 0>(0, c->bU, c->bF, c->lev[0].invd64, c->bR, nullptr, nullptr);
+    c->bfinalize(c->bdot_partials(n, c->bF, c->bF, nullptr), BF_FF, tol);
+    c->bfinalize(c->bdot_partials(n, c->bR, c->bR, nullptr), BF_RR0);
+    HIPCHK(hipMemcpyAsync(c->hbsc, c->bsc, B_NSLOTS * NB * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int j = 0; j < nrhs; j++)
+        if (!std::isfinite(c->hbsc[B_FF * NB + j])) { set_err("non-finite right-hand side"); return AMG_ERR_ARG; }
+    auto all_stopped = [&]() {
+        for (int j = 0; j < nrhs; j++)
+            if (c->hbsc[B_DONE * NB + j] == 0.0 && c->hbsc[B_FLAG * NB + j] == 0.0) return false;
+        return true;
+    };
+    double *P = c->bP, *Pn = c->bQ, *Q = c->bQ;
+    if (!all_stopped()) {
+        c->vcycle_blk(c->bR, c->bZ, 0, nullptr, nullptr);
+        c->copy<double, double>(n * NB, c->bZ, P);
+        const unsigned g = c->bgrid(n);
+        for (int k = 1; k <= itmax; k++) {
+            // Q = K P ; alpha ; X += P alpha, R -= Q alpha ; (R, R) per column
+            Q = (P == c->bP) ? c->bQ : c->bP;
+            Pn = P;
+            c->sell_blk<double, double, double, EPI_SPMV, 0>(0, P, nullptr, nullptr, Q, nullptr, nullptr);
+            hipLaunchKernelGGL(k_gram2, dim3(GRAM_BLOCKS), dim3(256), 0, st, n, P, Q, c->bR, c->bgram);
+            hipLaunchKernelGGL(k_bcg_small, dim3(1), dim3(256), 0, st, GRAM_BLOCKS, c->bgram, c->bsc, c->bgsave,
+                               c->bcoef, 0);
+            hipLaunchKernelGGL(k_bcg_xr, dim3(g), dim3(256), 0, st, n, c->bcoef, c->bU, c->bR, P, Q, c->bpartial);
+            HIPCHK(hipGetLastError());
+            c->bfinalize(g, BF_RR);
+            HIPCHK(hipMemcpyAsync(c->hbsc, c->bsc, B_NSLOTS * NB * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipEventRecord(c->ev_iter, st));
+            if (k < itmax) {
+                // Z = B R ; beta = -G^{-1} Q^T Z ; P = Z + P beta (into the buffer Q held)
+                c->vcycle_blk(c->bR, c->bZ, 0, nullptr, nullptr);
+                hipLaunchKernelGGL(k_gram2, dim3(GRAM_BLOCKS), dim3(256), 0, st, n, Q, c->bZ, nullptr, c->bgram);
+                hipLaunchKernelGGL(k_bcg_small, dim3(1), dim3(256), 0, st, GRAM_BLOCKS, c->bgram, c->bsc, c->bgsave,
+                                   c->bcoef, 1);
+                hipLaunchKernelGGL(k_bcg_p, dim3(g), dim3(256), 0, st, n, c->bcoef, c->bZ, P, Q);
+                HIPCHK(hipGetLastError());
+                P = Q;   // the new directions
+            }
+            HIPCHK(hipEventSynchronize(c->ev_iter));
+            if (all_stopped()) break;
+        }
+    }
+    (void)Pn;
+    hipLaunchKernelGGL(k_unpack_blk, dim3(nblocks(n)), dim3(256), 0, st, n, nrhs, (const double *)c->bU, U);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(c->hbsc, c->bsc, B_NSLOTS * NB * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    c->prof_collect();
+    amg_status status = AMG_OK;
+    for (int j = 0; j < nrhs; j++) {
+        const double ff = c->hbsc[B_FF * NB + j];
+        if (iters) iters[j] = (int)c->hbsc[B_ITERS * NB + j];
+        if (relres) relres[j] = ff > 0.0 ? std::sqrt(c->hbsc[B_RR * NB + j]) / std::sqrt(ff) : 0.0;
+        if (c->hbsc[B_FLAG * NB + j] != 0.0) {
+            status = AMG_ERR_BREAKDOWN;
+            set_err("block CG breakdown (Gram matrix not positive definite) in column " + std::to_string(j));
+        } else if (c->hbsc[B_DONE * NB + j] == 0.0 && status == AMG_OK) {
+            status = AMG_NOT_CONVERGED;
+        }
+    }
+    return status;
+}
+
 static amg_status solve_batched_impl(amg_ctx *c, int nrhs, const double *F, double *U, double tol, int *iters,
                                      double *relres)
 {
+    if (c->prm.krylov == 2) return solve_block_impl(c, nrhs, F, U, tol, iters, relres);
     const int64_t n = c->n;
-    const bool flex = c->prm.krylov == 1;
+    const bool flex = c->prm.krylov >= 1;
     const int itmax = c->prm.itmax;
     const bool graph = c->use_graph && !c->prof;
     amg_ctx::OnGraphStream on(c, graph);
