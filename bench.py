@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # SHA-256 of the kernel source they were taken with: reported only while the
 # kernel is unchanged (profiles/k_sell_c4_fp64_pmc.md).
 MEASURED_TRAFFIC = {
-    ("c4", "1cd4e7093d1885fff0ea5082c1876176913a6b9f7a5cef1e9b829ab74aecb8a2"): 5067483357,
+    ("c4", "7df9d98b962c2cec600f7ae03ab23d32b0ddc65e217d6a159f463fcbd82245fa"): 5067400364,
 }
 
 
