@@ -82,16 +82,34 @@ def cpu_baseline(cfg, seed, tol, iters_gpu, sample_iters):
     oracle.set_verbose(0)
     log(f"oracle: hierarchy of {h.nlevels} levels in {time.time() - t:.1f} s")
     F = Fcube if cfg["kind"] == "cube" else rhs_normal(len(rp) - 1, seed)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.set_threads(threads)
     t = time.time()
     res = h.solve(F, tol=tol, itmax=sample_iters)
     dt = time.time() - t
-    log(f"oracle: {res['iters']} PCG iterations in {dt:.1f} s")
+    log(f"oracle: {res['iters']} PCG iterations in {dt:.1f} s on {threads} threads")
     per_it = dt / max(res["iters"], 1)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the same solve on one core, a shorter sample (bitwise the same iterates)
+    one_iters = max(2, sample_iters // 5)
+    oracle.set_threads(1)
+    t = time.time()
+    res1 = h.solve(F, tol=tol, itmax=one_iters)
+    dt1 = time.time() - t
+    oracle.set_threads(threads)
+    log(f"oracle: {res1['iters']} PCG iterations in {dt1:.1f} s on 1 thread")
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": per_it * iters_gpu, "unit": "s", "cores": threads, "kind": "oracle",
             "sample": f"{res['iters']} PCG iterations (incl. the initial V-cycle) of the oracle on the same "
                       f"system, hierarchy built untimed, scaled by {iters_gpu} iterations; "
-                      f"SpMV row-parallel over {threads} OpenMP threads"}
+                      f"SpMV row-parallel over {threads} OpenMP threads",
+            "one_core": {"value": dt1 / max(res1["iters"], 1) * iters_gpu, "unit": "s", "cores": 1,
+                         "sample": f"{res1['iters']} iterations scaled by {iters_gpu}"},
+            "host": {"cpu": model, "logical_cpus": os.cpu_count()}}
 
 
 def main():
@@ -230,8 +248,13 @@ def main():
                            if args.mode == "paper" else "k_sell (level-0 SpMV / residual / smoother pass)")
                           if nrhs == 1 else "k_sell_blk (level-0 16-column SpMV / residual / smoother pass)",
                 "launches": prof["launches"], "avg_launch_ms": round(kernel_ms, 4),
+                "traffic_gbs": None, "traffic_frac": None,
                 "bytes_per_launch": round(prof["bytes"] / max(prof["launches"], 1))}
 
+    if roofline["traffic"] and kernel_ms > 0:
+        # measured HBM bytes per launch over the same launches' average time
+        roofline["traffic_gbs"] = round(roofline["traffic"] / (kernel_ms * 1e-3) / 1e9, 1)
+        roofline["traffic_frac"] = round(roofline["traffic_gbs"] / HBM_PEAK_GBS, 4)
     # a plain device copy of 1 GiB (read + write) timed on the same GPU, as the
     # attainable streaming bandwidth beside the nominal 8 TB/s
     roofline["copy_gbs"] = round(copy_bandwidth(torch), 1)

@@ -82,6 +82,7 @@ def lib():
         L.or_setup.argtypes = [C.c_int64, i64p, i32p, f64p, f64p, C.POINTER(Params), C.POINTER(C.c_void_p)]
         L.or_free.argtypes = [C.c_void_p]
         L.or_set_verbose.argtypes = [C.c_int]
+        L.or_set_threads.argtypes = [C.c_int]
         L.or_nlevels.argtypes = [C.c_void_p]
         L.or_level_info.argtypes = [C.c_void_p, C.c_int, i64p, i64p]
         L.or_level_matrix.argtypes = [C.c_void_p, C.c_int, i64p, i32p, f64p]
@@ -468,3 +469,8 @@ def bootstrap_w(rp, ci, v, w0, sweeps):
     w = np.zeros_like(w0)
     lib().or_bootstrap_w(len(w0), _p(rp, i64p), _p(ci, i32p), _p(v, f64p), _p(w0, f64p), int(sweeps), _p(w, f64p))
     return w
+
+
+def set_threads(n):
+    """Threads of the oracle's row-parallel SpMV (bitwise the same results)."""
+    lib().or_set_threads(int(n))

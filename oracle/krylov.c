@@ -56,6 +56,18 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 void or_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
              const double *x, double *y)
 {

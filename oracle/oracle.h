@@ -149,6 +149,8 @@ void or_chol_solve(int n, const double *L, const double *b, double *x);
 int  or_setup(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
               const double *w, const or_params *prm, or_hier **out);
 void or_free(or_hier *h);
+/* Threads of the row-parallel SpMV (OpenMP; results do not depend on it). */
+void or_set_threads(int n);
 /* Print one line per level built (progress of long set-ups) when v != 0. */
 void or_set_verbose(int v);
 int  or_nlevels(const or_hier *h);
