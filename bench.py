@@ -217,12 +217,14 @@ def main():
     ctx.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters = []
+    iters, marks = [], [t0]
     for s in range(args.steps):
-        out, it = one_solve()
+        out, it = one_solve()          # returns once the solve has finished on the device
         iters.append(it)
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    step_ms = sorted((b - a) * 1e3 for a, b in zip(marks[:-1], marks[1:]))
     prof = ctx.profile()
     ctx.set_profiling(False)
     ms = (t1 - t0) * 1e3 / args.steps
@@ -288,6 +290,7 @@ def main():
                                   f"matching AMG V-cycle ({amg_desc}), tol {args.tol}",
                       "mode": args.mode, "nrhs": nrhs, "converged": converged,
                       "iters": iters[-1], "relres_true": relres_true, "levels": len(levels),
+                      "ms_median": round(step_ms[len(step_ms) // 2], 3),
                       "opc": round(ctx.opc(), 4), "setup_s": round(setup_s, 2),
                       "setup_on_device": bool(args.setup_device),
                       "spmv_gbs": round(achieved, 1),
