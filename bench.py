@@ -118,13 +118,17 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c4")
-    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32", "batched", "blockcg", "learned", "paper"],
+    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32", "batched", "blockcg", "learned", "paper",
+                                                       "cheb"],
                     help="fp64: FP64 PCG (default); fp32: FP32 V-cycle inside FP64 FCG; "
                          "batched: 16 right-hand sides, FP32 block V-cycle inside FP64 FCG; "
                          "blockcg: the same 16 right-hand sides by block flexible CG; "
                          "learned: FP64 PCG with the MLP-predicted degree-4 polynomial smoothers; "
+                         "cheb: FP64 PCG with the fourth-kind Chebyshev l1-Jacobi smoother of --cheb-degree "
+                         "(configuration hierarchy otherwise); "
                          "paper: FP64 FCG with the paper's default preconditioner (aggregates of 8, "
                          "smoothed prolongator, Chebyshev l1-Jacobi, CG coarse solve)")
+    ap.add_argument("--cheb-degree", type=int, default=4)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--itmax", type=int, default=0, help="iteration limit (0: the workload's, else 1000)")
@@ -182,7 +186,9 @@ def main():
     torch.cuda.synchronize()
     t = time.time()
     kw = dict({"fp64": {}, "learned": {"smoother": 1}, "paper": amg.paper_default(cfg["p"]),
-               "blockcg": {"vcycle_fp32": 1, "krylov": 2}}.get(args.mode, {"vcycle_fp32": 1, "krylov": 1}))
+               "blockcg": {"vcycle_fp32": 1, "krylov": 2},
+               "cheb": {"smoother": 2, "cheb_degree": args.cheb_degree}}.get(
+        args.mode, {"vcycle_fp32": 1, "krylov": 1}))
     kw["itmax"] = args.itmax or cfg.get("itmax", 1000)
     if nrhs > 1:
         kw["nrhs"] = nrhs
@@ -269,8 +275,10 @@ def main():
     form = {"fp64": "FP64 PCG", "fp32": "FP32 V-cycle in FP64 FCG",
             "batched": "16 RHS, FP32 block V-cycle in FP64 FCG",
             "blockcg": "16 RHS, FP32 block V-cycle in FP64 block flexible CG",
-            "learned": "FP64 PCG, learned degree-4 polynomial smoothers", "paper": "FP64 FCG"}[args.mode]
-    smoother = "learned POLY4" if args.mode == "learned" else "l1-Jacobi 1/1"
+            "learned": "FP64 PCG, learned degree-4 polynomial smoothers", "paper": "FP64 FCG",
+            "cheb": "FP64 PCG"}[args.mode]
+    smoother = {"learned": "learned POLY4", "cheb": f"fourth-kind Chebyshev l1-Jacobi degree {args.cheb_degree}"}.get(
+        args.mode, "l1-Jacobi 1/1")
     amg_desc = f"m=2, {smoother}, Cholesky <= 200"
     if args.mode == "paper":
         amg_desc = (f"m=3 smoothed (omega 4/3), fourth-kind Chebyshev l1-Jacobi degree {kw['cheb_degree']}, "
@@ -283,7 +291,7 @@ def main():
         problem = f"Poisson, F~N(0,1) seed {args.seed}{'..' + str(args.seed + nrhs - 1) if nrhs > 1 else ''}"
     rec = {"metric": METRIC, "value": round(ms / 1e3, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "strong",
-           "vs_baseline": None, "dtype": "f64" if args.mode in ("fp64", "paper") else "f32/f64",
+           "vs_baseline": None, "dtype": "f64" if args.mode in ("fp64", "paper", "cheb", "learned") else "f32/f64",
            "data": "synthetic",
            "config": {"workload": f"{args.workload}: {cfg['d']}D {problem}, B-splines p={cfg['p']}, "
                                   f"n={cfg['n']}, N={N}, nnz={nnz}, {form} + "
