@@ -1770,7 +1770,7 @@ static amg_status solve_block_impl(amg_ctx *c, int nrhs, const double *F, double
             if (c->hbsc[B_DONE * NB + j] == 0.0 && c->hbsc[B_FLAG * NB + j] == 0.0) return false;
         return true;
     };
-    double *P = c->bP, *Pn = c->bQ, *Q = c->bQ;
+    double *P = c->bP, *Q = c->bQ;
     if (!all_stopped()) {
         c->vcycle_blk(c->bR, c->bZ, 0, nullptr, nullptr);
         c->copy<double, double>(n * NB, c->bZ, P);
@@ -1778,7 +1778,6 @@ static amg_status solve_block_impl(amg_ctx *c, int nrhs, const double *F, double
         for (int k = 1; k <= itmax; k++) {
             // Q = K P ; alpha ; X += P alpha, R -= Q alpha ; (R, R) per column
             Q = (P == c->bP) ? c->bQ : c->bP;
-            Pn = P;
             c->sell_blk<double, double, double, EPI_SPMV, 0>(0, P, nullptr, nullptr, Q, nullptr, nullptr);
             hipLaunchKernelGGL(k_gram2, dim3(GRAM_BLOCKS), dim3(256), 0, st, n, P, Q, c->bR, c->bgram);
             hipLaunchKernelGGL(k_bcg_small, dim3(1), dim3(256), 0, st, GRAM_BLOCKS, c->bgram, c->bsc, c->bgsave,
@@ -1802,7 +1801,6 @@ static amg_status solve_block_impl(amg_ctx *c, int nrhs, const double *F, double
             if (all_stopped()) break;
         }
     }
-    (void)Pn;
     hipLaunchKernelGGL(k_unpack_blk, dim3(nblocks(n)), dim3(256), 0, st, n, nrhs, (const double *)c->bU, U);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(c->hbsc, c->bsc, B_NSLOTS * NB * sizeof(double), hipMemcpyDeviceToHost, st));
