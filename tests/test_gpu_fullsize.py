@@ -11,6 +11,9 @@ residual.
 3D p=4, n=96 (640M entries): the FP32 V-cycle inside FP64 FCG against the
 FP64 PCG on the same system.
 3D p=5, n=64, variable kappa: sampled rows, plain and learned solves.
+The cube of Sec. 5.1 at p=3, k=96 with the paper's default preconditioner:
+the V-cycle (Cholesky coarse solve) is symmetric positive definite, and the
+FCG solve reaches an FP64 true residual of 1e-8.
 """
 import numpy as np
 import pytest
@@ -101,14 +104,16 @@ def test_c4_properties(oracle, amg, c4_system):
 
 
 @pytest.mark.timeout(900)
-def test_c4_batched_properties(oracle, amg, c4_system):
+@pytest.mark.parametrize("krylov", [1, 2])
+def test_c4_batched_properties(oracle, amg, c4_system, krylov):
     """16 right-hand sides (seeds 0..15), FP32 block V-cycle in FP64 FCG with
-    the autotuned block kernels, as bench.py --mode batched runs it."""
-    print("case c4 x 16: 3D p=3 n=128 seeds 0..15", flush=True)
+    the autotuned block kernels, as bench.py --mode batched runs it
+    (krylov = 2: block flexible CG, as --mode blockcg)."""
+    print(f"case c4 x 16: 3D p=3 n=128 seeds 0..15 krylov {krylov}", flush=True)
     from paper_2511_21268_amd.workloads import rhs_block
     rp, ci, v = c4_system
     N = len(rp) - 1
-    ctx = amg.Context(rp, ci, v, vcycle_fp32=1, krylov=1, nrhs=16)
+    ctx = amg.Context(rp, ci, v, vcycle_fp32=1, krylov=krylov, nrhs=16)
     print(f"  autotuned block variant {ctx.batched_variant()}", flush=True)
     Fh = rhs_block(N, range(16))
     out = ctx.solve_batched(torch.from_numpy(Fh).cuda(), tol=1e-8)
@@ -185,3 +190,28 @@ def test_c5_plain_and_learned(oracle, amg):
         its[name] = out["iters"]
         del ctx
     assert its["learned"] < its["l1"]
+
+
+@pytest.mark.timeout(900)
+def test_cube96_paper_preconditioner_properties(oracle, amg):
+    print("case cube p=3 k=96, the paper's default preconditioner", flush=True)
+    rp, ci, v, F = amg.iga_cube(3, 96)
+    prm = amg.paper_default(3)
+    # with the Cholesky coarse solve the V-cycle is a fixed SPD operator
+    ctx = amg.Context(rp, ci, v, **dict(prm, coarse_solver=0))
+    print(f"  levels {[ctx.level_info(l)[0] for l in range(ctx.nlevels)]}, opc {ctx.opc():.3f}, "
+          f"coarse formats {[ctx.format(l)['slice'] for l in range(1, ctx.nlevels - 1)]}", flush=True)
+    rng = np.random.default_rng(2)
+    y = torch.from_numpy(rng.standard_normal(len(F))).cuda()
+    z = torch.from_numpy(rng.standard_normal(len(F))).cuda()
+    By, Bz = ctx.vcycle(y), ctx.vcycle(z)
+    a, b = float(torch.dot(z, By)), float(torch.dot(y, Bz))
+    assert abs(a - b) <= 1e-10 * (abs(a) + abs(b)), (a, b)
+    assert float(torch.dot(y, By)) > 0 and float(torch.dot(z, Bz)) > 0
+    del ctx
+    ctx = amg.Context(rp, ci, v, **prm)
+    out = ctx.solve(torch.from_numpy(F).cuda(), tol=1e-8)
+    u = out["u"].cpu().numpy()
+    true = np.linalg.norm(F - oracle.spmv(rp, ci, v, u)) / np.linalg.norm(F)
+    print(f"  FCG: {out['iters']} iterations, true relres {true:.2e}", flush=True)
+    assert out["status"] == 0 and true <= 1e-8 * 1.0001 and out["iters"] <= 30
