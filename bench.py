@@ -118,12 +118,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c4")
-    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32", "batched", "blockcg", "learned", "paper",
-                                                       "cheb"],
+    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32", "batched", "blockcg", "learned", "learned32",
+                                                       "paper", "cheb"],
                     help="fp64: FP64 PCG (default); fp32: FP32 V-cycle inside FP64 FCG; "
                          "batched: 16 right-hand sides, FP32 block V-cycle inside FP64 FCG; "
                          "blockcg: the same 16 right-hand sides by block flexible CG; "
                          "learned: FP64 PCG with the MLP-predicted degree-4 polynomial smoothers; "
+                         "learned32: the same polynomials in the FP32 V-cycle inside FP64 FCG; "
                          "cheb: FP64 PCG with the fourth-kind Chebyshev l1-Jacobi smoother of --cheb-degree "
                          "(configuration hierarchy otherwise); "
                          "paper: FP64 FCG with the paper's default preconditioner (aggregates of 8, "
@@ -185,7 +186,8 @@ def main():
         F = torch.from_numpy(rhs_block(N, range(args.seed, args.seed + nrhs))).cuda()
     torch.cuda.synchronize()
     t = time.time()
-    kw = dict({"fp64": {}, "learned": {"smoother": 1}, "paper": amg.paper_default(cfg["p"]),
+    kw = dict({"fp64": {}, "learned": {"smoother": 1}, "learned32": {"smoother": 1, "vcycle_fp32": 1, "krylov": 1},
+               "paper": amg.paper_default(cfg["p"]),
                "blockcg": {"vcycle_fp32": 1, "krylov": 2},
                "cheb": {"smoother": 2, "cheb_degree": args.cheb_degree}}.get(
         args.mode, {"vcycle_fp32": 1, "krylov": 1}))
@@ -195,7 +197,7 @@ def main():
     if args.setup_device:
         kw["setup_device"] = 1
     ctx = amg.Context(rp, ci, v, **kw)
-    if args.mode == "learned":
+    if args.mode in ("learned", "learned32"):
         from paper_2511_21268_amd import learned
         accepted, coefs = learned.apply_learned(ctx)
         log(f"learned smoothers: accepted {accepted}, coefficients {[list(map(lambda x: round(x, 3), c)) for c in coefs]}")
@@ -276,8 +278,9 @@ def main():
             "batched": "16 RHS, FP32 block V-cycle in FP64 FCG",
             "blockcg": "16 RHS, FP32 block V-cycle in FP64 block flexible CG",
             "learned": "FP64 PCG, learned degree-4 polynomial smoothers", "paper": "FP64 FCG",
+            "learned32": "FP32 V-cycle with learned degree-4 polynomial smoothers in FP64 FCG",
             "cheb": "FP64 PCG"}[args.mode]
-    smoother = {"learned": "learned POLY4", "cheb": f"fourth-kind Chebyshev l1-Jacobi degree {args.cheb_degree}"}.get(
+    smoother = {"learned": "learned POLY4", "learned32": "learned POLY4", "cheb": f"fourth-kind Chebyshev l1-Jacobi degree {args.cheb_degree}"}.get(
         args.mode, "l1-Jacobi 1/1")
     amg_desc = f"m=2, {smoother}, Cholesky <= 200"
     if args.mode == "paper":

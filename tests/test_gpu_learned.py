@@ -124,3 +124,27 @@ def test_learned_smoother_gain(oracle, amg):
         gains.append(res["l1"][2] / res["learned"][2])
     print("time gains", gains)
     assert min(gains) > 1.0
+
+
+def test_learned_smoother_in_fp32_vcycle(oracle, amg):
+    """The learned polynomials inside the FP32 V-cycle (FP64 FCG outside): the
+    same accepted levels, an FP64 true residual under 1e-8, and an iteration
+    count within 2% of the FP64 learned form."""
+    from paper_2511_21268_amd import learned
+    if not os.path.exists(learned.WEIGHTS):
+        pytest.skip("trained weights not present")
+    rp, ci, v, F = learned.problem(5, 18, 3)
+    print("case learned fp32 p=5 n=18 seed=3", flush=True)
+    Ft = torch.from_numpy(F).cuda()
+    out = {}
+    for name, kw in (("fp64", dict(smoother=1)), ("fp32", dict(smoother=1, vcycle_fp32=1, krylov=1))):
+        ctx = amg.Context(rp, ci, v, itmax=2000, **kw)
+        acc, _ = learned.apply_learned(ctx)
+        o = ctx.solve(Ft, tol=1e-8)
+        u = o["u"].cpu().numpy()
+        true = np.linalg.norm(F - oracle.spmv(rp, ci, v, u)) / np.linalg.norm(F)
+        out[name] = (list(acc), o["iters"], true)
+    print(f"  {out}", flush=True)
+    assert out["fp32"][0] == out["fp64"][0]
+    assert out["fp32"][2] <= 1e-8 * 1.0001
+    assert abs(out["fp32"][1] - out["fp64"][1]) <= max(2, 0.02 * out["fp64"][1])
