@@ -47,8 +47,9 @@ typedef struct {
     int sweeps_per_level;   /* m pairwise matching sweeps composed per level
                                (aggregates of at most 2^m; Sec. 3.1 m-step);
                                default 2, range 1..3                            */
-    int max_coarse;         /* stop coarsening at <= this many rows and factor
-                               that level densely; default 200, range 1..2000   */
+    int max_coarse;         /* stop coarsening at <= this many rows; that level
+                               is solved by the coarse solver (coarse_solver);
+                               default 200, range 1..2000                       */
     int max_levels;         /* default 40                                       */
     int nu_pre, nu_post;    /* smoother sweeps before / after the coarse
                                correction (Sec. 3 steps 1 and 5); default 1, 1;
@@ -115,13 +116,17 @@ amg_status amg_params_default(amg_params *p);
  *  row_ptr[n+1] int64, col[nnz] int32 (sorted ascending within each row),
  *  val[nnz] FP64; K must be symmetric in pattern and values, with a positive
  *  diagonal entry stored in every row, and all values finite.
- *  w: host test vector of length n (Sec. 3.1 eq. (cij)); NULL means all ones.
+ *  w: host test vector of length n (Sec. 3.1 eq. (cij)); NULL means all ones;
+ *  with prm->bootstrap_sweeps > 0 it is the random start of the relaxation that
+ *  produces the test vector (required then).
  *  prm: NULL means defaults.  hip_stream: the hipStream_t every later call of
  *  this context is ordered on (NULL = the null stream).
  * Per level: edge weights c_ij = 1 - 2 k_ij w_i w_j / (k_ii w_i^2 + k_jj w_j^2)
  * (eq. (cij)), greedy matching in the order (c desc, min index, max index),
  * pairwise prolongator of eq. (prolongation), Galerkin K_c = P^T K P
- * (eq. (galerkin_matrix_projection)), composed m times.
+ * (eq. (galerkin_matrix_projection)), composed m times; with smooth_prolong the
+ * composed prolongator is smoothed and K_c = (P'^T K) P'.  On the host, or on
+ * the device with setup_device (the same hierarchy bit for bit).
  * Errors: AMG_ERR_ARG (n <= 0 or n >= 2^29, malformed or non-symmetric K,
  * non-finite values, missing or non-positive diagonal), AMG_ERR_NOT_SPD, AMG_ERR_STATE,
  * AMG_ERR_OOM, AMG_ERR_HIP.  On error *out is NULL.
