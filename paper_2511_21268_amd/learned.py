@@ -97,11 +97,12 @@ def _solve(ctx, F, tol, coefs):
     return out["iters"] if out["status"] == 0 else None
 
 
-def label_problem(p, n, seed, tol=1e-6, itmax=400, log=print):
-    """Features and best-coefficient labels of every non-coarsest level."""
+def label_problem(p, n, seed, tol=1e-6, itmax=400, log=print, setup_device=0):
+    """Features and best-coefficient labels of every non-coarsest level (the
+    hierarchy is the same bit for bit with the device set-up)."""
     import torch
     rp, ci, v, F = problem(p, n, seed)
-    ctx = amg.Context(rp, ci, v, smoother=1, itmax=itmax)
+    ctx = amg.Context(rp, ci, v, smoother=1, itmax=itmax, setup_device=setup_device)
     L = ctx.nlevels - 1
     Ft = torch.from_numpy(F).cuda()
     feats = np.stack([ctx.features(l) for l in range(L)])
@@ -125,11 +126,11 @@ def label_problem(p, n, seed, tol=1e-6, itmax=400, log=print):
     return feats, labels, dict(p=p, n=n, seed=seed, l1_iters=base, iters=it_best, a=choice)
 
 
-def generate(out, log=print):
+def generate(out, log=print, setup_device=0):
     X, T, meta = [], [], []
     for (p, n, seed) in TRAIN:
         t = time.time()
-        f, l, m = label_problem(p, n, seed, log=log)
+        f, l, m = label_problem(p, n, seed, log=log, setup_device=setup_device)
         X.append(f); T.append(l); meta.append(m)
         log(f"  labelled in {time.time() - t:.1f} s")
     np.savez(out, X=np.concatenate(X).astype(np.float32), T=np.concatenate(T).astype(np.float32),
@@ -218,6 +219,7 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     g = sub.add_parser("generate")
     g.add_argument("--out", required=True)
+    g.add_argument("--setup-device", action="store_true", help="build the hierarchies on the device")
     t = sub.add_parser("train")
     t.add_argument("--data", required=True)
     t.add_argument("--out", required=True)
@@ -225,7 +227,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)  # noqa: E731
     if args.cmd == "generate":
-        generate(args.out, log)
+        generate(args.out, log, setup_device=int(args.setup_device))
     else:
         train(args.data, args.out, steps=args.steps, log=log)
 
