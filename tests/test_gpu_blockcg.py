@@ -79,3 +79,25 @@ def test_block_fp32_vcycle_fewer_iterations(amg):
     ind = amg.Context(rp, ci, v, nrhs=16, krylov=1, vcycle_fp32=1).solve_batched(Ft, tol=1e-8)
     print(f"  block max {max(blk['iters'])}, independent max {max(ind['iters'])}", flush=True)
     assert blk["status"] == 0 and max(blk["iters"]) < max(ind["iters"])
+
+
+def test_block_edge_cases(oracle, amg):
+    """A zero right-hand side column is done before the first step (zero
+    solution, zero iterations) and does not change the other columns; a
+    single column of block CG is FCG(1)."""
+    rp, ci, v = _system(oracle, "poisson p3 n10")
+    n = len(rp) - 1
+    F = _rhs(n, 6, 11)
+    F0 = F.copy(); F0[:, 3] = 0.0
+    ctx = amg.Context(rp, ci, v, nrhs=16, krylov=2)
+    out = ctx.solve_batched(torch.from_numpy(np.ascontiguousarray(F0.T)).cuda().T, tol=1e-8)
+    U = out["U"].cpu().numpy()
+    assert out["status"] == 0 and out["iters"][3] == 0 and not U[:, 3].any()
+    h = oracle.Hierarchy(rp, ci, v)
+    ref = h.block_solve(F0, tol=1e-8)
+    assert all(abs(a - b) <= 1 for a, b in zip(out["iters"], ref["iters"]))
+    one = ctx.solve_batched(torch.from_numpy(np.ascontiguousarray(F[:, :1].T)).cuda().T, tol=1e-8)
+    single = amg.Context(rp, ci, v, krylov=1).solve(torch.from_numpy(F[:, 0].copy()).cuda(), tol=1e-8)
+    assert abs(one["iters"][0] - single["iters"]) <= 1
+    u1, us = one["U"][:, 0].cpu().numpy(), single["u"].cpu().numpy()
+    assert np.linalg.norm(u1 - us) <= 1e-7 * np.linalg.norm(us)

@@ -94,3 +94,16 @@ def test_device_setup_fullsize_c4(amg):
     print(f"  c4: device set-up (hierarchy + device images) {td:.1f} s, host hierarchy only {th:.1f} s, "
           f"levels {dev.nlevels}, rounds {tot} over {sw} sweeps (max {mx})", flush=True)
     _same_hierarchy(host, dev)
+
+
+def test_device_setup_single_level_and_stall(amg):
+    """A system at most max_coarse rows is one level (no matching at all); a
+    two-level build with a larger coarse size still equals the host's."""
+    rp, ci, v = amg.iga_poisson(2, 2, 10, want_F=False)[:3]        # 100 rows
+    dev = amg.Context(rp, ci, v, setup_device=1)
+    assert dev.nlevels == 1 and dev.setup_rounds() == (0, 0, 0)
+    host = amg.Context(rp, ci, v, host_only=True, max_coarse=50)
+    dev2 = amg.Context(rp, ci, v, setup_device=1, max_coarse=50)
+    _same_hierarchy(host, dev2)
+    F = torch.ones(len(rp) - 1, dtype=torch.float64, device="cuda")
+    assert dev.solve(F, tol=1e-10)["iters"] == 1
