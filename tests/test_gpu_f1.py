@@ -35,7 +35,9 @@ def _opc_table():
 
 
 def _system(oracle, name):
-    if name == "cube p3 k6":
+    if name == "cube p3 k24":
+        rp, ci, v, _, _ = oracle.cube_system(3, 24)
+    elif name == "cube p3 k6":
         rp, ci, v, _, _ = oracle.cube_system(3, 6)
     elif name == "cube p4 k12":
         rp, ci, v, _, _ = oracle.cube_system(4, 12)
@@ -59,6 +61,9 @@ VCYCLE_CASES = [
     ("poisson p2 n14", dict(smooth_prolong=1), 1e-12),
     ("poisson p2 n14", dict(coarse_solver=1), 1e-10),
     ("cube p3 k6", dict(smooth_prolong=1, nu_pre=2, nu_post=2), 1e-12),
+    # four levels, every coarse level and transfer held as a CSR image
+    ("cube p3 k24", dict(sweeps_per_level=3, smooth_prolong=1, smoother=2, cheb_degree=8, coarse_solver=0,
+                         max_coarse=40), 1e-12),
 ]
 
 
@@ -70,6 +75,8 @@ def test_f1_vcycle_parity(oracle, amg, ci_):
     h = oracle.Hierarchy(rp, ci, v, **prm)
     ctx = amg.Context(rp, ci, v, krylov=1, **prm)
     assert ctx.nlevels == h.nlevels >= 2
+    if name == "cube p3 k24":
+        assert ctx.nlevels >= 4 and all(ctx.format(l)["slice"] < 0 for l in range(1, ctx.nlevels - 1))
     rng = np.random.default_rng(ci_)
     for _ in range(3):
         r = rng.standard_normal(h.n)
