@@ -143,7 +143,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this path "
-              "is described in DESIGN.md and not built.", file=sys.stderr)
+              "(row slabs with halo exchange, all-reduced dots) is a design, not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -8,8 +8,8 @@ g(t) = 1 - e(t) = sum_k a_k t^{k+1} at the Chebyshev-Lobatto nodes NODES of (0, 
 output error moves e(t) by about twice its size, whereas errors in the monomial
 coefficients (tens to hundreds) are amplified into e(1).  The library's
 acceptance test (|e(t)| <= 1, e(t) < 1 on (0, 1]) decides per level, and a
-rejected level falls back to l1-Jacobi, so the plain method still judges
-convergence.
+rejected level falls back to l1-Jacobi, so convergence never rests on an
+unchecked prediction.
 
 Labels come from the method itself: for each training problem the smoother
 family e_a(t) = T_4((1 + a - 2t)/(1 - a)) / T_4((1 + a)/(1 - a)) (the degree-4
