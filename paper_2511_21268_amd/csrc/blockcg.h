@@ -9,7 +9,7 @@
 
 namespace amgk {
 
-constexpr int GRAM_BLOCKS = 512;   // fixed grid of the Gram-matrix partials
+constexpr int GRAM_BLOCKS = 2048;  // fixed grid of the Gram-matrix partials
 
 // Partials of A^T B and A^T C (16 x 16 each; C may be NULL): 16-row tiles of
 // A, B, C staged in LDS; thread (i, j) = (t / 16, t % 16) accumulates
@@ -39,36 +39,45 @@ __global__ __launch_bounds__(256) void k_gram2(int64_t n, const double *__restri
     partial[(int64_t)blockIdx.x * 512 + 256 + t] = g2;
 }
 
-// Final Gram sums (blocks in index order) and the small solve on the active
-// columns S (bactive):
+// Final Gram sums and the small solve on the active columns S (bactive):
 //   mode 0: G = first Gram (stored in gsave), H = second (P^T R);
 //           coef = G_SS^{-1} H_SS                       (alpha)
 //   mode 1: G = gsave, W = first Gram (Q^T Z);
 //           coef = -G_SS^{-1} W_SS                      (beta)
+// The 2 x 256 entries are summed over the blocks by four thread groups, group q
+// taking the blocks q, q + 4, ... in order, then the four group sums in order.
 // coef is 16 x 16 row-major (direction i, column j), zero outside S x S.  A
 // non-positive pivot marks every active column broken (flag slot).
-__global__ __launch_bounds__(256) void k_bcg_small(int nblk, const double *__restrict__ partial, double *sc,
-                                                   double *__restrict__ gsave, double *__restrict__ coef, int mode)
+__global__ __launch_bounds__(1024) void k_bcg_small(int nblk, const double *__restrict__ partial, double *sc,
+                                                    double *__restrict__ gsave, double *__restrict__ coef, int mode)
 {
     __shared__ double G[256], H[256], L[256], Y[256];
+    __shared__ double qa[4][256], qb[4][256];
     __shared__ int idx[NB];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x & 255, q = threadIdx.x >> 8;
     double a = 0.0, b = 0.0;
-    for (int k = 0; k < nblk; k++) {
+    for (int k = q; k < nblk; k += 4) {
         a += partial[(int64_t)k * 512 + t];
         b += partial[(int64_t)k * 512 + 256 + t];
     }
-    if (mode == 0) {
-        G[t] = a;
-        gsave[t] = a;
-        H[t] = b;
-    } else {
-        G[t] = gsave[t];
-        H[t] = -a;
-    }
-    coef[t] = 0.0;
+    qa[q][t] = a;
+    qb[q][t] = b;
     __syncthreads();
-    if (t != 0) return;
+    if (threadIdx.x < 256) {
+        a = ((qa[0][t] + qa[1][t]) + qa[2][t]) + qa[3][t];
+        b = ((qb[0][t] + qb[1][t]) + qb[2][t]) + qb[3][t];
+        if (mode == 0) {
+            G[t] = a;
+            gsave[t] = a;
+            H[t] = b;
+        } else {
+            G[t] = gsave[t];
+            H[t] = -a;
+        }
+        coef[t] = 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     int m = 0;
     for (int j = 0; j < NB; j++)
         if (bactive(sc, j)) idx[m++] = j;
@@ -79,7 +88,7 @@ __global__ __launch_bounds__(256) void k_bcg_small(int nblk, const double *__res
             for (int k = 0; k < c; k++) s -= L[r * NB + k] * L[c * NB + k];
             if (r == c) {
                 if (!(s > 0.0) || !isfinite(s)) {
-                    for (int q = 0; q < m; q++) sc[B_FLAG * NB + idx[q]] = 3.0;
+                    for (int z = 0; z < m; z++) sc[B_FLAG * NB + idx[z]] = 3.0;
                     return;
                 }
                 L[r * NB + r] = sqrt(s);
@@ -104,51 +113,63 @@ __global__ __launch_bounds__(256) void k_bcg_small(int nblk, const double *__res
         for (int c = 0; c < m; c++) coef[idx[r] * NB + idx[c]] = Y[r * NB + c];
 }
 
-// X += P alpha ; R -= Q alpha (element-parallel; row r = e / 16, column j);
-// per-column partials of (R, R) as k_bcg_update.
+// X += P alpha ; R -= Q alpha over 16-row tiles: the tile's rows of P and Q are
+// staged in LDS (one load per thread each), thread (row r, column j) of the
+// tile forms sum_i P_ri alpha_ij in ascending i; per-column partials of (R, R)
+// as k_bcg_update (the tiles of a block: blockIdx.x, + gridDim.x, ...).
 __global__ __launch_bounds__(256) void k_bcg_xr(int64_t n, const double *__restrict__ alpha, double *__restrict__ X,
                                                 double *__restrict__ R, const double *__restrict__ P,
                                                 const double *__restrict__ Q, double *__restrict__ partial)
 {
-    __shared__ double al[256];
+    __shared__ double al[256], ps[256], qs[256];
     __shared__ double lds[8 * NB];
-    al[threadIdx.x] = alpha[threadIdx.x];
-    __syncthreads();
-    const int j = threadIdx.x & (NB - 1);
+    const int t = threadIdx.x, r = t >> 4, j = t & (NB - 1);
+    al[t] = alpha[t];
     double s = 0.0;
-    const int64_t m = n * NB;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < m; e += (int64_t)gridDim.x * 256) {
-        const int64_t r = e >> 4;
-        double dx = 0.0, dr = 0.0;
+    for (int64_t r0 = (int64_t)blockIdx.x * 16; r0 < n; r0 += (int64_t)gridDim.x * 16) {
+        const int64_t row = r0 + r;
+        const bool in = row < n;
+        __syncthreads();
+        ps[t] = in ? P[row * NB + j] : 0.0;
+        qs[t] = in ? Q[row * NB + j] : 0.0;
+        __syncthreads();
+        if (in) {
+            double dx = 0.0, dr = 0.0;
 #pragma unroll
-        for (int i = 0; i < NB; i++) {
-            const double a = al[i * NB + j];
-            dx = fma(P[r * NB + i], a, dx);
-            dr = fma(Q[r * NB + i], a, dr);
+            for (int i = 0; i < NB; i++) {
+                const double a = al[i * NB + j];
+                dx = fma(ps[r * NB + i], a, dx);
+                dr = fma(qs[r * NB + i], a, dr);
+            }
+            const int64_t e = row * NB + j;
+            X[e] = X[e] + dx;
+            const double ri = R[e] - dr;
+            R[e] = ri;
+            s = fma(ri, ri, s);
         }
-        X[e] = X[e] + dx;
-        const double ri = R[e] - dr;
-        R[e] = ri;
-        s = fma(ri, ri, s);
     }
     blk_col_partials(s, 0.0, lds, partial);
 }
 
-// Pn = Z + P beta (element-parallel)
+// Pn = Z + P beta over 16-row tiles (P staged in LDS)
 __global__ __launch_bounds__(256) void k_bcg_p(int64_t n, const double *__restrict__ beta, const double *__restrict__ Z,
                                                const double *__restrict__ P, double *__restrict__ Pn)
 {
-    __shared__ double be[256];
-    be[threadIdx.x] = beta[threadIdx.x];
-    __syncthreads();
-    const int j = threadIdx.x & (NB - 1);
-    const int64_t m = n * NB;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < m; e += (int64_t)gridDim.x * 256) {
-        const int64_t r = e >> 4;
-        double t = 0.0;
+    __shared__ double be[256], ps[256];
+    const int t = threadIdx.x, r = t >> 4, j = t & (NB - 1);
+    be[t] = beta[t];
+    for (int64_t r0 = (int64_t)blockIdx.x * 16; r0 < n; r0 += (int64_t)gridDim.x * 16) {
+        const int64_t row = r0 + r;
+        const bool in = row < n;
+        __syncthreads();
+        ps[t] = in ? P[row * NB + j] : 0.0;
+        __syncthreads();
+        if (in) {
+            double acc = 0.0;
 #pragma unroll
-        for (int i = 0; i < NB; i++) t = fma(P[r * NB + i], be[i * NB + j], t);
-        Pn[e] = Z[e] + t;
+            for (int i = 0; i < NB; i++) acc = fma(ps[r * NB + i], be[i * NB + j], acc);
+            Pn[row * NB + j] = Z[row * NB + j] + acc;
+        }
     }
 }
 

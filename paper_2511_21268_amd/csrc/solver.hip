@@ -1780,7 +1780,7 @@ static amg_status solve_block_impl(amg_ctx *c, int nrhs, const double *F, double
             Q = (P == c->bP) ? c->bQ : c->bP;
             c->sell_blk<double, double, double, EPI_SPMV, 0>(0, P, nullptr, nullptr, Q, nullptr, nullptr);
             hipLaunchKernelGGL(k_gram2, dim3(GRAM_BLOCKS), dim3(256), 0, st, n, P, Q, c->bR, c->bgram);
-            hipLaunchKernelGGL(k_bcg_small, dim3(1), dim3(256), 0, st, GRAM_BLOCKS, c->bgram, c->bsc, c->bgsave,
+            hipLaunchKernelGGL(k_bcg_small, dim3(1), dim3(1024), 0, st, GRAM_BLOCKS, c->bgram, c->bsc, c->bgsave,
                                c->bcoef, 0);
             hipLaunchKernelGGL(k_bcg_xr, dim3(g), dim3(256), 0, st, n, c->bcoef, c->bU, c->bR, P, Q, c->bpartial);
             HIPCHK(hipGetLastError());
@@ -1791,7 +1791,7 @@ static amg_status solve_block_impl(amg_ctx *c, int nrhs, const double *F, double
                 // Z = B R ; beta = -G^{-1} Q^T Z ; P = Z + P beta (into the buffer Q held)
                 c->vcycle_blk(c->bR, c->bZ, 0, nullptr, nullptr);
                 hipLaunchKernelGGL(k_gram2, dim3(GRAM_BLOCKS), dim3(256), 0, st, n, Q, c->bZ, nullptr, c->bgram);
-                hipLaunchKernelGGL(k_bcg_small, dim3(1), dim3(256), 0, st, GRAM_BLOCKS, c->bgram, c->bsc, c->bgsave,
+                hipLaunchKernelGGL(k_bcg_small, dim3(1), dim3(1024), 0, st, GRAM_BLOCKS, c->bgram, c->bsc, c->bgsave,
                                    c->bcoef, 1);
                 hipLaunchKernelGGL(k_bcg_p, dim3(g), dim3(256), 0, st, n, c->bcoef, c->bZ, P, Q);
                 HIPCHK(hipGetLastError());
