@@ -9,7 +9,8 @@
 
 namespace amgk {
 
-constexpr int GRAM_BLOCKS = 2048;  // fixed grid of the Gram-matrix partials
+constexpr int GRAM_BLOCKS = 2048;  // fixed grid of the Gram-matrix partials (a multiple of 16)
+static_assert(GRAM_BLOCKS % 16 == 0, "k_bcg_small sums the partials in groups of 16 blocks");
 
 // Partials of A^T B and A^T C (16 x 16 each; C may be NULL): 16-row tiles of
 // A, B, C staged in LDS; thread (i, j) = (t / 16, t % 16) accumulates
@@ -45,7 +46,8 @@ __global__ __launch_bounds__(256) void k_gram2(int64_t n, const double *__restri
 //   mode 1: G = gsave, W = first Gram (Q^T Z);
 //           coef = -G_SS^{-1} W_SS                      (beta)
 // The 2 x 256 entries are summed over the blocks by four thread groups, group q
-// taking the blocks q, q + 4, ... in order, then the four group sums in order.
+// taking the blocks q, q + 4, ... (four interleaved chains per thread), then the
+// four group sums in order.
 // coef is 16 x 16 row-major (direction i, column j), zero outside S x S.  A
 // non-positive pivot marks every active column broken (flag slot).
 __global__ __launch_bounds__(1024) void k_bcg_small(int nblk, const double *__restrict__ partial, double *sc,
@@ -55,11 +57,17 @@ __global__ __launch_bounds__(1024) void k_bcg_small(int nblk, const double *__re
     __shared__ double qa[4][256], qb[4][256];
     __shared__ int idx[NB];
     const int t = threadIdx.x & 255, q = threadIdx.x >> 8;
-    double a = 0.0, b = 0.0;
-    for (int k = q; k < nblk; k += 4) {
-        a += partial[(int64_t)k * 512 + t];
-        b += partial[(int64_t)k * 512 + 256 + t];
+    // four independent chains per thread (blocks q, q+4, q+8, q+12 of each 16),
+    // combined in a fixed order; nblk is a multiple of 16
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+    for (int k = q; k < nblk; k += 16) {
+        const double *pk = partial + (int64_t)k * 512 + t;
+        a0 += pk[0];        b0 += pk[256];
+        a1 += pk[4 * 512];  b1 += pk[4 * 512 + 256];
+        a2 += pk[8 * 512];  b2 += pk[8 * 512 + 256];
+        a3 += pk[12 * 512]; b3 += pk[12 * 512 + 256];
     }
+    double a = (a0 + a1) + (a2 + a3), b = (b0 + b1) + (b2 + b3);
     qa[q][t] = a;
     qb[q][t] = b;
     __syncthreads();
