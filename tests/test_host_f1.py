@@ -19,11 +19,11 @@ def _systems():
 
 
 @pytest.mark.parametrize("name,sysm", list(_systems()))
-@pytest.mark.parametrize("coarse", [0, 1])
-def test_host_f1_hierarchy_bitwise(name, sysm, coarse):
+@pytest.mark.parametrize("coarse,omega", [(0, 4.0 / 3.0), (1, 4.0 / 3.0), (0, 0.9)])
+def test_host_f1_hierarchy_bitwise(name, sysm, coarse, omega):
     rp, ci, v = sysm
     prm = dict(sweeps_per_level=3, smooth_prolong=1, smoother=2, cheb_degree=8, coarse_solver=coarse,
-               max_coarse=40)
+               max_coarse=40, omega=omega)
     h = oracle.Hierarchy(rp, ci, v, **prm)
     ctx = amg.Context(rp, ci, v, host_only=True, krylov=1, **prm)
     assert ctx.nlevels == h.nlevels >= 2
@@ -52,3 +52,16 @@ def test_host_f1_param_checks():
             amg.Context(rp, ci, v, host_only=True, **kw)
     ctx = amg.Context(rp, ci, v, host_only=True)
     assert ctx.prolongator(0) is None
+
+
+def test_params_struct_matches_the_library():
+    """The binding's amg_params mirrors the C struct: the library's defaults read
+    back field by field (a shifted field would read garbage)."""
+    p = amg.params_default()
+    assert (p.sweeps_per_level, p.max_coarse, p.max_levels, p.nu_pre, p.nu_post) == (2, 200, 40, 1, 1)
+    assert (p.vcycle_fp32, p.smoother, p.krylov, p.match_positive_only, p.itmax, p.nrhs) == (0, 0, 0, 0, 1000, 1)
+    assert (p.slice_offsets, p.smooth_prolong, p.cheb_degree, p.coarse_solver, p.coarse_itmax) == (1, 0, 8, 0, 30)
+    assert p.omega == 4.0 / 3.0 and p.coarse_tol == 1e-4
+    assert (p.setup_device, p.bootstrap_sweeps) == (0, 0)
+    q = amg.paper_default(5)
+    assert q == dict(sweeps_per_level=3, smooth_prolong=1, smoother=2, cheb_degree=14, coarse_solver=1, krylov=1)

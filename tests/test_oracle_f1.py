@@ -47,7 +47,7 @@ def _small_system():
     return rp, ci, v, K, invd
 
 
-@pytest.mark.parametrize("k", [1, 2, 3, 8, 12])
+@pytest.mark.parametrize("k", [1, 2, 3, 8, 12, 14, 16])
 def test_cheb4_error_polynomial(k):
     rp, ci, v, K, invd = _small_system()
     rng = np.random.default_rng(k)
@@ -87,20 +87,20 @@ def _dense_tentative(agg, pc, nc):
     return P
 
 
-@pytest.mark.parametrize("case", ["cube", "poisson3d"])
-def test_smoothed_prolongator_and_galerkin_dense(case):
+@pytest.mark.parametrize("case,omega", [("cube", 4.0 / 3.0), ("poisson3d", 4.0 / 3.0), ("cube", 1.0),
+                                        ("poisson3d", 0.7)])
+def test_smoothed_prolongator_and_galerkin_dense(case, omega):
     if case == "cube":
         rp, ci, v, _, _ = oracle.cube_system(2, 5)
     else:
         rp, ci, v, _ = oracle.poisson_kron(3, 2, 6)
-    h = _f1_hier(rp, ci, v)
+    h = _f1_hier(rp, ci, v, omega=omega)
     assert h.rc == 0 and h.nlevels >= 2
     for l in range(h.nlevels - 1):
         K = _csr(*h.level_matrix(l)).toarray()
         agg, pc, invd, _ = h.level_agg(l)
         nc = h.level_info(l + 1)[0]
         P = _dense_tentative(agg, pc, nc)
-        omega = 4.0 / 3.0
         Pbar = P - omega * (invd[:, None] * (K @ P))
         Ps = _csr(*h.prolongator(l), ncols=nc).toarray()
         assert np.abs(Ps - Pbar).max() <= 1e-14 * np.abs(Pbar).max()
