@@ -130,6 +130,7 @@ def main():
                          "paper: FP64 FCG with the paper's default preconditioner (aggregates of 8, "
                          "smoothed prolongator, Chebyshev l1-Jacobi, CG coarse solve)")
     ap.add_argument("--cheb-degree", type=int, default=4)
+    ap.add_argument("--params", default="", help="JSON object of further amg_params fields, merged into the form's")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--itmax", type=int, default=0, help="iteration limit (0: the workload's, else 1000)")
@@ -196,6 +197,8 @@ def main():
         kw["nrhs"] = nrhs
     if args.setup_device:
         kw["setup_device"] = 1
+    if args.params:
+        kw.update(json.loads(args.params))
     ctx = amg.Context(rp, ci, v, **kw)
     if args.mode in ("learned", "learned32"):
         from paper_2511_21268_amd import learned
@@ -299,7 +302,7 @@ def main():
            "config": {"workload": f"{args.workload}: {cfg['d']}D {problem}, B-splines p={cfg['p']}, "
                                   f"n={cfg['n']}, N={N}, nnz={nnz}, {form} + "
                                   f"matching AMG V-cycle ({amg_desc}), tol {args.tol}",
-                      "mode": args.mode, "nrhs": nrhs, "converged": converged,
+                      "mode": args.mode, "params": kw, "nrhs": nrhs, "converged": converged,
                       "iters": iters[-1], "relres_true": relres_true, "levels": len(levels),
                       "ms_median": round(step_ms[len(step_ms) // 2], 3),
                       "opc": round(ctx.opc(), 4), "setup_s": round(setup_s, 2),
