@@ -131,6 +131,8 @@ def main():
                          "smoothed prolongator, Chebyshev l1-Jacobi, CG coarse solve)")
     ap.add_argument("--cheb-degree", type=int, default=4)
     ap.add_argument("--params", default="", help="JSON object of further amg_params fields, merged into the form's")
+    ap.add_argument("--learned", action="store_true",
+                    help="use the trained degree-4 polynomial smoothers (sets smoother = 1) in any form")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--itmax", type=int, default=0, help="iteration limit (0: the workload's, else 1000)")
@@ -199,8 +201,10 @@ def main():
         kw["setup_device"] = 1
     if args.params:
         kw.update(json.loads(args.params))
+    if args.learned:
+        kw["smoother"] = 1
     ctx = amg.Context(rp, ci, v, **kw)
-    if args.mode in ("learned", "learned32"):
+    if args.mode in ("learned", "learned32") or args.learned:
         from paper_2511_21268_amd import learned
         accepted, coefs = learned.apply_learned(ctx)
         log(f"learned smoothers: accepted {accepted}, coefficients {[list(map(lambda x: round(x, 3), c)) for c in coefs]}")

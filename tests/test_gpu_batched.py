@@ -139,3 +139,39 @@ def test_batched_fused_post_equals_unfused(oracle, amg, kw):
         assert abs(of["iters"][j] - ou["iters"][j]) <= (0 if not kw else 1), j
         a, b = of["U"][:, j], ou["U"][:, j]
         assert torch.linalg.norm(a - b) <= tol * torch.linalg.norm(b), j
+
+
+def test_batched_learned_polynomial_smoother(oracle, amg):
+    """The batched solve with the learned degree-4 polynomial smoothers: with
+    the FP64 V-cycle (one lane per row) every column matches its single-vector
+    learned solve; with the autotuned FP32 block V-cycle every column reaches
+    an FP64 true residual of 1e-8."""
+    import os
+    from paper_2511_21268_amd import learned
+    from paper_2511_21268_amd.workloads import rhs_block
+    if not os.path.exists(learned.WEIGHTS):
+        pytest.skip("trained weights not present")
+    rp, ci, v, _ = oracle.poisson_kron(3, 3, 20)
+    N = len(rp) - 1
+    Fh = rhs_block(N, range(6))
+    Ft = torch.from_numpy(Fh).cuda()
+    ctx = amg.Context(rp, ci, v, smoother=1)
+    acc, _ = learned.apply_learned(ctx)
+    print(f"case batched learned: accepted {acc}", flush=True)
+    out = ctx.solve_batched(Ft, tol=1e-8)
+    assert out["status"] == 0
+    U = out["U"].cpu().numpy()
+    for j in range(6):
+        single = ctx.solve(Ft[:, j].contiguous(), tol=1e-8)
+        us = single["u"].cpu().numpy()
+        assert out["iters"][j] == single["iters"]
+        assert np.linalg.norm(U[:, j] - us) <= 1e-12 * np.linalg.norm(us)
+    ctx32 = amg.Context(rp, ci, v, smoother=1, vcycle_fp32=1, krylov=1, nrhs=16)
+    learned.apply_learned(ctx32)
+    out32 = ctx32.solve_batched(Ft, tol=1e-8)
+    U32 = out32["U"].cpu().numpy()
+    assert out32["status"] == 0
+    for j in range(6):
+        true = np.linalg.norm(Fh[:, j] - oracle.spmv(rp, ci, v, U32[:, j])) / np.linalg.norm(Fh[:, j])
+        assert true <= 1e-8 * 1.0001, (j, true)
+    print(f"  iterations fp64 {out['iters']} fp32 {out32['iters']}", flush=True)
