@@ -10,6 +10,7 @@
 #include "kernels_blk.h"
 #include "blockcg.h"
 #include "mlp.h"
+#include "post_res.h"
 #include "setup_dev.h"
 
 #include <hip/hip_runtime.h>
@@ -709,6 +710,27 @@ struct amg_ctx {
         }
         return nb * SELL_WAVES;   // one dot partial per wavefront
     }
+    // Fused prolongation + residual of the polynomial post-smoothing on level l:
+    // y = u + P e, L.r <- L.r - (K P) e (needs K P and the pre-smoothing residual in L.r).
+    template <typename VT> void post_res_fused(int l, const VT *e, const VT *u, VT *y)
+    {
+        Level &L = lev[l];
+        const DevMat &A = L.KP;
+        unsigned nb = (unsigned)((A.nslices + SELL_WAVES - 1) / SELL_WAVES);
+        if (l == 0) prof_begin();
+        if (A.idx16)
+            hipLaunchKernelGGL((k_sell_post_res<VT, uint16_t>), dim3(nb), dim3(256), 0, stream, A.sv<VT, uint16_t>(),
+                               e, u, (VT *)L.r, L.agg, L.pc<VT>(), y);
+        else
+            hipLaunchKernelGGL((k_sell_post_res<VT, int32_t>), dim3(nb), dim3(256), 0, stream, A.sv<VT, int32_t>(),
+                               e, u, (VT *)L.r, L.agg, L.pc<VT>(), y);
+        HIPCHK(hipGetLastError());
+        if (l == 0) {
+            double bytes = (double)A.nnz * sizeof(VT) + A.index_bytes + (double)sizeof(VT) * lev[1].n +
+                           (double)sizeof(VT) * A.n * 5 + 4.0 * A.n;   // u, pc, r read, r and y written, agg
+            prof_end(bytes);
+        }
+    }
     void finalize(unsigned nblk, int op, int slot = 0)
     {
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, stream, partial, (int)nblk, sc, op, slot);
@@ -835,6 +857,19 @@ struct amg_ctx {
                 return nullptr;
             }
             post_fused<VT, VT>(l, e, u, u2, 0, nullptr, nullptr);
+            std::swap(u, u2);
+            s0 = 2;
+        } else if (L.poly_on && prm.nu_post >= 1 && L.KP.soff && fuse_post) {
+            // polynomial smoother: the first step's residual f - K (u + P e) = r - (K P) e
+            VT *c = (VT *)L.c, *c2 = (VT *)L.c2;
+            post_res_fused<VT>(l, e, u, u2);
+            std::swap(u, u2);
+            const VT *cr = poly_apply<VT, VT>(l, (const VT *)L.r, c, c2);
+            if (zout && prm.nu_post == 1) {
+                finish_sweep<VT, double>(l, u, cr, zout, ndot, g0, g1);
+                return nullptr;
+            }
+            finish_sweep<VT, VT>(l, u, cr, u2, 0, nullptr, nullptr);
             std::swap(u, u2);
             s0 = 2;
         } else {

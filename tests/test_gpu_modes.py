@@ -127,6 +127,12 @@ def test_polynomial_smoother_vcycle(oracle, amg, fp32, iters_match):
     zo = h.vcycle(r)
     tol = 2e-5 if fp32 else 1e-12
     assert np.linalg.norm(z - zo) <= tol * np.linalg.norm(zo)
+    # the prolongation fused into the first post-smoothing residual through K P
+    # equals the unfused V-cycle up to rounding
+    ctx.set_fused_post(False)
+    zu = ctx.vcycle(torch.from_numpy(r).cuda()).cpu().numpy()
+    ctx.set_fused_post(True)
+    assert np.linalg.norm(z - zu) <= (1e-5 if fp32 else 1e-13) * np.linalg.norm(zu)
     ref = h.solve(F, flexible=bool(fp32))
     out = ctx.solve(torch.from_numpy(F).cuda())
     assert out["status"] == 0 and out["relres_true"] <= 1e-8
