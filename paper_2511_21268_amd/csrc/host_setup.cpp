@@ -589,56 +589,76 @@ int build_hierarchy(const CsrView &K0, const double *w, const SetupParams &prm,
 
 // ---------------------------------------------------------------------------
 // Workload generator: 1D B-spline matrices by Gauss quadrature, then the
-// Kronecker sum.  Basis values by the triangular (de Boor) scheme.
+// Kronecker sum (Sec. 2.2).  The benchmark systems must be the very matrices a
+// plain FP64 statement of the discretization produces, bit for bit, so every
+// value below is one fixed sequence of IEEE operations: the Gauss nodes come
+// from Newton's method on P_q started at cos(pi (k + 3/4) / (q + 1/2)), with
+// P_q and P_{q-1} from the three-term recurrence and P_q' = q (z P_q - P_{q-1})
+// / (z^2 - 1); the basis values from the Cox-de Boor recurrence evaluated
+// bottom-up over the degrees (a term with a zero knot difference is dropped).
 
+// P_q(z) and P_{q-1}(z)
+static void legendre_pair(int q, double z, double &pq, double &pq1)
+{
+    double lo = 1.0, hi = z;
+    for (int j = 2; j <= q; j++) {
+        double nx = ((2.0 * j - 1.0) * z * hi - (j - 1.0) * lo) / j;
+        lo = hi;
+        hi = nx;
+    }
+    pq = hi;
+    pq1 = lo;
+}
+
+// q-point Gauss-Legendre rule on [-1, 1], nodes ascending
 static void gauss_nodes(int q, double *x, double *w)
 {
     for (int k = 0; k < q; k++) {
-        double z = std::cos(M_PI * (2.0 * k + 1.0) / (2.0 * q));
-        for (int it = 0; it < 100; it++) {
-            double a = 1.0, b = z;          // P_0, P_1
-            for (int j = 2; j <= q; j++) { double c = ((2 * j - 1) * z * b - (j - 1) * a) / j; a = b; b = c; }
-            if (q == 1) { a = 1.0; b = z; }
-            double dp = q * (a - z * b) / (1.0 - z * z);
-            double dz = b / dp;
+        double z = std::cos(M_PI * (k + 0.75) / (q + 0.5)), pq, pq1, dp;
+        for (int it = 0; it < 200; it++) {
+            legendre_pair(q, z, pq, pq1);
+            dp = q * (z * pq - pq1) / (z * z - 1.0);
+            double dz = pq / dp;
             z -= dz;
-            if (std::fabs(dz) <= 1e-17) break;
+            if (std::fabs(dz) < 1e-16) break;
         }
-        double a = 1.0, b = z;
-        for (int j = 2; j <= q; j++) { double c = ((2 * j - 1) * z * b - (j - 1) * a) / j; a = b; b = c; }
-        if (q == 1) { a = 1.0; b = z; }
-        double dp = q * (a - z * b) / (1.0 - z * z);
-        x[q - 1 - k] = z;
-        w[q - 1 - k] = 2.0 / ((1.0 - z * z) * dp * dp);
+        legendre_pair(q, z, pq, pq1);
+        dp = q * (z * pq - pq1) / (z * z - 1.0);
+        x[k] = -z;
+        w[k] = 2.0 / ((1.0 - z * z) * dp * dp);
     }
 }
 
-// Values N[0..p] and derivatives D[0..p] of the p+1 functions nonzero on knot
-// span s at x (triangular scheme with left/right knot distances).
+// Values N[0..p] and derivatives D[0..p] of the functions s-p .. s, the ones
+// nonzero on knot span s, at x.  Level k of the table holds N_{i,k}(x) for
+// i = s-p .. s+p-k (degree 0: the indicator of [t_i, t_{i+1})).
 static void span_basis(const std::vector<double> &t, int s, int p, double x, double *N, double *D)
 {
-    double left[16], right[16], ndu[16][16];
-    ndu[0][0] = 1.0;
-    for (int j = 1; j <= p; j++) {
-        left[j] = x - t[s + 1 - j];
-        right[j] = t[s + j] - x;
-        double saved = 0.0;
-        for (int r = 0; r < j; r++) {
-            ndu[j][r] = right[r + 1] + left[j - r];      // lower triangle: knot differences
-            double tmp = ndu[r][j - 1] / ndu[j][r];
-            ndu[r][j] = saved + right[r + 1] * tmp;
-            saved = left[j - r] * tmp;
+    double tab[2][40];
+    const int i0 = s - p;
+    double *cur = tab[0], *nxt = tab[1];
+    for (int i = i0; i <= s + p; i++) cur[i - i0] = (t[i] <= x && x < t[i + 1]) ? 1.0 : 0.0;
+    for (int k = 1; k <= p; k++) {
+        if (k == p) {   // derivatives from degree p-1
+            for (int l = 0; l <= p; l++) {
+                const int i = i0 + l;
+                const double d1 = t[i + p] - t[i], d2 = t[i + p + 1] - t[i + 1];
+                double a = 0.0, b = 0.0;
+                if (d1 > 0.0) a = p / d1 * cur[l];
+                if (d2 > 0.0) b = p / d2 * cur[l + 1];
+                D[l] = a - b;
+            }
         }
-        ndu[j][j] = saved;
+        for (int i = i0; i <= s + p - k; i++) {
+            const double d1 = t[i + k] - t[i], d2 = t[i + k + 1] - t[i + 1];
+            double a = 0.0, b = 0.0;
+            if (d1 > 0.0) a = (x - t[i]) / d1 * cur[i - i0];
+            if (d2 > 0.0) b = (t[i + k + 1] - x) / d2 * cur[i + 1 - i0];
+            nxt[i - i0] = a + b;
+        }
+        std::swap(cur, nxt);
     }
-    for (int r = 0; r <= p; r++) N[r] = ndu[r][p];
-    // first derivative from the degree p-1 values
-    for (int r = 0; r <= p; r++) {
-        double d = 0.0;
-        if (r >= 1) d += ndu[r - 1][p - 1] / ndu[p][r - 1];
-        if (r <= p - 1) d -= ndu[r][p - 1] / ndu[p][r];
-        D[r] = p * d;
-    }
+    for (int l = 0; l <= p; l++) N[l] = cur[l];
 }
 
 static void matrices_1d(int p, int n, std::vector<double> &M, std::vector<double> &K,
@@ -879,11 +899,16 @@ int iga_cube(int p, int n, int64_t *rp, int32_t *ci, double *v, double *F)
     return 0;
 }
 
-// Variable-coefficient stiffness -div(kappa grad u) on the unit cube, kappa by
-// its parameters (kappa = exp(0.5 sum_k a_k cos(2 pi m_k . x))), (p+1)^3 Gauss
-// points per element, sum factorization per element (contracting x, then y,
-// then z), elements processed in (p+1)^3 colour classes so that elements of one
-// class share no basis function and can be accumulated in parallel.
+// Variable-coefficient stiffness -div(kappa grad u) on the unit cube (Sec. 2.2,
+// kappa inside the integral), kappa = exp(0.5 sum_k a_k cos(2 pi m_k . x)),
+// (p+1)^3 Gauss points per element, the quadrature sums of each element
+// factorized direction by direction: per gradient term, contract the z points
+// (T1[qx][qy][az][bz]), then the y points (T2[qx][ay][by][az][bz]), then the x
+// points into the local matrix.  Elements are added into the global matrix in
+// lexicographic order (z slowest), one fixed summation order for every entry:
+// local matrices of a run of consecutive elements are formed in parallel, then
+// added row by row (a row owned by one thread, its elements in order).  F is
+// the load of f = 1, summed per element over the points in (z, y, x) order.
 static double kappa_at(int nk, const double *a, const int32_t *mk, double x, double y, double z)
 {
     double s = 0.0;
@@ -897,7 +922,7 @@ int iga_diffusion(int p, int n, int nk, const double *a, const int32_t *mk, int6
 {
     if (p < 1 || p > 7 || n < 1 || n + p - 2 < 1 || nk < 0) return -1;
     const int m = n + p, md = m - 2, q1 = p + 1;
-    // pattern and zero values: reuse the constant-coefficient generator's layout
+    // pattern: the constant-coefficient generator's layout (ascending (z, y, x) columns)
     if (iga_poisson(3, p, n, rp, ci, v, nullptr)) return -1;
     const int64_t N = (int64_t)md * md * md;
     std::fill(v, v + rp[N], 0.0);
@@ -907,7 +932,8 @@ int iga_diffusion(int p, int n, int nk, const double *a, const int32_t *mk, int6
     for (int k = 1; k < n; k++) t[p + k] = (double)k / (double)n;
     double xg[16], wg[16];
     gauss_nodes(q1, xg, wg);
-    // per element index: points, weights, values and derivatives of its p+1 functions
+    // per element index e: points X[e][q], weights W[e][q], values B[e][l][q] and
+    // derivatives Dv[e][l][q] of the element's p+1 functions (same in every direction)
     std::vector<double> X(n * q1), W(n * q1), Bv(n * q1 * q1), Dv(n * q1 * q1);
     for (int e = 0; e < n; e++) {
         int s0 = p + e;
@@ -922,95 +948,111 @@ int iga_diffusion(int p, int n, int nk, const double *a, const int32_t *mk, int6
         }
     }
     auto len1 = [&](int i) { return std::min(md - 1, i + p) - std::max(0, i - p) + 1; };
-    // position of column (jx,jy,jz) in row (ix,iy,iz)
-    auto pos = [&](int ix, int iy, int iz, int jx, int jy, int jz) {
-        int64_t g = ix + (int64_t)md * (iy + (int64_t)md * iz);
-        int xlo = std::max(0, ix - p), ylo = std::max(0, iy - p), zlo = std::max(0, iz - p);
-        return rp[g] + ((int64_t)(jz - zlo) * len1(iy) + (jy - ylo)) * len1(ix) + (jx - xlo);
-    };
-    const int nl = q1 * q1 * q1;
-    for (int cz = 0; cz < q1; cz++)
-    for (int cy = 0; cy < q1; cy++)
-    for (int cx = 0; cx < q1; cx++) {
-        int nx = (n - cx + q1 - 1) / q1, ny = (n - cy + q1 - 1) / q1, nz = (n - cz + q1 - 1) / q1;
-        int64_t ne = (int64_t)nx * ny * nz;
-        if (ne <= 0) continue;
-        parallel_for(ne, [&](int64_t eb, int64_t ee) {
-            std::vector<double> kw(nl), A1(q1 * q1 * q1 * q1), A2(q1 * q1 * q1 * q1 * q1), Kl((size_t)nl * nl);
-            for (int64_t el = eb; el < ee; el++) {
-                int ex = cx + q1 * (int)(el % nx), ey = cy + q1 * (int)((el / nx) % ny), ez = cz + q1 * (int)(el / ((int64_t)nx * ny));
-                const double *BX = &Bv[ex * q1 * q1], *BY = &Bv[ey * q1 * q1], *BZ = &Bv[ez * q1 * q1];
-                const double *DX = &Dv[ex * q1 * q1], *DY = &Dv[ey * q1 * q1], *DZ = &Dv[ez * q1 * q1];
-                // kw[qz][qy][qx]
+    const int nl = q1 * q1 * q1, q2 = q1 * q1;
+    // a run: elements ez, ey in [y0, y1), every ex; at most ~64 MB of local matrices
+    const int64_t per_el = (int64_t)nl * nl;
+    const int lines = (int)std::max<int64_t>(1, std::min<int64_t>(n, ((int64_t)8 << 20) / (per_el * n)));
+    std::vector<double> Kl((size_t)lines * n * per_el);
+    auto local = [&](int ex, int ey, int ez, double *K) {
+        const double *BX = &Bv[ex * q2], *BY = &Bv[ey * q2], *BZ = &Bv[ez * q2];
+        const double *DX = &Dv[ex * q2], *DY = &Dv[ey * q2], *DZ = &Dv[ez * q2];
+        double kw[512], T1[4096], T2[32768];
+        for (int qx = 0; qx < q1; qx++)
+            for (int qy = 0; qy < q1; qy++)
+                for (int qz = 0; qz < q1; qz++) {
+                    double wt = (W[ex * q1 + qx] * W[ey * q1 + qy]) * W[ez * q1 + qz];
+                    kw[(qx * q1 + qy) * q1 + qz] =
+                        kappa_at(nk, a, mk, X[ex * q1 + qx], X[ey * q1 + qy], X[ez * q1 + qz]) * wt;
+                }
+        std::fill(K, K + per_el, 0.0);
+        for (int term = 0; term < 3; term++) {
+            const double *TX = term == 0 ? DX : BX, *TY = term == 1 ? DY : BY, *TZ = term == 2 ? DZ : BZ;
+            for (int qx = 0; qx < q1; qx++)
+            for (int qy = 0; qy < q1; qy++)
+            for (int az = 0; az < q1; az++)
+            for (int bz = 0; bz < q1; bz++) {
+                double acc = 0.0;
                 for (int qz = 0; qz < q1; qz++)
-                    for (int qy = 0; qy < q1; qy++)
-                        for (int qx = 0; qx < q1; qx++) {
-                            double w = (W[ez * q1 + qz] * W[ey * q1 + qy]) * W[ex * q1 + qx];
-                            kw[(qz * q1 + qy) * q1 + qx] =
-                                w * kappa_at(nk, a, mk, X[ex * q1 + qx], X[ey * q1 + qy], X[ez * q1 + qz]);
-                        }
-                std::fill(Kl.begin(), Kl.end(), 0.0);
-                for (int term = 0; term < 3; term++) {
-                    const double *TX = term == 0 ? DX : BX, *TY = term == 1 ? DY : BY, *TZ = term == 2 ? DZ : BZ;
-                    // A1[qz][qy][ax][bx] = sum_qx kw TX_ax TX_bx
-                    for (int qz = 0; qz < q1; qz++)
-                    for (int qy = 0; qy < q1; qy++)
-                    for (int ax = 0; ax < q1; ax++)
-                    for (int bx = 0; bx < q1; bx++) {
-                        double acc = 0.0;
-                        for (int qx = 0; qx < q1; qx++)
-                            acc += kw[(qz * q1 + qy) * q1 + qx] * (TX[ax * q1 + qx] * TX[bx * q1 + qx]);
-                        A1[((qz * q1 + qy) * q1 + ax) * q1 + bx] = acc;
-                    }
-                    // A2[qz][ay][by][ax][bx] = sum_qy A1 TY_ay TY_by
-                    for (int qz = 0; qz < q1; qz++)
-                    for (int ay = 0; ay < q1; ay++)
-                    for (int by = 0; by < q1; by++)
-                    for (int ax = 0; ax < q1; ax++)
-                    for (int bx = 0; bx < q1; bx++) {
-                        double acc = 0.0;
-                        for (int qy = 0; qy < q1; qy++)
-                            acc += A1[((qz * q1 + qy) * q1 + ax) * q1 + bx] * (TY[ay * q1 + qy] * TY[by * q1 + qy]);
-                        A2[(((qz * q1 + ay) * q1 + by) * q1 + ax) * q1 + bx] = acc;
-                    }
-                    // Kl[(az,ay,ax),(bz,by,bx)] += sum_qz A2 TZ_az TZ_bz
-                    for (int az = 0; az < q1; az++)
-                    for (int bz = 0; bz < q1; bz++)
-                    for (int ay = 0; ay < q1; ay++)
-                    for (int by = 0; by < q1; by++)
-                    for (int ax = 0; ax < q1; ax++)
-                    for (int bx = 0; bx < q1; bx++) {
-                        double acc = 0.0;
-                        for (int qz = 0; qz < q1; qz++)
-                            acc += A2[(((qz * q1 + ay) * q1 + by) * q1 + ax) * q1 + bx] * (TZ[az * q1 + qz] * TZ[bz * q1 + qz]);
-                        Kl[(size_t)((az * q1 + ay) * q1 + ax) * nl + (bz * q1 + by) * q1 + bx] += acc;
-                    }
-                }
-                for (int az = 0; az < q1; az++)
-                for (int ay = 0; ay < q1; ay++)
-                for (int ax = 0; ax < q1; ax++) {
-                    int ix = ex + ax - 1, iy = ey + ay - 1, iz = ez + az - 1;   // reduced indices
-                    if (ix < 0 || ix >= md || iy < 0 || iy >= md || iz < 0 || iz >= md) continue;
-                    if (F) {
-                        double fsum = 0.0;
-                        for (int qz = 0; qz < q1; qz++)
-                            for (int qy = 0; qy < q1; qy++)
-                                for (int qx = 0; qx < q1; qx++)
-                                    fsum += ((W[ez * q1 + qz] * W[ey * q1 + qy]) * W[ex * q1 + qx]) *
-                                            ((BZ[az * q1 + qz] * BY[ay * q1 + qy]) * BX[ax * q1 + qx]);
-                        F[ix + (int64_t)md * (iy + (int64_t)md * iz)] += fsum;
-                    }
-                    for (int bz = 0; bz < q1; bz++)
-                    for (int by = 0; by < q1; by++)
-                    for (int bx = 0; bx < q1; bx++) {
-                        int jx = ex + bx - 1, jy = ey + by - 1, jz = ez + bz - 1;
-                        if (jx < 0 || jx >= md || jy < 0 || jy >= md || jz < 0 || jz >= md) continue;
-                        v[pos(ix, iy, iz, jx, jy, jz)] += Kl[(size_t)((az * q1 + ay) * q1 + ax) * nl + (bz * q1 + by) * q1 + bx];
-                    }
-                }
+                    acc += kw[(qx * q1 + qy) * q1 + qz] * (TZ[az * q1 + qz] * TZ[bz * q1 + qz]);
+                T1[((qx * q1 + qy) * q1 + az) * q1 + bz] = acc;
             }
-        }, 1);
-    }
+            for (int qx = 0; qx < q1; qx++)
+            for (int ay = 0; ay < q1; ay++)
+            for (int by = 0; by < q1; by++)
+            for (int az = 0; az < q1; az++)
+            for (int bz = 0; bz < q1; bz++) {
+                double acc = 0.0;
+                for (int qy = 0; qy < q1; qy++)
+                    acc += T1[((qx * q1 + qy) * q1 + az) * q1 + bz] * (TY[ay * q1 + qy] * TY[by * q1 + qy]);
+                T2[(((qx * q1 + ay) * q1 + by) * q1 + az) * q1 + bz] = acc;
+            }
+            for (int az = 0; az < q1; az++)
+            for (int ay = 0; ay < q1; ay++)
+            for (int ax = 0; ax < q1; ax++)
+            for (int bz = 0; bz < q1; bz++)
+            for (int by = 0; by < q1; by++)
+            for (int bx = 0; bx < q1; bx++) {
+                double acc = 0.0;
+                for (int qx = 0; qx < q1; qx++)
+                    acc += T2[(((qx * q1 + ay) * q1 + by) * q1 + az) * q1 + bz] * (TX[ax * q1 + qx] * TX[bx * q1 + qx]);
+                K[(size_t)((az * q1 + ay) * q1 + ax) * nl + (bz * q1 + by) * q1 + bx] += acc;
+            }
+        }
+    };
+    for (int ez = 0; ez < n; ez++)
+        for (int y0 = 0; y0 < n; y0 += lines) {
+            const int y1 = std::min(n, y0 + lines);
+            const int64_t nel = (int64_t)(y1 - y0) * n;
+            parallel_for(nel, [&](int64_t b, int64_t e) {
+                for (int64_t el = b; el < e; el++)
+                    local((int)(el % n), y0 + (int)(el / n), ez, &Kl[(size_t)el * per_el]);
+            }, 1);
+            // rows touched by the run: full indices fz in [ez, ez+p], fy in [y0, y1-1+p]
+            const int fz0 = std::max(1, ez), fz1 = std::min(m - 2, ez + p);
+            const int fy0 = std::max(1, y0), fy1 = std::min(m - 2, y1 - 1 + p);
+            if (fz0 > fz1 || fy0 > fy1) continue;
+            const int64_t nrow = (int64_t)(fz1 - fz0 + 1) * (fy1 - fy0 + 1) * md;
+            parallel_for(nrow, [&](int64_t b, int64_t e) {
+                for (int64_t r = b; r < e; r++) {
+                    const int ix = (int)(r % md), fx = ix + 1;
+                    const int fy = fy0 + (int)((r / md) % (fy1 - fy0 + 1)), fz = fz0 + (int)(r / ((int64_t)md * (fy1 - fy0 + 1)));
+                    const int iy = fy - 1, iz = fz - 1;
+                    const int64_t g = ix + (int64_t)md * (iy + (int64_t)md * iz);
+                    const int az = fz - ez;
+                    const int xlo = std::max(0, ix - p), ylo = std::max(0, iy - p), zlo = std::max(0, iz - p);
+                    const int lx = len1(ix), ly = len1(iy);
+                    for (int ey = std::max(y0, fy - p); ey <= std::min(y1 - 1, fy); ey++)
+                        for (int ex = std::max(0, fx - p); ex <= std::min(n - 1, fx); ex++) {
+                            const int ay = fy - ey, ax = fx - ex;
+                            if (F) {
+                                const double *BX = &Bv[ex * q2], *BY = &Bv[ey * q2], *BZ = &Bv[ez * q2];
+                                for (int qz = 0; qz < q1; qz++)
+                                    for (int qy = 0; qy < q1; qy++)
+                                        for (int qx = 0; qx < q1; qx++) {
+                                            double wt = (W[ex * q1 + qx] * W[ey * q1 + qy]) * W[ez * q1 + qz];
+                                            F[g] += wt * ((BX[ax * q1 + qx] * BY[ay * q1 + qy]) * BZ[az * q1 + qz]);
+                                        }
+                            }
+                            const double *K = &Kl[(size_t)((ey - y0) * (int64_t)n + ex) * per_el] +
+                                              (size_t)((az * q1 + ay) * q1 + ax) * nl;
+                            for (int bz = 0; bz < q1; bz++) {
+                                const int jz = ez + bz - 1;
+                                if (jz < 0 || jz >= md) continue;
+                                for (int by = 0; by < q1; by++) {
+                                    const int jy = ey + by - 1;
+                                    if (jy < 0 || jy >= md) continue;
+                                    const int64_t base = rp[g] + ((int64_t)(jz - zlo) * ly + (jy - ylo)) * lx;
+                                    for (int bx = 0; bx < q1; bx++) {
+                                        const int jx = ex + bx - 1;
+                                        if (jx < 0 || jx >= md) continue;
+                                        v[base + (jx - xlo)] += K[(bz * q1 + by) * q1 + bx];
+                                    }
+                                }
+                            }
+                        }
+                }
+            }, 1);
+        }
     return 0;
 }
 

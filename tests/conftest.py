@@ -1,5 +1,6 @@
 import os
 import sys
+import warnings
 
 import pytest
 
@@ -20,29 +21,70 @@ def oracle():
     return o
 
 
-def _iters_match(gpu_iters, ref, tol, margin=1e-2, long_run=300, long_frac=0.01):
+class MarginalStop(UserWarning):
+    """An FP64 iteration count one apart from the oracle's at a stopping test
+    that the rounding order decides (the oracle's residual within MARGIN of
+    the tolerance)."""
+
+
+MARGIN = 1e-6   # relative distance of the oracle's stopping residual from tol
+LONG_RUN = 300  # iterations from which a full-solve count is not compared
+
+
+def _iters_match(gpu_iters, ref, tol, margin=MARGIN):
     """FP64 iteration counts against the oracle's.  The GPU sums its dots in
-    blocks, the oracle in index order; their residual histories drift apart
-    by rounding, slowly (last digits over ~100 CG iterations) and, over
-    hundreds of iterations on a badly conditioned system, by up to a few
-    percent (measured: 3D p = 4, n = 12, FCG(1): the oracle stops at 463, the
-    GPU at 463 to 465 depending only on the summation order of its dots).
-    Accepted: equal counts; one apart when the stop is marginal (the oracle's
-    relative residual at the earlier count within `margin` of tol); and for
-    runs of at least `long_run` iterations, counts within `long_frac` of the
-    oracle's.  Callers then compare the GPU iterate with the oracle's iterate
-    at the same count."""
+    blocks (one partial per wavefront, then a fixed-order final sum), the
+    oracle in index order, so the two recursive residual histories agree only
+    to rounding.  Accepted: equal counts; or one apart when the oracle's
+    relative residual at the earlier of the two counts lies within `margin`
+    (relative) of tol, i.e. the stopping test itself is decided by rounding --
+    reported as a MarginalStop warning carrying both counts.  Runs of
+    LONG_RUN or more iterations are compared at fixed counts instead
+    (`fixed_count_parity`), not through this rule."""
     o = ref["iters"]
     if gpu_iters == o:
-        return True
-    if o >= long_run and abs(gpu_iters - o) <= max(1, round(long_frac * o)):
-        print(f"  long run: oracle {o}, gpu {gpu_iters} iterations", flush=True)
         return True
     if abs(gpu_iters - o) != 1:
         return False
     h = ref["hist"][min(gpu_iters, o)]
-    print(f"  stop moved by one: oracle {o}, gpu {gpu_iters}, oracle relres there {h:.6e} (tol {tol:.1e})", flush=True)
-    return abs(h - tol) <= margin * tol
+    rel = abs(h / tol - 1.0)
+    if rel <= margin:
+        warnings.warn(MarginalStop(f"marginal stop: oracle {o}, gpu {gpu_iters} iterations, oracle relres "
+                                   f"{h:.9e} at {min(gpu_iters, o)} (|relres/tol - 1| = {rel:.1e})"))
+        return True
+    return False
+
+
+def stop_margin(ref, tol):
+    """Relative distance of the oracle's last two recursive residuals from tol."""
+    h = ref["hist"]
+    return min(abs(h[-1] / tol - 1.0), abs(h[-2] / tol - 1.0)) if len(h) >= 2 else float("inf")
+
+
+def _fixed_count_parity(h, make_ctx, F, counts, flexible=False):
+    """Runs that are too long for count parity: the GPU and the oracle each do
+    exactly k iterations (tol = 0, itmax = k, no stopping decision), and the
+    iterates are returned with their relative difference, for each k."""
+    import numpy as np
+    import torch
+    out = []
+    Ft = torch.from_numpy(F).cuda()
+    for k in counts:
+        ref = h.solve(F, tol=0.0, itmax=k, flexible=flexible)
+        ctx = make_ctx(k)
+        got = ctx.solve(Ft, tol=0.0, check=False)
+        assert got["iters"] == k and ref["iters"] == k
+        u = got["u"].cpu().numpy()
+        err = np.linalg.norm(u - ref["u"]) / np.linalg.norm(ref["u"])
+        print(f"  after {k} iterations: relative difference of the iterates {err:.2e}", flush=True)
+        out.append((k, err))
+        del ctx
+    return out
+
+
+@pytest.fixture(scope="session")
+def fixed_count_parity():
+    return _fixed_count_parity
 
 
 @pytest.fixture(scope="session")

@@ -32,7 +32,11 @@ def amg():
 
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("k,p", [(12, 3), (12, 4), (12, 5), (12, 6), (24, 3), (24, 4), (24, 5)])
-def test_cube_parity(oracle, amg, iters_match, oracle_iterate, k, p):
+def test_cube_parity(oracle, amg, iters_match, oracle_iterate, fixed_count_parity, k, p):
+    """Runs of LONG_RUN iterations or more (k = 12, p = 5 and 6: ~955 and
+    ~2460) are compared at fixed counts (no stopping decision) instead of
+    through their stop."""
+    from conftest import LONG_RUN
     print(f"case cube k={k} p={p}", flush=True)
     rp, ci, v, F, lift = oracle.cube_system(p, k)
     h = oracle.Hierarchy(rp, ci, v)
@@ -44,22 +48,27 @@ def test_cube_parity(oracle, amg, iters_match, oracle_iterate, k, p):
         assert np.array_equal(a, ao) and np.array_equal(pc, pco), l
     out = ctx.solve(torch.from_numpy(F).cuda(), tol=1e-8)
     u = out["u"].cpu().numpy()
-    assert out["status"] == 0 and iters_match(out["iters"], ref, 1e-8)
+    assert out["status"] == 0 and out["relres_true"] <= 1e-8 * 1.0001
+    e, nr = oracle.cube_error(p, k, u, lift)
+    print(f"  N={len(F)}: {out['iters']} iterations (oracle {ref['iters']}; Table 1(a), paper's preconditioner: "
+          f"{TABLE_1A[k][p]}), L2 error {e / nr:.2e}", flush=True)
+    assert e / nr < 1e-4
+    if ref["iters"] >= LONG_RUN:
+        for kk, err in fixed_count_parity(h, lambda kk: amg.Context(rp, ci, v, itmax=kk), F, (100, 300)):
+            assert err <= 1e-10, (kk, err)
+        return
+    assert iters_match(out["iters"], ref, 1e-8)
     uo = oracle_iterate(h, F, ref, out["iters"])
     # The mixed Dirichlet/Neumann system is far more sensitive to rounding
     # order than the all-Dirichlet one (its iterate at 1e-8 sits 1e-7..1e-4
-    # from the solution), so the iterate bar is relative to the algebraic
-    # error the solve itself leaves: the two iterates must agree to 1% of it.
+    # from the solution): the iterate difference is also set against the
+    # algebraic error the solve itself leaves.
     ex = h.solve(F, tol=1e-13, itmax=20000)["u"]
     alg = np.linalg.norm(uo - ex) / np.linalg.norm(ex)
     err = np.linalg.norm(u - uo) / np.linalg.norm(uo)
-    e, nr = oracle.cube_error(p, k, u, lift)
     eo, _ = oracle.cube_error(p, k, uo, lift)
-    print(f"  N={len(F)}: {out['iters']} iterations (Table 1(a), paper's preconditioner: {TABLE_1A[k][p]}), "
-          f"iterate difference {err:.2e} (algebraic error {alg:.2e}), L2 error {e / nr:.2e} (oracle {eo / nr:.2e})",
-          flush=True)
-    assert err <= 1e-2 * alg
-    assert e / nr < 1e-4
+    print(f"  iterate difference {err:.2e} (algebraic error {alg:.2e}), oracle L2 error {eo / nr:.2e}", flush=True)
+    assert err <= 1e-10
 
 
 @pytest.mark.timeout(900)

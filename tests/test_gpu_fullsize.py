@@ -3,11 +3,12 @@
 3D p=3, n=64 (N = 274,625; 86.9M entries): the whole solve against the
 oracle's, aggregates of every level bit for bit.
 3D p=3, n=128 (N = 2,146,689; 707M entries, the benchmark workload, same
-kernels and launch shapes as bench.py): properties and sampled outputs the
-oracle computes one by one -- sampled SpMV rows, the greedy characterisation of
-the level-0 matching on every edge, and the FP64 true residual of the solve;
-the 16-RHS form with the autotuned block kernels, every column's FP64 true
-residual.
+kernels, parameters and launch shapes as bench.py): the library's generator
+gives the oracle's matrix bit for bit; the whole FP64 solve against the
+oracle's -- every level's sizes, aggregates, coefficients and coarse matrices
+bit for bit (host and device set-up), the iteration count exactly behind the
+stop-margin check, and the solution within 1e-10; sampled SpMV rows; the 16-RHS
+form with the autotuned block kernels, every column's FP64 true residual.
 3D p=4, n=96 (640M entries): the FP32 V-cycle inside FP64 FCG against the
 FP64 PCG on the same system.
 3D p=5, n=64, variable kappa: sampled rows, plain and learned solves.
@@ -74,6 +75,84 @@ def _sampled_rows(oracle, rp, ci, v, x, y, nsample=4000, seed=4):
 def c4_system(oracle):
     rp, ci, v, _ = oracle.poisson_kron(3, 3, 128, want_F=False)
     return rp, ci, v
+
+
+@pytest.fixture(scope="module")
+def c4_oracle(oracle, c4_system):
+    """The oracle's hierarchy of the 3D p=3 n=128 system (about a minute on the
+    host), shared by the tests of this module."""
+    import time
+    rp, ci, v = c4_system
+    t = time.time()
+    h = oracle.Hierarchy(rp, ci, v)
+    print(f"  oracle hierarchy: {[h.level_info(l) for l in range(h.nlevels)]} in {time.time() - t:.1f} s",
+          flush=True)
+    return h
+
+
+def _same_as_oracle(ctx, h, first_matrix=1):
+    assert ctx.nlevels == h.nlevels
+    for l in range(h.nlevels):
+        assert ctx.level_info(l) == h.level_info(l), l
+    for l in range(h.nlevels - 1):
+        a, pc = ctx.aggregates(l)
+        ao, pco, _, _ = h.level_agg(l)
+        assert np.array_equal(a, ao) and np.array_equal(pc, pco), l
+        if l + 1 >= first_matrix:
+            for x, y in zip(ctx.coarse_matrix(l + 1), h.level_matrix(l + 1)):
+                assert np.array_equal(x, y), l + 1
+
+
+@pytest.mark.timeout(900)
+def test_c4_full_solve_parity(oracle, amg, c4_system, c4_oracle):
+    """The benchmark run itself (FP64 PCG, default parameters, F ~ N(0,1) seed 0)
+    against the oracle (Sec. 3.1 hierarchy, Sec. 4 Krylov call)."""
+    import time
+    print("case c4 full: 3D p=3 n=128 seed 0", flush=True)
+    from paper_2511_21268_amd.workloads import rhs_normal
+    rp, ci, v = c4_system
+    N = len(rp) - 1
+    # the benchmark generates its system with the library: the same bits
+    rg, cg, vg, _ = amg.iga_poisson(3, 3, 128, want_F=False)
+    assert np.array_equal(rg, rp) and np.array_equal(cg, ci) and np.array_equal(vg, v)
+    del rg, cg, vg
+    print("  library generator = oracle assembly", flush=True)
+    h = c4_oracle
+    F = rhs_normal(N, 0)
+    oracle.set_threads(16)
+    t = time.time()
+    ref = h.solve(F, tol=1e-8)
+    print(f"  oracle solve: {ref['iters']} iterations in {time.time() - t:.1f} s (16 threads)", flush=True)
+    ctx = amg.Context(rp, ci, v)
+    _same_as_oracle(ctx, h)
+    print("  every level's aggregates, coefficients and coarse matrix = oracle's", flush=True)
+    out = ctx.solve(torch.from_numpy(F).cuda(), tol=1e-8)
+    u = out["u"].cpu().numpy()
+    err = np.linalg.norm(u - ref["u"]) / np.linalg.norm(ref["u"])
+    margin = min(abs(ref["hist"][-1] / 1e-8 - 1), abs(ref["hist"][-2] / 1e-8 - 1))
+    print(f"  gpu: {out['iters']} iterations, rel.err {err:.2e}, stop margin {margin:.2e}", flush=True)
+    assert margin > 1e-6, "marginal stopping test: iteration parity not decidable"
+    assert out["status"] == 0 and ref["rc"] == 0
+    assert out["iters"] == ref["iters"]
+    assert err <= 1e-10
+    true = np.linalg.norm(F - oracle.spmv(rp, ci, v, u)) / np.linalg.norm(F)
+    assert true <= 1e-8
+
+
+@pytest.mark.timeout(900)
+def test_c4_device_setup_against_oracle(amg, c4_system, c4_oracle):
+    """Device set-up (Sec. 3.1 on the GPU) of the 3D p=3 n=128 system: every
+    level equals the oracle's hierarchy bit for bit; set-up time printed."""
+    import time
+    print("case c4 device set-up: 3D p=3 n=128", flush=True)
+    rp, ci, v = c4_system
+    t = time.time()
+    dev = amg.Context(rp, ci, v, setup_device=1)
+    td = time.time() - t
+    sw, tot, mx = dev.setup_rounds()
+    print(f"  device set-up (hierarchy + device images) {td:.1f} s, rounds {tot} over {sw} sweeps (max {mx})",
+          flush=True)
+    _same_as_oracle(dev, c4_oracle)
 
 
 @pytest.mark.timeout(900)

@@ -23,9 +23,11 @@ def amg():
 
 
 @pytest.mark.parametrize("d,p,n", [(2, 2, 32), (3, 3, 16), (3, 4, 12)])
-def test_fcg_fp64_parity(oracle, amg, iters_match, oracle_iterate, d, p, n):
+def test_fcg_fp64_parity(oracle, amg, iters_match, oracle_iterate, fixed_count_parity, d, p, n):
     """FCG(1) with the FP64 V-cycle: same iterations and iterates as the
-    oracle's flexible CG."""
+    oracle's flexible CG.  A run of LONG_RUN iterations or more (3D p = 4
+    n = 12: ~463) is compared at fixed counts instead of through its stop."""
+    from conftest import LONG_RUN
     print(f"case fcg64 d={d} p={p} n={n}", flush=True)
     from paper_2511_21268_amd.workloads import rhs_normal
     rp, ci, v, _ = oracle.poisson_kron(d, p, n)
@@ -35,14 +37,18 @@ def test_fcg_fp64_parity(oracle, amg, iters_match, oracle_iterate, d, p, n):
     ctx = amg.Context(rp, ci, v, krylov=1)
     out = ctx.solve(torch.from_numpy(F).cuda(), tol=1e-8)
     u = out["u"].cpu().numpy()
-    assert out["status"] == 0 and iters_match(out["iters"], ref, 1e-8)
+    print(f"  {out['iters']} iterations (oracle {ref['iters']}), true relres {out['relres_true']:.2e}", flush=True)
+    assert out["status"] == 0 and out["relres_true"] <= 1e-8 * 1.0001
+    if ref["iters"] >= LONG_RUN:
+        for k, err in fixed_count_parity(h, lambda k: amg.Context(rp, ci, v, krylov=1, itmax=k), F,
+                                         (100, 200, ref["iters"]), flexible=True):
+            assert err <= 1e-10, (k, err)
+        return
+    assert iters_match(out["iters"], ref, 1e-8)
     uo = oracle_iterate(h, F, ref, out["iters"], flexible=True)
     err = np.linalg.norm(u - uo) / np.linalg.norm(uo)
-    print(f"  {out['iters']} iterations, rel. error against the oracle iterate {err:.2e}", flush=True)
-    # the rounding drift of the two iterations grows with their length (p = 4:
-    # ~465 FCG(1) iterations, measured 1.4e-10); both iterates are far closer to
-    # each other than to the exact solution (residual 1e-8 times the conditioning)
-    assert err <= (1e-10 if ref["iters"] < 300 else 1e-9)
+    print(f"  rel. error against the oracle iterate {err:.2e}", flush=True)
+    assert err <= 1e-10
 
 
 @pytest.mark.parametrize("d,p,n", [(2, 2, 32), (3, 3, 16), (3, 4, 12), (3, 4, 20)])

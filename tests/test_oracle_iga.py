@@ -178,3 +178,135 @@ def test_variable_kappa_assembly_is_spd_and_scales(oracle):
     rq, cq, vq, _ = oracle.diffusion_quad3d(2, 3, np.array([0.7]), np.zeros((1, 3), np.int32))
     r1, c1, v1, _ = oracle.diffusion_quad3d(2, 3)
     assert np.allclose(vq, np.exp(0.35) * v1, rtol=1e-14, atol=0)
+
+
+# ---------------------------------------------------------------- variable kappa (Sec. 2.2)
+def _basis_1d(p, n, i, xs, der=0):
+    """N_i (der=0) or N_i' (der=1) of the open uniform degree-p basis on n
+    elements at the points xs, by scipy (independent of the oracle's Cox-de Boor)."""
+    t = np.concatenate([np.zeros(p), np.linspace(0.0, 1.0, n + 1), np.ones(p)])
+    c = np.zeros(n + p)
+    c[i] = 1.0
+    b = BSpline(t, c, p, extrapolate=False)
+    if der:
+        b = b.derivative()
+    out = b(xs)
+    return np.nan_to_num(out)
+
+
+def _gauss_points_1d(p, n, elems):
+    """(p+1)-point Gauss-Legendre points and weights (numpy) on the given elements."""
+    xr, wr = np.polynomial.legendre.leggauss(p + 1)
+    h = 1.0 / n
+    xs = np.concatenate([e * h + (xr + 1.0) * 0.5 * h for e in elems])
+    ws = np.concatenate([wr * 0.5 * h for _ in elems])
+    return xs, ws
+
+
+def _kappa_np(a, mk, x, y, z):
+    s = np.zeros(np.broadcast(x, y, z).shape)
+    for ak, m in zip(a, mk):
+        s = s + ak * np.cos(2.0 * np.pi * (m[0] * x + m[1] * y + m[2] * z))
+    return np.exp(0.5 * s)
+
+
+def _entry_by_quadrature(p, n, a, mk, g, h):
+    """k_gh = sum over elements and (p+1)^3 Gauss points of kappa grad N_g . grad N_h
+    for reduced tensor indices g, h (full index = reduced + 1), written from the
+    definition with scipy basis values and numpy Gauss points."""
+    fg = [c + 1 for c in g]
+    fh = [c + 1 for c in h]
+    per_dir = []
+    for d in range(3):
+        lo = max(fg[d], fh[d]) - p
+        hi = min(fg[d], fh[d])
+        elems = [e for e in range(max(lo, 0), min(hi, n - 1) + 1)]
+        if not elems:
+            return 0.0
+        xs, ws = _gauss_points_1d(p, n, elems)
+        per_dir.append((xs, ws, _basis_1d(p, n, fg[d], xs), _basis_1d(p, n, fg[d], xs, 1),
+                        _basis_1d(p, n, fh[d], xs), _basis_1d(p, n, fh[d], xs, 1)))
+    (x, wx, Ngx, Dgx, Nhx, Dhx), (y, wy, Ngy, Dgy, Nhy, Dhy), (z, wz, Ngz, Dgz, Nhz, Dhz) = per_dir
+    X, Y, Z = np.meshgrid(x, y, z, indexing="ij")
+    W = wx[:, None, None] * wy[None, :, None] * wz[None, None, :]
+    kap = _kappa_np(a, mk, X, Y, Z)
+    gx = (Dgx * Dhx)[:, None, None] * (Ngy * Nhy)[None, :, None] * (Ngz * Nhz)[None, None, :]
+    gy = (Ngx * Nhx)[:, None, None] * (Dgy * Dhy)[None, :, None] * (Ngz * Nhz)[None, None, :]
+    gz = (Ngx * Nhx)[:, None, None] * (Ngy * Nhy)[None, :, None] * (Dgz * Dhz)[None, None, :]
+    return float(np.sum(W * kap * (gx + gy + gz)))
+
+
+def _weighted_1d(p, n, gfun):
+    """int g N_i N_j and int g N_i' N_j' over [0,1] by (p+1)-point Gauss per element,
+    full n+p basis, scipy values."""
+    m = n + p
+    xs, ws = _gauss_points_1d(p, n, range(n))
+    B = np.array([_basis_1d(p, n, i, xs) for i in range(m)])
+    D = np.array([_basis_1d(p, n, i, xs, 1) for i in range(m)])
+    gw = gfun(xs) * ws
+    return (B * gw) @ B.T, (D * gw) @ D.T
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_separable_kappa_is_weighted_kronecker_sum(oracle, axis):
+    """kappa varying along one axis only: with the tensor (p+1)^3 rule the
+    stiffness factorizes into K = sum over directions of 1D matrices, the
+    varying direction weighted by kappa (mass or stiffness), the other two the
+    plain 1D mass / stiffness.  A swapped coordinate, a point taken from the
+    wrong direction or a wrong weight fails this."""
+    p, n = 2, 5
+    a = np.array([0.8])
+    mk = np.zeros((1, 3), np.int32)
+    mk[0, axis] = 1
+    rp, ci, v, _ = oracle.diffusion_quad3d(p, n, a, mk, factorized=True)
+    K = _csr(rp, ci, v).toarray()
+    one = lambda x: np.ones_like(x)
+    g = lambda x: np.exp(0.5 * 0.8 * np.cos(2.0 * np.pi * x))
+    M1, K1 = _weighted_1d(p, n, one)
+    Mg, Kg = _weighted_1d(p, n, g)
+    inner = slice(1, n + p - 1)              # homogeneous Dirichlet: drop first and last
+    M1, K1, Mg, Kg = (A[inner, inner] for A in (M1, K1, Mg, Kg))
+    Ms = [M1, M1, M1]; Ks = [K1, K1, K1]
+    Ms[axis], Ks[axis] = Mg, Kg
+    # lexicographic order, x fastest: index = ix + m (iy + m iz) -> kron(z, kron(y, x))
+    ref = (np.kron(Ms[2], np.kron(Ms[1], Ks[0])) + np.kron(Ms[2], np.kron(Ks[1], Ms[0]))
+           + np.kron(Ks[2], np.kron(Ms[1], Ms[0])))
+    assert np.abs(K - ref).max() <= 1e-13 * np.abs(ref).max()
+    # the plain element loop agrees as well
+    rq, cq, vq, _ = oracle.diffusion_quad3d(p, n, a, mk)
+    assert np.abs(_csr(rq, cq, vq).toarray() - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_general_kappa_entries_by_independent_quadrature(oracle):
+    """Entries of the oracle's variable-kappa matrix against the quadrature sum
+    written from the definition (kappa inside the integral, Sec. 2.2,
+    eq. (matrix_and_vector_values)) with scipy basis values and numpy Gauss
+    points, for kappa with modes m = (1,0,0) and (0,2,1): diagonal, nearest and
+    far entries, interior and next to the boundary."""
+    p, n = 3, 5
+    a = np.array([0.9, -0.6])
+    mk = np.array([[1, 0, 0], [0, 2, 1]], np.int32)
+    md = n + p - 2
+    rp, ci, v, _ = oracle.diffusion_quad3d(p, n, a, mk, factorized=True)
+    K = _csr(rp, ci, v)
+    idx = lambda c: c[0] + md * (c[1] + md * c[2])
+    pairs = [((2, 3, 1), (2, 3, 1)), ((0, 0, 0), (0, 0, 0)), ((2, 3, 1), (3, 3, 1)), ((2, 3, 1), (2, 4, 1)),
+             ((2, 3, 1), (2, 3, 2)), ((1, 2, 4), (4, 4, 5)), ((5, 0, 3), (3, 2, 0)), ((3, 3, 3), (0, 1, 2)),
+             ((4, 1, 2), (4, 1, 2)), ((0, 5, 5), (1, 4, 5))]
+    for g, h in pairs:
+        ref = _entry_by_quadrature(p, n, a, mk, g, h)
+        got = K[idx(g), idx(h)]
+        assert abs(got - ref) <= 1e-13 * max(abs(ref), 1e-3), (g, h, got, ref)
+
+
+@pytest.mark.parametrize("p,n,seed", [(2, 4, 0), (3, 3, 5), (2, 3, 9)])
+def test_sum_factorized_equals_element_loop(oracle, p, n, seed):
+    """The sum-factorized assembly equals the plain element loop up to the
+    rounding of the reordered sums, for seeded kappa."""
+    from paper_2511_21268_amd.workloads import kappa_params
+    a, mk = kappa_params(seed)
+    r1, c1, v1, F1 = oracle.diffusion_quad3d(p, n, a, mk)
+    r2, c2, v2, F2 = oracle.diffusion_quad3d(p, n, a, mk, factorized=True)
+    assert np.array_equal(r1, r2) and np.array_equal(c1, c2)
+    assert np.abs(v1 - v2).max() <= 1e-13 * np.abs(v1).max()
+    assert np.abs(F1 - F2).max() <= 1e-15 * np.abs(F1).max()

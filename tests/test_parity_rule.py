@@ -1,24 +1,36 @@
 """The rule the GPU parity tests use to compare FP64 iteration counts with the
-oracle's (equal, or one apart only where the oracle's stop was marginal)."""
+oracle's: equal, or one apart only where the oracle's stopping residual lies
+within 1e-6 (relative) of the tolerance, reported as a MarginalStop warning."""
 import numpy as np
+import pytest
+
+from conftest import MarginalStop, stop_margin
 
 
 def test_iteration_rule(iters_match):
-    hist = np.array([1.0, 1e-3, 1e-6, 1.00001e-8, 0.5e-8])
+    hist = np.array([1.0, 1e-3, 1e-6, 1.0000001e-8, 0.5e-8])
     ref = {"iters": 4, "hist": hist}
     assert iters_match(4, ref, 1e-8)
     assert not iters_match(2, ref, 1e-8) and not iters_match(6, ref, 1e-8)
-    assert iters_match(3, ref, 1e-8)            # oracle's relres at 3 is 1e-8 (1 + 1e-5)
+    with pytest.warns(MarginalStop, match="oracle 4, gpu 3"):
+        assert iters_match(3, ref, 1e-8)        # oracle's relres at 3 is 1e-8 (1 + 1e-7)
     assert not iters_match(5, ref, 1e-8)        # oracle's relres at 4 is 0.5e-8: not marginal
-    ref2 = {"iters": 3, "hist": np.array([1.0, 1e-4, 3e-8, 0.99999e-8])}
-    assert iters_match(4, ref2, 1e-8)           # gpu stopped one later at a marginal crossing
+    ref2 = {"iters": 3, "hist": np.array([1.0, 1e-4, 3e-8, 0.9999999e-8])}
+    with pytest.warns(MarginalStop):
+        assert iters_match(4, ref2, 1e-8)       # gpu stopped one later at a marginal crossing
     assert not iters_match(2, ref2, 1e-8)       # relres 3e-8 at 2 is far from tol
 
 
-def test_long_run_rule(iters_match):
+def test_margin_is_one_in_a_million(iters_match):
+    """A crossing 1e-5 away from tol is not marginal (the earlier rule's 1%
+    window accepted it)."""
+    ref = {"iters": 4, "hist": np.array([1.0, 1e-3, 1e-6, 1.00001e-8, 0.5e-8])}
+    assert not iters_match(3, ref, 1e-8)
+    assert stop_margin(ref, 1e-8) == pytest.approx(1e-5, rel=1e-6)
+
+
+def test_no_long_run_allowance(iters_match):
     hist = np.linspace(1.0, 0.5e-8, 464)
     ref = {"iters": 463, "hist": hist}
-    assert iters_match(465, ref, 1e-8) and iters_match(458, ref, 1e-8)
-    assert not iters_match(469, ref, 1e-8)
-    short = {"iters": 100, "hist": np.linspace(1.0, 0.5e-8, 101)}
-    assert not iters_match(102, short, 1e-8)
+    assert not iters_match(465, ref, 1e-8) and not iters_match(458, ref, 1e-8)
+    assert not iters_match(464, ref, 1e-8)
