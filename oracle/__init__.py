@@ -83,6 +83,7 @@ def lib():
         L.or_free.argtypes = [C.c_void_p]
         L.or_set_verbose.argtypes = [C.c_int]
         L.or_set_threads.argtypes = [C.c_int]
+        L.or_set_dot_order.argtypes = [C.c_int]
         L.or_nlevels.argtypes = [C.c_void_p]
         L.or_level_info.argtypes = [C.c_void_p, C.c_int, i64p, i64p]
         L.or_level_matrix.argtypes = [C.c_void_p, C.c_int, i64p, i32p, f64p]
@@ -474,3 +475,18 @@ def bootstrap_w(rp, ci, v, w0, sweeps):
 def set_threads(n):
     """Threads of the oracle's row-parallel SpMV (bitwise the same results)."""
     lib().or_set_threads(int(n))
+
+
+class descending_dots:
+    """Context in which the oracle sums its dot products in descending index
+    order (a second rounding order of the same algorithm; the default is
+    ascending): the spread between the two orders is the size of the
+    differences that rounding order alone makes in a given solve."""
+
+    def __enter__(self):
+        lib().or_set_dot_order(1)
+        return self
+
+    def __exit__(self, *exc):
+        lib().or_set_dot_order(0)
+        return False

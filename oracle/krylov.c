@@ -46,7 +46,11 @@
  *  - stop when ||r_k||_2 <= tol ||F||_2 on the recursive residual; iters counts
  *    the completed updates of u; F = 0 returns u = 0 after 0 iterations;
  *  - SpMV row sums and dots are sequential in ascending index order (the SpMV
- *    is parallel over rows only, so any thread count gives the same bits).
+ *    is parallel over rows only, so any thread count gives the same bits);
+ *    or_set_dot_order(1) sums the dots in descending index order instead: a
+ *    second, equally plain rounding order of the same algorithm (the paper
+ *    fixes none), used by the tests to measure how far rounding order alone
+ *    moves the iterates of a given system.
  *
  * Parity unpinned: iteration counts of the benchmark configurations (the paper
  * prints counts only for its own preconditioner, tolerance and boundary data).
@@ -79,10 +83,16 @@ void or_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
     }
 }
 
+static int dot_descending = 0;
+void or_set_dot_order(int descending) { dot_descending = descending ? 1 : 0; }
+
 double or_dot(int64_t n, const double *x, const double *y)
 {
     double s = 0.0;
-    for (int64_t i = 0; i < n; i++) s = s + x[i] * y[i];
+    if (dot_descending)
+        for (int64_t i = n - 1; i >= 0; i--) s = s + x[i] * y[i];
+    else
+        for (int64_t i = 0; i < n; i++) s = s + x[i] * y[i];
     return s;
 }
 

@@ -168,6 +168,8 @@ void or_level_prolongator(const or_hier *h, int l, int64_t *rp, int32_t *ci, dou
 void or_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
              const double *x, double *y);
 double or_dot(int64_t n, const double *x, const double *y);
+/* 0 (default): dots summed in ascending index order; 1: descending */
+void or_set_dot_order(int descending);
 /* z = B r, one V-cycle from level l with zero initial guess. */
 void or_vcycle(const or_hier *h, int l, const double *r, double *z);
 /* Preconditioned CG (flexible = 0) or FCG(1) (flexible = 1) on level 0.

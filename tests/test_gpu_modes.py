@@ -26,8 +26,10 @@ def amg():
 def test_fcg_fp64_parity(oracle, amg, iters_match, oracle_iterate, fixed_count_parity, d, p, n):
     """FCG(1) with the FP64 V-cycle: same iterations and iterates as the
     oracle's flexible CG.  A run of LONG_RUN iterations or more (3D p = 4
-    n = 12: ~463) is compared at fixed counts instead of through its stop."""
-    from conftest import LONG_RUN
+    n = 12: ~463) is compared at fixed counts instead of through its stop;
+    the iterates to 1e-10, or within the oracle's own rounding-order spread
+    where a long run has amplified rounding beyond that (within_rounding)."""
+    from conftest import LONG_RUN, order_spread, within_rounding
     print(f"case fcg64 d={d} p={p} n={n}", flush=True)
     from paper_2511_21268_amd.workloads import rhs_normal
     rp, ci, v, _ = oracle.poisson_kron(d, p, n)
@@ -40,15 +42,16 @@ def test_fcg_fp64_parity(oracle, amg, iters_match, oracle_iterate, fixed_count_p
     print(f"  {out['iters']} iterations (oracle {ref['iters']}), true relres {out['relres_true']:.2e}", flush=True)
     assert out["status"] == 0 and out["relres_true"] <= 1e-8 * 1.0001
     if ref["iters"] >= LONG_RUN:
-        for k, err in fixed_count_parity(h, lambda k: amg.Context(rp, ci, v, krylov=1, itmax=k), F,
-                                         (100, 200, ref["iters"]), flexible=True):
-            assert err <= 1e-10, (k, err)
+        for k, err, spread in fixed_count_parity(h, lambda k: amg.Context(rp, ci, v, krylov=1, itmax=k), F,
+                                                 (100, 200, ref["iters"]), flexible=True):
+            assert within_rounding(err, spread), (k, err, spread)
         return
     assert iters_match(out["iters"], ref, 1e-8)
     uo = oracle_iterate(h, F, ref, out["iters"], flexible=True)
     err = np.linalg.norm(u - uo) / np.linalg.norm(uo)
-    print(f"  rel. error against the oracle iterate {err:.2e}", flush=True)
-    assert err <= 1e-10
+    spread = order_spread(h, F, out["iters"], flexible=True, u_asc=uo)
+    print(f"  rel. error against the oracle iterate {err:.2e}, oracle order spread {spread:.2e}", flush=True)
+    assert within_rounding(err, spread), (err, spread)
 
 
 @pytest.mark.parametrize("d,p,n", [(2, 2, 32), (3, 3, 16), (3, 4, 12), (3, 4, 20)])

@@ -34,3 +34,43 @@ def test_no_long_run_allowance(iters_match):
     ref = {"iters": 463, "hist": hist}
     assert not iters_match(465, ref, 1e-8) and not iters_match(458, ref, 1e-8)
     assert not iters_match(464, ref, 1e-8)
+
+
+def test_rounding_bar():
+    """Iterates of long runs: 1e-10, or ORDER_FACTOR times the oracle's own
+    ascending-versus-descending spread, whichever is larger."""
+    from conftest import ORDER_FACTOR, within_rounding
+    assert within_rounding(9e-11, 1e-14) and not within_rounding(2e-10, 1e-14)
+    assert within_rounding(ORDER_FACTOR * 1e-7, 1e-7)
+    assert not within_rounding(1.01 * ORDER_FACTOR * 1e-7, 1e-7)
+
+
+def test_descending_dot_order(oracle):
+    """The oracle's second dot order: the descending sum equals the ascending
+    sum of the reversed vectors bit for bit, both lie within the sequential
+    summation bound of the exactly rounded value, and the context restores the
+    default order."""
+    import math
+    rng = np.random.default_rng(11)
+    x, y = rng.standard_normal(10001), rng.standard_normal(10001)
+    asc = oracle.dot(x, y)
+    with oracle.descending_dots():
+        desc = oracle.dot(x, y)
+    assert desc == oracle.dot(x[::-1].copy(), y[::-1].copy())
+    assert oracle.dot(x, y) == asc
+    exact = math.fsum(float(a) * float(b) for a, b in zip(x, y))   # products rounded once, as in both sums
+    bound = len(x) * np.finfo(float).eps * float(np.abs(x) @ np.abs(y))
+    assert abs(asc - exact) <= bound and abs(desc - exact) <= bound
+    assert asc != desc   # the two orders round differently for this draw
+
+
+def test_order_spread_is_rounding_sized(oracle):
+    """On a short all-Dirichlet solve the two dot orders move the iterate only
+    at rounding level."""
+    from conftest import order_spread
+    from paper_2511_21268_amd.workloads import rhs_normal
+    rp, ci, v, _ = oracle.poisson_kron(2, 2, 16)
+    F = rhs_normal(len(rp) - 1, 1)
+    h = oracle.Hierarchy(rp, ci, v)
+    s = order_spread(h, F, 8)
+    assert 0.0 < s < 1e-13
