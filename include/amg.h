@@ -357,6 +357,20 @@ amg_status amg_mlp_forward(const uint16_t *w, const float *X, int B, float *Y, f
 amg_status amg_mlp_backward(const uint16_t *w, const float *X, const float *act, const float *Y, const float *T,
                             int B, float *del, float *grad, float *loss, void *hip_stream);
 
+/* amg_mlp_backward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc): the per-sample deltas live in a static device array of the
+ * library, AMG_MLP_NOALLOC_MAX_B * AMG_MLP_NDEL floats (8.7 MB) per device,
+ * held until the process ends, so no workspace argument and no allocation of
+ * any kind.  Arguments, results and bits as amg_mlp_backward; B above
+ * AMG_MLP_NOALLOC_MAX_B returns AMG_ERR_ARG.  The array is shared by every
+ * call on a device: calls that overlap on one GPU (other streams, other
+ * threads) race on it and must be serialized by the caller; a call leaves its
+ * deltas there, and the next call overwrites what it reads before reading it. */
+#define AMG_MLP_NOALLOC_MAX_B 16384
+amg_status amg_mlp_backward_noalloc(const uint16_t *w, const float *X, const float *act, const float *Y,
+                                    const float *T, int B, float *grad, float *loss, void *hip_stream);
+
 /* One Adam step (b1 = 0.9, b2 = 0.999, eps = 1e-8) on the FP32 master weights
  * with bias correction for step >= 1, then w = BF16(master) (round to nearest
  * even).  step = 0 only rounds master into w. */

@@ -24,9 +24,11 @@ EXPORTS = ["amg_params_default", "amg_setup", "pcg_solve", "pcg_solve_batched", 
            "amg_iga_poisson_size", "amg_iga_poisson", "amg_iga_diffusion", "amg_level_features",
            "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_adam", "amg_set_learned_poly",
            "amg_get_batched_variant", "amg_set_batched_variant", "amg_set_option", "amg_sell_spmv_host",
-           "amg_iga_cube_size", "amg_iga_cube", "amg_get_prolongator", "amg_get_setup_rounds"]
+           "amg_iga_cube_size", "amg_iga_cube", "amg_get_prolongator", "amg_get_setup_rounds",
+           "amg_mlp_backward_noalloc"]
 AMG_OPT_GRAPH, AMG_OPT_FUSE_POST = 1, 2
 MLP_NPARAM, MLP_NFEAT, MLP_NACT, MLP_NDEL = 4996, 8, 128, 132
+MLP_NOALLOC_MAX_B = 16384
 
 
 class AmgError(RuntimeError):
@@ -98,6 +100,7 @@ def lib():
         L.amg_level_features.argtypes = [vp, C.c_int, C.POINTER(C.c_float)]
         L.amg_mlp_forward.argtypes = [vp, vp, C.c_int, vp, vp, vp]
         L.amg_mlp_backward.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp, vp]
+        L.amg_mlp_backward_noalloc.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp]
         L.amg_mlp_adam.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_float, vp]
         L.amg_set_option.argtypes = [vp, C.c_int, C.c_int]
         L.amg_sell_spmv_host.argtypes = [C.c_int64, C.c_int64, i64p, i32p, f64p, C.c_int, C.c_int, f64p, f64p,

@@ -2221,6 +2221,64 @@ amg_status amg_mlp_backward(const uint16_t *w, const float *X, const float *act,
     return AMG_OK;
 }
 
+// ---- the MLP gradient without allocation ----------------------------------
+//
+// Per-sample deltas of the backward pass in a file-scope device array instead
+// of a caller workspace, for callers that cannot allocate device memory.  Each
+// device holds its own copy of the array (until the process ends); host code
+// reaches it only through the address hipGetSymbolAddress returns on that
+// device, looked up once per device on the first call there.
+constexpr int MLP_NOALLOC_MAX_B = AMG_MLP_NOALLOC_MAX_B;
+static __device__ __align__(256) float scratch[(size_t)MLP_NOALLOC_MAX_B * MLP_DEL];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mx;
+float *scratch_ptr[MAX_DEVICES] = {};
+
+// device address of this device's scratch array (nullptr and a message on error)
+float *scratch_on_current_device()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+        set_err("no current HIP device (or device index >= 64)");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> g(scratch_mx);
+    if (!scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_err(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return nullptr;
+        }
+        scratch_ptr[dev] = static_cast<float *>(ptr);
+    }
+    return scratch_ptr[dev];
+}
+}  // namespace
+
+amg_status amg_mlp_backward_noalloc(const uint16_t *w, const float *X, const float *act, const float *Y,
+                                    const float *T, int B, float *grad, float *loss, void *hip_stream)
+{
+    g_err.clear();
+    if (!w || !X || !act || !Y || !T || !grad || B < 1) { set_err("NULL argument or B < 1"); return AMG_ERR_ARG; }
+    if (B > MLP_NOALLOC_MAX_B) {
+        set_err("B = " + std::to_string(B) + " exceeds the static workspace of " + std::to_string(MLP_NOALLOC_MAX_B) +
+                " samples (use amg_mlp_backward with a workspace)");
+        return AMG_ERR_ARG;
+    }
+    float *del = scratch_on_current_device();
+    if (!del) return AMG_ERR_HIP;
+    hipStream_t st = (hipStream_t)hip_stream;
+    // k_mlp_delta writes every delta of samples 0..B-1 before k_mlp_grad reads
+    // them (stream order), so nothing left by an earlier call is read
+    hipLaunchKernelGGL(k_mlp_delta, dim3((B + 63) / 64), dim3(64), 0, st, w, act, Y, T, B, del);
+    hipLaunchKernelGGL(k_mlp_grad, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, st, X, act, del, Y, T, B, grad, loss);
+    if (hipGetLastError() != hipSuccess) { set_err("launch failed"); return AMG_ERR_HIP; }
+    return AMG_OK;
+}
+
 amg_status amg_mlp_adam(float *master, uint16_t *w, const float *grad, float *m, float *v, int step, float lr,
                         void *hip_stream)
 {
