@@ -178,12 +178,14 @@ amg_status amg_vcycle(amg_ctx *c, const double *r, double *z);
 amg_status amg_spmv(amg_ctx *c, int level, const double *x, double *y);
 
 /*
- * Variant of the block kernels used by pcg_solve_batched: lpr lanes per matrix
- * row (1: the single-vector SELL-64 image, one lane per row and 16 columns per
- * lane; 4, 8 or 16: the SELL-(64/lpr) block image, 16/lpr columns per lane)
- * and threads per block (256 or 512).  amg_setup with prm.nrhs > 1 sets the
+ * Variant of the block kernels used by pcg_solve_batched on the images without
+ * staged windows (coarse levels, the K P images of the fused post-smoothing,
+ * and every image when AMG_OPT_BLOCK_WINDOW is 0): lpr lanes per matrix row
+ * (1: the single-vector SELL-64 image, one lane per row and 16 columns per
+ * lane; 4, 8 or 16: SELL-(64/lpr) block images, 16/lpr columns per lane) and
+ * threads per block (256 or 512).  amg_setup with prm.nrhs > 1 sets the
  * fastest by timing; amg_set_batched_variant overrides it (lpr 4/8/16 only when
- * that image was built, i.e. the autotuner's choice).
+ * those images were built, i.e. the autotuner's choice).
  */
 amg_status amg_get_batched_variant(const amg_ctx *c, int *lpr, int *threads);
 amg_status amg_set_batched_variant(amg_ctx *c, int lpr, int threads);
@@ -244,7 +246,9 @@ amg_status amg_match(int64_t n, const int64_t *row_ptr, const int32_t *col, cons
  * image (C in {4, 8, 16, 32, 64}) of the n x ncols CSR matrix K the way the
  * library does -- layout 0: row order and per-entry indices; 1: shared column
  * offsets where they fit (square matrices only); 2: rows sorted by length
- * within windows of 4 slices -- and computes y = K x (host arrays, x of length
+ * within windows of 4 slices; 3: as 1, with the shared-offset slices walked
+ * the way the block kernels stage x windows (runs of consecutive offsets, the
+ * rows each run reads copied once; C = 64 only) -- and computes y = K x (host arrays, x of length
  * ncols, y of length n) by walking that image as the matrix-pass kernels do:
  * groups of 8 entries, columns rebuilt from shared offsets (clamped where the
  * slice needs it), 16-bit deltas or int32 columns, the slot -> row map.  Every
@@ -272,9 +276,19 @@ const char *amg_last_error(void);
  *   the first post-smoothing sweep, using f - K (u + P e) = r - (K P) e with the
  *   residual r of the pre-smoothed iterate and a stored K P (about 40% of K's
  *   entries): one full matrix pass per level becomes a K P pass.  Equal to the
- *   unfused V-cycle up to rounding. */
-typedef enum { AMG_OPT_GRAPH = 1, AMG_OPT_FUSE_POST = 2 } amg_option;
+ *   unfused V-cycle up to rounding.
+ * AMG_OPT_BLOCK_WINDOW (default 4; autotuned between 2 and 4 by amg_setup
+ *   with prm.nrhs > 1): the block kernels of pcg_solve_batched on a matrix
+ *   image whose slices share column offsets (stencil matrices) copy, for each
+ *   run of consecutive offsets of a slice, the rows of X the run reads into an
+ *   LDS window once instead of gathering a 16-column row of X per entry, with
+ *   `value` rows (and 16 / value columns) per lane; 0 turns this off (those
+ *   images then take the lanes-per-row variant of amg_set_batched_variant).
+ *   Bitwise the same results in every setting.
+ * amg_get_option returns the current value of an option. */
+typedef enum { AMG_OPT_GRAPH = 1, AMG_OPT_FUSE_POST = 2, AMG_OPT_BLOCK_WINDOW = 3 } amg_option;
 amg_status amg_set_option(amg_ctx *c, int option, int value);
+amg_status amg_get_option(const amg_ctx *c, int option, int *value);
 
 /* ------------------------------------------------------------------------
  * Measurement.  While enabled, every launch of the level-0 sparse

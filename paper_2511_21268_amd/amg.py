@@ -25,8 +25,8 @@ EXPORTS = ["amg_params_default", "amg_setup", "pcg_solve", "pcg_solve_batched", 
            "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_adam", "amg_set_learned_poly",
            "amg_get_batched_variant", "amg_set_batched_variant", "amg_set_option", "amg_sell_spmv_host",
            "amg_iga_cube_size", "amg_iga_cube", "amg_get_prolongator", "amg_get_setup_rounds",
-           "amg_mlp_backward_noalloc"]
-AMG_OPT_GRAPH, AMG_OPT_FUSE_POST = 1, 2
+           "amg_mlp_backward_noalloc", "amg_get_option"]
+AMG_OPT_GRAPH, AMG_OPT_FUSE_POST, AMG_OPT_BLOCK_WINDOW = 1, 2, 3
 MLP_NPARAM, MLP_NFEAT, MLP_NACT, MLP_NDEL = 4996, 8, 128, 132
 MLP_NOALLOC_MAX_B = 16384
 
@@ -103,6 +103,7 @@ def lib():
         L.amg_mlp_backward_noalloc.argtypes = [vp, vp, vp, vp, vp, C.c_int, vp, vp, vp]
         L.amg_mlp_adam.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_float, vp]
         L.amg_set_option.argtypes = [vp, C.c_int, C.c_int]
+        L.amg_get_option.argtypes = [vp, C.c_int, C.POINTER(C.c_int)]
         L.amg_sell_spmv_host.argtypes = [C.c_int64, C.c_int64, i64p, i32p, f64p, C.c_int, C.c_int, f64p, f64p,
                                          i64p, i64p]
         L.amg_get_batched_variant.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
@@ -287,6 +288,15 @@ class Context:
 
     def set_fused_post(self, on):
         _check(lib().amg_set_option(self.h, AMG_OPT_FUSE_POST, int(on)))
+
+    def set_block_window(self, rows):
+        """0: no staged x windows; 2 or 4: windows with that many rows per lane."""
+        _check(lib().amg_set_option(self.h, AMG_OPT_BLOCK_WINDOW, int(rows)))
+
+    def option(self, opt):
+        v = C.c_int()
+        _check(lib().amg_get_option(self.h, opt, C.byref(v)))
+        return v.value
 
     def batched_variant(self):
         lpr = C.c_int(); thr = C.c_int()

@@ -42,6 +42,7 @@ typedef unsigned vu4 __attribute__((ext_vector_type(4)));
 typedef int vi4 __attribute__((ext_vector_type(4)));
 
 constexpr int SLICE = 64;
+constexpr int WIN_LMAX = 8;            // longest offset run one staged x window covers
 constexpr int SELL_WAVES = 4;          // slices (wavefronts) per 256-thread block
 constexpr int RED_THREADS = 256;
 
@@ -149,6 +150,10 @@ template <typename VT, typename IT> struct Sell {
     const int32_t *perm;    // row of each slot (slices sorted by row length), -1 past
                             // the last row; nullptr: slot s * C + r holds row s * C + r
                             // (always so for shared-offset slices)
+    const int32_t *shrun;   // parallel to shoff: from each list's position, its runs
+                            // of consecutive offsets (at most WIN_LMAX long) in
+                            // order, packed as first offset * 16 + length, then 0
+                            // (0 first: no run table for that list)
 
     // row held by slot q, or -1
     __device__ __forceinline__ int64_t row_of(int64_t q) const

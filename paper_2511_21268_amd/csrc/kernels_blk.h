@@ -141,6 +141,317 @@ __global__ __launch_bounds__(256) void k_sell_blk(const Sell<VT, IT> A, const VT
     }
 }
 
+// ---- block matrix pass with staged x windows --------------------------------
+//
+// In a slice with shared column offsets, a run of consecutive offsets o, o+1,
+// ..., o+L-1 (for a stencil matrix: the 2p+1 entries of one x-line, the same
+// (y, z) displacement) makes lane r read rows row0 + r + o + t, t < L, of X:
+// the 64 lanes together touch only the 64 + L - 1 consecutive rows
+// row0 + o .. row0 + o + 62 + L.  The wave copies those rows (16 columns each)
+// into its own LDS window once per run, with coalesced loads, and every lane
+// then reads its L rows from LDS; without the window each entry of each row
+// gathers a full 16-column row of X from the cache hierarchy (64 B in FP32,
+// 128 B in FP64), the traffic that bounds the one-lane-per-row kernel.
+//
+// The window is held chunk-major: 16-byte chunk c (G consecutive columns) of
+// window row w at W[c * WIN_STRIDE + w].  Lanes load the rows row-major (lane
+// q takes chunk q % CH of row q / CH, so a wave's load is contiguous memory)
+// and the odd stride spreads the chunks a group of lanes writes over distinct
+// banks.
+//
+// Each row's entries are summed in ascending column order (the padding
+// entries of a shared list, value 0, are skipped: an FMA with a zero product
+// leaves a nonzero or +0 sum unchanged), so each column carries the
+// single-vector kernels' bits.  Slices with per-row indices take k_sell_blk's
+// gather path.  The window is private to its wave: only that wave's own LDS
+// operations order its accesses (in-order per wave), fenced for the compiler
+// by wave_lds_sync.
+constexpr int WIN_STRIDE = 73;   // window rows per chunk column (>= SLICE + WIN_LMAX - 1, odd)
+constexpr int XCDS = 8;          // accelerator complex dies sharing the grid (one L2 each)
+
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename VT> struct Chunk16;
+template <> struct Chunk16<double> {
+    typedef vd2 type;
+    static __device__ inline void unpack(type q, double *o) { o[0] = q.x; o[1] = q.y; }
+};
+template <> struct Chunk16<float> {
+    typedef vf4 type;
+    static __device__ inline void unpack(type q, float *o) { o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w; }
+};
+
+// Register blocking: with R > 1 a lane owns R consecutive rows and 16 / R
+// columns (lane = g * R + q: rows R g .. R g + R - 1; 16-byte chunks q, q + R,
+// q + 2R, ... of each row), so a window row read from LDS serves the lane's
+// rows at every offset that reaches it: R + L - 1 window rows per lane and run
+// instead of R L, at the price of R matrix values per entry (each read by the
+// R lanes of a row group).  The chunk assignment and the odd window stride
+// keep each 16-lane phase of a window read on 16 distinct bank groups.  Per
+// column the row sums keep ascending entry order and the dots keep the
+// single-vector kernels' butterfly order (the row bits above log2 R are lane
+// bits, the ones below are summed in registers, in the same order).
+template <typename VT, typename FT, typename OT, typename IT, int EPI, int NDOT, int R>
+__global__ __launch_bounds__(256) void k_sellw_blk(const Sell<VT, IT> A, const VT *__restrict__ X,
+                                                   const FT *__restrict__ F, const VT *__restrict__ invd,
+                                                   OT *__restrict__ Y, const double *__restrict__ G0,
+                                                   const double *__restrict__ G1, double *__restrict__ partial,
+                                                   VT coef)
+{
+    typedef typename Chunk16<VT>::type CT;
+    constexpr int G = 16 / (int)sizeof(VT);           // values per 16-byte chunk (= SELL group)
+    constexpr int CH = NB / G;                        // chunks per row of X
+    constexpr int CPL = NB / R;                       // columns per lane
+    constexpr int CPC = CH / R;                       // chunks per lane
+    static_assert(CH % R == 0 && (R & (R - 1)) == 0, "R must be a power of two dividing the chunks per row");
+    constexpr int WN = CH * WIN_STRIDE;               // chunks per window
+    constexpr int NLD = (CH * (SLICE + WIN_LMAX - 1) + 63) / 64;   // staging loads per lane
+    __shared__ CT win[SELL_WAVES * WN];
+    const int lane = threadIdx.x & 63, wid = wave_id();
+    // XCD-aware order: the hardware deals blocks to the XCDs round-robin, so
+    // block b runs on XCD b % XCDS; it takes logical block (b % XCDS) * per +
+    // b / XCDS, giving every XCD one contiguous range of slices, whose windows
+    // overlap (x-lines and planes of the stencil) in that XCD's own L2.  Dot
+    // partials stay indexed by logical slice.
+    const int64_t nlb = (A.nslices + SELL_WAVES - 1) / SELL_WAVES, per = (nlb + XCDS - 1) / XCDS;
+    const int64_t lb = (int64_t)(blockIdx.x % XCDS) * per + blockIdx.x / XCDS;
+    if (lb >= nlb) return;   // padding block of the last XCD's range
+    const int64_t s = lb * SELL_WAVES + wid;
+    const int64_t w_id = s;
+    const int64_t ib = s < A.nslices ? A.ibase[s] : 0;
+    // the slice's runs, 64 per vector register (packed: offset << 4 | length;
+    // a list without a run table has 0 first and takes the gather path)
+    const int32_t *rt = A.shrun + (ib < 0 ? (-1 - ib) >> 1 : 0);
+    const int64_t base = s < A.nslices ? A.soff[s] : 0;
+    const int width = s < A.nslices ? (int)((A.soff[s + 1] - base) / SLICE) : 0;
+    int32_t runs = (ib < 0 && lane < width) ? rt[lane] : 0;
+    if (ib < 0 && __builtin_amdgcn_readfirstlane(runs) != 0) {
+        const int g = lane / R, q = lane % R;
+        VT acc[R][CPL];
+#pragma unroll
+        for (int i = 0; i < R; i++)
+#pragma unroll
+            for (int j = 0; j < CPL; j++) acc[i][j] = 0;
+        const int64_t row0 = s * SLICE;
+        const int hi = (int)(A.ncols - 1);   // rows below 2^29 (checked at set-up)
+        CT *W = win + wid * WN;
+        const CT *Xc = reinterpret_cast<const CT *>(X);
+        // software pipeline over the runs: while run rho is summed from the
+        // LDS window, the window rows and value groups of run rho + 1 are in
+        // flight into registers (st, gv), so memory latency overlaps the
+        // arithmetic
+        // values: the 16-byte groups (G entries of one row) that hold entries
+        // kr .. kr + WIN_LMAX - 1, loaded whole, so each group of the stream
+        // is fetched by one instruction; the run's values start at entry kr % G
+        // of the first group
+        constexpr int NGR = (WIN_LMAX + G - 1) / G + 1;
+        CT st[NLD], gv[NGR][R];
+        VT vc[WIN_LMAX][R];
+        int off = 0;
+        auto issue = [&](int32_t pk, int kr) {
+            // window rows g0 .. g0 + 62 + L, every load issued before any LDS
+            // write; rows past the window and outside [0, hi] are clamped
+            // (loaded but never read)
+            const int g0 = (int)row0 + (pk >> 4);
+#pragma unroll
+            for (int i = 0; i < NLD; i++) {
+                const int qq = i * 64 + lane, w = qq / CH, c = qq % CH;
+                const int gr = min(max(g0 + w, 0), hi);
+                st[i] = Xc[(int64_t)gr * CH + c];
+            }
+            // groups of the lane's rows R g + i (groups past the slice clamped
+            // to its last one, unused)
+            const int gmax = (width - 1) / G;
+            off = kr % G;
+#pragma unroll
+            for (int j = 0; j < NGR; j++) {
+                const int gi = min(kr / G + j, gmax);
+#pragma unroll
+                for (int i = 0; i < R; i++)
+                    gv[j][i] = *reinterpret_cast<const CT *>(A.val + base + (int64_t)gi * (G * SLICE) + (R * g + i) * G);
+            }
+        };
+        int k = 0, rho = 0;
+        int32_t pk = __builtin_amdgcn_readfirstlane(runs);
+        issue(pk, 0);
+        while (pk != 0) {
+            const int L = pk & 15;
+#pragma unroll
+            for (int i = 0; i < NLD; i++) {
+                const int qq = i * 64 + lane, w = qq / CH, c = qq % CH;
+                if (w < WIN_STRIDE) W[c * WIN_STRIDE + w] = st[i];
+            }
+            // this run's values from its groups (off is wave-uniform)
+#pragma unroll
+            for (int i = 0; i < R; i++) {
+                VT e[NGR * G];
+#pragma unroll
+                for (int j = 0; j < NGR; j++) Chunk16<VT>::unpack(gv[j][i], e + j * G);
+#pragma unroll
+                for (int oo = 0; oo < G; oo++)
+                    if (off == oo)
+#pragma unroll
+                        for (int t = 0; t < WIN_LMAX; t++) vc[t][i] = e[oo + t];
+            }
+            // next run: its table entry (a new register of 64 entries every 64 runs)
+            const int kn = k + L;
+            rho++;
+            if ((rho & 63) == 0) runs = (rho + lane < width) ? rt[rho + lane] : 0;
+            const int32_t pn = kn < width ? __builtin_amdgcn_readlane(runs, rho & 63) : 0;
+            wave_lds_sync();
+            if (pn != 0) issue(pn, kn);
+            // window row R g + w serves row R g + i at entry k + (w - i)
+#pragma unroll
+            for (int w = 0; w < R + WIN_LMAX - 1; w++) {
+                if (w < R + L - 1) {
+                    VT xv[CPL];
+#pragma unroll
+                    for (int cc = 0; cc < CPC; cc++)
+                        Chunk16<VT>::unpack(W[(q + cc * R) * WIN_STRIDE + R * g + w], xv + cc * G);
+#pragma unroll
+                    for (int i = 0; i < R; i++) {
+                        const int t = w - i;
+                        if (t >= 0 && t < WIN_LMAX && t < L)
+#pragma unroll
+                            for (int j = 0; j < CPL; j++) acc[i][j] = fma(vc[t][i], xv[j], acc[i][j]);
+                    }
+                }
+            }
+            wave_lds_sync();
+            k = kn;
+            pk = pn;
+        }
+        // epilogue: local column jj = cc * G + u is column (q + cc R) G + u
+        double d0[R][CPL], d1[R][CPL];
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+            const int64_t rr = row0 + R * g + i;
+            const bool live = rr < A.nrows;   // shared-offset slices are never sorted
+            const VT di = (live && (EPI == EPI_SMOOTH || EPI == EPI_POLY)) ? invd[rr] : (VT)0;
+#pragma unroll
+            for (int jj = 0; jj < CPL; jj++) {
+                d0[i][jj] = 0.0;
+                d1[i][jj] = 0.0;
+                if (!live) continue;
+                const int64_t o = rr * NB + (q + (jj / G) * R) * G + jj % G;
+                const VT a = acc[i][jj];
+                if (EPI == EPI_SPMV) {
+                    Y[o] = (OT)a;
+                    if (NDOT >= 1) d0[i][jj] = (double)X[o] * (double)a;
+                    if (NDOT >= 2) d1[i][jj] = (double)X[o] * G1[o];
+                } else if (EPI == EPI_RESID) {
+                    Y[o] = (OT)((VT)F[o] - a);
+                } else if (EPI == EPI_SMOOTH) {
+                    VT out = X[o] + di * ((VT)F[o] - a);
+                    Y[o] = (OT)out;
+                    if (NDOT >= 1) d0[i][jj] = (double)out * G0[o];
+                    if (NDOT >= 2) d1[i][jj] = (double)out * G1[o];
+                } else {
+                    Y[o] = (OT)(coef * (di * (VT)F[o]) + di * a);
+                }
+            }
+        }
+        if (NDOT >= 1) {
+            // the single-vector butterfly over the 64 rows: row bits >= log2 R
+            // across lanes (xor 32 .. R), then the bits below in registers
+#pragma unroll
+            for (int i = 0; i < R; i++)
+#pragma unroll
+                for (int jj = 0; jj < CPL; jj++)
+                    for (int o = 32; o >= R; o >>= 1) {
+                        d0[i][jj] += __shfl_xor(d0[i][jj], o, 64);
+                        if (NDOT >= 2) d1[i][jj] += __shfl_xor(d1[i][jj], o, 64);
+                    }
+#pragma unroll
+            for (int o = R / 2; o >= 1; o >>= 1) {
+                double t0[R][CPL], t1[R][CPL];
+#pragma unroll
+                for (int i = 0; i < R; i++)
+#pragma unroll
+                    for (int jj = 0; jj < CPL; jj++) {
+                        t0[i][jj] = d0[i][jj] + d0[i ^ o][jj];
+                        t1[i][jj] = d1[i][jj] + d1[i ^ o][jj];
+                    }
+#pragma unroll
+                for (int i = 0; i < R; i++)
+#pragma unroll
+                    for (int jj = 0; jj < CPL; jj++) { d0[i][jj] = t0[i][jj]; d1[i][jj] = t1[i][jj]; }
+            }
+            if (g == 0)
+#pragma unroll
+                for (int jj = 0; jj < CPL; jj++) {
+                    const int j = (q + (jj / G) * R) * G + jj % G;
+                    partial[(2 * w_id) * NB + j] = d0[0][jj];
+                    partial[(2 * w_id + 1) * NB + j] = NDOT >= 2 ? d1[0][jj] : 0.0;
+                }
+        }
+        return;
+    }
+    // slices with per-row indices (and the waves past the last slice): the
+    // gather path of k_sell_blk
+    double d0[NB], d1[NB];
+#pragma unroll
+    for (int j = 0; j < NB; j++) { d0[j] = 0.0; d1[j] = 0.0; }
+    if (s < A.nslices) {
+        const int64_t row = A.row_of(s * SLICE + lane);
+        VT acc[NB];
+#pragma unroll
+        for (int j = 0; j < NB; j++) acc[j] = 0;
+        sell_row<SLICE>(A, s, lane, [&](const VT *v, const int *c) {
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                VT xv[NB];
+                BlkVec<VT>::load(X + (int64_t)c[t] * NB, xv);
+#pragma unroll
+                for (int j = 0; j < NB; j++) acc[j] = fma(v[t], xv[j], acc[j]);
+            }
+        });
+        if (row >= 0) {
+            const int64_t o = row * NB;
+            if (EPI == EPI_SPMV) {
+#pragma unroll
+                for (int j = 0; j < NB; j++) {
+                    Y[o + j] = (OT)acc[j];
+                    if (NDOT >= 1) d0[j] = (double)X[o + j] * (double)acc[j];
+                    if (NDOT >= 2) d1[j] = (double)X[o + j] * G1[o + j];
+                }
+            } else if (EPI == EPI_RESID) {
+#pragma unroll
+                for (int j = 0; j < NB; j++) Y[o + j] = (OT)((VT)F[o + j] - acc[j]);
+            } else if (EPI == EPI_SMOOTH) {
+                const VT di = invd[row];
+#pragma unroll
+                for (int j = 0; j < NB; j++) {
+                    VT out = X[o + j] + di * ((VT)F[o + j] - acc[j]);
+                    Y[o + j] = (OT)out;
+                    if (NDOT >= 1) d0[j] = (double)out * G0[o + j];
+                    if (NDOT >= 2) d1[j] = (double)out * G1[o + j];
+                }
+            } else {
+                const VT di = invd[row];
+#pragma unroll
+                for (int j = 0; j < NB; j++) Y[o + j] = (OT)(coef * (di * (VT)F[o + j]) + di * acc[j]);
+            }
+        }
+    }
+    if (NDOT >= 1) {
+#pragma unroll
+        for (int j = 0; j < NB; j++) {
+            const double t0 = wave_sum(d0[j]);
+            const double t1 = NDOT >= 2 ? wave_sum(d1[j]) : 0.0;
+            if (lane == 0) {
+                partial[(2 * w_id) * NB + j] = t0;
+                partial[(2 * w_id + 1) * NB + j] = t1;
+            }
+        }
+    }
+}
+
 // Block matrix pass with LPR lanes per row: the wave covers a slice of
 // C = 64 / LPR rows of a SELL-C image (same group layout as SELL-64 with the
 // slice height C), lane = (row r = lane / LPR, quarter q = lane % LPR), each
@@ -575,10 +886,25 @@ __global__ __launch_bounds__(256) void k_bcg_pupdate(int64_t n, const double *__
         p[e] = fma(be, p[e], z[e]);
 }
 
+// First stage of k_bfinalize for many partials: the strided sums that its
+// thread t would form (partials t, t + FIN_THREADS, ... in ascending order),
+// one grid thread per (t, dot, column): strided[(d * NB + j) * FIN_THREADS + t].
+__global__ __launch_bounds__(256) void k_bfin_strided(const double *__restrict__ partial, int nblk,
+                                                      double *__restrict__ strided)
+{
+    const int idx = blockIdx.x * 256 + threadIdx.x;   // < 2 * NB * FIN_THREADS
+    const int j = idx % NB, d = (idx / NB) % 2, t = idx / (2 * NB);
+    double s = 0.0;
+    for (int b = t; b < nblk; b += FIN_THREADS) s += partial[(2 * b + d) * NB + j];
+    strided[(d * NB + j) * FIN_THREADS + t] = s;
+}
+
 // Final per-column sums of the partials (index order) and the scalar
 // recurrences, masks and iteration counters of the 16 independent solves.
+// With strided != nullptr the per-thread strided sums come from
+// k_bfin_strided (the same values).
 __global__ __launch_bounds__(FIN_THREADS) void k_bfinalize(const double *__restrict__ partial, int nblk, double *sc,
-                                                           int op, double tol)
+                                                           int op, double tol, const double *__restrict__ strided)
 {
     // per column the order of k_finalize: thread strides, butterfly, waves in order
     constexpr int NW = FIN_THREADS / 64;
@@ -587,9 +913,17 @@ __global__ __launch_bounds__(FIN_THREADS) void k_bfinalize(const double *__restr
     double s0[NB], s1[NB];
 #pragma unroll
     for (int j = 0; j < NB; j++) { s0[j] = 0.0; s1[j] = 0.0; }
-    for (int b = threadIdx.x; b < nblk; b += FIN_THREADS)
+    if (strided) {
 #pragma unroll
-        for (int j = 0; j < NB; j++) { s0[j] += partial[(2 * b) * NB + j]; s1[j] += partial[(2 * b + 1) * NB + j]; }
+        for (int j = 0; j < NB; j++) {
+            s0[j] = strided[j * FIN_THREADS + threadIdx.x];
+            s1[j] = strided[(NB + j) * FIN_THREADS + threadIdx.x];
+        }
+    } else {
+        for (int b = threadIdx.x; b < nblk; b += FIN_THREADS)
+#pragma unroll
+            for (int j = 0; j < NB; j++) { s0[j] += partial[(2 * b) * NB + j]; s1[j] += partial[(2 * b + 1) * NB + j]; }
+    }
 #pragma unroll
     for (int j = 0; j < NB; j++) { s0[j] = wave_sum(s0[j]); s1[j] = wave_sum(s1[j]); }
     if (lane == 0)

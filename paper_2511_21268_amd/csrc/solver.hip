@@ -79,7 +79,7 @@ struct SellHost {
     std::vector<double> v64;
     std::vector<float> v32;
     std::vector<uint16_t> d16;
-    std::vector<int32_t> c32, col0, shoff;
+    std::vector<int32_t> c32, col0, shoff, shrun;
 };
 
 // Ascending union of the column offsets (column - row) of the rows of slice s,
@@ -226,6 +226,24 @@ void build_sell(const CsrView &K, int C, bool want64, bool want32, bool shared, 
     }
     S.shoff.assign(sh, 0);
     for (const auto &kv : lists) std::copy(kv.first.begin(), kv.first.end(), S.shoff.begin() + kv.second);
+    // run table of each list for the block kernels' staged x windows: its
+    // runs of consecutive offsets (o, o+1, ...), at most WIN_LMAX long, in
+    // order from the list's position, packed as o * 16 + length, then 0; a
+    // list with an offset beyond +-2^27 gets no table (first entry 0)
+    S.shrun.assign(sh, 0);
+    for (const auto &kv : lists) {
+        const std::vector<int32_t> &u = kv.first;
+        bool fits = true;
+        for (int32_t o : u) fits = fits && o >= -(1 << 27) && o < (1 << 27);
+        if (!fits) continue;
+        int64_t rho = 0;
+        for (size_t k = 0; k < u.size();) {
+            size_t L = 1;
+            while (L < (size_t)WIN_LMAX && k + L < u.size() && u[k + L] == u[k] + (int32_t)L) L++;
+            S.shrun[kv.second + rho++] = u[k] * 16 + (int32_t)L;
+            k += L;
+        }
+    }
     amgiga::parallel_for(S.nslices, [&](int64_t sb, int64_t se) {
         for (int64_t s = sb; s < se; s++) {
             const int64_t base = S.soff[s];
@@ -267,7 +285,7 @@ struct DevMat {
     double index_bytes = 0.0;
     int idx16 = 1, C = SLICE, sorted = 0;
     int64_t *soff = nullptr, *ibase = nullptr;
-    int32_t *col0 = nullptr, *c32 = nullptr, *shoff = nullptr, *perm = nullptr;
+    int32_t *col0 = nullptr, *c32 = nullptr, *shoff = nullptr, *perm = nullptr, *shrun = nullptr;
     uint16_t *d16 = nullptr;
     double *v64 = nullptr;
     float *v32 = nullptr;
@@ -282,7 +300,7 @@ struct DevMat {
     template <typename IT> const IT *idx() const;
     template <typename VT, typename IT> Sell<VT, IT> sv() const
     {
-        return Sell<VT, IT>{n, ncols, nslices, soff, ibase, val<VT>(), idx<IT>(), col0, shoff, perm};
+        return Sell<VT, IT>{n, ncols, nslices, soff, ibase, val<VT>(), idx<IT>(), col0, shoff, perm, shrun};
     }
 };
 template <> const double *DevMat::val<double>() const { return v64; }
@@ -339,9 +357,11 @@ struct amg_ctx {
     int64_t partial_cap = 0;
     // batched solve (allocated on first use)
     double *bR = nullptr, *bZ = nullptr, *bP = nullptr, *bQ = nullptr, *bU = nullptr, *bF = nullptr;
-    double *bY = nullptr, *bsc = nullptr, *hbsc = nullptr, *bpartial = nullptr;
+    double *bY = nullptr, *bsc = nullptr, *hbsc = nullptr, *bpartial = nullptr, *bstrided = nullptr;
     double *bgram = nullptr, *bcoef = nullptr, *bgsave = nullptr;   // block CG: Gram partials, alpha / beta, G
     int blk_lpr = 1, blk_threads = 256;   // block-kernel variant (autotuned when prm.nrhs > 1)
+    int blk_win = 4;       // stencil images: staged-window block kernel with this many rows per lane (0: off)
+    int blk_img_lpr = 0;   // lanes per row the SELL-(64/lpr) block images were built for (0: none)
     // graph replay of the iteration body (single: [0]=CG [1]=FCG; batched likewise)
     int use_graph = 0;
     int fuse_post = 1;   // fused prolongation + post-smoothing through K P (when built)
@@ -435,7 +455,8 @@ struct amg_ctx {
     }
     void release(DevMat &M)
     {
-        release(M.soff); release(M.ibase); release(M.shoff); release(M.perm); release(M.col0); release(M.c32);
+        release(M.soff); release(M.ibase); release(M.shoff); release(M.shrun); release(M.perm); release(M.col0);
+        release(M.c32);
         release(M.d16);
         release(M.v64); release(M.v32);
         release(M.crp); release(M.cci); release(M.cv);
@@ -503,7 +524,10 @@ struct amg_ctx {
         A.nshared = S.nshared; A.index_bytes = S.index_bytes;
         A.soff = upload(S.soff);
         A.ibase = upload(S.ibase);
-        if (!S.shoff.empty()) A.shoff = upload(S.shoff);
+        if (!S.shoff.empty()) {
+            A.shoff = upload(S.shoff);
+            A.shrun = upload(S.shrun);
+        }
         if (S.sorted) A.perm = upload(S.perm);
         if (want64) A.v64 = upload(S.v64);
         if (want32) A.v32 = upload(S.v32);
@@ -512,20 +536,16 @@ struct amg_ctx {
         if (!S.c32.empty()) A.c32 = upload(S.c32);
         return A;
     }
-    // Time one batched iteration's level-0 passes (FP64 outer SpMV + two V-cycle
-    // passes in the V-cycle precision) for the current block variant.
-    template <typename VT> float time_blk_variant()
+    // Device time of body(), best of two after one warm-up run.
+    template <class Body> float time_passes(Body body)
     {
-        Level &L = lev[0];
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         float best = 1e30f;
         for (int rep = 0; rep < 3; rep++) {
             HIPCHK(hipEventRecord(e0, stream));
-            sell_blk<double, double, double, EPI_SPMV, 1>(0, bP, nullptr, nullptr, bQ, nullptr, nullptr);
-            sell_blk<VT, double, VT, EPI_RESID, 0>(0, (const VT *)L.bu, bR, L.invd<VT>(), (VT *)L.br, nullptr, nullptr);
-            sell_blk<VT, double, VT, EPI_RESID, 0>(0, (const VT *)L.bu, bR, L.invd<VT>(), (VT *)L.br, nullptr, nullptr);
+            body();
             HIPCHK(hipEventRecord(e1, stream));
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0.f;
@@ -536,62 +556,116 @@ struct amg_ctx {
         (void)hipEventDestroy(e1);
         return best;
     }
-    // Autotuner of the block kernels: builds the level-0 block image for 4, 8
-    // and 16 lanes per row, times each with 256 and 512 threads per block (and the
-    // one-lane-per-row kernel on the SELL-64 image), keeps the fastest, and
-    // builds the coarse levels' block images for the chosen slice height.
+    // The level-0 passes of one batched iteration: FP64 outer SpMV and two
+    // passes in the V-cycle precision.
+    template <typename VT> void level0_passes()
+    {
+        Level &L = lev[0];
+        sell_blk<double, double, double, EPI_SPMV, 1>(0, bP, nullptr, nullptr, bQ, nullptr, nullptr);
+        sell_blk<VT, double, VT, EPI_RESID, 0>(0, (const VT *)L.bu, bR, L.invd<VT>(), (VT *)L.br, nullptr, nullptr);
+        sell_blk<VT, double, VT, EPI_RESID, 0>(0, (const VT *)L.bu, bR, L.invd<VT>(), (VT *)L.br, nullptr, nullptr);
+    }
+    // The passes over images that take the lanes-per-row variant: the level-0
+    // K P pass, a level-1 residual pass and, without staged windows at level
+    // 0, the level-0 passes.
+    template <typename VT> void variant_passes(bool with_level0)
+    {
+        if (with_level0) level0_passes<VT>();
+        if (nlev > 1 && lev[0].KP.soff)
+            bpost_fused<VT, VT>(0, (const VT *)lev[1].bu, (const VT *)lev[0].bu, (VT *)lev[0].bu2, 0, nullptr, nullptr);
+        if (nlev > 2) {
+            Level &L = lev[1];
+            sell_blk<VT, VT, VT, EPI_RESID, 0>(1, (const VT *)L.bu, (const VT *)L.bf, L.invd<VT>(), (VT *)L.br,
+                                               nullptr, nullptr);
+        }
+    }
+    // Autotuner of the block kernels.  Stencil images (shared column offsets,
+    // in practice level 0) take the staged-window kernel: its rows per lane
+    // (2 or 4) are timed on the level-0 passes.  The other images -- coarse
+    // levels and the K P images of the fused post-smoothing -- take 1 lane per
+    // row on the SELL-64 images or 4, 8 or 16 on SELL-(64/lanes) images with
+    // 256 or 512 threads per block, timed on the level-0 K P pass and a
+    // level-1 pass; the fastest variant's images are then built for every level.
     void tune_blocks(const CsrView &K0)
     {
         blk_alloc();
         const bool f32 = fp32();
-        for (double *v : {bP, bR}) {
+        for (double *v : {bP, bR})
             hipLaunchKernelGGL((k_fill<double>), dim3(vgrid(n * NB)), dim3(256), 0, stream, n * NB, 1.0, v);
-        }
-        if (f32) hipLaunchKernelGGL((k_fill<float>), dim3(vgrid(n * NB)), dim3(256), 0, stream, n * NB, 1.0f, (float *)lev[0].bu);
-        else hipLaunchKernelGGL((k_fill<double>), dim3(vgrid(n * NB)), dim3(256), 0, stream, n * NB, 1.0, (double *)lev[0].bu);
+        for (int l = 0; l < std::min(nlev, 2); l++)
+            for (void *v : {lev[l].bu, lev[l].bf}) {
+                if (f32) hipLaunchKernelGGL((k_fill<float>), dim3(vgrid(lev[l].n * NB)), dim3(256), 0, stream,
+                                            lev[l].n * NB, 1.0f, (float *)v);
+                else hipLaunchKernelGGL((k_fill<double>), dim3(vgrid(lev[l].n * NB)), dim3(256), 0, stream,
+                                        lev[l].n * NB, 1.0, (double *)v);
+            }
         HIPCHK(hipGetLastError());
         int prof_saved = prof;
         prof = 0;
-        struct Best { int lpr, thr; float ms; } best{1, 256, 1e30f};
         blk_lpr = 1;
         blk_threads = 256;
-        float t1 = f32 ? time_blk_variant<float>() : time_blk_variant<double>();
-        tune_log.push_back({"lpr=1 threads=256", t1});
-        best = {1, 256, t1};
-        DevMat keep;
-        int keep_lpr = 0;
+        const bool win0 = lev[0].A.nshared > 0 && lev[0].A.shrun != nullptr;
+        if (win0) {
+            int best_r = 4;
+            float best_t = 1e30f;
+            for (int R : {2, 4}) {
+                blk_win = R;
+                float t = f32 ? time_passes([&] { level0_passes<float>(); }) : time_passes([&] { level0_passes<double>(); });
+                tune_log.push_back({"window rows per lane " + std::to_string(R), t});
+                if (t < best_t) { best_t = t; best_r = R; }
+            }
+            blk_win = best_r;
+        }
+        const bool lvl0 = !(win0 && blk_win > 0);
+        struct Best { int lpr, thr; float ms; } best{1, 256, 1e30f};
+        best.ms = f32 ? time_passes([&] { variant_passes<float>(lvl0); }) : time_passes([&] { variant_passes<double>(lvl0); });
+        tune_log.push_back({"lpr=1 threads=256", best.ms});
+        // level-0 K P product, formed once for every candidate image
+        amgiga::Csr kp0;
+        if (nlev > 1) kp0 = amgiga::kp_product(K0, host.lev[1].n, host.lev[0].agg.data(), host.lev[0].pc.data());
+        struct Imgs { DevMat a0, a1, kp0; };
+        Imgs keep;
         for (int lpr : {4, 8, 16}) {
-            DevMat img = upload_sell(K0, 64 / lpr, true, f32);
-            lev[0].Ab = img;
+            Imgs im;
+            if (lvl0) im.a0 = upload_sell(K0, 64 / lpr, true, f32);
+            if (nlev > 2) im.a1 = upload_sell(amgiga::view(host.lev[1].K), 64 / lpr, !f32, f32);
+            if (nlev > 1) im.kp0 = upload_sell(amgiga::view(kp0), 64 / lpr, !f32, f32, host.lev[1].n);
+            lev[0].Ab = im.a0;
+            if (nlev > 2) lev[1].Ab = im.a1;
+            if (nlev > 1) lev[0].KPb = im.kp0;
+            bool won = false;
             for (int thr : {256, 512}) {
                 blk_lpr = lpr;
                 blk_threads = thr;
-                float t = f32 ? time_blk_variant<float>() : time_blk_variant<double>();
+                float t = f32 ? time_passes([&] { variant_passes<float>(lvl0); })
+                              : time_passes([&] { variant_passes<double>(lvl0); });
                 tune_log.push_back({"lpr=" + std::to_string(lpr) + " threads=" + std::to_string(thr), t});
-                if (t < best.ms) best = {lpr, thr, t};
+                if (t < best.ms) { best = {lpr, thr, t}; won = true; }
             }
-            if (best.lpr == lpr) {
-                if (keep_lpr) release(keep);
-                keep = img;
-                keep_lpr = lpr;
+            lev[0].Ab = DevMat(); lev[0].KPb = DevMat();
+            if (nlev > 2) lev[1].Ab = DevMat();
+            if (won) {
+                release(keep.a0); release(keep.a1); release(keep.kp0);
+                keep = im;
             } else {
-                release(img);
+                release(im.a0); release(im.a1); release(im.kp0);
             }
-            lev[0].Ab = DevMat();
         }
         prof = prof_saved;
         blk_lpr = best.lpr;
         blk_threads = best.thr;
         if (best.lpr > 1) {
-            lev[0].Ab = keep;
-            for (int l = 1; l < nlev - 1; l++)
+            lev[0].Ab = keep.a0;
+            if (nlev > 2) lev[1].Ab = keep.a1;
+            if (nlev > 1) lev[0].KPb = keep.kp0;
+            for (int l = 2; l < nlev - 1; l++)
                 lev[l].Ab = upload_sell(amgiga::view(host.lev[l].K), 64 / best.lpr, !f32, f32);
-            for (int l = 0; l < nlev - 1; l++) {
-                CsrView K = l == 0 ? K0 : amgiga::view(host.lev[l].K);
-                amgiga::Csr kp = amgiga::kp_product(K, host.lev[l + 1].n, host.lev[l].agg.data(),
-                                                    host.lev[l].pc.data());
+            for (int l = 1; l < nlev - 1; l++) {
+                amgiga::Csr kp = amgiga::kp_product(amgiga::view(host.lev[l].K), host.lev[l + 1].n,
+                                                    host.lev[l].agg.data(), host.lev[l].pc.data());
                 lev[l].KPb = upload_sell(amgiga::view(kp), 64 / best.lpr, !f32, f32, host.lev[l + 1].n);
             }
+            blk_img_lpr = best.lpr;
         }
         HIPCHK(hipStreamSynchronize(stream));
     }
@@ -1078,6 +1152,7 @@ struct amg_ctx {
         bY = alloc<double>((size_t)std::max(nL, 1) * NB);
         bsc = alloc<double>(B_NSLOTS * NB);
         bpartial = alloc<double>((size_t)partial_cap * NB);
+        bstrided = alloc<double>((size_t)2 * NB * FIN_THREADS);
         bgram = alloc<double>((size_t)GRAM_BLOCKS * 512);
         bcoef = alloc<double>(256);
         bgsave = alloc<double>(256);
@@ -1111,19 +1186,34 @@ struct amg_ctx {
         const DevMat &B = lev[l].Ab;
         unsigned nb;
         if (l == 0) prof_begin();
-        if (blk_lpr > 1 && B.soff && B.val<VT>()) {
+        if (blk_win > 0 && A.nshared > 0 && A.shrun && A.val<VT>()) {
+            // stencil image: staged x windows, blk_win rows per lane; the grid
+            // is padded to a multiple of the XCD count (XCD-aware slice order)
+            const unsigned lgrid = sell_blocks(l);
+            const unsigned grid = (lgrid + XCDS - 1) / XCDS * XCDS;
+            nb = lgrid * SELL_WAVES;   // dot partials: one per wavefront of a logical block
+#define BLKW(IT, R) hipLaunchKernelGGL((k_sellw_blk<VT, FT, OT, IT, EPI, NDOT, R>), dim3(grid), dim3(256), 0, stream, \
+                                       A.sv<VT, IT>(), x, f, invd, y, g0, g1, bpartial, coef)
+            if (A.idx16) {
+                if (blk_win == 2) BLKW(uint16_t, 2);
+                else BLKW(uint16_t, 4);
+            } else {
+                if (blk_win == 2) BLKW(int32_t, 2);
+                else BLKW(int32_t, 4);
+            }
+#undef BLKW
+        } else if (blk_lpr > 1 && B.soff && B.val<VT>()) {
             nb = blk_lpr == 4   ? launch_sellb<VT, FT, OT, EPI, NDOT, 4>(B, x, f, invd, y, g0, g1, coef)
                  : blk_lpr == 8 ? launch_sellb<VT, FT, OT, EPI, NDOT, 8>(B, x, f, invd, y, g0, g1, coef)
                                 : launch_sellb<VT, FT, OT, EPI, NDOT, 16>(B, x, f, invd, y, g0, g1, coef);
         } else {
             const unsigned grid = sell_blocks(l);
             nb = grid * SELL_WAVES;   // dot partials: one per wavefront
-            if (A.idx16)
-                hipLaunchKernelGGL((k_sell_blk<VT, FT, OT, uint16_t, EPI, NDOT>), dim3(grid), dim3(256), 0, stream,
-                                   A.sv<VT, uint16_t>(), x, f, invd, y, g0, g1, bpartial, coef);
-            else
-                hipLaunchKernelGGL((k_sell_blk<VT, FT, OT, int32_t, EPI, NDOT>), dim3(grid), dim3(256), 0, stream,
-                                   A.sv<VT, int32_t>(), x, f, invd, y, g0, g1, bpartial, coef);
+#define BLK1(KER, IT) hipLaunchKernelGGL((KER<VT, FT, OT, IT, EPI, NDOT>), dim3(grid), dim3(256), 0, stream, \
+                                         A.sv<VT, IT>(), x, f, invd, y, g0, g1, bpartial, coef)
+            if (A.idx16) BLK1(k_sell_blk, uint16_t);
+            else BLK1(k_sell_blk, int32_t);
+#undef BLK1
         }
         HIPCHK(hipGetLastError());
         if (l == 0) {
@@ -1139,7 +1229,15 @@ struct amg_ctx {
     }
     void bfinalize(unsigned nblk, int op, double tol = 0.0)
     {
-        hipLaunchKernelGGL(k_bfinalize, dim3(1), dim3(FIN_THREADS), 0, stream, bpartial, (int)nblk, bsc, op, tol);
+        // many partials (one per wavefront of a level-0 pass): the strided sums
+        // of the single final block over a wide grid first
+        const double *st = nullptr;
+        if (nblk > 4 * FIN_THREADS) {
+            hipLaunchKernelGGL(k_bfin_strided, dim3(2 * NB * FIN_THREADS / 256), dim3(256), 0, stream, bpartial,
+                               (int)nblk, bstrided);
+            st = bstrided;
+        }
+        hipLaunchKernelGGL(k_bfinalize, dim3(1), dim3(FIN_THREADS), 0, stream, bpartial, (int)nblk, bsc, op, tol, st);
         HIPCHK(hipGetLastError());
     }
     // grid of the element-parallel block vector kernels (a multiple of 16 threads)
@@ -1568,13 +1666,17 @@ amg_status amg_setup_host(int64_t n, const int64_t *row_ptr, const int32_t *col,
     return setup_common(n, row_ptr, col, val, w, prm, nullptr, 1, out);
 }
 
+// window rows per chunk column of the block kernels' staged x windows
+static constexpr int WIN_STRIDE_HOST = WIN_STRIDE;
+
 amg_status amg_sell_spmv_host(int64_t n, int64_t ncols, const int64_t *row_ptr, const int32_t *col,
                               const double *val, int C, int layout, const double *x, double *y,
                               int64_t *shared_slices, int64_t *stored)
 {
     g_err.clear();
     if (n <= 0 || ncols <= 0 || !row_ptr || !col || !val || !x || !y || (C != 4 && C != 8 && C != 16 && C != 32 &&
-        C != 64) || layout < 0 || layout > 2 || (layout == 1 && ncols != n)) {
+        C != 64) || layout < 0 || layout > 3 || (layout >= 1 && layout != 2 && ncols != n) ||
+        (layout == 3 && C != SLICE)) {
         set_err("bad size, NULL array, slice height or layout");
         return AMG_ERR_ARG;
     }
@@ -1588,10 +1690,59 @@ amg_status amg_sell_spmv_host(int64_t n, int64_t ncols, const int64_t *row_ptr, 
     }
     CsrView K{n, row_ptr, col, val};
     SellHost S;
-    build_sell(K, C, true, false, layout == 1, layout == 2 ? 4 * C : 0, S);
+    build_sell(K, C, true, false, layout == 1 || layout == 3, layout == 2 ? 4 * C : 0, S);
     const int32_t hi = (int32_t)(ncols - 1);
     auto bad = [&](int64_t c) { return c < 0 || c > hi; };
+    if (layout == 3) {
+        // shared-offset slices walked as the block kernels' staged x windows:
+        // per run of the run table, window rows g0 + w (w < 63 + L, clamped
+        // where the slice needs it) are copied, then lane r reads window row
+        // r + t for the run's t-th entry; every row copied and every window
+        // slot read is checked
+        std::vector<double> win(WIN_STRIDE_HOST);
+        for (int64_t s = 0; s < S.nslices; s++) {
+            const int64_t ib = S.ibase[s];
+            if (ib >= 0) continue;   // per-row-index slices: the gather path of layout 1
+            const int64_t base = S.soff[s];
+            const int width = (int)((S.soff[s + 1] - base) / C);
+            const int64_t e = -1 - ib;
+            if ((e >> 1) + width > (int64_t)S.shoff.size()) { set_err("offset list past its array"); return AMG_ERR_STATE; }
+            const int32_t *so = S.shoff.data() + (e >> 1), *rt = S.shrun.data() + (e >> 1);
+            if (rt[0] == 0) {
+                // no run table: the gather walk below
+                continue;
+            }
+            std::vector<double> acc(C, 0.0);
+            int k = 0;
+            for (int rho = 0; k < width; rho++) {
+                const int32_t pk = rt[rho];
+                if (pk == 0) break;
+                const int L = pk & 15;
+                if (L < 1 || L > WIN_LMAX || k + L > width) { set_err("run past the list or too long"); return AMG_ERR_STATE; }
+                if ((pk >> 4) != so[k]) { set_err("run table and offset list disagree"); return AMG_ERR_STATE; }
+                for (int t = 1; t < L; t++)
+                    if (so[k + t] != so[k] + t) { set_err("run of non-consecutive offsets"); return AMG_ERR_STATE; }
+                const int64_t g0 = s * C + so[k];
+                for (int w = 0; w < C + L - 1; w++) {
+                    int64_t g = g0 + w;
+                    if (!(e & 1)) g = std::min<int64_t>(std::max<int64_t>(g, 0), hi);
+                    if (bad(g) || w >= WIN_STRIDE_HOST) { set_err("window row out of range"); return AMG_ERR_STATE; }
+                    win[w] = x[g];
+                }
+                for (int r = 0; r < C; r++)
+                    for (int t = 0; t < L; t++) {
+                        if (r + t >= C + L - 1) { set_err("window slot not staged"); return AMG_ERR_STATE; }
+                        const int kk = k + t;
+                        acc[r] = std::fma(S.v64[base + (kk / 2) * 2 * C + r * 2 + (kk % 2)], win[r + t], acc[r]);
+                    }
+                k += L;
+            }
+            for (int r = 0; r < C; r++)
+                if (s * C + r < n) y[s * C + r] = acc[r];
+        }
+    }
     for (int64_t s = 0; s < S.nslices; s++) {
+        if (layout == 3 && S.ibase[s] < 0 && S.shrun[(-1 - S.ibase[s]) >> 1] != 0) continue;
         const int64_t base = S.soff[s];
         const int width = (int)((S.soff[s + 1] - base) / C);
         const int64_t ib = S.ibase[s];
@@ -2012,6 +2163,26 @@ amg_status amg_set_option(amg_ctx *c, int option, int value)
     switch (option) {
     case AMG_OPT_GRAPH: c->use_graph = value ? 1 : 0; break;
     case AMG_OPT_FUSE_POST: c->fuse_post = value ? 1 : 0; c->drop_graphs(); break;
+    case AMG_OPT_BLOCK_WINDOW:
+        if (value != 0 && value != 2 && value != 4) {
+            set_err("AMG_OPT_BLOCK_WINDOW takes 0 (off) or 2 or 4 rows per lane");
+            return AMG_ERR_ARG;
+        }
+        c->blk_win = value;
+        c->drop_graphs();
+        break;
+    default: set_err("unknown option"); return AMG_ERR_ARG;
+    }
+    return AMG_OK;
+}
+
+amg_status amg_get_option(const amg_ctx *c, int option, int *value)
+{
+    if (!c || !value) { set_err("NULL argument"); return AMG_ERR_ARG; }
+    switch (option) {
+    case AMG_OPT_GRAPH: *value = c->use_graph; break;
+    case AMG_OPT_FUSE_POST: *value = c->fuse_post; break;
+    case AMG_OPT_BLOCK_WINDOW: *value = c->blk_win; break;
     default: set_err("unknown option"); return AMG_ERR_ARG;
     }
     return AMG_OK;
@@ -2031,8 +2202,9 @@ amg_status amg_set_batched_variant(amg_ctx *c, int lpr, int threads)
         set_err("lpr must be 1, 4, 8 or 16 and threads 256 or 512");
         return AMG_ERR_ARG;
     }
-    if (lpr > 1 && (c->lev[0].Ab.C != 64 / lpr || !c->lev[0].Ab.soff)) {
-        set_err("no block image with that many lanes per row (build with prm.nrhs > 1)");
+    if (lpr > 1 && c->blk_img_lpr != lpr) {
+        set_err("no block images with that many lanes per row (built by amg_setup with prm.nrhs > 1 for the "
+                "autotuner's choice only)");
         return AMG_ERR_ARG;
     }
     if (lpr == 1 && threads != 256) { set_err("the one-lane-per-row kernels use 256 threads"); return AMG_ERR_ARG; }

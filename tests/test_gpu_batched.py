@@ -175,3 +175,39 @@ def test_batched_learned_polynomial_smoother(oracle, amg):
         true = np.linalg.norm(Fh[:, j] - oracle.spmv(rp, ci, v, U32[:, j])) / np.linalg.norm(Fh[:, j])
         assert true <= 1e-8 * 1.0001, (j, true)
     print(f"  iterations fp64 {out['iters']} fp32 {out32['iters']}", flush=True)
+
+
+@pytest.mark.parametrize("case", ["3d-p3-n16", "2d-p5-n40", "2d-p2-n61", "kappa-p4-n8"])
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_block_window_equals_gather(oracle, amg, case, fp32):
+    """The block passes with staged x windows (2 or 4 rows per lane)
+    against the gather kernel they replace: every column bit for bit, FP64
+    and FP32 V-cycles;
+    x-runs longer than one window (p = 5), slices straddling x-lines, a
+    partly filled last slice, variable coefficients."""
+    print(f"case block window {case} fp32={fp32}", flush=True)
+    from paper_2511_21268_amd.workloads import kappa_params, rhs_block
+    if case == "kappa-p4-n8":
+        a, mk = kappa_params(3)
+        rp, ci, v, _ = oracle.diffusion_quad3d(4, 8, a, mk, factorized=True)
+    else:
+        d, p, n = (int(t[1:]) if t[0] in "pn" else int(t[0]) for t in case.split("-"))
+        rp, ci, v, _ = oracle.poisson_kron(d, p, n)
+    N = len(rp) - 1
+    Ft = torch.from_numpy(rhs_block(N, range(16))).cuda()
+    kw = dict(vcycle_fp32=1, krylov=1) if fp32 else {}
+    ctx = amg.Context(rp, ci, v, **kw)
+    assert ctx.format(0)["shared_slices"] > 0
+    assert ctx.option(amg.amg.AMG_OPT_BLOCK_WINDOW) == 4       # the default without autotuning
+    outs = {}
+    for rows in (0, 2, 4):
+        ctx.set_block_window(rows)
+        outs[rows] = ctx.solve_batched(Ft, tol=1e-8)
+    assert outs[0]["status"] == 0
+    for rows in (2, 4):
+        assert outs[rows]["iters"] == outs[0]["iters"], rows
+        assert torch.equal(outs[rows]["U"], outs[0]["U"]), rows
+    print(f"  iterations {outs[0]['iters']}", flush=True)
+    for bad in (1, 3):
+        with pytest.raises(amg.AmgError):
+            ctx.set_block_window(bad)

@@ -47,16 +47,19 @@ def test_layouts_compute_Kx(oracle, amg, C):
         x = np.random.default_rng(1).standard_normal(n)
         ref, scale = _ref(rp, ci, v, x, n)
         ys = []
-        for layout in (0, 1, 2):
+        # layout 3 (C = 64 only): shared-offset slices through the block
+        # kernels' staged x windows (runs of consecutive offsets)
+        for layout in ((0, 1, 2, 3) if C == 64 else (0, 1, 2)):
             y, shared, stored = amg.sell_spmv_host(rp, ci, v, x, C_slice=C, layout=layout)
             assert np.all(np.abs(y - ref) <= 8 * np.finfo(float).eps * scale + 1e-300), (name, layout)
             assert stored >= len(v)
-            if layout != 1:
+            if layout in (0, 2):
                 assert shared == 0
             ys.append(y)
-            if layout == 1 and name in ("2d-p2", "3d-p3") and C == 64:
+            if layout in (1, 3) and name in ("2d-p2", "3d-p3", "3d-kappa-p5") and C == 64:
                 assert shared > 0, name
-        assert np.array_equal(ys[0], ys[1]) and np.array_equal(ys[0], ys[2]), name
+        for y in ys[1:]:
+            assert np.array_equal(ys[0], y), name
 
 
 def test_rectangular_KP_image(oracle, amg):
@@ -87,3 +90,25 @@ def test_sorted_windows_reduce_padding(oracle, amg):
     _, _, plain = amg.sell_spmv_host(rpl, cil, vl, x, C_slice=64, layout=0)
     _, _, srt = amg.sell_spmv_host(rpl, cil, vl, x, C_slice=64, layout=2)
     assert srt < plain
+
+
+def test_window_walk_edge_cases(oracle, amg):
+    """The staged-window walk on stencils whose x-runs are longer than one
+    window (p = 5: runs of 11 split 8 + 3), whose slices straddle x-lines and
+    planes (n + p - 2 not a multiple of 64), a single short slice, and a
+    partially filled last slice: bitwise the gather walk."""
+    cases = [(oracle.poisson_kron(2, 5, 64)[:3], True),    # x-runs of 11: windows of 8 + 3
+             (oracle.poisson_kron(2, 3, 70)[:3], True),    # slices straddle x-lines
+             (oracle.poisson_kron(3, 1, 66)[:3], True),    # and planes; runs of 3
+             (oracle.poisson_kron(2, 2, 61)[:3], True),    # last slice partly filled
+             (oracle.poisson_kron(2, 3, 3)[:3], False)]    # one slice of 16 rows, no shared list
+    for (rp, ci, v), shared in cases:
+        n = len(rp) - 1
+        x = np.random.default_rng(n).standard_normal(n)
+        y1, sh1, _ = amg.sell_spmv_host(rp, ci, v, x, C_slice=64, layout=1)
+        y3, sh3, _ = amg.sell_spmv_host(rp, ci, v, x, C_slice=64, layout=3)
+        assert sh1 == sh3 and (sh3 > 0) == shared, n
+        assert np.array_equal(y1, y3), n
+    rp, ci, v = cases[0][0]
+    with pytest.raises(Exception):
+        amg.sell_spmv_host(rp, ci, v, np.zeros(len(rp) - 1), C_slice=16, layout=3)
