@@ -44,6 +44,23 @@ typedef int vi4 __attribute__((ext_vector_type(4)));
 constexpr int SLICE = 64;
 constexpr int WIN_LMAX = 8;            // longest offset run one staged x window covers
 constexpr int SELL_WAVES = 4;          // slices (wavefronts) per 256-thread block
+constexpr int XCDS = 8;                // accelerator complex dies sharing the grid (one L2 each)
+
+// XCD-aware block order (used by the staged-window block kernel).  The
+// hardware deals blocks to the XCDs round-robin (block b runs on XCD b % XCDS);
+// block b takes logical block (b % XCDS) * per + b / XCDS, so every XCD works
+// through one contiguous range of slices and the neighbouring rows its loads
+// reach stay in that XCD's L2.  Grids are padded to a multiple of XCDS;
+// xcd_block returns -1 for a padding block.  Dot partials are indexed by
+// logical block, so the order of every sum does not depend on this mapping.
+// (The single-vector matrix passes keep the plain order: measured the same.)
+__device__ __forceinline__ int64_t xcd_block(int64_t nlb)
+{
+    const int64_t per = (nlb + XCDS - 1) / XCDS;
+    const int64_t lb = (int64_t)(blockIdx.x % XCDS) * per + blockIdx.x / XCDS;
+    return lb < nlb ? lb : -1;
+}
+inline unsigned xcd_grid(int64_t nlb) { return (unsigned)((nlb + XCDS - 1) / XCDS * XCDS); }
 constexpr int RED_THREADS = 256;
 
 enum Epi { EPI_SPMV = 0, EPI_RESID = 1, EPI_SMOOTH = 2, EPI_POLY = 3, EPI_ADD = 4 };
@@ -266,7 +283,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 {
     const int lane = threadIdx.x & 63, wid = wave_id();
     const int64_t s = (int64_t)blockIdx.x * SELL_WAVES + wid;
-    const int64_t nrows = A.nrows;
     double d0 = 0.0, d1 = 0.0;
     if (s < A.nslices) {
         const int64_t row = A.row_of(s * SLICE + lane);

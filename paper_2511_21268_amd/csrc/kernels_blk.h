@@ -167,7 +167,6 @@ __global__ __launch_bounds__(256) void k_sell_blk(const Sell<VT, IT> A, const VT
 // operations order its accesses (in-order per wave), fenced for the compiler
 // by wave_lds_sync.
 constexpr int WIN_STRIDE = 73;   // window rows per chunk column (>= SLICE + WIN_LMAX - 1, odd)
-constexpr int XCDS = 8;          // accelerator complex dies sharing the grid (one L2 each)
 
 __device__ inline void wave_lds_sync()
 {
@@ -213,14 +212,10 @@ __global__ __launch_bounds__(256) void k_sellw_blk(const Sell<VT, IT> A, const V
     constexpr int NLD = (CH * (SLICE + WIN_LMAX - 1) + 63) / 64;   // staging loads per lane
     __shared__ CT win[SELL_WAVES * WN];
     const int lane = threadIdx.x & 63, wid = wave_id();
-    // XCD-aware order: the hardware deals blocks to the XCDs round-robin, so
-    // block b runs on XCD b % XCDS; it takes logical block (b % XCDS) * per +
-    // b / XCDS, giving every XCD one contiguous range of slices, whose windows
-    // overlap (x-lines and planes of the stencil) in that XCD's own L2.  Dot
-    // partials stay indexed by logical slice.
-    const int64_t nlb = (A.nslices + SELL_WAVES - 1) / SELL_WAVES, per = (nlb + XCDS - 1) / XCDS;
-    const int64_t lb = (int64_t)(blockIdx.x % XCDS) * per + blockIdx.x / XCDS;
-    if (lb >= nlb) return;   // padding block of the last XCD's range
+    // XCD-aware order (xcd_block): every XCD one contiguous range of slices,
+    // whose windows overlap (x-lines and planes of the stencil) in its L2
+    const int64_t lb = xcd_block((A.nslices + SELL_WAVES - 1) / SELL_WAVES);
+    if (lb < 0) return;
     const int64_t s = lb * SELL_WAVES + wid;
     const int64_t w_id = s;
     const int64_t ib = s < A.nslices ? A.ibase[s] : 0;

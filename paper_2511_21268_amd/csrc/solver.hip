@@ -1190,7 +1190,7 @@ struct amg_ctx {
             // stencil image: staged x windows, blk_win rows per lane; the grid
             // is padded to a multiple of the XCD count (XCD-aware slice order)
             const unsigned lgrid = sell_blocks(l);
-            const unsigned grid = (lgrid + XCDS - 1) / XCDS * XCDS;
+            const unsigned grid = xcd_grid(lgrid);
             nb = lgrid * SELL_WAVES;   // dot partials: one per wavefront of a logical block
 #define BLKW(IT, R) hipLaunchKernelGGL((k_sellw_blk<VT, FT, OT, IT, EPI, NDOT, R>), dim3(grid), dim3(256), 0, stream, \
                                        A.sv<VT, IT>(), x, f, invd, y, g0, g1, bpartial, coef)
