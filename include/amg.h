@@ -151,6 +151,15 @@ amg_status pcg_solve(amg_ctx *c, const double *F, double *u, double tol,
                      int *iters, double *relres, double *relres_true);
 
 /*
+ * Residual history of the last pcg_solve on this context (the Krylov call's
+ * trace output of Sec. 4): ||r_k||_2 / ||F||_2 of the recursion for
+ * k = 0 .. iterations (iterations + 1 values; empty before the first solve and
+ * for F = 0).  hist: host, the first min(cap, count) values are written (may
+ * be NULL when cap is 0); count (host, may be NULL): the number available.
+ */
+amg_status amg_get_residual_history(const amg_ctx *c, double *hist, int cap, int *count);
+
+/*
  * Solve nrhs independent systems K U[:,k] = F[:,k] sharing every matrix pass:
  * one block SpMV and one block V-cycle per iteration, each column with its own
  * FCG(1) scalars, converged columns frozen.
@@ -300,6 +309,14 @@ amg_status amg_get_option(const amg_ctx *c, int option, int *value);
  */
 amg_status amg_set_profiling(amg_ctx *c, int enable);
 amg_status amg_get_profile(amg_ctx *c, int64_t *launches, double *ms, double *bytes);
+/* The same figures for one kind of level-0 pass (any output may be NULL):
+ * SpMV with its dots (the Krylov product), residual, smoother sweep,
+ * polynomial-smoother step, the fused K P prolongation + post-smoothing pass,
+ * other passes (Chebyshev steps, prolongation with a smoothed prolongator).
+ * amg_set_profiling(c, 1) clears them with the totals. */
+typedef enum { AMG_PASS_SPMV = 0, AMG_PASS_RESID = 1, AMG_PASS_SMOOTH = 2, AMG_PASS_POLY = 3, AMG_PASS_KP = 4,
+               AMG_PASS_OTHER = 5, AMG_PASS_KINDS = 6 } amg_pass_kind;
+amg_status amg_get_profile_pass(const amg_ctx *c, int kind, int64_t *launches, double *ms, double *bytes);
 /* Description of a level's single-vector layout: slice height, stored
  * entries with padding, index bytes per entry in slices with per-entry
  * indices (2 or 4), and the number of slices (of ceil(n / slice)) that store

@@ -25,10 +25,12 @@ EXPORTS = ["amg_params_default", "amg_setup", "pcg_solve", "pcg_solve_batched", 
            "amg_mlp_forward", "amg_mlp_backward", "amg_mlp_adam", "amg_set_learned_poly",
            "amg_get_batched_variant", "amg_set_batched_variant", "amg_set_option", "amg_sell_spmv_host",
            "amg_iga_cube_size", "amg_iga_cube", "amg_get_prolongator", "amg_get_setup_rounds",
-           "amg_mlp_backward_noalloc", "amg_get_option"]
+           "amg_mlp_backward_noalloc", "amg_get_option", "amg_get_profile_pass",
+           "amg_get_residual_history"]
 AMG_OPT_GRAPH, AMG_OPT_FUSE_POST, AMG_OPT_BLOCK_WINDOW = 1, 2, 3
 MLP_NPARAM, MLP_NFEAT, MLP_NACT, MLP_NDEL = 4996, 8, 128, 132
 MLP_NOALLOC_MAX_B = 16384
+PASS_KINDS = ("spmv", "resid", "smooth", "poly", "kp", "other")   # amg_pass_kind order
 
 
 class AmgError(RuntimeError):
@@ -91,6 +93,8 @@ def lib():
         L.amg_last_error.restype = C.c_char_p
         L.amg_set_profiling.argtypes = [vp, C.c_int]
         L.amg_get_profile.argtypes = [vp, i64p, f64p, f64p]
+        L.amg_get_profile_pass.argtypes = [vp, C.c_int, i64p, f64p, f64p]
+        L.amg_get_residual_history.argtypes = [vp, f64p, C.c_int, C.POINTER(C.c_int)]
         L.amg_get_format.argtypes = [vp, C.c_int, C.POINTER(C.c_int), i64p, C.POINTER(C.c_int), i64p]
         L.amg_iga_poisson_size.argtypes = [C.c_int, C.c_int, C.c_int, i64p, i64p]
         L.amg_iga_poisson.argtypes = [C.c_int, C.c_int, C.c_int, i64p, i32p, f64p, f64p]
@@ -326,10 +330,25 @@ class Context:
     def set_profiling(self, on):
         _check(lib().amg_set_profiling(self.h, int(on)))
 
+    def residual_history(self):
+        """||r_k|| / ||F|| of the last solve, k = 0 .. iterations (numpy array)."""
+        cnt = C.c_int()
+        _check(lib().amg_get_residual_history(self.h, None, 0, C.byref(cnt)))
+        h = np.zeros(cnt.value)
+        if cnt.value:
+            _check(lib().amg_get_residual_history(self.h, _p(h, f64p), cnt.value, C.byref(cnt)))
+        return h
+
     def profile(self):
         n = C.c_int64(); ms = C.c_double(); by = C.c_double()
         _check(lib().amg_get_profile(self.h, C.byref(n), C.byref(ms), C.byref(by)))
-        return dict(launches=n.value, ms=ms.value, bytes=by.value)
+        passes = {}
+        for k, name in enumerate(PASS_KINDS):
+            pn = C.c_int64(); pms = C.c_double(); pby = C.c_double()
+            _check(lib().amg_get_profile_pass(self.h, k, C.byref(pn), C.byref(pms), C.byref(pby)))
+            if pn.value:
+                passes[name] = dict(launches=pn.value, ms=pms.value, bytes=pby.value)
+        return dict(launches=n.value, ms=ms.value, bytes=by.value, passes=passes)
 
     # ---- operators ---------------------------------------------------------------
     def vcycle(self, r):

@@ -36,7 +36,8 @@ def build(verbose=False):
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
          + inc + ["-c", os.path.join(CSRC, "setup_dev.hip"), "-o", sdev_o])
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, dev_o, sdev_o, host_o, "-pthread"])
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, dev_o, sdev_o, host_o, "-pthread",
+          "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -7,6 +7,8 @@
 #include <string>
 #include <vector>
 
+#include "layout.h"
+
 namespace amgiga {
 
 struct Csr {
@@ -115,6 +117,31 @@ void iga_cube_size(int p, int n, int64_t *N, int64_t *nnz);
 int iga_cube(int p, int n, int64_t *rp, int32_t *ci, double *v, double *F);
 int iga_diffusion(int p, int n, int nk, const double *a, const int32_t *mk, int64_t *rp, int32_t *ci, double *v,
                   double *F);
+
+// SELL-C image of a matrix as the device kernels read it (layout described in
+// kernels.h): per-slice value offsets soff, index-stream bases ibase (< 0: a
+// shared column-offset list at shoff, with its run table in shrun), values in
+// FP64 and/or FP32, 16-bit deltas with first columns or int32 columns, and the
+// slot -> row map of sorted images.
+struct SellHost {
+    int64_t nslices = 0, stored = 0, nshared = 0;
+    int sorted = 0;
+    std::vector<int32_t> perm;
+    double index_bytes = 0.0;   // index data a pass must read (no padding)
+    int idx16 = 1;
+    std::vector<int64_t> soff, ibase;
+    std::vector<double> v64;
+    std::vector<float> v32;
+    std::vector<uint16_t> d16;
+    std::vector<int32_t> c32, col0, shoff, shrun;
+};
+std::vector<int32_t> slice_offsets(const CsrView &K, int64_t s, int C, int64_t limit);
+int64_t count_shared(const CsrView &K, int C);
+void build_sell(const CsrView &K, int C, bool want64, bool want32, bool shared, int sigma, SellHost &S);
+// y = K x walked through the image as the kernels walk it (layouts of
+// amg_sell_spmv_host); 0, or -6 with err set when a read would leave its array.
+int sell_spmv_walk(const CsrView &K, int64_t ncols, int C, int layout, const double *x, double *y,
+                   int64_t *shared_slices, int64_t *stored, std::string &err);
 
 // Runs f(begin, end) over [0, n) split in contiguous chunks on host threads
 // (serially when n < serial_below).

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 
 namespace amgiga {
@@ -1053,6 +1054,316 @@ int iga_diffusion(int p, int n, int nk, const double *a, const int32_t *mk, int6
                 }
             }, 1);
         }
+    return 0;
+}
+
+
+// ---------------------------------------------------------------------------
+// Device matrix images (SELL-C) built on the host, and their host walk.
+
+
+// Ascending union of the column offsets (column - row) of the rows of slice s,
+// or an empty list when it would be longer than `limit`.
+std::vector<int32_t> slice_offsets(const CsrView &K, int64_t s, int C, int64_t limit)
+{
+    std::vector<int32_t> u, m;
+    for (int64_t r = s * C; r < std::min(K.n, (s + 1) * C); r++) {
+        m.clear();
+        size_t a = 0;
+        for (int64_t k = K.rp[r]; k < K.rp[r + 1]; k++) {
+            const int32_t o = (int32_t)(K.ci[k] - r);
+            while (a < u.size() && u[a] < o) m.push_back(u[a++]);
+            if (a < u.size() && u[a] == o) a++;
+            m.push_back(o);
+        }
+        while (a < u.size()) m.push_back(u[a++]);
+        if ((int64_t)m.size() > limit) return {};
+        u.swap(m);
+    }
+    return u;
+}
+
+// Number of C-row slices whose offset unions would be stored once.
+int64_t count_shared(const CsrView &K, int C)
+{
+    const int64_t ns = (K.n + C - 1) / C;
+    std::atomic<int64_t> cnt{0};
+    parallel_for(ns, [&](int64_t sb, int64_t se) {
+        int64_t c = 0;
+        for (int64_t s = sb; s < se; s++) {
+            int64_t w = 0;
+            for (int64_t r = s * C; r < std::min(K.n, (s + 1) * C); r++) w = std::max(w, K.rp[r + 1] - K.rp[r]);
+            if (w > 0 && !slice_offsets(K, s, C, (w + 7) / 8 * 8).empty()) c++;
+        }
+        cnt += c;
+    }, 1);
+    return cnt.load();
+}
+
+// SELL-C image of a CSR matrix (slice height C rows; group layout of kernels.h).
+// With `shared`, a slice whose offset union is no wider than its longest row
+// (both rounded up to 8) stores the union once; the others keep per-row indices.
+// With sigma > 0 (no shared offsets then), the rows of every window of sigma
+// consecutive rows are placed in the window's slots by decreasing length (ties
+// by index), so the slices of a window pad to similar lengths; perm[slot]
+// gives the row of each slot (-1 for the slots past the last row).
+void build_sell(const CsrView &K, int C, bool want64, bool want32, bool shared, int sigma, SellHost &S)
+{
+    const int64_t n = K.n;
+    S.nslices = (n + C - 1) / C;
+    const int64_t nslot = S.nslices * C;
+    if (sigma > 0) shared = false;
+    std::vector<int32_t> rowof(nslot, -1);
+    auto len = [&](int64_t r) { return K.rp[r + 1] - K.rp[r]; };
+    parallel_for((n + std::max(sigma, 1) - 1) / std::max(sigma, 1), [&](int64_t wb, int64_t we) {
+        for (int64_t w = wb; w < we; w++) {
+            const int64_t a = w * std::max(sigma, 1), e = std::min(n, a + std::max(sigma, 1));
+            for (int64_t r = a; r < e; r++) rowof[r] = (int32_t)r;
+            if (sigma > 0)
+                std::stable_sort(rowof.begin() + a, rowof.begin() + e,
+                                 [&](int32_t x, int32_t y) { return len(x) > len(y); });
+        }
+    }, 1);
+    S.sorted = sigma > 0 ? 1 : 0;
+    if (S.sorted) S.perm = rowof;
+    std::vector<int64_t> wd(S.nslices);
+    std::vector<std::vector<int32_t>> U(S.nslices);
+    parallel_for(S.nslices, [&](int64_t sb, int64_t se) {
+        for (int64_t s = sb; s < se; s++) {
+            int64_t w = 0;
+            for (int64_t q = s * C; q < (s + 1) * C; q++)
+                if (rowof[q] >= 0) w = std::max(w, len(rowof[q]));
+            wd[s] = (w + 7) / 8 * 8;
+            if (shared && w > 0) U[s] = slice_offsets(K, s, C, wd[s]);
+        }
+    }, 1);
+    S.soff.assign(S.nslices + 1, 0);
+    S.ibase.assign(S.nslices, 0);
+    int64_t ib = 0, sh = 0;
+    S.nshared = 0;
+    S.index_bytes = 0.0;
+    // identical offset lists (the interior slices of a stencil matrix) are
+    // stored once, so the wavefronts reading them share cache lines
+    std::map<std::vector<int32_t>, int64_t> lists;
+    for (int64_t s = 0; s < S.nslices; s++) {
+        const int64_t w = U[s].empty() ? wd[s] : (int64_t)(U[s].size() + 7) / 8 * 8;
+        S.soff[s + 1] = S.soff[s] + C * w;
+        if (U[s].empty()) {
+            S.ibase[s] = ib;
+            ib += C * w;
+        } else {
+            // every lane r of the slice (rows s*C .. s*C+C-1, padding rows
+            // included) reads column row + offset for every stored offset,
+            // the padding offsets 0 included
+            const int64_t lo = s * C + std::min<int64_t>(0, U[s].front());
+            const int64_t hi = s * C + C - 1 + std::max<int64_t>(0, U[s].back());
+            const int64_t inrange = (lo >= 0 && hi < n) ? 1 : 0;
+            auto it = lists.find(U[s]);
+            if (it == lists.end()) {
+                it = lists.emplace(U[s], sh).first;
+                sh += w;
+                S.index_bytes += 4.0 * (double)U[s].size();
+            }
+            S.ibase[s] = -1 - (2 * it->second + inrange);
+            S.nshared++;
+        }
+    }
+    S.stored = S.soff[S.nslices];
+    int maxd = 0;
+    int64_t dnnz = 0, drows = 0;
+    {
+        std::mutex mx;
+        parallel_for(S.nslices, [&](int64_t sb, int64_t se) {
+            int m = 0;
+            int64_t z = 0, nr = 0;
+            for (int64_t s = sb; s < se; s++) {
+                if (!U[s].empty()) continue;
+                for (int64_t q = s * C; q < (s + 1) * C; q++) {
+                    const int64_t r = rowof[q];
+                    if (r < 0) continue;
+                    for (int64_t k = K.rp[r] + 1; k < K.rp[r + 1]; k++) m = std::max(m, K.ci[k] - K.ci[k - 1]);
+                    z += K.rp[r + 1] - K.rp[r];
+                    nr++;
+                }
+            }
+            std::lock_guard<std::mutex> g(mx);
+            maxd = std::max(maxd, m);
+            dnnz += z;
+            drows += nr;
+        }, 1);
+    }
+    S.idx16 = maxd <= 65535 ? 1 : 0;
+    S.index_bytes += S.idx16 ? 2.0 * (double)dnnz + 4.0 * (double)drows : 4.0 * (double)dnnz;
+    if (want64) S.v64.assign(S.stored, 0.0);
+    if (want32) S.v32.assign(S.stored, 0.0f);
+    if (ib > 0) {
+        if (S.idx16) {
+            S.d16.assign(ib, 0);
+            S.col0.assign(S.nslices * C, 0);
+        } else {
+            S.c32.assign(ib, 0);
+        }
+    }
+    S.shoff.assign(sh, 0);
+    for (const auto &kv : lists) std::copy(kv.first.begin(), kv.first.end(), S.shoff.begin() + kv.second);
+    // run table of each list for the block kernels' staged x windows: its
+    // runs of consecutive offsets (o, o+1, ...), at most amgk::WIN_LMAX long, in
+    // order from the list's position, packed as o * 16 + length, then 0; a
+    // list with an offset beyond +-2^27 gets no table (first entry 0)
+    S.shrun.assign(sh, 0);
+    for (const auto &kv : lists) {
+        const std::vector<int32_t> &u = kv.first;
+        bool fits = true;
+        for (int32_t o : u) fits = fits && o >= -(1 << 27) && o < (1 << 27);
+        if (!fits) continue;
+        int64_t rho = 0;
+        for (size_t k = 0; k < u.size();) {
+            size_t L = 1;
+            while (L < (size_t)amgk::WIN_LMAX && k + L < u.size() && u[k + L] == u[k] + (int32_t)L) L++;
+            S.shrun[kv.second + rho++] = u[k] * 16 + (int32_t)L;
+            k += L;
+        }
+    }
+    parallel_for(S.nslices, [&](int64_t sb, int64_t se) {
+        for (int64_t s = sb; s < se; s++) {
+            const int64_t base = S.soff[s];
+            const int64_t w = (S.soff[s + 1] - base) / C;
+            const bool sl = !U[s].empty();
+            for (int lane = 0; lane < C; lane++) {
+                const int64_t q = s * C + lane, r = rowof[q];
+                const int64_t len = r >= 0 ? K.rp[r + 1] - K.rp[r] : 0;
+                const int64_t r0 = r >= 0 ? K.rp[r] : 0;
+                auto put = [&](int64_t k, double v) {
+                    if (want64) S.v64[base + (k / 2) * 2 * C + lane * 2 + (k % 2)] = v;
+                    if (want32) S.v32[base + (k / 4) * 4 * C + lane * 4 + (k % 4)] = (float)v;
+                };
+                if (sl) {
+                    int64_t j = 0;
+                    for (int64_t k = 0; k < (int64_t)U[s].size() && j < len; k++)
+                        if (K.ci[r0 + j] - r == U[s][k]) put(k, K.v[r0 + j++]);
+                    continue;
+                }
+                const int64_t ibs = S.ibase[s];
+                if (S.idx16 && r >= 0) S.col0[q] = K.ci[r0];
+                for (int64_t k = 0; k < w; k++) {
+                    put(k, k < len ? K.v[r0 + k] : 0.0);
+                    if (S.idx16) {
+                        int d = (k >= 1 && k < len) ? K.ci[r0 + k] - K.ci[r0 + k - 1] : 0;
+                        S.d16[ibs + (k / 8) * 8 * C + lane * 8 + (k % 8)] = (uint16_t)d;
+                    } else {
+                        int32_t c = k < len ? K.ci[r0 + k] : (len > 0 ? K.ci[r0 + len - 1] : 0);
+                        S.c32[ibs + (k / 4) * 4 * C + lane * 4 + (k % 4)] = c;
+                    }
+                }
+            }
+        }
+    }, 1);
+}
+
+
+// y = K x by walking the SELL-C image of K the way the device kernels do (see
+// amg_sell_spmv_host in amg.h for the layouts); every column and window slot
+// the walk reads is checked.  0, or AMG_ERR_STATE (-6) with a message.
+int sell_spmv_walk(const CsrView &K, int64_t ncols, int C, int layout, const double *x, double *y,
+                   int64_t *shared_slices, int64_t *stored, std::string &err)
+{
+    auto fail = [&](const char *m) { err = m; return -6; };
+    const int64_t n = K.n;
+    SellHost S;
+    build_sell(K, C, true, false, layout == 1 || layout == 3, layout == 2 ? 4 * C : 0, S);
+    const int32_t hi = (int32_t)(ncols - 1);
+    auto bad = [&](int64_t c) { return c < 0 || c > hi; };
+    if (layout == 3) {
+        // shared-offset slices walked as the block kernels' staged x windows:
+        // per run of the run table, window rows g0 + w (w < 63 + L, clamped
+        // where the slice needs it) are copied, then lane r reads window row
+        // r + t for the run's t-th entry; every row copied and every window
+        // slot read is checked
+        std::vector<double> win(amgk::WIN_STRIDE);
+        for (int64_t s = 0; s < S.nslices; s++) {
+            const int64_t ib = S.ibase[s];
+            if (ib >= 0) continue;   // per-row-index slices: the gather path of layout 1
+            const int64_t base = S.soff[s];
+            const int width = (int)((S.soff[s + 1] - base) / C);
+            const int64_t e = -1 - ib;
+            if ((e >> 1) + width > (int64_t)S.shoff.size()) { return fail("offset list past its array"); }
+            const int32_t *so = S.shoff.data() + (e >> 1), *rt = S.shrun.data() + (e >> 1);
+            if (rt[0] == 0) {
+                // no run table: the gather walk below
+                continue;
+            }
+            std::vector<double> acc(C, 0.0);
+            int k = 0;
+            for (int rho = 0; k < width; rho++) {
+                const int32_t pk = rt[rho];
+                if (pk == 0) break;
+                const int L = pk & 15;
+                if (L < 1 || L > amgk::WIN_LMAX || k + L > width) { return fail("run past the list or too long"); }
+                if ((pk >> 4) != so[k]) { return fail("run table and offset list disagree"); }
+                for (int t = 1; t < L; t++)
+                    if (so[k + t] != so[k] + t) { return fail("run of non-consecutive offsets"); }
+                const int64_t g0 = s * C + so[k];
+                for (int w = 0; w < C + L - 1; w++) {
+                    int64_t g = g0 + w;
+                    if (!(e & 1)) g = std::min<int64_t>(std::max<int64_t>(g, 0), hi);
+                    if (bad(g) || w >= amgk::WIN_STRIDE) { return fail("window row out of range"); }
+                    win[w] = x[g];
+                }
+                for (int r = 0; r < C; r++)
+                    for (int t = 0; t < L; t++) {
+                        if (r + t >= C + L - 1) { return fail("window slot not staged"); }
+                        const int kk = k + t;
+                        acc[r] = std::fma(S.v64[base + (kk / 2) * 2 * C + r * 2 + (kk % 2)], win[r + t], acc[r]);
+                    }
+                k += L;
+            }
+            for (int r = 0; r < C; r++)
+                if (s * C + r < n) y[s * C + r] = acc[r];
+        }
+    }
+    for (int64_t s = 0; s < S.nslices; s++) {
+        if (layout == 3 && S.ibase[s] < 0 && S.shrun[(-1 - S.ibase[s]) >> 1] != 0) continue;
+        const int64_t base = S.soff[s];
+        const int width = (int)((S.soff[s + 1] - base) / C);
+        const int64_t ib = S.ibase[s];
+        for (int r = 0; r < C; r++) {
+            const int64_t slot = s * C + r;
+            const int64_t row = S.sorted ? (int64_t)S.perm[slot] : (slot < n ? slot : -1);
+            double acc = 0.0;
+            if (ib < 0) {
+                if (S.sorted) { return fail("shared offsets in a sorted image"); }
+                const int64_t e = -1 - ib;
+                const int32_t *so = S.shoff.data() + (e >> 1);
+                if ((e >> 1) + width > (int64_t)S.shoff.size()) { return fail("offset list past its array"); }
+                for (int k = 0; k < width; k++) {
+                    int64_t c = slot + so[k];
+                    if (!(e & 1)) c = std::min<int64_t>(std::max<int64_t>(c, 0), hi);
+                    if (bad(c)) { return fail("shared-offset column out of range"); }
+                    acc = std::fma(S.v64[base + (k / 2) * 2 * C + r * 2 + (k % 2)], x[c], acc);
+                }
+            } else if (S.idx16) {
+                int64_t c = S.col0.empty() ? 0 : S.col0[slot];
+                for (int k = 0; k < width; k++) {
+                    const int64_t q = ib + (k / 8) * 8 * C + r * 8 + (k % 8);
+                    if (q >= (int64_t)S.d16.size()) { return fail("delta stream past its array"); }
+                    c += S.d16[q];
+                    if (bad(c)) { return fail("delta column out of range"); }
+                    acc = std::fma(S.v64[base + (k / 2) * 2 * C + r * 2 + (k % 2)], x[c], acc);
+                }
+            } else {
+                for (int k = 0; k < width; k++) {
+                    const int64_t q = ib + (k / 4) * 4 * C + r * 4 + (k % 4);
+                    if (q >= (int64_t)S.c32.size()) { return fail("column stream past its array"); }
+                    const int64_t c = S.c32[q];
+                    if (bad(c)) { return fail("int32 column out of range"); }
+                    acc = std::fma(S.v64[base + (k / 2) * 2 * C + r * 2 + (k % 2)], x[c], acc);
+                }
+            }
+            if (row >= 0) y[row] = acc;
+        }
+    }
+    if (shared_slices) *shared_slices = S.nshared;
+    if (stored) *stored = S.stored;
     return 0;
 }
 

@@ -34,6 +34,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "layout.h"
+
 namespace amgk {
 
 typedef double vd2 __attribute__((ext_vector_type(2)));
@@ -42,7 +44,6 @@ typedef unsigned vu4 __attribute__((ext_vector_type(4)));
 typedef int vi4 __attribute__((ext_vector_type(4)));
 
 constexpr int SLICE = 64;
-constexpr int WIN_LMAX = 8;            // longest offset run one staged x window covers
 constexpr int SELL_WAVES = 4;          // slices (wavefronts) per 256-thread block
 constexpr int XCDS = 8;                // accelerator complex dies sharing the grid (one L2 each)
 

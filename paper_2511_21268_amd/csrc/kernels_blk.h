@@ -166,7 +166,6 @@ __global__ __launch_bounds__(256) void k_sell_blk(const Sell<VT, IT> A, const VT
 // gather path.  The window is private to its wave: only that wave's own LDS
 // operations order its accesses (in-order per wave), fenced for the compiler
 // by wave_lds_sync.
-constexpr int WIN_STRIDE = 73;   // window rows per chunk column (>= SLICE + WIN_LMAX - 1, odd)
 
 __device__ inline void wave_lds_sync()
 {

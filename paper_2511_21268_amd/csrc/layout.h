@@ -1,0 +1,8 @@
+// Constants of the device matrix layout shared by the kernels (HIP) and the
+// host code that builds and checks the images (plain C++).
+#pragma once
+
+namespace amgk {
+constexpr int WIN_LMAX = 8;      // longest offset run one staged x window covers
+constexpr int WIN_STRIDE = 73;   // window rows per chunk column (>= 64 + WIN_LMAX - 1, odd)
+}  // namespace amgk

@@ -14,6 +14,7 @@
 #include "setup_dev.h"
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <atomic>
@@ -30,8 +31,28 @@
 using namespace amgk;
 using amgiga::CsrView;
 using amgiga::HostHierarchy;
+using amgiga::SellHost;
+using amgiga::build_sell;
+using amgiga::count_shared;
 
 static thread_local std::string g_err;
+
+// rocTX range over a scope (host side: the solve, each Krylov iteration, each
+// V-cycle level's launches), for traces taken with a marker-tracing profiler;
+// without one the calls do nothing.
+struct TxRange {
+    explicit TxRange(const char *m) { roctxRangePushA(m); }
+    ~TxRange() { roctxRangePop(); }
+};
+static const char *level_label(int l)
+{
+    static const std::vector<std::string> names = [] {
+        std::vector<std::string> v;
+        for (int i = 0; i < 64; i++) v.push_back("amg level " + std::to_string(i));
+        return v;
+    }();
+    return names[(size_t)std::min(std::max(l, 0), 63)].c_str();
+}
 
 namespace {
 
@@ -69,217 +90,6 @@ inline unsigned nblocks(int64_t n, int per = 256) { return (unsigned)((n + per -
 inline unsigned vgrid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256)); }
 
 // Host-side sliced-ELL image of one level (layout described in kernels.h).
-struct SellHost {
-    int64_t nslices = 0, stored = 0, nshared = 0;
-    int sorted = 0;
-    std::vector<int32_t> perm;
-    double index_bytes = 0.0;   // index data a pass must read (no padding)
-    int idx16 = 1;
-    std::vector<int64_t> soff, ibase;
-    std::vector<double> v64;
-    std::vector<float> v32;
-    std::vector<uint16_t> d16;
-    std::vector<int32_t> c32, col0, shoff, shrun;
-};
-
-// Ascending union of the column offsets (column - row) of the rows of slice s,
-// or an empty list when it would be longer than `limit`.
-static std::vector<int32_t> slice_offsets(const CsrView &K, int64_t s, int C, int64_t limit)
-{
-    std::vector<int32_t> u, m;
-    for (int64_t r = s * C; r < std::min(K.n, (s + 1) * C); r++) {
-        m.clear();
-        size_t a = 0;
-        for (int64_t k = K.rp[r]; k < K.rp[r + 1]; k++) {
-            const int32_t o = (int32_t)(K.ci[k] - r);
-            while (a < u.size() && u[a] < o) m.push_back(u[a++]);
-            if (a < u.size() && u[a] == o) a++;
-            m.push_back(o);
-        }
-        while (a < u.size()) m.push_back(u[a++]);
-        if ((int64_t)m.size() > limit) return {};
-        u.swap(m);
-    }
-    return u;
-}
-
-// Number of C-row slices whose offset unions would be stored once.
-static int64_t count_shared(const CsrView &K, int C)
-{
-    const int64_t ns = (K.n + C - 1) / C;
-    std::atomic<int64_t> cnt{0};
-    amgiga::parallel_for(ns, [&](int64_t sb, int64_t se) {
-        int64_t c = 0;
-        for (int64_t s = sb; s < se; s++) {
-            int64_t w = 0;
-            for (int64_t r = s * C; r < std::min(K.n, (s + 1) * C); r++) w = std::max(w, K.rp[r + 1] - K.rp[r]);
-            if (w > 0 && !slice_offsets(K, s, C, (w + 7) / 8 * 8).empty()) c++;
-        }
-        cnt += c;
-    }, 1);
-    return cnt.load();
-}
-
-// SELL-C image of a CSR matrix (slice height C rows; group layout of kernels.h).
-// With `shared`, a slice whose offset union is no wider than its longest row
-// (both rounded up to 8) stores the union once; the others keep per-row indices.
-// With sigma > 0 (no shared offsets then), the rows of every window of sigma
-// consecutive rows are placed in the window's slots by decreasing length (ties
-// by index), so the slices of a window pad to similar lengths; perm[slot]
-// gives the row of each slot (-1 for the slots past the last row).
-void build_sell(const CsrView &K, int C, bool want64, bool want32, bool shared, int sigma, SellHost &S)
-{
-    const int64_t n = K.n;
-    S.nslices = (n + C - 1) / C;
-    const int64_t nslot = S.nslices * C;
-    if (sigma > 0) shared = false;
-    std::vector<int32_t> rowof(nslot, -1);
-    auto len = [&](int64_t r) { return K.rp[r + 1] - K.rp[r]; };
-    amgiga::parallel_for((n + std::max(sigma, 1) - 1) / std::max(sigma, 1), [&](int64_t wb, int64_t we) {
-        for (int64_t w = wb; w < we; w++) {
-            const int64_t a = w * std::max(sigma, 1), e = std::min(n, a + std::max(sigma, 1));
-            for (int64_t r = a; r < e; r++) rowof[r] = (int32_t)r;
-            if (sigma > 0)
-                std::stable_sort(rowof.begin() + a, rowof.begin() + e,
-                                 [&](int32_t x, int32_t y) { return len(x) > len(y); });
-        }
-    }, 1);
-    S.sorted = sigma > 0 ? 1 : 0;
-    if (S.sorted) S.perm = rowof;
-    std::vector<int64_t> wd(S.nslices);
-    std::vector<std::vector<int32_t>> U(S.nslices);
-    amgiga::parallel_for(S.nslices, [&](int64_t sb, int64_t se) {
-        for (int64_t s = sb; s < se; s++) {
-            int64_t w = 0;
-            for (int64_t q = s * C; q < (s + 1) * C; q++)
-                if (rowof[q] >= 0) w = std::max(w, len(rowof[q]));
-            wd[s] = (w + 7) / 8 * 8;
-            if (shared && w > 0) U[s] = slice_offsets(K, s, C, wd[s]);
-        }
-    }, 1);
-    S.soff.assign(S.nslices + 1, 0);
-    S.ibase.assign(S.nslices, 0);
-    int64_t ib = 0, sh = 0;
-    S.nshared = 0;
-    S.index_bytes = 0.0;
-    // identical offset lists (the interior slices of a stencil matrix) are
-    // stored once, so the wavefronts reading them share cache lines
-    std::map<std::vector<int32_t>, int64_t> lists;
-    for (int64_t s = 0; s < S.nslices; s++) {
-        const int64_t w = U[s].empty() ? wd[s] : (int64_t)(U[s].size() + 7) / 8 * 8;
-        S.soff[s + 1] = S.soff[s] + C * w;
-        if (U[s].empty()) {
-            S.ibase[s] = ib;
-            ib += C * w;
-        } else {
-            // every lane r of the slice (rows s*C .. s*C+C-1, padding rows
-            // included) reads column row + offset for every stored offset,
-            // the padding offsets 0 included
-            const int64_t lo = s * C + std::min<int64_t>(0, U[s].front());
-            const int64_t hi = s * C + C - 1 + std::max<int64_t>(0, U[s].back());
-            const int64_t inrange = (lo >= 0 && hi < n) ? 1 : 0;
-            auto it = lists.find(U[s]);
-            if (it == lists.end()) {
-                it = lists.emplace(U[s], sh).first;
-                sh += w;
-                S.index_bytes += 4.0 * (double)U[s].size();
-            }
-            S.ibase[s] = -1 - (2 * it->second + inrange);
-            S.nshared++;
-        }
-    }
-    S.stored = S.soff[S.nslices];
-    int maxd = 0;
-    int64_t dnnz = 0, drows = 0;
-    {
-        std::mutex mx;
-        amgiga::parallel_for(S.nslices, [&](int64_t sb, int64_t se) {
-            int m = 0;
-            int64_t z = 0, nr = 0;
-            for (int64_t s = sb; s < se; s++) {
-                if (!U[s].empty()) continue;
-                for (int64_t q = s * C; q < (s + 1) * C; q++) {
-                    const int64_t r = rowof[q];
-                    if (r < 0) continue;
-                    for (int64_t k = K.rp[r] + 1; k < K.rp[r + 1]; k++) m = std::max(m, K.ci[k] - K.ci[k - 1]);
-                    z += K.rp[r + 1] - K.rp[r];
-                    nr++;
-                }
-            }
-            std::lock_guard<std::mutex> g(mx);
-            maxd = std::max(maxd, m);
-            dnnz += z;
-            drows += nr;
-        }, 1);
-    }
-    S.idx16 = maxd <= 65535 ? 1 : 0;
-    S.index_bytes += S.idx16 ? 2.0 * (double)dnnz + 4.0 * (double)drows : 4.0 * (double)dnnz;
-    if (want64) S.v64.assign(S.stored, 0.0);
-    if (want32) S.v32.assign(S.stored, 0.0f);
-    if (ib > 0) {
-        if (S.idx16) {
-            S.d16.assign(ib, 0);
-            S.col0.assign(S.nslices * C, 0);
-        } else {
-            S.c32.assign(ib, 0);
-        }
-    }
-    S.shoff.assign(sh, 0);
-    for (const auto &kv : lists) std::copy(kv.first.begin(), kv.first.end(), S.shoff.begin() + kv.second);
-    // run table of each list for the block kernels' staged x windows: its
-    // runs of consecutive offsets (o, o+1, ...), at most WIN_LMAX long, in
-    // order from the list's position, packed as o * 16 + length, then 0; a
-    // list with an offset beyond +-2^27 gets no table (first entry 0)
-    S.shrun.assign(sh, 0);
-    for (const auto &kv : lists) {
-        const std::vector<int32_t> &u = kv.first;
-        bool fits = true;
-        for (int32_t o : u) fits = fits && o >= -(1 << 27) && o < (1 << 27);
-        if (!fits) continue;
-        int64_t rho = 0;
-        for (size_t k = 0; k < u.size();) {
-            size_t L = 1;
-            while (L < (size_t)WIN_LMAX && k + L < u.size() && u[k + L] == u[k] + (int32_t)L) L++;
-            S.shrun[kv.second + rho++] = u[k] * 16 + (int32_t)L;
-            k += L;
-        }
-    }
-    amgiga::parallel_for(S.nslices, [&](int64_t sb, int64_t se) {
-        for (int64_t s = sb; s < se; s++) {
-            const int64_t base = S.soff[s];
-            const int64_t w = (S.soff[s + 1] - base) / C;
-            const bool sl = !U[s].empty();
-            for (int lane = 0; lane < C; lane++) {
-                const int64_t q = s * C + lane, r = rowof[q];
-                const int64_t len = r >= 0 ? K.rp[r + 1] - K.rp[r] : 0;
-                const int64_t r0 = r >= 0 ? K.rp[r] : 0;
-                auto put = [&](int64_t k, double v) {
-                    if (want64) S.v64[base + (k / 2) * 2 * C + lane * 2 + (k % 2)] = v;
-                    if (want32) S.v32[base + (k / 4) * 4 * C + lane * 4 + (k % 4)] = (float)v;
-                };
-                if (sl) {
-                    int64_t j = 0;
-                    for (int64_t k = 0; k < (int64_t)U[s].size() && j < len; k++)
-                        if (K.ci[r0 + j] - r == U[s][k]) put(k, K.v[r0 + j++]);
-                    continue;
-                }
-                const int64_t ibs = S.ibase[s];
-                if (S.idx16 && r >= 0) S.col0[q] = K.ci[r0];
-                for (int64_t k = 0; k < w; k++) {
-                    put(k, k < len ? K.v[r0 + k] : 0.0);
-                    if (S.idx16) {
-                        int d = (k >= 1 && k < len) ? K.ci[r0 + k] - K.ci[r0 + k - 1] : 0;
-                        S.d16[ibs + (k / 8) * 8 * C + lane * 8 + (k % 8)] = (uint16_t)d;
-                    } else {
-                        int32_t c = k < len ? K.ci[r0 + k] : (len > 0 ? K.ci[r0 + len - 1] : 0);
-                        S.c32[ibs + (k / 4) * 4 * C + lane * 4 + (k % 4)] = c;
-                    }
-                }
-            }
-        }
-    }, 1);
-}
-
 struct DevMat {
     int64_t n = 0, ncols = 0, nnz = 0, nslices = 0, stored = 0, nshared = 0;
     double index_bytes = 0.0;
@@ -424,6 +234,7 @@ struct amg_ctx {
     amgiga::DevSetupInfo setup_info;
     double *sc = nullptr;
     double *hsc = nullptr;     // pinned host copy of the scalar block
+    std::vector<double> hist;  // ||r_k|| / ||F|| of the last pcg_solve, k = 0 .. iterations
     hipEvent_t ev_iter = nullptr;
     std::vector<void *> allocs;
     // profiling
@@ -431,6 +242,9 @@ struct amg_ctx {
     std::vector<hipEvent_t> evpool;
     size_t evused = 0;
     std::vector<double> evbytes;
+    std::vector<int> evkind;
+    int64_t pk_launches[AMG_PASS_KINDS] = {};
+    double pk_ms[AMG_PASS_KINDS] = {}, pk_bytes[AMG_PASS_KINDS] = {};
     int64_t prof_launches = 0;
     double prof_ms = 0.0, prof_bytes = 0.0;
 
@@ -696,11 +510,12 @@ struct amg_ctx {
         }
         HIPCHK(hipEventRecord(evpool[evused], stream));
     }
-    void prof_end(double bytes)
+    void prof_end(double bytes, int kind)
     {
         if (!prof) return;
         HIPCHK(hipEventRecord(evpool[evused + 1], stream));
         evbytes.push_back(bytes);
+        evkind.push_back(kind);
         evused += 2;
     }
     void prof_collect()
@@ -712,9 +527,19 @@ struct amg_ctx {
             prof_ms += ms;
             prof_launches++;
             prof_bytes += evbytes[k / 2];
+            const int kd = evkind[k / 2];
+            pk_ms[kd] += ms;
+            pk_launches[kd]++;
+            pk_bytes[kd] += evbytes[k / 2];
         }
         evused = 0;
         evbytes.clear();
+        evkind.clear();
+    }
+    static constexpr int pass_kind(int epi)
+    {
+        return epi == EPI_SPMV ? AMG_PASS_SPMV : epi == EPI_RESID ? AMG_PASS_RESID
+             : epi == EPI_SMOOTH ? AMG_PASS_SMOOTH : epi == EPI_POLY ? AMG_PASS_POLY : AMG_PASS_OTHER;
     }
     // algorithmic bytes of one level-0 pass: matrix without padding + vectors
     double pass_bytes(int vb, int nvec) const
@@ -735,7 +560,7 @@ struct amg_ctx {
                        (NDOT >= 2 ? 1 : 0) + (EPI == EPI_SMOOTH && NDOT >= 1 ? 1 : 0);
             prof_begin();
             launch_sell<VT, FT, OT, EPI, NDOT>(A, nb, x, f, invd, y, g0, g1, coef);
-            prof_end(pass_bytes((int)sizeof(VT), nvec));
+            prof_end(pass_bytes((int)sizeof(VT), nvec), pass_kind(EPI));
         } else {
             launch_sell<VT, FT, OT, EPI, NDOT>(A, nb, x, f, invd, y, g0, g1, coef);
         }
@@ -780,7 +605,7 @@ struct amg_ctx {
                            (double)sizeof(VT) * lev[1].n +                         // e gathered once
                            (double)sizeof(VT) * A.n * 4 + 4.0 * A.n +               // u, r, invd, pc, agg
                            (double)sizeof(OT) * A.n + 8.0 * A.n * ndot;              // y, dot partners
-            prof_end(bytes);
+            prof_end(bytes, AMG_PASS_KP);
         }
         return nb * SELL_WAVES;   // one dot partial per wavefront
     }
@@ -802,7 +627,7 @@ struct amg_ctx {
         if (l == 0) {
             double bytes = (double)A.nnz * sizeof(VT) + A.index_bytes + (double)sizeof(VT) * lev[1].n +
                            (double)sizeof(VT) * A.n * 5 + 4.0 * A.n;   // u, pc, r read, r and y written, agg
-            prof_end(bytes);
+            prof_end(bytes, AMG_PASS_KP);
         }
     }
     void finalize(unsigned nblk, int op, int slot = 0)
@@ -877,6 +702,7 @@ struct amg_ctx {
     template <typename VT, typename FT>
     VT *vlevel(int l, const FT *f, double *zout, int ndot, const double *g0, const double *g1, bool u_ready)
     {
+        TxRange tx(level_label(l));
         Level &L = lev[l];
         VT *u = (VT *)L.u, *u2 = (VT *)L.u2;
         // 1. pre-smoothing from the zero guess
@@ -1016,7 +842,7 @@ struct amg_ctx {
             // MODES 1/2 read x, r or f, u unless first, and write u, r; MODE 1
             // also reads invd and writes dn
             const int nvec = MODE == 0 ? 5 : (first ? 4 : 5) + (MODE == 1 ? 2 : 0);
-            prof_end(pass_bytes(8, nvec));
+            prof_end(pass_bytes(8, nvec), AMG_PASS_OTHER);
         }
     }
 
@@ -1219,11 +1045,15 @@ struct amg_ctx {
         if (l == 0) {
             // 16 columns: matrix once, 16 vectors of each kind
             const DevMat &M = lev[0].A;
-            int nvec = 2 + (EPI == EPI_RESID ? 1 : 0) + (EPI == EPI_SMOOTH ? 1 : 0) + (EPI == EPI_POLY ? 1 : 0) +
-                       (NDOT >= 2 ? 1 : 0) + (EPI == EPI_SMOOTH && NDOT >= 1 ? 1 : 0);
-            double bytes = (double)M.nnz * sizeof(VT) + M.index_bytes + (double)nvec * NB * sizeof(VT) * M.n +
+            // 16 columns: matrix once; X read and Y written once; F for the
+            // residual, smoother and polynomial passes; invd per row; the FP64
+            // dot partners (SpMV: G1 with two dots; smoother: G0, G1)
+            const bool usesF = EPI == EPI_RESID || EPI == EPI_SMOOTH || EPI == EPI_POLY;
+            const int ndp = EPI == EPI_SPMV ? (NDOT >= 2 ? 1 : 0) : EPI == EPI_SMOOTH ? NDOT : 0;
+            double bytes = (double)M.nnz * sizeof(VT) + M.index_bytes +
+                           (double)NB * M.n * (sizeof(VT) + sizeof(OT) + (usesF ? sizeof(FT) : 0) + 8.0 * ndp) +
                            ((EPI == EPI_SMOOTH || EPI == EPI_POLY) ? (double)sizeof(VT) * M.n : 0.0);
-            prof_end(bytes);
+            prof_end(bytes, pass_kind(EPI));
         }
         return nb;
     }
@@ -1295,7 +1125,7 @@ struct amg_ctx {
             double bytes = (double)A.nnz * sizeof(VT) + A.index_bytes + (double)NB * sizeof(VT) * lev[1].n + (double)NB * sizeof(VT) * A.n * 2 +
                            (double)sizeof(VT) * A.n * 2 + 4.0 * A.n + (double)NB * sizeof(OT) * A.n +
                            8.0 * NB * A.n * ndot;
-            prof_end(bytes);
+            prof_end(bytes, AMG_PASS_KP);
         }
         return multi ? nb : nb * SELL_WAVES;   // one-lane kernel: a dot partial per wavefront
     }
@@ -1333,6 +1163,7 @@ struct amg_ctx {
     template <typename VT, typename FT>
     VT *vlevel_blk(int l, const FT *f, double *zout, int ndot, const double *g0, const double *g1, bool u_ready)
     {
+        TxRange tx(level_label(l));
         Level &L = lev[l];
         VT *u = (VT *)L.bu, *u2 = (VT *)L.bu2;
         if (!u_ready) {
@@ -1574,6 +1405,7 @@ static amg_status setup_common(int64_t n, const int64_t *row_ptr, const int32_t 
                                const double *w, const amg_params *prm, void *hip_stream, int host_only,
                                amg_ctx **out)
 {
+    TxRange tx("amg_setup");
     g_err.clear();
     if (!out) { set_err("NULL out"); return AMG_ERR_ARG; }
     *out = nullptr;
@@ -1666,9 +1498,6 @@ amg_status amg_setup_host(int64_t n, const int64_t *row_ptr, const int32_t *col,
     return setup_common(n, row_ptr, col, val, w, prm, nullptr, 1, out);
 }
 
-// window rows per chunk column of the block kernels' staged x windows
-static constexpr int WIN_STRIDE_HOST = WIN_STRIDE;
-
 amg_status amg_sell_spmv_host(int64_t n, int64_t ncols, const int64_t *row_ptr, const int32_t *col,
                               const double *val, int C, int layout, const double *x, double *y,
                               int64_t *shared_slices, int64_t *stored)
@@ -1689,102 +1518,10 @@ amg_status amg_sell_spmv_host(int64_t n, int64_t ncols, const int64_t *row_ptr, 
             }
     }
     CsrView K{n, row_ptr, col, val};
-    SellHost S;
-    build_sell(K, C, true, false, layout == 1 || layout == 3, layout == 2 ? 4 * C : 0, S);
-    const int32_t hi = (int32_t)(ncols - 1);
-    auto bad = [&](int64_t c) { return c < 0 || c > hi; };
-    if (layout == 3) {
-        // shared-offset slices walked as the block kernels' staged x windows:
-        // per run of the run table, window rows g0 + w (w < 63 + L, clamped
-        // where the slice needs it) are copied, then lane r reads window row
-        // r + t for the run's t-th entry; every row copied and every window
-        // slot read is checked
-        std::vector<double> win(WIN_STRIDE_HOST);
-        for (int64_t s = 0; s < S.nslices; s++) {
-            const int64_t ib = S.ibase[s];
-            if (ib >= 0) continue;   // per-row-index slices: the gather path of layout 1
-            const int64_t base = S.soff[s];
-            const int width = (int)((S.soff[s + 1] - base) / C);
-            const int64_t e = -1 - ib;
-            if ((e >> 1) + width > (int64_t)S.shoff.size()) { set_err("offset list past its array"); return AMG_ERR_STATE; }
-            const int32_t *so = S.shoff.data() + (e >> 1), *rt = S.shrun.data() + (e >> 1);
-            if (rt[0] == 0) {
-                // no run table: the gather walk below
-                continue;
-            }
-            std::vector<double> acc(C, 0.0);
-            int k = 0;
-            for (int rho = 0; k < width; rho++) {
-                const int32_t pk = rt[rho];
-                if (pk == 0) break;
-                const int L = pk & 15;
-                if (L < 1 || L > WIN_LMAX || k + L > width) { set_err("run past the list or too long"); return AMG_ERR_STATE; }
-                if ((pk >> 4) != so[k]) { set_err("run table and offset list disagree"); return AMG_ERR_STATE; }
-                for (int t = 1; t < L; t++)
-                    if (so[k + t] != so[k] + t) { set_err("run of non-consecutive offsets"); return AMG_ERR_STATE; }
-                const int64_t g0 = s * C + so[k];
-                for (int w = 0; w < C + L - 1; w++) {
-                    int64_t g = g0 + w;
-                    if (!(e & 1)) g = std::min<int64_t>(std::max<int64_t>(g, 0), hi);
-                    if (bad(g) || w >= WIN_STRIDE_HOST) { set_err("window row out of range"); return AMG_ERR_STATE; }
-                    win[w] = x[g];
-                }
-                for (int r = 0; r < C; r++)
-                    for (int t = 0; t < L; t++) {
-                        if (r + t >= C + L - 1) { set_err("window slot not staged"); return AMG_ERR_STATE; }
-                        const int kk = k + t;
-                        acc[r] = std::fma(S.v64[base + (kk / 2) * 2 * C + r * 2 + (kk % 2)], win[r + t], acc[r]);
-                    }
-                k += L;
-            }
-            for (int r = 0; r < C; r++)
-                if (s * C + r < n) y[s * C + r] = acc[r];
-        }
-    }
-    for (int64_t s = 0; s < S.nslices; s++) {
-        if (layout == 3 && S.ibase[s] < 0 && S.shrun[(-1 - S.ibase[s]) >> 1] != 0) continue;
-        const int64_t base = S.soff[s];
-        const int width = (int)((S.soff[s + 1] - base) / C);
-        const int64_t ib = S.ibase[s];
-        for (int r = 0; r < C; r++) {
-            const int64_t slot = s * C + r;
-            const int64_t row = S.sorted ? (int64_t)S.perm[slot] : (slot < n ? slot : -1);
-            double acc = 0.0;
-            if (ib < 0) {
-                if (S.sorted) { set_err("shared offsets in a sorted image"); return AMG_ERR_STATE; }
-                const int64_t e = -1 - ib;
-                const int32_t *so = S.shoff.data() + (e >> 1);
-                if ((e >> 1) + width > (int64_t)S.shoff.size()) { set_err("offset list past its array"); return AMG_ERR_STATE; }
-                for (int k = 0; k < width; k++) {
-                    int64_t c = slot + so[k];
-                    if (!(e & 1)) c = std::min<int64_t>(std::max<int64_t>(c, 0), hi);
-                    if (bad(c)) { set_err("shared-offset column out of range"); return AMG_ERR_STATE; }
-                    acc = std::fma(S.v64[base + (k / 2) * 2 * C + r * 2 + (k % 2)], x[c], acc);
-                }
-            } else if (S.idx16) {
-                int64_t c = S.col0.empty() ? 0 : S.col0[slot];
-                for (int k = 0; k < width; k++) {
-                    const int64_t q = ib + (k / 8) * 8 * C + r * 8 + (k % 8);
-                    if (q >= (int64_t)S.d16.size()) { set_err("delta stream past its array"); return AMG_ERR_STATE; }
-                    c += S.d16[q];
-                    if (bad(c)) { set_err("delta column out of range"); return AMG_ERR_STATE; }
-                    acc = std::fma(S.v64[base + (k / 2) * 2 * C + r * 2 + (k % 2)], x[c], acc);
-                }
-            } else {
-                for (int k = 0; k < width; k++) {
-                    const int64_t q = ib + (k / 4) * 4 * C + r * 4 + (k % 4);
-                    if (q >= (int64_t)S.c32.size()) { set_err("column stream past its array"); return AMG_ERR_STATE; }
-                    const int64_t c = S.c32[q];
-                    if (bad(c)) { set_err("int32 column out of range"); return AMG_ERR_STATE; }
-                    acc = std::fma(S.v64[base + (k / 2) * 2 * C + r * 2 + (k % 2)], x[c], acc);
-                }
-            }
-            if (row >= 0) y[row] = acc;
-        }
-    }
-    if (shared_slices) *shared_slices = S.nshared;
-    if (stored) *stored = S.stored;
-    return AMG_OK;
+    std::string err;
+    const int st = amgiga::sell_spmv_walk(K, ncols, C, layout, x, y, shared_slices, stored, err);
+    if (st != 0) set_err(err);
+    return (amg_status)st;
 }
 
 amg_status amg_match(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val, const double *w,
@@ -1806,7 +1543,9 @@ void amg_destroy(amg_ctx *c) { delete c; }
 static amg_status solve_impl(amg_ctx *c, const double *F, double *u_user, double tol, int *iters, double *relres,
                              double *relres_true)
 {
+    TxRange tx("pcg_solve");
     const int64_t n = c->n;
+    c->hist.clear();
     const bool flex = c->prm.krylov >= 1;
     const int itmax = c->prm.itmax;
     const bool graph = c->use_graph && !c->prof;
@@ -1840,6 +1579,7 @@ static amg_status solve_impl(amg_ctx *c, const double *F, double *u_user, double
     }
     const double nF = std::sqrt(ff);
     double rr = c->hsc[S_RR];
+    c->hist.push_back(std::sqrt(rr) / nF);
     amg_status status = AMG_NOT_CONVERGED;
     int k = 0;
     // iteration body, part A: q = K p, (p, q) [, (p, r)] -> alpha;
@@ -1873,6 +1613,7 @@ static amg_status solve_impl(amg_ctx *c, const double *F, double *u_user, double
             c->gB[flex] = c->capture(partB);
         }
         for (k = 1; k <= itmax; k++) {
+            TxRange txi("pcg iteration");
             if (graph) HIPCHK(hipGraphLaunch(c->gA[flex], st));
             else partA();
             HIPCHK(hipEventRecord(c->ev_iter, st));
@@ -1889,6 +1630,7 @@ static amg_status solve_impl(amg_ctx *c, const double *F, double *u_user, double
                 break;
             }
             rr = c->hsc[S_RR];
+            c->hist.push_back(std::sqrt(rr) / nF);
             if (std::sqrt(rr) <= tol * nF) { status = AMG_OK; break; }
         }
         if (k > itmax) k = itmax;
@@ -1931,6 +1673,7 @@ amg_status pcg_solve(amg_ctx *c, const double *F, double *u, double tol, int *it
 static amg_status solve_block_impl(amg_ctx *c, int nrhs, const double *F, double *U, double tol, int *iters,
                                    double *relres)
 {
+    TxRange tx("pcg_solve_batched (block CG)");
     const int64_t n = c->n;
     const int itmax = c->prm.itmax;
     hipStream_t st = c->stream;
@@ -2010,6 +1753,7 @@ static amg_status solve_block_impl(amg_ctx *c, int nrhs, const double *F, double
 static amg_status solve_batched_impl(amg_ctx *c, int nrhs, const double *F, double *U, double tol, int *iters,
                                      double *relres)
 {
+    TxRange tx("pcg_solve_batched");
     if (c->prm.krylov == 2) return solve_block_impl(c, nrhs, F, U, tol, iters, relres);
     const int64_t n = c->n;
     const bool flex = c->prm.krylov >= 1;
@@ -2176,6 +1920,15 @@ amg_status amg_set_option(amg_ctx *c, int option, int value)
     return AMG_OK;
 }
 
+amg_status amg_get_residual_history(const amg_ctx *c, double *hist, int cap, int *count)
+{
+    if (!c || cap < 0 || (cap > 0 && !hist)) { set_err("NULL context or buffer, or cap < 0"); return AMG_ERR_ARG; }
+    const int m = (int)c->hist.size();
+    for (int k = 0; k < std::min(m, cap); k++) hist[k] = c->hist[(size_t)k];
+    if (count) *count = m;
+    return AMG_OK;
+}
+
 amg_status amg_get_option(const amg_ctx *c, int option, int *value)
 {
     if (!c || !value) { set_err("NULL argument"); return AMG_ERR_ARG; }
@@ -2304,6 +2057,20 @@ amg_status amg_set_profiling(amg_ctx *c, int enable)
     c->prof_launches = 0;
     c->prof_ms = 0.0;
     c->prof_bytes = 0.0;
+    for (int k = 0; k < AMG_PASS_KINDS; k++) {
+        c->pk_launches[k] = 0;
+        c->pk_ms[k] = 0.0;
+        c->pk_bytes[k] = 0.0;
+    }
+    return AMG_OK;
+}
+
+amg_status amg_get_profile_pass(const amg_ctx *c, int kind, int64_t *launches, double *ms, double *bytes)
+{
+    if (!c || kind < 0 || kind >= AMG_PASS_KINDS) { set_err("NULL context or unknown pass kind"); return AMG_ERR_ARG; }
+    if (launches) *launches = c->pk_launches[kind];
+    if (ms) *ms = c->pk_ms[kind];
+    if (bytes) *bytes = c->pk_bytes[kind];
     return AMG_OK;
 }
 

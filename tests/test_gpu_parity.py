@@ -225,3 +225,22 @@ def test_shared_offset_slices(oracle, amg, case):
             assert bt["status"] == 0 and all(same_iters(x, y) for x, y in zip(bt["iters"], bb["iters"])), (lpr, thr)
             assert all(close(bt["U"][:, j], bb["U"][:, j], Fb[:, j]) for j in range(3)), (lpr, thr)
         t.close()
+
+
+def test_residual_history_matches_oracle(oracle, amg):
+    """The residual history of pcg_solve (the Krylov call's trace output,
+    Sec. 4): ||r_k|| / ||F|| for k = 0 .. iterations, against the oracle's."""
+    print("case residual history 2D p=2 n=32 seed 0", flush=True)
+    from paper_2511_21268_amd.workloads import rhs_normal
+    rp, ci, v, _ = oracle.poisson_kron(2, 2, 32)
+    F = rhs_normal(len(rp) - 1, 0)
+    ref = oracle.Hierarchy(rp, ci, v).solve(F, tol=1e-8)
+    ctx = amg.Context(rp, ci, v)
+    assert len(ctx.residual_history()) == 0
+    out = ctx.solve(torch.from_numpy(F).cuda(), tol=1e-8)
+    h = ctx.residual_history()
+    assert len(h) == out["iters"] + 1 == len(ref["hist"])
+    assert h[0] == 1.0 and h[-1] == pytest.approx(out["relres"], rel=1e-15)
+    np.testing.assert_allclose(h, ref["hist"], rtol=1e-9)
+    out0 = ctx.solve(torch.zeros_like(torch.from_numpy(F)).cuda(), tol=1e-8)
+    assert out0["iters"] == 0 and len(ctx.residual_history()) == 0
