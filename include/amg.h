@@ -294,8 +294,17 @@ const char *amg_last_error(void);
  *   `value` rows (and 16 / value columns) per lane; 0 turns this off (those
  *   images then take the lanes-per-row variant of amg_set_batched_variant).
  *   Bitwise the same results in every setting.
+ * AMG_OPT_TAIL (default on): the coarsest levels of the V-cycle -- from the
+ *   first level down whose every level has at most 2048 rows and 60,000
+ *   entries -- run in one persistent single-workgroup kernel per V-cycle
+ *   (residual, restriction, Cholesky solve, fused post-smoothing, level after
+ *   level) instead of one launch per step; single-vector and batched solves,
+ *   l1-Jacobi with one pre- and one post-sweep and the fused post-smoothing
+ *   only (else the per-level kernels run).  Bitwise the same results.
+ *   amg_get_option returns the first tail level, or 0 when the tail is off or
+ *   not available.
  * amg_get_option returns the current value of an option. */
-typedef enum { AMG_OPT_GRAPH = 1, AMG_OPT_FUSE_POST = 2, AMG_OPT_BLOCK_WINDOW = 3 } amg_option;
+typedef enum { AMG_OPT_GRAPH = 1, AMG_OPT_FUSE_POST = 2, AMG_OPT_BLOCK_WINDOW = 3, AMG_OPT_TAIL = 4 } amg_option;
 amg_status amg_set_option(amg_ctx *c, int option, int value);
 amg_status amg_get_option(const amg_ctx *c, int option, int *value);
 

@@ -326,6 +326,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     }
 }
 
+// One row of the fused prolongation + post-smoothing (k_sell_post, the block
+// variants and the V-cycle tail share it, so their bits agree):
+// u' = u + pc e_agg, y = u' + invd (r - acc).
+template <typename VT> __device__ __forceinline__ VT post_update(VT u, VT pc, VT e, VT invd, VT r, VT acc)
+{
+    VT up = u + pc * e;
+    return up + invd * (r - acc);
+}
+
 // Prolongation fused with the first l1-Jacobi post-smoothing sweep:
 //   u' = u + P e,   y = u' + D^{-1} (f - K u') = u' + D^{-1} (r - (K P) e)
 // with r = f - K u kept from the residual pass and acc = ((K P) e)_row taken
@@ -350,8 +359,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
             for (int t = 0; t < 8; t++) acc = fma(v[t], ld32(e, c[t]), acc);
         });
         if (row >= 0) {
-            VT up = u[row] + pc[row] * e[agg[row]];
-            VT out = up + invd[row] * (r[row] - acc);
+            VT out = post_update(u[row], pc[row], e[agg[row]], invd[row], r[row], acc);
             y[row] = (OT)out;
             if (NDOT >= 1) d0 = (double)out * g0[row];
             if (NDOT >= 2) d1 = (double)out * g1[row];

@@ -603,8 +603,7 @@ __global__ __launch_bounds__(256) void k_sell_blk_post(const Sell<VT, IT> A, con
             const VT di = invd[row], pi = pc[row];
 #pragma unroll
             for (int j = 0; j < NB; j++) {
-                VT up = U[o + j] + pi * E[a + j];
-                VT out = up + di * (R[o + j] - acc[j]);
+                VT out = post_update(U[o + j], pi, E[a + j], di, R[o + j], acc[j]);
                 Y[o + j] = (OT)out;
                 if (NDOT >= 1) d0[j] = (double)out * G0[o + j];
                 if (NDOT >= 2) d1[j] = (double)out * G1[o + j];
@@ -662,8 +661,7 @@ __global__ __launch_bounds__(512) void k_sellb_post(const Sell<VT, IT> A, const 
             const VT di = invd[row], pi = pc[row];
 #pragma unroll
             for (int j = 0; j < RPL; j++) {
-                VT up = U[o + j] + pi * E[a + j];
-                VT out = up + di * (R[o + j] - acc[j]);
+                VT out = post_update(U[o + j], pi, E[a + j], di, R[o + j], acc[j]);
                 Y[o + j] = (OT)out;
                 if (NDOT >= 1) d0[j] += (double)out * G0[o + j];
                 if (NDOT >= 2) d1[j] += (double)out * G1[o + j];

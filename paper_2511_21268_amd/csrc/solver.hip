@@ -12,6 +12,7 @@
 #include "mlp.h"
 #include "post_res.h"
 #include "setup_dev.h"
+#include "tail.h"
 
 #include <hip/hip_runtime.h>
 #include <rocprofiler-sdk-roctx/roctx.h>
@@ -175,6 +176,11 @@ struct amg_ctx {
     // graph replay of the iteration body (single: [0]=CG [1]=FCG; batched likewise)
     int use_graph = 0;
     int fuse_post = 1;   // fused prolongation + post-smoothing through K P (when built)
+    // V-cycle tail in one persistent workgroup (k_vtail): levels tail_start ..
+    // nlev-2 and the coarsest; device arrays of their TailLevel descriptors for
+    // the single-vector and the 16-column buffers
+    int use_tail = 1, tail_start = -1;
+    void *tail_dev = nullptr, *tail_dev_blk = nullptr;
     hipStream_t gstream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     double *uw = nullptr;
@@ -548,6 +554,74 @@ struct amg_ctx {
         return (double)A.nnz * vb + A.index_bytes + (double)nvec * 8.0 * A.n;
     }
 
+    // ---- the V-cycle tail ------------------------------------------------------
+    // Levels from tail_start on qualify when each is small (at most TAIL_ROWS
+    // rows and TAIL_NNZ entries: one workgroup walks it in about the time a
+    // launch takes) and the coarsest fits the tail's LDS; the tail is used
+    // when the V-cycle is the l1-Jacobi one with one pre- and one post-sweep
+    // and the fused K P post-smoothing, no polynomial smoother on those levels.
+    static constexpr int64_t TAIL_ROWS = 2048, TAIL_NNZ = 60000;
+    void choose_tail()
+    {
+        tail_start = -1;
+        if (nlev < 3 || nL > TAIL_MAX_COARSE || general_vcycle()) return;
+        for (int l = nlev - 2; l >= 1; l--) {
+            if (lev[l].n > TAIL_ROWS || lev[l].nnz > TAIL_NNZ || !lev[l].KP.soff || !lev[l].A.soff) break;
+            tail_start = l;
+        }
+        // descriptors uploaded now, never inside a graph capture
+        if (tail_start > 0) tail_dev = fp32() ? tail_descriptors<float>(false) : tail_descriptors<double>(false);
+    }
+    bool tail_usable() const
+    {
+        if (!use_tail || tail_start < 1 || !fuse_post || prm.nu_pre != 1 || prm.nu_post != 1) return false;
+        for (int l = tail_start; l < nlev - 1; l++)
+            if (lev[l].poly_on) return false;
+        return true;
+    }
+    template <typename VT> void *tail_descriptors(bool blk)
+    {
+        std::vector<TailLevel<VT>> T;
+        for (int l = tail_start; l < nlev - 1; l++) {
+            Level &L = lev[l];
+            TailLevel<VT> d{};
+            d.a16 = L.A.idx16;
+            if (d.a16) d.A16 = L.A.sv<VT, uint16_t>();
+            else d.A32 = L.A.sv<VT, int32_t>();
+            d.p16 = L.KP.idx16;
+            if (d.p16) d.P16 = L.KP.sv<VT, uint16_t>();
+            else d.P32 = L.KP.sv<VT, int32_t>();
+            d.mw = L.mw;
+            d.n = L.n;
+            d.invd = L.invd<VT>();
+            d.pc = L.pc<VT>();
+            d.agg = L.agg;
+            d.members = L.members;
+            d.f = (VT *)(blk ? L.bf : L.f);
+            d.u = (VT *)(blk ? L.bu : L.u);
+            d.u2 = (VT *)(blk ? L.bu2 : L.u2);
+            d.r = (VT *)(blk ? L.br : L.r);
+            T.push_back(d);
+        }
+        return upload(T);
+    }
+    // run the tail; returns the post-smoothed correction of level tail_start
+    template <typename VT> VT *run_tail(bool blk)
+    {
+        const int nt = nlev - 1 - tail_start;
+        Level &C = lev[nlev - 1];
+        if (blk) {
+            hipLaunchKernelGGL((k_vtail_blk<VT>), dim3(1), dim3(TAIL_THREADS), 0, stream,
+                               (const TailLevel<VT> *)tail_dev_blk, nt, nL, ldL, Linv, LinvT, (VT *)C.bf,
+                               (VT *)C.bu, bY);
+        } else {
+            hipLaunchKernelGGL((k_vtail<VT>), dim3(1), dim3(TAIL_THREADS), 0, stream, (const TailLevel<VT> *)tail_dev,
+                               nt, nL, ldL, Linv, LinvT, (VT *)C.f, (VT *)C.u);
+        }
+        HIPCHK(hipGetLastError());
+        return (VT *)(blk ? lev[tail_start].bu2 : lev[tail_start].u2);
+    }
+
     // ---- kernel launchers --------------------------------------------------
     template <typename VT, typename FT, typename OT, int EPI, int NDOT>
     void sell(int l, const VT *x, const FT *f, const VT *invd, OT *y, const double *g0, const double *g1,
@@ -745,6 +819,8 @@ struct amg_ctx {
             hipLaunchKernelGGL((k_coarse_solve<VT>), dim3(1), dim3(256), 0, stream, nL, ldL, Linv, LinvT,
                                (const VT *)C.f, e);
             HIPCHK(hipGetLastError());
+        } else if (l + 1 == tail_start && tail_usable()) {
+            e = run_tail<VT>(false);
         } else {
             e = vlevel<VT, VT>(l + 1, (const VT *)C.f, nullptr, 0, nullptr, nullptr, true);
         }
@@ -982,6 +1058,7 @@ struct amg_ctx {
         bgram = alloc<double>((size_t)GRAM_BLOCKS * 512);
         bcoef = alloc<double>(256);
         bgsave = alloc<double>(256);
+        if (tail_start > 0) tail_dev_blk = fp32() ? tail_descriptors<float>(true) : tail_descriptors<double>(true);
         HIPCHK(hipHostMalloc((void **)&hbsc, B_NSLOTS * NB * sizeof(double), hipHostMallocDefault));
     }
     unsigned blk_grid(const DevMat &B) const
@@ -1201,6 +1278,8 @@ struct amg_ctx {
         if (coarsest) {
             e = (VT *)C.bu;
             coarse_blk<VT>((const VT *)C.bf, e);
+        } else if (l + 1 == tail_start && tail_usable()) {
+            e = run_tail<VT>(true);
         } else {
             e = vlevel_blk<VT, VT>(l + 1, (const VT *)C.bf, nullptr, 0, nullptr, nullptr, true);
         }
@@ -1366,6 +1445,7 @@ static amg_status build_device(amg_ctx *c, const CsrView &K0)
     c->sc = c->alloc<double>(S_NSLOTS);
     HIPCHK(hipHostMalloc((void **)&c->hsc, S_NSLOTS * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipEventCreateWithFlags(&c->ev_iter, hipEventDisableTiming));
+    c->choose_tail();
     if (c->prm.nrhs > 1) c->tune_blocks(K0);
     HIPCHK(hipStreamSynchronize(c->stream));
     return AMG_OK;
@@ -1907,6 +1987,7 @@ amg_status amg_set_option(amg_ctx *c, int option, int value)
     switch (option) {
     case AMG_OPT_GRAPH: c->use_graph = value ? 1 : 0; break;
     case AMG_OPT_FUSE_POST: c->fuse_post = value ? 1 : 0; c->drop_graphs(); break;
+    case AMG_OPT_TAIL: c->use_tail = value ? 1 : 0; c->drop_graphs(); break;
     case AMG_OPT_BLOCK_WINDOW:
         if (value != 0 && value != 2 && value != 4) {
             set_err("AMG_OPT_BLOCK_WINDOW takes 0 (off) or 2 or 4 rows per lane");
@@ -1935,6 +2016,7 @@ amg_status amg_get_option(const amg_ctx *c, int option, int *value)
     switch (option) {
     case AMG_OPT_GRAPH: *value = c->use_graph; break;
     case AMG_OPT_FUSE_POST: *value = c->fuse_post; break;
+    case AMG_OPT_TAIL: *value = c->use_tail && c->tail_start > 0 ? c->tail_start : 0; break;
     case AMG_OPT_BLOCK_WINDOW: *value = c->blk_win; break;
     default: set_err("unknown option"); return AMG_ERR_ARG;
     }
