@@ -294,13 +294,16 @@ const char *amg_last_error(void);
  *   `value` rows (and 16 / value columns) per lane; 0 turns this off (those
  *   images then take the lanes-per-row variant of amg_set_batched_variant).
  *   Bitwise the same results in every setting.
- * AMG_OPT_TAIL (default on): the coarsest levels of the V-cycle -- from the
+ * AMG_OPT_TAIL (default off): the coarsest levels of the V-cycle -- from the
  *   first level down whose every level has at most 2048 rows and 60,000
  *   entries -- run in one persistent single-workgroup kernel per V-cycle
  *   (residual, restriction, Cholesky solve, fused post-smoothing, level after
  *   level) instead of one launch per step; single-vector and batched solves,
  *   l1-Jacobi with one pre- and one post-sweep and the fused post-smoothing
- *   only (else the per-level kernels run).  Bitwise the same results.
+ *   only (else the per-level kernels run).  Bitwise the same results.  Off by
+ *   default: on the 2.1M-unknown cube the single workgroup takes longer than
+ *   the per-level launches it replaces (0.3% of a single-vector solve, 2% of
+ *   a 16-column one), whose launch gaps the stream already hides.
  *   amg_get_option returns the first tail level, or 0 when the tail is off or
  *   not available.
  * amg_get_option returns the current value of an option. */

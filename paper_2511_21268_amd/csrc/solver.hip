@@ -178,8 +178,11 @@ struct amg_ctx {
     int fuse_post = 1;   // fused prolongation + post-smoothing through K P (when built)
     // V-cycle tail in one persistent workgroup (k_vtail): levels tail_start ..
     // nlev-2 and the coarsest; device arrays of their TailLevel descriptors for
-    // the single-vector and the 16-column buffers
-    int use_tail = 1, tail_start = -1;
+    // the single-vector and the 16-column buffers; off by default (measured
+    // on the 2.1M-unknown cube: one workgroup walking the last levels takes
+    // longer than the per-level launches it replaces, 9 us per V-cycle single
+    // vector and 110 us per 16-column V-cycle)
+    int use_tail = 0, tail_start = -1;
     void *tail_dev = nullptr, *tail_dev_blk = nullptr;
     hipStream_t gstream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;

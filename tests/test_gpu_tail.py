@@ -31,6 +31,8 @@ def test_tail_equals_per_level_kernels(oracle, amg, d, p, n, fp32):
     N = len(rp) - 1
     kw = dict(vcycle_fp32=1, krylov=1) if fp32 else {}
     ctx = amg.Context(rp, ci, v, **kw)
+    assert ctx.option(AMG_OPT_TAIL) == 0   # off by default
+    ctx.set_tail(1)
     first = ctx.option(AMG_OPT_TAIL)
     print(f"  levels {[ctx.level_info(l)[0] for l in range(ctx.nlevels)]}, tail from level {first}", flush=True)
     assert first >= 1
