@@ -1279,7 +1279,7 @@ int sell_spmv_walk(const CsrView &K, int64_t ncols, int C, int layout, const dou
         // where the slice needs it) are copied, then lane r reads window row
         // r + t for the run's t-th entry; every row copied and every window
         // slot read is checked
-        std::vector<double> win(amgk::WIN_STRIDE);
+        std::vector<double> win(amgk::WIN_ROWS);
         for (int64_t s = 0; s < S.nslices; s++) {
             const int64_t ib = S.ibase[s];
             if (ib >= 0) continue;   // per-row-index slices: the gather path of layout 1
@@ -1306,7 +1306,7 @@ int sell_spmv_walk(const CsrView &K, int64_t ncols, int C, int layout, const dou
                 for (int w = 0; w < C + L - 1; w++) {
                     int64_t g = g0 + w;
                     if (!(e & 1)) g = std::min<int64_t>(std::max<int64_t>(g, 0), hi);
-                    if (bad(g) || w >= amgk::WIN_STRIDE) { return fail("window row out of range"); }
+                    if (bad(g) || w >= amgk::WIN_ROWS) { return fail("window row out of range"); }
                     win[w] = x[g];
                 }
                 for (int r = 0; r < C; r++)

@@ -11,6 +11,7 @@
 // single solve; only the norms of the stopping test ((F,F), (r,r)), summed by
 // the element-parallel vector kernels, take another order.
 #pragma once
+#include <type_traits>
 #include "kernels.h"
 
 namespace amgk {
@@ -148,31 +149,36 @@ __global__ __launch_bounds__(256) void k_sell_blk(const Sell<VT, IT> A, const VT
 // (y, z) displacement) makes lane r read rows row0 + r + o + t, t < L, of X:
 // the 64 lanes together touch only the 64 + L - 1 consecutive rows
 // row0 + o .. row0 + o + 62 + L.  The wave copies those rows (16 columns each)
-// into its own LDS window once per run, with coalesced loads, and every lane
-// then reads its L rows from LDS; without the window each entry of each row
-// gathers a full 16-column row of X from the cache hierarchy (64 B in FP32,
-// 128 B in FP64), the traffic that bounds the one-lane-per-row kernel.
+// into its own LDS window once per run and every lane then reads its rows from
+// LDS; without the window each entry of each row gathers a full 16-column row
+// of X from the cache hierarchy (64 B in FP32, 128 B in FP64), the traffic
+// that bounds the one-lane-per-row kernel.
 //
-// The window is held chunk-major: 16-byte chunk c (G consecutive columns) of
-// window row w at W[c * WIN_STRIDE + w].  Lanes load the rows row-major (lane
-// q takes chunk q % CH of row q / CH, so a wave's load is contiguous memory)
-// and the odd stride spreads the chunks a group of lanes writes over distinct
-// banks.
+// The copy is a direct global-to-LDS load (global_load_lds_dwordx4): no
+// registers hold the window on its way, and the wave's instruction i writes
+// 16-byte slots 64 i .. 64 i + 63 of the window in lane order.  The window is
+// row-major with one pad slot per row (row w, 16-byte chunk c at slot
+// w (CH + 1) + c, CH chunks per row): the lanes of one load instruction read
+// consecutive chunks of consecutive rows (the pad slot takes the next row's
+// first chunk, never read), and the stride CH + 1 puts the chunks a group of
+// lanes reads for R-row blocks on distinct banks.
 //
 // Each row's entries are summed in ascending column order (the padding
 // entries of a shared list, value 0, are skipped: an FMA with a zero product
 // leaves a nonzero or +0 sum unchanged), so each column carries the
 // single-vector kernels' bits.  Slices with per-row indices take k_sell_blk's
-// gather path.  The window is private to its wave: only that wave's own LDS
-// operations order its accesses (in-order per wave), fenced for the compiler
-// by wave_lds_sync.
-
-__device__ inline void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+// gather path.
+//
+// Each wave owns two windows and alternates between them by run: the copy of
+// run rho + 1 and the load of its values are in flight while run rho is summed.
+// The order is kept by explicit waits: before a copy into a window, for every
+// LDS read of the wave (lgkmcnt 0: the window's last reads were two runs
+// back); before the sums of a run, for all of the wave's vector memory loads
+// (vmcnt 0: that run's copy and values were issued one run earlier).
+// Measured on the c4 level 0 (p = 3): the copies and value loads (14 per run
+// in FP64) keep the texture address unit busy 86% of the pass, each 1 KB
+// request missing L1 (an L2 round trip of ~600 cycles); the sums themselves
+// take a third of the VALU time.
 
 template <typename VT> struct Chunk16;
 template <> struct Chunk16<double> {
@@ -184,16 +190,123 @@ template <> struct Chunk16<float> {
     static __device__ inline void unpack(type q, float *o) { o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w; }
 };
 
-// Register blocking: with R > 1 a lane owns R consecutive rows and 16 / R
-// columns (lane = g * R + q: rows R g .. R g + R - 1; 16-byte chunks q, q + R,
-// q + 2R, ... of each row), so a window row read from LDS serves the lane's
-// rows at every offset that reaches it: R + L - 1 window rows per lane and run
-// instead of R L, at the price of R matrix values per entry (each read by the
-// R lanes of a row group).  The chunk assignment and the odd window stride
-// keep each 16-lane phase of a window read on 16 distinct bank groups.  Per
-// column the row sums keep ascending entry order and the dots keep the
-// single-vector kernels' butterfly order (the row bits above log2 R are lane
-// bits, the ones below are summed in registers, in the same order).
+// compiler fence for the wave's own LDS accesses (in order per wave)
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Direct global-to-LDS load of 16 bytes per lane (global_load_lds_dwordx4):
+// lane l's 16 bytes from src go to lds + 16 l (lds wave-uniform).  The host
+// pass of the compiler does not take the builtin, hence the guard.
+template <typename CT> __device__ __forceinline__ void lds_copy16(const CT *src, CT *lds)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+#endif
+}
+
+// An empty asm statement reading v: the compiler keeps v in its registers
+// up to this point (device code only; the host pass never runs it).
+template <typename T> __device__ __forceinline__ void keep_in_vgprs(const T &v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : : "v"(v));
+#endif
+}
+
+// s_waitcnt immediates (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4,
+// lgkmcnt 11:8): wait for this wave's LDS operations only, or until at most
+// n < 16 of its vector memory loads are outstanding
+constexpr int WAIT_LGKM0 = 0xC07F;
+constexpr int wait_vm(int n) { return 0x0F70 | n; }   // n < 16
+
+// Value held by lane i of each aligned group of R lanes (R = 2 or 4), to
+// every lane of the group: one DPP quad permutation per 32 bits.
+template <int R, int I> struct GroupPerm {
+    static constexpr int ctrl = R == 4 ? (I | I << 2 | I << 4 | I << 6) : (I | I << 2 | (2 + I) << 4 | (2 + I) << 6);
+};
+template <int R, int I> __device__ __forceinline__ float group_bcast(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), GroupPerm<R, I>::ctrl, 0xF,
+                                                              0xF, true));
+}
+template <int R, int I> __device__ __forceinline__ double group_bcast(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, GroupPerm<R, I>::ctrl, 0xF, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), GroupPerm<R, I>::ctrl, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, (uint64_t)lo | (uint64_t)hi << 32);
+}
+template <int R, typename VT> __device__ __forceinline__ VT group_bcast(VT v, int i)
+{
+    // i is a constant after unrolling: the switch folds
+    switch (i) {
+    case 0: return group_bcast<R, 0>(v);
+    case 1: return group_bcast<R, 1>(v);
+    case 2: return group_bcast<R, R == 4 ? 2 : 0>(v);
+    default: return group_bcast<R, R == 4 ? 3 : 1>(v);
+    }
+}
+
+// One run of L entries (a compile-time length, so that the sums run without
+// branches) from a staged window, the run's values starting at entry OFF of
+// the lane's first value group: window row R g + w serves row R g + i at
+// entry w - i.  Wr points at the lane's first window read.
+template <typename VT, int R, int NGR> struct WinRun {
+    typedef typename Chunk16<VT>::type CT;
+    static constexpr int G = 16 / (int)sizeof(VT), CH = NB / G, CPL = NB / R, CPC = CH / R, WS = CH + 1;
+    template <int OFF, int L>
+    static __device__ __forceinline__ void run(VT (&acc)[R][CPL], const CT *Wr, const CT (&vg)[NGR])
+    {
+        static_assert(OFF + L <= NGR * G, "run past its value groups");
+        VT e[NGR * G];
+#pragma unroll
+        for (int j = 0; j < NGR; j++) Chunk16<VT>::unpack(vg[j], e + j * G);
+#pragma unroll
+        for (int w = 0; w < R + L - 1; w++) {
+            VT xv[CPL];
+#pragma unroll
+            for (int cc = 0; cc < CPC; cc++) Chunk16<VT>::unpack(Wr[w * WS + cc * R], xv + cc * G);
+#pragma unroll
+            for (int i = 0; i < R; i++) {
+                const int t = w - i;
+                if (t >= 0 && t < L) {
+                    const VT v = group_bcast<R>(e[OFF + t], i);
+#pragma unroll
+                    for (int j = 0; j < CPL; j++) acc[i][j] = fma(v, xv[j], acc[i][j]);
+                }
+            }
+        }
+    }
+    template <int OFF>
+    static __device__ __forceinline__ void len(VT (&acc)[R][CPL], const CT *Wr, const CT (&vg)[NGR], int L)
+    {
+        static_assert(WIN_LMAX == 7, "one case per run length");
+        switch (L) {
+        case 1: run<OFF, 1>(acc, Wr, vg); break;
+        case 2: run<OFF, 2>(acc, Wr, vg); break;
+        case 3: run<OFF, 3>(acc, Wr, vg); break;
+        case 4: run<OFF, 4>(acc, Wr, vg); break;
+        case 5: run<OFF, 5>(acc, Wr, vg); break;
+        case 6: run<OFF, 6>(acc, Wr, vg); break;
+        default: run<OFF, WIN_LMAX>(acc, Wr, vg); break;
+        }
+    }
+};
+
+// Register blocking: with R rows per lane, lane = g * R + q owns rows R g ..
+// R g + R - 1 and 16 / R columns (16-byte chunks q, q + R, q + 2R, ... of each
+// row), so a window row read from LDS serves the lane's rows at every offset
+// that reaches it: R + L - 1 window reads per chunk and run instead of R L.
+// Each lane loads the value groups of its own row (row0 + lane, one coalesced
+// 16-byte load per group) and takes the other rows of its block from their
+// lanes by DPP.  Per column the row sums keep ascending entry order and the
+// dots keep the single-vector kernels' butterfly order (the row bits above
+// log2 R are lane bits, the ones below are summed in registers, in the same
+// order).
 template <typename VT, typename FT, typename OT, typename IT, int EPI, int NDOT, int R>
 __global__ __launch_bounds__(256) void k_sellw_blk(const Sell<VT, IT> A, const VT *__restrict__ X,
                                                    const FT *__restrict__ F, const VT *__restrict__ invd,
@@ -206,10 +319,13 @@ __global__ __launch_bounds__(256) void k_sellw_blk(const Sell<VT, IT> A, const V
     constexpr int CH = NB / G;                        // chunks per row of X
     constexpr int CPL = NB / R;                       // columns per lane
     constexpr int CPC = CH / R;                       // chunks per lane
-    static_assert(CH % R == 0 && (R & (R - 1)) == 0, "R must be a power of two dividing the chunks per row");
-    constexpr int WN = CH * WIN_STRIDE;               // chunks per window
-    constexpr int NLD = (CH * (SLICE + WIN_LMAX - 1) + 63) / 64;   // staging loads per lane
-    __shared__ CT win[SELL_WAVES * WN];
+    static_assert(CH % R == 0 && (R == 2 || R == 4), "R must be 2 or 4");
+    constexpr int WS = CH + 1;                        // window row stride in chunks
+    constexpr int NLD = (WIN_ROWS * WS + 63) / 64;    // copy instructions per window
+    constexpr int WN = NLD * 64;                      // chunks per window
+    constexpr int XROWS = (WN - 1) / CH + 1;          // rows of X one copy may touch
+    constexpr int NGR = (WIN_LMAX + G - 1) / G + 1;   // value groups covering one run
+    __shared__ CT win[SELL_WAVES * 2 * WN];   // two windows per wave
     const int lane = threadIdx.x & 63, wid = wave_id();
     // XCD-aware order (xcd_block): every XCD one contiguous range of slices,
     // whose windows overlap (x-lines and planes of the stencil) in its L2
@@ -233,92 +349,87 @@ __global__ __launch_bounds__(256) void k_sellw_blk(const Sell<VT, IT> A, const V
             for (int j = 0; j < CPL; j++) acc[i][j] = 0;
         const int64_t row0 = s * SLICE;
         const int hi = (int)(A.ncols - 1);   // rows below 2^29 (checked at set-up)
-        CT *W = win + wid * WN;
+        CT *W = win + wid * 2 * WN;   // windows W and W + WN, alternating by run
         const CT *Xc = reinterpret_cast<const CT *>(X);
-        // software pipeline over the runs: while run rho is summed from the
-        // LDS window, the window rows and value groups of run rho + 1 are in
-        // flight into registers (st, gv), so memory latency overlaps the
-        // arithmetic
-        // values: the 16-byte groups (G entries of one row) that hold entries
-        // kr .. kr + WIN_LMAX - 1, loaded whole, so each group of the stream
-        // is fetched by one instruction; the run's values start at entry kr % G
-        // of the first group
-        constexpr int NGR = (WIN_LMAX + G - 1) / G + 1;
-        CT st[NLD], gv[NGR][R];
-        VT vc[WIN_LMAX][R];
-        int off = 0;
-        auto issue = [&](int32_t pk, int kr) {
-            // window rows g0 .. g0 + 62 + L, every load issued before any LDS
-            // write; rows past the window and outside [0, hi] are clamped
-            // (loaded but never read)
-            const int g0 = (int)row0 + (pk >> 4);
+        const CT *Wr = W + R * g * WS + q;   // the lane's first window read
+        const int gmax = (width - 1) / G;
+        // the window of the run at offset o: rows row0 + o + w; slot 64 i + lane
+        // holds chunk xc = slot - slot / WS past the window's first chunk
+        auto copy = [&](int g0, CT *D) {
+            if (g0 >= 0 && g0 + XROWS - 1 <= hi) {
+                const CT *src = Xc + (int64_t)g0 * CH;
 #pragma unroll
-            for (int i = 0; i < NLD; i++) {
-                const int qq = i * 64 + lane, w = qq / CH, c = qq % CH;
-                const int gr = min(max(g0 + w, 0), hi);
-                st[i] = Xc[(int64_t)gr * CH + c];
+                for (int i = 0; i < NLD; i++) {
+                    const int slot = i * 64 + lane;
+                    lds_copy16(src + (slot - slot / WS), D + i * 64);
+                }
+            } else {
+                // first and last slices: rows outside [0, hi] clamped (loaded,
+                // never read)
+#pragma unroll
+                for (int i = 0; i < NLD; i++) {
+                    const int slot = i * 64 + lane, xc = slot - slot / WS;
+                    const int gr = min(max(g0 + xc / CH, 0), hi);
+                    lds_copy16(Xc + (int64_t)gr * CH + xc % CH, D + i * 64);
+                }
             }
-            // groups of the lane's rows R g + i (groups past the slice clamped
-            // to its last one, unused)
-            const int gmax = (width - 1) / G;
-            off = kr % G;
+        };
+        // value groups of the lane's own row holding entries kr .. kr + WIN_LMAX
+        // - 1 (groups past the slice clamped to its last one, unused)
+        auto load_vals = [&](CT (&dst)[NGR], int kr) {
 #pragma unroll
             for (int j = 0; j < NGR; j++) {
                 const int gi = min(kr / G + j, gmax);
-#pragma unroll
-                for (int i = 0; i < R; i++)
-                    gv[j][i] = *reinterpret_cast<const CT *>(A.val + base + (int64_t)gi * (G * SLICE) + (R * g + i) * G);
+                dst[j] = *reinterpret_cast<const CT *>(A.val + base + (int64_t)gi * (G * SLICE) + lane * G);
             }
         };
+        // per run: wait for its window and values (issued one run ahead),
+        // issue the next run's window into the other buffer and its values,
+        // then sum this run while those are in flight
         int k = 0, rho = 0;
         int32_t pk = __builtin_amdgcn_readfirstlane(runs);
-        issue(pk, 0);
-        while (pk != 0) {
+        auto step = [&](const CT (&vg)[NGR], CT (&vn)[NGR], auto BUFC) {
+            constexpr int BUF = decltype(BUFC)::value;
             const int L = pk & 15;
-#pragma unroll
-            for (int i = 0; i < NLD; i++) {
-                const int qq = i * 64 + lane, w = qq / CH, c = qq % CH;
-                if (w < WIN_STRIDE) W[c * WIN_STRIDE + w] = st[i];
-            }
-            // this run's values from its groups (off is wave-uniform)
-#pragma unroll
-            for (int i = 0; i < R; i++) {
-                VT e[NGR * G];
-#pragma unroll
-                for (int j = 0; j < NGR; j++) Chunk16<VT>::unpack(gv[j][i], e + j * G);
-#pragma unroll
-                for (int oo = 0; oo < G; oo++)
-                    if (off == oo)
-#pragma unroll
-                        for (int t = 0; t < WIN_LMAX; t++) vc[t][i] = e[oo + t];
-            }
-            // next run: its table entry (a new register of 64 entries every 64 runs)
             const int kn = k + L;
             rho++;
             if ((rho & 63) == 0) runs = (rho + lane < width) ? rt[rho + lane] : 0;
             const int32_t pn = kn < width ? __builtin_amdgcn_readlane(runs, rho & 63) : 0;
+            // this run's window and values have arrived, and every LDS read of
+            // the other window (two runs back) has returned
+            __builtin_amdgcn_s_waitcnt(wait_vm(0));
+            __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
             wave_lds_sync();
-            if (pn != 0) issue(pn, kn);
-            // window row R g + w serves row R g + i at entry k + (w - i)
-#pragma unroll
-            for (int w = 0; w < R + WIN_LMAX - 1; w++) {
-                if (w < R + L - 1) {
-                    VT xv[CPL];
-#pragma unroll
-                    for (int cc = 0; cc < CPC; cc++)
-                        Chunk16<VT>::unpack(W[(q + cc * R) * WIN_STRIDE + R * g + w], xv + cc * G);
-#pragma unroll
-                    for (int i = 0; i < R; i++) {
-                        const int t = w - i;
-                        if (t >= 0 && t < WIN_LMAX && t < L)
-#pragma unroll
-                            for (int j = 0; j < CPL; j++) acc[i][j] = fma(vc[t][i], xv[j], acc[i][j]);
-                    }
+            if (pn != 0) copy((int)row0 + (pn >> 4), W + (1 - BUF) * WN);
+            load_vals(vn, kn);
+            typedef WinRun<VT, R, NGR> WR;
+            const CT *Wb = Wr + BUF * WN;
+            if (G == 2) {
+                if (k & 1) WR::template len<1>(acc, Wb, vg, L);
+                else WR::template len<0>(acc, Wb, vg, L);
+            } else {
+                switch (k & (G - 1)) {
+                case 0: WR::template len<0>(acc, Wb, vg, L); break;
+                case 1: WR::template len<1>(acc, Wb, vg, L); break;
+                case 2: WR::template len<2 % G>(acc, Wb, vg, L); break;
+                default: WR::template len<3 % G>(acc, Wb, vg, L); break;
                 }
             }
-            wave_lds_sync();
+            // the next run's value registers stay allocated through the sums
+            // of every run length (a dead group would be reused, and its
+            // register then waited for)
+#pragma unroll
+            for (int j = 0; j < NGR; j++) keep_in_vgprs(vn[j]);
             k = kn;
             pk = pn;
+        };
+        CT va[NGR], vb[NGR];
+        copy((int)row0 + (pk >> 4), W);
+        load_vals(va, 0);
+        while (pk != 0) {
+            step(va, vb, std::integral_constant<int, 0>());
+            if (pk == 0) break;
+            step(vb, va, std::integral_constant<int, 1>());
         }
         // epilogue: local column jj = cc * G + u is column (q + cc R) G + u
         double d0[R][CPL], d1[R][CPL];

@@ -3,6 +3,6 @@
 #pragma once
 
 namespace amgk {
-constexpr int WIN_LMAX = 8;      // longest offset run one staged x window covers
-constexpr int WIN_STRIDE = 73;   // window rows per chunk column (>= 64 + WIN_LMAX - 1, odd)
+constexpr int WIN_LMAX = 7;      // longest offset run one staged x window covers
+constexpr int WIN_ROWS = 64 + WIN_LMAX - 1;   // rows of one staged x window
 }  // namespace amgk
