@@ -157,6 +157,7 @@ def main():
         return
 
     import paper_2511_21268_amd as amg
+    from paper_2511_21268_amd import amg as amgmod
     from paper_2511_21268_amd.workloads import CONFIGS, rhs_normal
 
     cfg = CONFIGS[args.workload]
@@ -207,7 +208,9 @@ def main():
     fmt = ctx.format(0)
     log(f"setup {setup_s:.1f} s, levels {levels}, opc {ctx.opc():.3f}, format {fmt}")
     if nrhs > 1:
-        log(f"block kernels (autotuned): lanes per row, threads = {ctx.batched_variant()}")
+        log(f"block kernels (autotuned): lanes per row, threads = {ctx.batched_variant()}; window rows per lane "
+            f"{ctx.option(amgmod.AMG_OPT_BLOCK_WINDOW)}, shared windows (mask: 1 FP64, 2 FP32) "
+            f"{ctx.option(amgmod.AMG_OPT_WINDOW_SHARE)}")
     del rp, ci, v
 
     def one_solve():
@@ -327,6 +330,9 @@ def main():
                       "setup_on_device": bool(args.setup_device),
                       "spmv_gbs": round(achieved, 1),
                       "block_variant": list(ctx.batched_variant()) if nrhs > 1 else None,
+                      "block_window": ({"rows_per_lane": ctx.option(amgmod.AMG_OPT_BLOCK_WINDOW),
+                                        "shared_mask": ctx.option(amgmod.AMG_OPT_WINDOW_SHARE)}
+                                       if nrhs > 1 else None),
                       "graph_replay": bool(args.graph),
                       "roofline_from": "one eager profiled solve after the timed steps" if args.graph
                       else "the timed steps"},

@@ -257,7 +257,9 @@ amg_status amg_match(int64_t n, const int64_t *row_ptr, const int32_t *col, cons
  * offsets where they fit (square matrices only); 2: rows sorted by length
  * within windows of 4 slices; 3: as 1, with the shared-offset slices walked
  * the way the block kernels stage x windows (runs of consecutive offsets, the
- * rows each run reads copied once; C = 64 only) -- and computes y = K x (host arrays, x of length
+ * rows each run reads copied once; C = 64 only); 4: as 3, with the windows
+ * shared by blocks of four slices through the stage tables of the batched
+ * set-up (AMG_OPT_WINDOW_SHARE; C = 64 only) -- and computes y = K x (host arrays, x of length
  * ncols, y of length n) by walking that image as the matrix-pass kernels do:
  * groups of 8 entries, columns rebuilt from shared offsets (clamped where the
  * slice needs it), 16-bit deltas or int32 columns, the slot -> row map.  Every
@@ -306,8 +308,23 @@ const char *amg_last_error(void);
  *   a 16-column one), whose launch gaps the stream already hides.
  *   amg_get_option returns the first tail level, or 0 when the tail is off or
  *   not available.
+ * AMG_OPT_WINDOW_SHARE (a mask, default 3; autotuned by amg_setup with
+ *   prm.nrhs > 1): with AMG_OPT_BLOCK_WINDOW on, the four slices of a
+ *   256-thread block share their windows in the passes over FP64 values (bit
+ *   0) and over FP32 values (bit 1): amg_setup groups the slices of every
+ *   stencil image in fours one grid line apart (slice stride 1..4, the one
+ *   that copies the fewest rows) and lists, per block, the windows of X rows
+ *   the block copies once for all four waves and which run of which wave each
+ *   serves, in each wave's run order.  amg_get_option returns the mask, 0 for
+ *   an image without such lists.  Bitwise the same results.
  * amg_get_option returns the current value of an option. */
-typedef enum { AMG_OPT_GRAPH = 1, AMG_OPT_FUSE_POST = 2, AMG_OPT_BLOCK_WINDOW = 3, AMG_OPT_TAIL = 4 } amg_option;
+typedef enum {
+    AMG_OPT_GRAPH = 1,
+    AMG_OPT_FUSE_POST = 2,
+    AMG_OPT_BLOCK_WINDOW = 3,
+    AMG_OPT_TAIL = 4,
+    AMG_OPT_WINDOW_SHARE = 5
+} amg_option;
 amg_status amg_set_option(amg_ctx *c, int option, int value);
 amg_status amg_get_option(const amg_ctx *c, int option, int *value);
 

@@ -135,6 +135,24 @@ struct SellHost {
     std::vector<uint16_t> d16;
     std::vector<int32_t> c32, col0, shoff, shrun;
 };
+// Windows shared by the four waves (slices) of a workgroup in the block
+// kernels: logical workgroup b holds slices tab[8b .. 8b+3] (ids past the last
+// slice: none) and, in order, stages st[2 tab[8b+4]] .. of count tab[8b+5];
+// stage t copies X rows st[2t] .. st[2t] + WIN_WG_ROWS - 1 and byte k of st[2t+1]
+// says whether wave k sums its next run from it (bit 7) and at which row of the
+// window that run's range starts (bits 0-6).  Each wave's runs are taken in
+// order.  Slices are grouped by stride sigma: groups of 4 sigma consecutive
+// slices make sigma workgroups of every sigma-th slice (so that with sigma
+// slices per grid line the windows of neighbouring lines coincide); slices
+// past the last full group go four consecutive ones per workgroup.
+struct WgStages {
+    int sigma = 0;
+    int64_t nwg = 0, copied_rows = 0, runs = 0;
+    std::vector<int32_t> tab, st;
+};
+void build_wg_stages(const SellHost &S, int C, int64_t nwg, int sigma, WgStages &W);
+// the stride of 1..4 with the fewest copied window rows
+void choose_wg_stages(const SellHost &S, int C, int64_t nwg, WgStages &W);
 std::vector<int32_t> slice_offsets(const CsrView &K, int64_t s, int C, int64_t limit);
 int64_t count_shared(const CsrView &K, int C);
 void build_sell(const CsrView &K, int C, bool want64, bool want32, bool shared, int sigma, SellHost &S);

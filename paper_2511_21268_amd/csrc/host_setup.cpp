@@ -1264,13 +1264,98 @@ void build_sell(const CsrView &K, int C, bool want64, bool want32, bool shared, 
 // y = K x by walking the SELL-C image of K the way the device kernels do (see
 // amg_sell_spmv_host in amg.h for the layouts); every column and window slot
 // the walk reads is checked.  0, or AMG_ERR_STATE (-6) with a message.
+void build_wg_stages(const SellHost &S, int C, int64_t nwg, int sigma, WgStages &W)
+{
+    W = WgStages();
+    W.sigma = sigma;
+    W.nwg = nwg;
+    W.tab.assign(nwg * 8, 0);
+    const int64_t slots = 4 * nwg, group = 4 * (int64_t)sigma, full = slots / group * group;
+    auto slice_of = [&](int64_t b, int k) -> int64_t {
+        if (4 * b < full) {
+            const int64_t g = b / sigma, j = b % sigma;
+            return g * group + j + (int64_t)k * sigma;
+        }
+        return 4 * b + k;
+    };
+    // a wave's runs: window-range start rows and lengths, in order
+    auto runs_of = [&](int64_t s, std::vector<std::pair<int64_t, int>> &r) {
+        r.clear();
+        if (s >= S.nslices || S.ibase[s] >= 0) return;
+        const int64_t e = -1 - S.ibase[s];
+        const int32_t *rt = S.shrun.data() + (e >> 1);
+        const int width = (int)((S.soff[s + 1] - S.soff[s]) / C);
+        int k = 0;
+        for (int rho = 0; k < width && rt[rho] != 0; rho++) {
+            r.push_back({s * C + (rt[rho] >> 4), rt[rho] & 15});
+            k += rt[rho] & 15;
+        }
+    };
+    std::vector<int32_t> cnt(nwg, 0);
+    std::vector<std::vector<int32_t>> per(nwg);
+    parallel_for(nwg, [&](int64_t b0, int64_t b1) {
+        std::vector<std::pair<int64_t, int>> r[4];
+        for (int64_t b = b0; b < b1; b++) {
+            size_t ptr[4] = {0, 0, 0, 0};
+            for (int k = 0; k < 4; k++) {
+                const int64_t s = slice_of(b, k);
+                W.tab[8 * b + k] = (int32_t)s;
+                runs_of(s, r[k]);
+            }
+            std::vector<int32_t> &out = per[b];
+            for (;;) {
+                int64_t g0 = INT64_MAX;
+                for (int k = 0; k < 4; k++)
+                    if (ptr[k] < r[k].size()) g0 = std::min(g0, r[k][ptr[k]].first);
+                if (g0 == INT64_MAX) break;
+                uint32_t info = 0;
+                for (int k = 0; k < 4; k++) {
+                    if (ptr[k] >= r[k].size()) continue;
+                    const int64_t shift = r[k][ptr[k]].first - g0;
+                    if (shift + C - 1 + r[k][ptr[k]].second > amgk::WIN_WG_ROWS) continue;
+                    info |= (uint32_t)(0x80 | shift) << (8 * k);
+                    ptr[k]++;
+                }
+                out.push_back((int32_t)g0);
+                out.push_back((int32_t)info);
+            }
+            cnt[b] = (int32_t)(out.size() / 2);
+        }
+    });
+    int64_t total = 0;
+    for (int64_t b = 0; b < nwg; b++) {
+        W.tab[8 * b + 4] = (int32_t)total;
+        W.tab[8 * b + 5] = cnt[b];
+        total += cnt[b];
+    }
+    W.st.resize(2 * total);
+    parallel_for(nwg, [&](int64_t b0, int64_t b1) {
+        for (int64_t b = b0; b < b1; b++) std::copy(per[b].begin(), per[b].end(), W.st.begin() + 2 * (int64_t)W.tab[8 * b + 4]);
+    });
+    W.copied_rows = total * amgk::WIN_WG_ROWS;
+    int64_t runs = 0;
+    for (int64_t t = 0; t < total; t++)
+        for (int k = 0; k < 4; k++) runs += (W.st[2 * t + 1] >> (8 * k)) & 0x80 ? 1 : 0;
+    W.runs = runs;
+}
+
+void choose_wg_stages(const SellHost &S, int C, int64_t nwg, WgStages &W)
+{
+    W = WgStages();
+    for (int sigma = 1; sigma <= 4; sigma++) {
+        WgStages T;
+        build_wg_stages(S, C, nwg, sigma, T);
+        if (W.sigma == 0 || T.copied_rows < W.copied_rows) W = std::move(T);
+    }
+}
+
 int sell_spmv_walk(const CsrView &K, int64_t ncols, int C, int layout, const double *x, double *y,
                    int64_t *shared_slices, int64_t *stored, std::string &err)
 {
     auto fail = [&](const char *m) { err = m; return -6; };
     const int64_t n = K.n;
     SellHost S;
-    build_sell(K, C, true, false, layout == 1 || layout == 3, layout == 2 ? 4 * C : 0, S);
+    build_sell(K, C, true, false, layout == 1 || layout >= 3, layout == 2 ? 4 * C : 0, S);
     const int32_t hi = (int32_t)(ncols - 1);
     auto bad = [&](int64_t c) { return c < 0 || c > hi; };
     if (layout == 3) {
@@ -1321,8 +1406,67 @@ int sell_spmv_walk(const CsrView &K, int64_t ncols, int C, int layout, const dou
                 if (s * C + r < n) y[s * C + r] = acc[r];
         }
     }
+    if (layout == 4) {
+        // the same slices walked through the block stage tables: per block of
+        // four slices, per stage, the window rows g0 + w (w < WIN_WG_ROWS,
+        // clamped) are copied once, and every wave taking part sums its next
+        // run from the window rows at its shift; every run of every slice must
+        // be taken exactly once, in order
+        amgiga::WgStages W;
+        const int64_t nwg = (S.nslices + 3) / 4;
+        choose_wg_stages(S, C, nwg, W);
+        std::vector<char> seen(4 * nwg, 0);
+        std::vector<double> win(amgk::WIN_WG_ROWS);
+        for (int64_t b = 0; b < nwg; b++) {
+            int64_t sl[4];
+            int kk[4] = {0, 0, 0, 0}, rho[4] = {0, 0, 0, 0}, width[4] = {0, 0, 0, 0};
+            const int32_t *rt[4] = {nullptr, nullptr, nullptr, nullptr};
+            std::vector<double> acc(4 * (size_t)C, 0.0);
+            for (int k = 0; k < 4; k++) {
+                sl[k] = W.tab[8 * b + k];
+                if (sl[k] < 0 || sl[k] >= 4 * nwg || seen[sl[k]]) { return fail("block table: slice missing or twice"); }
+                seen[sl[k]] = 1;
+                if (sl[k] < S.nslices && S.ibase[sl[k]] < 0) {
+                    const int64_t e = -1 - S.ibase[sl[k]];
+                    if (S.shrun[e >> 1] != 0) rt[k] = S.shrun.data() + (e >> 1);
+                    width[k] = (int)((S.soff[sl[k] + 1] - S.soff[sl[k]]) / C);
+                }
+            }
+            const int64_t t0 = W.tab[8 * b + 4], nst = W.tab[8 * b + 5];
+            if (t0 < 0 || t0 + nst > (int64_t)W.st.size() / 2) { return fail("stage list past its array"); }
+            for (int64_t t = t0; t < t0 + nst; t++) {
+                const int64_t g0 = W.st[2 * t];
+                for (int w = 0; w < amgk::WIN_WG_ROWS; w++) win[w] = x[std::min<int64_t>(std::max<int64_t>(g0 + w, 0), hi)];
+                for (int k = 0; k < 4; k++) {
+                    const int me = (W.st[2 * t + 1] >> (8 * k)) & 0xFF;
+                    if (!(me & 0x80)) continue;
+                    if (!rt[k] || kk[k] >= width[k] || rt[k][rho[k]] == 0) { return fail("stage for a wave without a run"); }
+                    const int32_t pk = rt[k][rho[k]];
+                    const int L = pk & 15, sh = me & 0x7F;
+                    if (L < 1 || L > amgk::WIN_LMAX || kk[k] + L > width[k]) { return fail("run past the list or too long"); }
+                    if (sl[k] * C + (pk >> 4) != g0 + sh) { return fail("run not at its window shift"); }
+                    if (sh + C - 1 + L > amgk::WIN_WG_ROWS) { return fail("run past its window"); }
+                    const int64_t base = S.soff[sl[k]];
+                    for (int r = 0; r < C; r++)
+                        for (int u = 0; u < L; u++) {
+                            const int e2 = kk[k] + u;
+                            acc[k * C + r] = std::fma(S.v64[base + (e2 / 2) * 2 * C + r * 2 + (e2 % 2)], win[sh + r + u],
+                                                      acc[k * C + r]);
+                        }
+                    kk[k] += L;
+                    rho[k]++;
+                }
+            }
+            for (int k = 0; k < 4; k++) {
+                if (!rt[k]) continue;
+                if (kk[k] < width[k] && rt[k][rho[k]] != 0) { return fail("runs left after the last stage"); }
+                for (int r = 0; r < C; r++)
+                    if (sl[k] * C + r < n) y[sl[k] * C + r] = acc[k * C + r];
+            }
+        }
+    }
     for (int64_t s = 0; s < S.nslices; s++) {
-        if (layout == 3 && S.ibase[s] < 0 && S.shrun[(-1 - S.ibase[s]) >> 1] != 0) continue;
+        if (layout >= 3 && S.ibase[s] < 0 && S.shrun[(-1 - S.ibase[s]) >> 1] != 0) continue;
         const int64_t base = S.soff[s];
         const int width = (int)((S.soff[s + 1] - base) / C);
         const int64_t ib = S.ibase[s];

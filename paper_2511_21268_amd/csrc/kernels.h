@@ -172,6 +172,8 @@ template <typename VT, typename IT> struct Sell {
                             // of consecutive offsets (at most WIN_LMAX long) in
                             // order, packed as first offset * 16 + length, then 0
                             // (0 first: no run table for that list)
+    const int32_t *wgtab;   // window stages shared by the four waves of a block
+    const int32_t *wgst;    // (layout in host.h: WgStages); nullptr: none
 
     // row held by slot q, or -1
     __device__ __forceinline__ int64_t row_of(int64_t q) const

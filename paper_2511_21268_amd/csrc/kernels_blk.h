@@ -307,6 +307,150 @@ template <typename VT, int R, int NGR> struct WinRun {
 // dots keep the single-vector kernels' butterfly order (the row bits above
 // log2 R are lane bits, the ones below are summed in registers, in the same
 // order).
+// Epilogue of the window kernels for the R rows (row0 + R g + i) and 16 / R
+// columns (16-byte chunks q, q + R, ... of each row) a lane owns; the dot
+// partials of the slice go to slot w_id.
+template <typename VT, typename FT, typename OT, int EPI, int NDOT, int R>
+__device__ __forceinline__ void win_epilogue(VT (&acc)[R][NB / R], int64_t row0, int64_t nrows, int g, int q,
+                                             const VT *__restrict__ X, const FT *__restrict__ F,
+                                             const VT *__restrict__ invd, OT *__restrict__ Y,
+                                             const double *__restrict__ G0, const double *__restrict__ G1,
+                                             double *__restrict__ partial, int64_t w_id, VT coef)
+{
+    constexpr int G = 16 / (int)sizeof(VT), CPL = NB / R;
+    // epilogue: local column jj = cc * G + u is column (q + cc R) G + u
+    double d0[R][CPL], d1[R][CPL];
+#pragma unroll
+    for (int i = 0; i < R; i++) {
+        const int64_t rr = row0 + R * g + i;
+        const bool live = rr < nrows;   // shared-offset slices are never sorted
+        const VT di = (live && (EPI == EPI_SMOOTH || EPI == EPI_POLY)) ? invd[rr] : (VT)0;
+#pragma unroll
+        for (int jj = 0; jj < CPL; jj++) {
+            d0[i][jj] = 0.0;
+            d1[i][jj] = 0.0;
+            if (!live) continue;
+            const int64_t o = rr * NB + (q + (jj / G) * R) * G + jj % G;
+            const VT a = acc[i][jj];
+            if (EPI == EPI_SPMV) {
+                Y[o] = (OT)a;
+                if (NDOT >= 1) d0[i][jj] = (double)X[o] * (double)a;
+                if (NDOT >= 2) d1[i][jj] = (double)X[o] * G1[o];
+            } else if (EPI == EPI_RESID) {
+                Y[o] = (OT)((VT)F[o] - a);
+            } else if (EPI == EPI_SMOOTH) {
+                VT out = X[o] + di * ((VT)F[o] - a);
+                Y[o] = (OT)out;
+                if (NDOT >= 1) d0[i][jj] = (double)out * G0[o];
+                if (NDOT >= 2) d1[i][jj] = (double)out * G1[o];
+            } else {
+                Y[o] = (OT)(coef * (di * (VT)F[o]) + di * a);
+            }
+        }
+    }
+    if (NDOT >= 1) {
+        // the single-vector butterfly over the 64 rows: row bits >= log2 R
+        // across lanes (xor 32 .. R), then the bits below in registers
+#pragma unroll
+        for (int i = 0; i < R; i++)
+#pragma unroll
+            for (int jj = 0; jj < CPL; jj++)
+                for (int o = 32; o >= R; o >>= 1) {
+                    d0[i][jj] += __shfl_xor(d0[i][jj], o, 64);
+                    if (NDOT >= 2) d1[i][jj] += __shfl_xor(d1[i][jj], o, 64);
+                }
+#pragma unroll
+        for (int o = R / 2; o >= 1; o >>= 1) {
+            double t0[R][CPL], t1[R][CPL];
+#pragma unroll
+            for (int i = 0; i < R; i++)
+#pragma unroll
+                for (int jj = 0; jj < CPL; jj++) {
+                    t0[i][jj] = d0[i][jj] + d0[i ^ o][jj];
+                    t1[i][jj] = d1[i][jj] + d1[i ^ o][jj];
+                }
+#pragma unroll
+            for (int i = 0; i < R; i++)
+#pragma unroll
+                for (int jj = 0; jj < CPL; jj++) { d0[i][jj] = t0[i][jj]; d1[i][jj] = t1[i][jj]; }
+        }
+        if (g == 0)
+#pragma unroll
+            for (int jj = 0; jj < CPL; jj++) {
+                const int j = (q + (jj / G) * R) * G + jj % G;
+                partial[(2 * w_id) * NB + j] = d0[0][jj];
+                partial[(2 * w_id + 1) * NB + j] = NDOT >= 2 ? d1[0][jj] : 0.0;
+            }
+    }
+}
+
+// Slice s of an image with per-row indices (or past the last slice: zero dot
+// partials) in a wave of the window kernels: k_sell_blk's gather walk.
+template <typename VT, typename FT, typename OT, typename IT, int EPI, int NDOT>
+__device__ __forceinline__ void gather_slice(const Sell<VT, IT> &A, int64_t s, int lane, const VT *__restrict__ X,
+                                             const FT *__restrict__ F, const VT *__restrict__ invd,
+                                             OT *__restrict__ Y, const double *__restrict__ G0,
+                                             const double *__restrict__ G1, double *__restrict__ partial,
+                                             int64_t w_id, VT coef)
+{
+    double d0[NB], d1[NB];
+#pragma unroll
+    for (int j = 0; j < NB; j++) { d0[j] = 0.0; d1[j] = 0.0; }
+    if (s < A.nslices) {
+        const int64_t row = A.row_of(s * SLICE + lane);
+        VT acc[NB];
+#pragma unroll
+        for (int j = 0; j < NB; j++) acc[j] = 0;
+        sell_row<SLICE>(A, s, lane, [&](const VT *v, const int *c) {
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                VT xv[NB];
+                BlkVec<VT>::load(X + (int64_t)c[t] * NB, xv);
+#pragma unroll
+                for (int j = 0; j < NB; j++) acc[j] = fma(v[t], xv[j], acc[j]);
+            }
+        });
+        if (row >= 0) {
+            const int64_t o = row * NB;
+            if (EPI == EPI_SPMV) {
+#pragma unroll
+                for (int j = 0; j < NB; j++) {
+                    Y[o + j] = (OT)acc[j];
+                    if (NDOT >= 1) d0[j] = (double)X[o + j] * (double)acc[j];
+                    if (NDOT >= 2) d1[j] = (double)X[o + j] * G1[o + j];
+                }
+            } else if (EPI == EPI_RESID) {
+#pragma unroll
+                for (int j = 0; j < NB; j++) Y[o + j] = (OT)((VT)F[o + j] - acc[j]);
+            } else if (EPI == EPI_SMOOTH) {
+                const VT di = invd[row];
+#pragma unroll
+                for (int j = 0; j < NB; j++) {
+                    VT out = X[o + j] + di * ((VT)F[o + j] - acc[j]);
+                    Y[o + j] = (OT)out;
+                    if (NDOT >= 1) d0[j] = (double)out * G0[o + j];
+                    if (NDOT >= 2) d1[j] = (double)out * G1[o + j];
+                }
+            } else {
+                const VT di = invd[row];
+#pragma unroll
+                for (int j = 0; j < NB; j++) Y[o + j] = (OT)(coef * (di * (VT)F[o + j]) + di * acc[j]);
+            }
+        }
+    }
+    if (NDOT >= 1) {
+#pragma unroll
+        for (int j = 0; j < NB; j++) {
+            const double t0 = wave_sum(d0[j]);
+            const double t1 = NDOT >= 2 ? wave_sum(d1[j]) : 0.0;
+            if (lane == 0) {
+                partial[(2 * w_id) * NB + j] = t0;
+                partial[(2 * w_id + 1) * NB + j] = t1;
+            }
+        }
+    }
+}
+
 template <typename VT, typename FT, typename OT, typename IT, int EPI, int NDOT, int R>
 __global__ __launch_bounds__(256) void k_sellw_blk(const Sell<VT, IT> A, const VT *__restrict__ X,
                                                    const FT *__restrict__ F, const VT *__restrict__ invd,
@@ -431,130 +575,139 @@ __global__ __launch_bounds__(256) void k_sellw_blk(const Sell<VT, IT> A, const V
             if (pk == 0) break;
             step(vb, va, std::integral_constant<int, 1>());
         }
-        // epilogue: local column jj = cc * G + u is column (q + cc R) G + u
-        double d0[R][CPL], d1[R][CPL];
-#pragma unroll
-        for (int i = 0; i < R; i++) {
-            const int64_t rr = row0 + R * g + i;
-            const bool live = rr < A.nrows;   // shared-offset slices are never sorted
-            const VT di = (live && (EPI == EPI_SMOOTH || EPI == EPI_POLY)) ? invd[rr] : (VT)0;
-#pragma unroll
-            for (int jj = 0; jj < CPL; jj++) {
-                d0[i][jj] = 0.0;
-                d1[i][jj] = 0.0;
-                if (!live) continue;
-                const int64_t o = rr * NB + (q + (jj / G) * R) * G + jj % G;
-                const VT a = acc[i][jj];
-                if (EPI == EPI_SPMV) {
-                    Y[o] = (OT)a;
-                    if (NDOT >= 1) d0[i][jj] = (double)X[o] * (double)a;
-                    if (NDOT >= 2) d1[i][jj] = (double)X[o] * G1[o];
-                } else if (EPI == EPI_RESID) {
-                    Y[o] = (OT)((VT)F[o] - a);
-                } else if (EPI == EPI_SMOOTH) {
-                    VT out = X[o] + di * ((VT)F[o] - a);
-                    Y[o] = (OT)out;
-                    if (NDOT >= 1) d0[i][jj] = (double)out * G0[o];
-                    if (NDOT >= 2) d1[i][jj] = (double)out * G1[o];
-                } else {
-                    Y[o] = (OT)(coef * (di * (VT)F[o]) + di * a);
-                }
-            }
-        }
-        if (NDOT >= 1) {
-            // the single-vector butterfly over the 64 rows: row bits >= log2 R
-            // across lanes (xor 32 .. R), then the bits below in registers
-#pragma unroll
-            for (int i = 0; i < R; i++)
-#pragma unroll
-                for (int jj = 0; jj < CPL; jj++)
-                    for (int o = 32; o >= R; o >>= 1) {
-                        d0[i][jj] += __shfl_xor(d0[i][jj], o, 64);
-                        if (NDOT >= 2) d1[i][jj] += __shfl_xor(d1[i][jj], o, 64);
-                    }
-#pragma unroll
-            for (int o = R / 2; o >= 1; o >>= 1) {
-                double t0[R][CPL], t1[R][CPL];
-#pragma unroll
-                for (int i = 0; i < R; i++)
-#pragma unroll
-                    for (int jj = 0; jj < CPL; jj++) {
-                        t0[i][jj] = d0[i][jj] + d0[i ^ o][jj];
-                        t1[i][jj] = d1[i][jj] + d1[i ^ o][jj];
-                    }
-#pragma unroll
-                for (int i = 0; i < R; i++)
-#pragma unroll
-                    for (int jj = 0; jj < CPL; jj++) { d0[i][jj] = t0[i][jj]; d1[i][jj] = t1[i][jj]; }
-            }
-            if (g == 0)
-#pragma unroll
-                for (int jj = 0; jj < CPL; jj++) {
-                    const int j = (q + (jj / G) * R) * G + jj % G;
-                    partial[(2 * w_id) * NB + j] = d0[0][jj];
-                    partial[(2 * w_id + 1) * NB + j] = NDOT >= 2 ? d1[0][jj] : 0.0;
-                }
-        }
+        win_epilogue<VT, FT, OT, EPI, NDOT, R>(acc, row0, A.nrows, g, q, X, F, invd, Y, G0, G1, partial, w_id, coef);
         return;
     }
-    // slices with per-row indices (and the waves past the last slice): the
-    // gather path of k_sell_blk
-    double d0[NB], d1[NB];
+    gather_slice<VT, FT, OT, IT, EPI, NDOT>(A, s, lane, X, F, invd, Y, G0, G1, partial, w_id, coef);
+}
+
+// The same pass with windows shared by the four waves of a block: the block's
+// slices and its stages come from the image's stage table (WgStages, built at
+// set-up), every stage's WIN_WG_ROWS rows of X are copied once into the
+// block's LDS (the four waves each issuing a share of the copy) and every
+// wave whose next run lies in them sums that run from there.  With slices one
+// grid line apart, the runs of neighbouring lines (y displacements) fall into
+// the same windows: at c4 the block copies 0.39 of the rows its waves would
+// copy alone.  Two windows alternate by stage; one block barrier per stage
+// orders the copies (each wave waits for its own share, vmcnt 0, before the
+// barrier) and the reads (all of a window's readers are past the barrier
+// before the next copy into it is issued).  Sums, dots and epilogues are the
+// per-wave kernel's, in the same order.
+template <typename VT, typename FT, typename OT, typename IT, int EPI, int NDOT, int R>
+__global__ __launch_bounds__(256, 4) void k_sellws_blk(const Sell<VT, IT> A, const VT *__restrict__ X,
+                                                    const FT *__restrict__ F, const VT *__restrict__ invd,
+                                                    OT *__restrict__ Y, const double *__restrict__ G0,
+                                                    const double *__restrict__ G1, double *__restrict__ partial,
+                                                    VT coef)
+{
+    typedef typename Chunk16<VT>::type CT;
+    constexpr int G = 16 / (int)sizeof(VT);
+    constexpr int CH = NB / G;
+    constexpr int CPL = NB / R;
+    static_assert(CH % R == 0 && (R == 2 || R == 4), "R must be 2 or 4");
+    constexpr int WS = CH + 1;
+    constexpr int NLD = (WIN_WG_ROWS * WS + 63) / 64;   // copy instructions per window (shared by the waves)
+    constexpr int WN = NLD * 64;
+    constexpr int XROWS = (WN - 1) / CH + 1;
+    constexpr int NGR = (WIN_LMAX + G - 1) / G + 1;
+    __shared__ CT win[2 * WN];
+    const int lane = threadIdx.x & 63, wid = wave_id();
+    const int64_t lb = xcd_block((A.nslices + SELL_WAVES - 1) / SELL_WAVES);
+    if (lb < 0) return;   // the whole block
+    const int32_t *wt = A.wgtab + lb * 8;
+    const int64_t s = wt[wid];
+    const int st0 = wt[4], nst = wt[5];
+    const int64_t ib = s < A.nslices ? A.ibase[s] : 0;
+    const int32_t *rt = A.shrun + (ib < 0 ? (-1 - ib) >> 1 : 0);
+    const int64_t base = s < A.nslices ? A.soff[s] : 0;
+    const int width = s < A.nslices ? (int)((A.soff[s + 1] - base) / SLICE) : 0;
+    int32_t runs = (ib < 0 && lane < width) ? rt[lane] : 0;
+    const bool mine = ib < 0 && __builtin_amdgcn_readfirstlane(runs) != 0;
+    if (!mine) gather_slice<VT, FT, OT, IT, EPI, NDOT>(A, s, lane, X, F, invd, Y, G0, G1, partial, s, coef);
+    if (nst == 0) return;   // the whole block
+    const int g = lane / R, q = lane % R;
+    VT acc[R][CPL];
 #pragma unroll
-    for (int j = 0; j < NB; j++) { d0[j] = 0.0; d1[j] = 0.0; }
-    if (s < A.nslices) {
-        const int64_t row = A.row_of(s * SLICE + lane);
-        VT acc[NB];
+    for (int i = 0; i < R; i++)
 #pragma unroll
-        for (int j = 0; j < NB; j++) acc[j] = 0;
-        sell_row<SLICE>(A, s, lane, [&](const VT *v, const int *c) {
+        for (int j = 0; j < CPL; j++) acc[i][j] = 0;
+    const int64_t row0 = s * SLICE;
+    const int hi = (int)(A.ncols - 1);
+    const CT *Xc = reinterpret_cast<const CT *>(X);
+    const CT *Wl = win + R * g * WS + q;   // the lane's first read in a window at row shift 0
+    const int gmax = (width - 1) / G;
+    // this wave's share of the copy of the window at row g0 into buffer D:
+    // instructions i = wid, wid + 4, ...
+    auto copy = [&](int g0, CT *D) {
+        if (g0 >= 0 && g0 + XROWS - 1 <= hi) {
+            const CT *src = Xc + (int64_t)g0 * CH;
 #pragma unroll
-            for (int t = 0; t < 8; t++) {
-                VT xv[NB];
-                BlkVec<VT>::load(X + (int64_t)c[t] * NB, xv);
-#pragma unroll
-                for (int j = 0; j < NB; j++) acc[j] = fma(v[t], xv[j], acc[j]);
+            for (int i0 = 0; i0 < NLD; i0 += SELL_WAVES) {
+                const int i = i0 + wid;
+                if (i < NLD) {
+                    const int slot = i * 64 + lane;
+                    lds_copy16(src + (slot - slot / WS), D + i * 64);
+                }
             }
-        });
-        if (row >= 0) {
-            const int64_t o = row * NB;
-            if (EPI == EPI_SPMV) {
+        } else {
 #pragma unroll
-                for (int j = 0; j < NB; j++) {
-                    Y[o + j] = (OT)acc[j];
-                    if (NDOT >= 1) d0[j] = (double)X[o + j] * (double)acc[j];
-                    if (NDOT >= 2) d1[j] = (double)X[o + j] * G1[o + j];
+            for (int i0 = 0; i0 < NLD; i0 += SELL_WAVES) {
+                const int i = i0 + wid;
+                if (i < NLD) {
+                    const int slot = i * 64 + lane, xc = slot - slot / WS;
+                    const int gr = min(max(g0 + xc / CH, 0), hi);
+                    lds_copy16(Xc + (int64_t)gr * CH + xc % CH, D + i * 64);
                 }
-            } else if (EPI == EPI_RESID) {
+            }
+        }
+    };
+    auto load_vals = [&](CT (&dst)[NGR], int kr) {
 #pragma unroll
-                for (int j = 0; j < NB; j++) Y[o + j] = (OT)((VT)F[o + j] - acc[j]);
-            } else if (EPI == EPI_SMOOTH) {
-                const VT di = invd[row];
-#pragma unroll
-                for (int j = 0; j < NB; j++) {
-                    VT out = X[o + j] + di * ((VT)F[o + j] - acc[j]);
-                    Y[o + j] = (OT)out;
-                    if (NDOT >= 1) d0[j] = (double)out * G0[o + j];
-                    if (NDOT >= 2) d1[j] = (double)out * G1[o + j];
-                }
+        for (int j = 0; j < NGR; j++) {
+            const int gi = min(kr / G + j, gmax);
+            dst[j] = *reinterpret_cast<const CT *>(A.val + base + (int64_t)gi * (G * SLICE) + lane * G);
+        }
+    };
+    int k = 0, rho = 0;
+    int32_t pk = mine ? __builtin_amdgcn_readfirstlane(runs) : 0;
+    CT vg[NGR], vn[NGR];
+    if (mine) load_vals(vg, 0);
+    const int32_t *st = A.wgst + 2 * (int64_t)st0;
+    copy(st[0], win);
+    for (int t = 0; t < nst; t++) {
+        // this wave's share of window t and its values have arrived; after the
+        // barrier every share has, and every read of window t - 1 is done
+        __builtin_amdgcn_s_waitcnt(wait_vm(0));
+        __syncthreads();
+        if (t + 1 < nst) copy(st[2 * (t + 1)], win + ((t + 1) & 1) * WN);
+        const int me = (st[2 * t + 1] >> (8 * wid)) & 0xFF;
+        if (me & 0x80) {
+            const int L = pk & 15;
+            const int kn = k + L;
+            rho++;
+            if ((rho & 63) == 0) runs = (rho + lane < width) ? rt[rho + lane] : 0;
+            const int32_t pn = kn < width ? __builtin_amdgcn_readlane(runs, rho & 63) : 0;
+            load_vals(vn, kn);
+            typedef WinRun<VT, R, NGR> WR;
+            const CT *Wb = Wl + (t & 1) * WN + (me & 0x7F) * WS;
+            if (G == 2) {
+                if (k & 1) WR::template len<1>(acc, Wb, vg, L);
+                else WR::template len<0>(acc, Wb, vg, L);
             } else {
-                const VT di = invd[row];
-#pragma unroll
-                for (int j = 0; j < NB; j++) Y[o + j] = (OT)(coef * (di * (VT)F[o + j]) + di * acc[j]);
+                switch (k & (G - 1)) {
+                case 0: WR::template len<0>(acc, Wb, vg, L); break;
+                case 1: WR::template len<1>(acc, Wb, vg, L); break;
+                case 2: WR::template len<2 % G>(acc, Wb, vg, L); break;
+                default: WR::template len<3 % G>(acc, Wb, vg, L); break;
+                }
             }
+#pragma unroll
+            for (int j = 0; j < NGR; j++) vg[j] = vn[j];
+            k = kn;
+            pk = pn;
         }
     }
-    if (NDOT >= 1) {
-#pragma unroll
-        for (int j = 0; j < NB; j++) {
-            const double t0 = wave_sum(d0[j]);
-            const double t1 = NDOT >= 2 ? wave_sum(d1[j]) : 0.0;
-            if (lane == 0) {
-                partial[(2 * w_id) * NB + j] = t0;
-                partial[(2 * w_id + 1) * NB + j] = t1;
-            }
-        }
-    }
+    if (mine) win_epilogue<VT, FT, OT, EPI, NDOT, R>(acc, row0, A.nrows, g, q, X, F, invd, Y, G0, G1, partial, s, coef);
 }
 
 // Block matrix pass with LPR lanes per row: the wave covers a slice of

@@ -97,6 +97,10 @@ struct DevMat {
     int idx16 = 1, C = SLICE, sorted = 0;
     int64_t *soff = nullptr, *ibase = nullptr;
     int32_t *col0 = nullptr, *c32 = nullptr, *shoff = nullptr, *perm = nullptr, *shrun = nullptr;
+    // windows shared by the four slices of a block (batched stencil images)
+    int32_t *wgtab = nullptr, *wgst = nullptr;
+    int wg_sigma = 0;
+    double wg_ratio = 0.0;   // rows the shared windows copy / rows per-wave windows copy
     uint16_t *d16 = nullptr;
     double *v64 = nullptr;
     float *v32 = nullptr;
@@ -111,7 +115,7 @@ struct DevMat {
     template <typename IT> const IT *idx() const;
     template <typename VT, typename IT> Sell<VT, IT> sv() const
     {
-        return Sell<VT, IT>{n, ncols, nslices, soff, ibase, val<VT>(), idx<IT>(), col0, shoff, perm, shrun};
+        return Sell<VT, IT>{n, ncols, nslices, soff, ibase, val<VT>(), idx<IT>(), col0, shoff, perm, shrun, wgtab, wgst};
     }
 };
 template <> const double *DevMat::val<double>() const { return v64; }
@@ -173,6 +177,9 @@ struct amg_ctx {
     int blk_lpr = 1, blk_threads = 256;   // block-kernel variant (autotuned when prm.nrhs > 1)
     int blk_win = 4;       // stencil images: staged-window block kernel with this many rows per lane (0: off)
     int blk_img_lpr = 0;   // lanes per row the SELL-(64/lpr) block images were built for (0: none)
+    // windows shared by a block's slices where the image has stage tables:
+    // bit 0 for the passes over FP64 values, bit 1 over FP32 values
+    int blk_share = 3;
     // graph replay of the iteration body (single: [0]=CG [1]=FCG; batched likewise)
     int use_graph = 0;
     int fuse_post = 1;   // fused prolongation + post-smoothing through K P (when built)
@@ -279,6 +286,7 @@ struct amg_ctx {
     void release(DevMat &M)
     {
         release(M.soff); release(M.ibase); release(M.shoff); release(M.shrun); release(M.perm); release(M.col0);
+        release(M.wgtab); release(M.wgst);
         release(M.c32);
         release(M.d16);
         release(M.v64); release(M.v32);
@@ -350,6 +358,18 @@ struct amg_ctx {
         if (!S.shoff.empty()) {
             A.shoff = upload(S.shoff);
             A.shrun = upload(S.shrun);
+            if (C == SLICE && S.nshared > 0) {
+                // the block kernels' windows shared by a block's slices
+                amgiga::WgStages W;
+                amgiga::choose_wg_stages(S, C, (S.nslices + SELL_WAVES - 1) / SELL_WAVES, W);
+                const double per_wave = (double)W.runs * amgk::WIN_ROWS;
+                if (W.runs > 0 && W.st.size() / 2 < ((size_t)1 << 31)) {
+                    A.wgtab = upload(W.tab);
+                    A.wgst = upload(W.st);
+                    A.wg_sigma = W.sigma;
+                    A.wg_ratio = (double)W.copied_rows / per_wave;
+                }
+            }
         }
         if (S.sorted) A.perm = upload(S.perm);
         if (want64) A.v64 = upload(S.v64);
@@ -384,7 +404,9 @@ struct amg_ctx {
     template <typename VT> void level0_passes()
     {
         Level &L = lev[0];
-        sell_blk<double, double, double, EPI_SPMV, 1>(0, bP, nullptr, nullptr, bQ, nullptr, nullptr);
+        // the outer product with the dots of the Krylov method in use
+        if (prm.krylov) sell_blk<double, double, double, EPI_SPMV, 2>(0, bP, nullptr, nullptr, bQ, nullptr, bR);
+        else sell_blk<double, double, double, EPI_SPMV, 1>(0, bP, nullptr, nullptr, bQ, nullptr, nullptr);
         sell_blk<VT, double, VT, EPI_RESID, 0>(0, (const VT *)L.bu, bR, L.invd<VT>(), (VT *)L.br, nullptr, nullptr);
         sell_blk<VT, double, VT, EPI_RESID, 0>(0, (const VT *)L.bu, bR, L.invd<VT>(), (VT *)L.br, nullptr, nullptr);
     }
@@ -429,15 +451,23 @@ struct amg_ctx {
         blk_threads = 256;
         const bool win0 = lev[0].A.nshared > 0 && lev[0].A.shrun != nullptr;
         if (win0) {
-            int best_r = 4;
+            int best_r = 4, best_share = 0;
             float best_t = 1e30f;
-            for (int R : {2, 4}) {
-                blk_win = R;
-                float t = f32 ? time_passes([&] { level0_passes<float>(); }) : time_passes([&] { level0_passes<double>(); });
-                tune_log.push_back({"window rows per lane " + std::to_string(R), t});
-                if (t < best_t) { best_t = t; best_r = R; }
+            for (int share : {0, 1, 2, 3}) {
+                if (share && !lev[0].A.wgtab) continue;
+                if ((share & 2) && !f32) continue;   // no pass over FP32 values
+                blk_share = share;
+                for (int R : {2, 4}) {
+                    blk_win = R;
+                    float t = f32 ? time_passes([&] { level0_passes<float>(); })
+                                  : time_passes([&] { level0_passes<double>(); });
+                    tune_log.push_back({"shared windows " + std::to_string(share) + ", window rows per lane " +
+                                        std::to_string(R), t});
+                    if (t < best_t) { best_t = t; best_r = R; best_share = share; }
+                }
             }
             blk_win = best_r;
+            blk_share = best_share;
         }
         const bool lvl0 = !(win0 && blk_win > 0);
         struct Best { int lpr, thr; float ms; } best{1, 256, 1e30f};
@@ -1100,7 +1130,17 @@ struct amg_ctx {
             nb = lgrid * SELL_WAVES;   // dot partials: one per wavefront of a logical block
 #define BLKW(IT, R) hipLaunchKernelGGL((k_sellw_blk<VT, FT, OT, IT, EPI, NDOT, R>), dim3(grid), dim3(256), 0, stream, \
                                        A.sv<VT, IT>(), x, f, invd, y, g0, g1, bpartial, coef)
-            if (A.idx16) {
+#define BLKWS(IT, R) hipLaunchKernelGGL((k_sellws_blk<VT, FT, OT, IT, EPI, NDOT, R>), dim3(grid), dim3(256), 0, \
+                                        stream, A.sv<VT, IT>(), x, f, invd, y, g0, g1, bpartial, coef)
+            if ((blk_share & (sizeof(VT) == 8 ? 1 : 2)) && A.wgtab) {
+                if (A.idx16) {
+                    if (blk_win == 2) BLKWS(uint16_t, 2);
+                    else BLKWS(uint16_t, 4);
+                } else {
+                    if (blk_win == 2) BLKWS(int32_t, 2);
+                    else BLKWS(int32_t, 4);
+                }
+            } else if (A.idx16) {
                 if (blk_win == 2) BLKW(uint16_t, 2);
                 else BLKW(uint16_t, 4);
             } else {
@@ -1108,6 +1148,7 @@ struct amg_ctx {
                 else BLKW(int32_t, 4);
             }
 #undef BLKW
+#undef BLKWS
         } else if (blk_lpr > 1 && B.soff && B.val<VT>()) {
             nb = blk_lpr == 4   ? launch_sellb<VT, FT, OT, EPI, NDOT, 4>(B, x, f, invd, y, g0, g1, coef)
                  : blk_lpr == 8 ? launch_sellb<VT, FT, OT, EPI, NDOT, 8>(B, x, f, invd, y, g0, g1, coef)
@@ -1587,8 +1628,8 @@ amg_status amg_sell_spmv_host(int64_t n, int64_t ncols, const int64_t *row_ptr, 
 {
     g_err.clear();
     if (n <= 0 || ncols <= 0 || !row_ptr || !col || !val || !x || !y || (C != 4 && C != 8 && C != 16 && C != 32 &&
-        C != 64) || layout < 0 || layout > 3 || (layout >= 1 && layout != 2 && ncols != n) ||
-        (layout == 3 && C != SLICE)) {
+        C != 64) || layout < 0 || layout > 4 || (layout >= 1 && layout != 2 && ncols != n) ||
+        (layout >= 3 && C != SLICE)) {
         set_err("bad size, NULL array, slice height or layout");
         return AMG_ERR_ARG;
     }
@@ -1991,6 +2032,14 @@ amg_status amg_set_option(amg_ctx *c, int option, int value)
     case AMG_OPT_GRAPH: c->use_graph = value ? 1 : 0; break;
     case AMG_OPT_FUSE_POST: c->fuse_post = value ? 1 : 0; c->drop_graphs(); break;
     case AMG_OPT_TAIL: c->use_tail = value ? 1 : 0; c->drop_graphs(); break;
+    case AMG_OPT_WINDOW_SHARE:
+        if (value < 0 || value > 3) {
+            set_err("AMG_OPT_WINDOW_SHARE takes a mask: 1 FP64-value passes, 2 FP32-value passes");
+            return AMG_ERR_ARG;
+        }
+        c->blk_share = value;
+        c->drop_graphs();
+        break;
     case AMG_OPT_BLOCK_WINDOW:
         if (value != 0 && value != 2 && value != 4) {
             set_err("AMG_OPT_BLOCK_WINDOW takes 0 (off) or 2 or 4 rows per lane");
@@ -2020,6 +2069,7 @@ amg_status amg_get_option(const amg_ctx *c, int option, int *value)
     case AMG_OPT_GRAPH: *value = c->use_graph; break;
     case AMG_OPT_FUSE_POST: *value = c->fuse_post; break;
     case AMG_OPT_TAIL: *value = c->use_tail && c->tail_start > 0 ? c->tail_start : 0; break;
+    case AMG_OPT_WINDOW_SHARE: *value = c->lev[0].A.wgtab ? c->blk_share : 0; break;
     case AMG_OPT_BLOCK_WINDOW: *value = c->blk_win; break;
     default: set_err("unknown option"); return AMG_ERR_ARG;
     }

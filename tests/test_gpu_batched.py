@@ -180,9 +180,9 @@ def test_batched_learned_polynomial_smoother(oracle, amg):
 @pytest.mark.parametrize("case", ["3d-p3-n16", "2d-p5-n40", "2d-p2-n61", "kappa-p4-n8"])
 @pytest.mark.parametrize("fp32", [0, 1])
 def test_block_window_equals_gather(oracle, amg, case, fp32):
-    """The block passes with staged x windows (2 or 4 rows per lane)
-    against the gather kernel they replace: every column bit for bit, FP64
-    and FP32 V-cycles;
+    """The block passes with staged x windows (2 or 4 rows per lane; per
+    wave, and shared by the four slices of a block) against the gather kernel
+    they replace: every column bit for bit, FP64 and FP32 V-cycles;
     x-runs longer than one window (p = 5), slices straddling x-lines, a
     partly filled last slice, variable coefficients."""
     print(f"case block window {case} fp32={fp32}", flush=True)
@@ -199,15 +199,22 @@ def test_block_window_equals_gather(oracle, amg, case, fp32):
     ctx = amg.Context(rp, ci, v, **kw)
     assert ctx.format(0)["shared_slices"] > 0
     assert ctx.option(amg.amg.AMG_OPT_BLOCK_WINDOW) == 4       # the default without autotuning
+    assert ctx.option(amg.amg.AMG_OPT_WINDOW_SHARE) == 3   # shared windows in every pass, the default
     outs = {}
-    for rows in (0, 2, 4):
-        ctx.set_block_window(rows)
-        outs[rows] = ctx.solve_batched(Ft, tol=1e-8)
-    assert outs[0]["status"] == 0
-    for rows in (2, 4):
-        assert outs[rows]["iters"] == outs[0]["iters"], rows
-        assert torch.equal(outs[rows]["U"], outs[0]["U"]), rows
-    print(f"  iterations {outs[0]['iters']}", flush=True)
+    for share in (0, 3):
+        ctx.set_window_share(share)
+        for rows in (0, 2, 4):
+            ctx.set_block_window(rows)
+            outs[share, rows] = ctx.solve_batched(Ft, tol=1e-8)
+    ref = outs[0, 0]
+    assert ref["status"] == 0
+    for key, out in outs.items():
+        assert out["iters"] == ref["iters"], key
+        assert torch.equal(out["U"], ref["U"]), key
+    print(f"  iterations {ref['iters']}", flush=True)
+    for bad in (-1, 4):
+        with pytest.raises(amg.AmgError):
+            ctx.set_window_share(bad)
     for bad in (1, 3):
         with pytest.raises(amg.AmgError):
             ctx.set_block_window(bad)

@@ -47,16 +47,17 @@ def test_layouts_compute_Kx(oracle, amg, C):
         x = np.random.default_rng(1).standard_normal(n)
         ref, scale = _ref(rp, ci, v, x, n)
         ys = []
-        # layout 3 (C = 64 only): shared-offset slices through the block
-        # kernels' staged x windows (runs of consecutive offsets)
-        for layout in ((0, 1, 2, 3) if C == 64 else (0, 1, 2)):
+        # layouts 3 and 4 (C = 64 only): shared-offset slices through the
+        # block kernels' staged x windows (runs of consecutive offsets), per
+        # wave and shared by the four slices of a block
+        for layout in ((0, 1, 2, 3, 4) if C == 64 else (0, 1, 2)):
             y, shared, stored = amg.sell_spmv_host(rp, ci, v, x, C_slice=C, layout=layout)
             assert np.all(np.abs(y - ref) <= 8 * np.finfo(float).eps * scale + 1e-300), (name, layout)
             assert stored >= len(v)
             if layout in (0, 2):
                 assert shared == 0
             ys.append(y)
-            if layout in (1, 3) and name in ("2d-p2", "3d-p3", "3d-kappa-p5") and C == 64:
+            if layout in (1, 3, 4) and name in ("2d-p2", "3d-p3", "3d-kappa-p5") and C == 64:
                 assert shared > 0, name
         for y in ys[1:]:
             assert np.array_equal(ys[0], y), name
@@ -107,8 +108,11 @@ def test_window_walk_edge_cases(oracle, amg):
         x = np.random.default_rng(n).standard_normal(n)
         y1, sh1, _ = amg.sell_spmv_host(rp, ci, v, x, C_slice=64, layout=1)
         y3, sh3, _ = amg.sell_spmv_host(rp, ci, v, x, C_slice=64, layout=3)
-        assert sh1 == sh3 and (sh3 > 0) == shared, n
+        y4, sh4, _ = amg.sell_spmv_host(rp, ci, v, x, C_slice=64, layout=4)
+        assert sh1 == sh3 == sh4 and (sh3 > 0) == shared, n
         assert np.array_equal(y1, y3), n
+        assert np.array_equal(y1, y4), n
     rp, ci, v = cases[0][0]
-    with pytest.raises(Exception):
-        amg.sell_spmv_host(rp, ci, v, np.zeros(len(rp) - 1), C_slice=16, layout=3)
+    for layout in (3, 4):
+        with pytest.raises(Exception):
+            amg.sell_spmv_host(rp, ci, v, np.zeros(len(rp) - 1), C_slice=16, layout=layout)
