@@ -32,7 +32,11 @@ HBM_PEAK_GBS = 8000.0
 # (kernels.h, solver.hip) are the ones the counters were taken with (SHA-256 of
 # the two files, concatenated), else null.
 TRAFFIC_SOURCE = "profiles/k_sell_c4_fp64_pmc.md"
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # (workload, SHA-256 of kernels.h + solver.hip): bytes per launch, SpMV and
+    # residual launches of one solve
+    ("c4", "06d5e2a90a7c8119cb49853f55eef763c535b25daf6f23367637e88046cf9950"): 5934637179,
+}
 
 
 def kernel_source_sha():
@@ -46,6 +50,27 @@ def kernel_source_sha():
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def stream_read_gbs(torch, amgmod, nbytes=4 << 30):
+    """The streaming-read reference (amg_stream_read: 16-byte nontemporal loads,
+    as the matrix passes) over a 4 GiB buffer of ones, best of five after one
+    warm-up, timed with events on torch's current stream (the probe's stream);
+    the per-thread sums are checked against the buffer's."""
+    buf = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    sink = torch.empty(2048 * 256, dtype=torch.float64, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for rep in range(6):
+        e0.record()
+        amgmod.stream_read(buf, sink)
+        e1.record()
+        e1.synchronize()
+        if rep:
+            best = min(best, e0.elapsed_time(e1))
+    assert float(sink.sum()) == nbytes // 8
+    del buf, sink
+    return nbytes / (best * 1e-3) / 1e9
 
 
 def cpu_baseline(cfg, seed, tol, iters_gpu, u_gpu, one_core_iters):
@@ -275,7 +300,8 @@ def main():
     kernel_ms = dms / max(dl, 1)
     achieved = dby / (dms * 1e-3) / 1e9 if dms > 0 else 0.0
     if nrhs > 1:
-        kname = "k_sellw_blk (level-0 16-column SpMV / residual / smoother pass, staged x windows)"
+        kname = ("k_sellw_blk / k_sellws_blk (level-0 16-column SpMV / residual / smoother pass, staged x "
+                 "windows, per wave / shared by a block)")
     elif args.mode in ("paper", "cheb"):
         kname = "k_sell_cheb + k_sell (level-0 Chebyshev / SpMV / residual passes)"
     else:
@@ -292,7 +318,10 @@ def main():
                                "frac": round(d["bytes"] / (d["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
                                if d["ms"] > 0 else None}
                            for k, d in prof["passes"].items()}}
-    log(f"level-0 passes: {json.dumps(roofline['passes'])}")
+    sgbs = stream_read_gbs(torch, amgmod)
+    roofline["stream_read_gbs"] = round(sgbs, 1)
+    roofline["frac_of_stream"] = round(achieved / sgbs, 4)
+    log(f"level-0 passes: {json.dumps(roofline['passes'])}; streaming read {sgbs:.1f} GB/s")
 
     cpu = None
     if not args.no_cpu_baseline and args.mode == "fp64" and cfg["kind"] in ("poisson", "cube"):

@@ -346,6 +346,14 @@ amg_status amg_get_profile(amg_ctx *c, int64_t *launches, double *ms, double *by
 typedef enum { AMG_PASS_SPMV = 0, AMG_PASS_RESID = 1, AMG_PASS_SMOOTH = 2, AMG_PASS_POLY = 3, AMG_PASS_KP = 4,
                AMG_PASS_OTHER = 5, AMG_PASS_KINDS = 6 } amg_pass_kind;
 amg_status amg_get_profile_pass(const amg_ctx *c, int kind, int64_t *launches, double *ms, double *bytes);
+/* Streaming-read reference for the rooflines (no step of the solve): reads
+ * `bytes` of device memory at buf (16-byte aligned, bytes a multiple of 16)
+ * once, with the 16-byte nontemporal loads of the matrix passes, on `stream`
+ * (a hipStream_t, NULL = default), in min(sink_len / 256, 65536) blocks of 256
+ * threads; thread t writes the sum of the doubles it read to sink[t] (device
+ * array of sink_len >= 256 doubles, caller-owned).  Asynchronous: time it with
+ * events on the same stream.  AMG_ERR_ARG for a bad pointer, size or sink. */
+amg_status amg_stream_read(const void *buf, int64_t bytes, double *sink, int64_t sink_len, void *stream);
 /* Description of a level's single-vector layout: slice height, stored
  * entries with padding, index bytes per entry in slices with per-entry
  * indices (2 or 4), and the number of slices (of ceil(n / slice)) that store

@@ -26,7 +26,7 @@ EXPORTS = ["amg_params_default", "amg_setup", "pcg_solve", "pcg_solve_batched", 
            "amg_get_batched_variant", "amg_set_batched_variant", "amg_set_option", "amg_sell_spmv_host",
            "amg_iga_cube_size", "amg_iga_cube", "amg_get_prolongator", "amg_get_setup_rounds",
            "amg_mlp_backward_noalloc", "amg_get_option", "amg_get_profile_pass",
-           "amg_get_residual_history"]
+           "amg_get_residual_history", "amg_stream_read"]
 AMG_OPT_GRAPH, AMG_OPT_FUSE_POST, AMG_OPT_BLOCK_WINDOW, AMG_OPT_TAIL, AMG_OPT_WINDOW_SHARE = 1, 2, 3, 4, 5
 MLP_NPARAM, MLP_NFEAT, MLP_NACT, MLP_NDEL = 4996, 8, 128, 132
 MLP_NOALLOC_MAX_B = 16384
@@ -95,6 +95,7 @@ def lib():
         L.amg_get_profile.argtypes = [vp, i64p, f64p, f64p]
         L.amg_get_profile_pass.argtypes = [vp, C.c_int, i64p, f64p, f64p]
         L.amg_get_residual_history.argtypes = [vp, f64p, C.c_int, C.POINTER(C.c_int)]
+        L.amg_stream_read.argtypes = [vp, C.c_int64, vp, C.c_int64, vp]
         L.amg_get_format.argtypes = [vp, C.c_int, C.POINTER(C.c_int), i64p, C.POINTER(C.c_int), i64p]
         L.amg_iga_poisson_size.argtypes = [C.c_int, C.c_int, C.c_int, i64p, i64p]
         L.amg_iga_poisson.argtypes = [C.c_int, C.c_int, C.c_int, i64p, i32p, f64p, f64p]
@@ -170,6 +171,17 @@ def iga_diffusion(p, n, a, mk, want_F=True):
     _check(lib().amg_iga_diffusion(p, n, len(a_), _p(a_, f64p), _p(m_, i32p), _p(rp, i64p), _p(ci, i32p),
                                    _p(v, f64p), _p(F, f64p) if want_F else None))
     return rp, ci, v, F
+
+
+def stream_read(buf, sink, stream=None):
+    """One streaming read of the device tensor buf (amg_stream_read): thread t
+    of the probe writes the sum of what it read to sink[t] (float64 device
+    tensor).  Asynchronous on `stream` (torch's current stream by default)."""
+    import torch
+    assert buf.is_cuda and sink.is_cuda and sink.dtype == torch.float64 and buf.is_contiguous()
+    st = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(lib().amg_stream_read(C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
+                                 C.c_void_p(sink.data_ptr()), sink.numel(), C.c_void_p(st)))
 
 
 def sell_spmv_host(indptr, indices, data, x, C_slice=64, layout=1, ncols=None):

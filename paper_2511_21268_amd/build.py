@@ -35,8 +35,12 @@ def build(verbose=False):
     _run([HIPCC, "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
          + inc + ["-c", os.path.join(CSRC, "setup_dev.hip"), "-o", sdev_o])
+    probe_o = os.path.join(bdir, "probe.o")
+    _run([HIPCC, "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
+         + inc + ["-c", os.path.join(CSRC, "probe.hip"), "-o", probe_o])
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, dev_o, sdev_o, host_o, "-pthread",
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, dev_o, sdev_o, probe_o, host_o, "-pthread",
           "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"])
     os.replace(tmp, LIB)
     return LIB
