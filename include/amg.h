@@ -348,11 +348,13 @@ typedef enum { AMG_PASS_SPMV = 0, AMG_PASS_RESID = 1, AMG_PASS_SMOOTH = 2, AMG_P
 amg_status amg_get_profile_pass(const amg_ctx *c, int kind, int64_t *launches, double *ms, double *bytes);
 /* Streaming-read reference for the rooflines (no step of the solve): reads
  * `bytes` of device memory at buf (16-byte aligned, bytes a multiple of 16)
- * once, with the 16-byte nontemporal loads of the matrix passes, on `stream`
- * (a hipStream_t, NULL = default), in min(sink_len / 256, 65536) blocks of 256
- * threads; thread t writes the sum of the doubles it read to sink[t] (device
- * array of sink_len >= 256 doubles, caller-owned).  Asynchronous: time it with
- * events on the same stream.  AMG_ERR_ARG for a bad pointer, size or sink. */
+ * once, with the 16-byte nontemporal loads of the matrix passes (each wave
+ * 4 KB contiguous chunks, four loads in flight), on `stream` (a hipStream_t,
+ * NULL = default), in min(sink_len / 256, 65536) blocks of 256 threads (2048:
+ * eight per compute unit, the fastest grid measured); thread t writes the sum
+ * of the doubles it read to sink[t] (device array of sink_len >= 256 doubles,
+ * caller-owned).  Asynchronous: time it with events on the same stream.
+ * AMG_ERR_ARG for a bad pointer, size or sink. */
 amg_status amg_stream_read(const void *buf, int64_t bytes, double *sink, int64_t sink_len, void *stream);
 /* Description of a level's single-vector layout: slice height, stored
  * entries with padding, index bytes per entry in slices with per-entry
