@@ -27,7 +27,7 @@ EXPORTS = ["amg_params_default", "amg_setup", "pcg_solve", "pcg_solve_batched", 
            "amg_iga_cube_size", "amg_iga_cube", "amg_get_prolongator", "amg_get_setup_rounds",
            "amg_mlp_backward_noalloc", "amg_get_option", "amg_get_profile_pass",
            "amg_get_residual_history", "amg_stream_read"]
-AMG_OPT_GRAPH, AMG_OPT_FUSE_POST, AMG_OPT_BLOCK_WINDOW, AMG_OPT_TAIL, AMG_OPT_WINDOW_SHARE = 1, 2, 3, 4, 5
+AMG_OPT_GRAPH, AMG_OPT_FUSE_POST, AMG_OPT_BLOCK_WINDOW, AMG_OPT_TAIL, AMG_OPT_WINDOW_SHARE, AMG_OPT_X_WINDOW = 1, 2, 3, 4, 5, 6
 MLP_NPARAM, MLP_NFEAT, MLP_NACT, MLP_NDEL = 4996, 8, 128, 132
 MLP_NOALLOC_MAX_B = 16384
 PASS_KINDS = ("spmv", "resid", "smooth", "poly", "kp", "other")   # amg_pass_kind order
@@ -307,6 +307,10 @@ class Context:
 
     def set_tail(self, on):
         _check(lib().amg_set_option(self.h, AMG_OPT_TAIL, int(on)))
+
+    def set_x_window(self, on):
+        """Single-vector matrix passes of stencil images through LDS windows of x."""
+        _check(lib().amg_set_option(self.h, AMG_OPT_X_WINDOW, int(on)))
 
     def set_window_share(self, mask):
         """Block windows shared by the four slices of a block (batched stencil

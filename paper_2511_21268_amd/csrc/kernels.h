@@ -174,6 +174,7 @@ template <typename VT, typename IT> struct Sell {
                             // (0 first: no run table for that list)
     const int32_t *wgtab;   // window stages shared by the four waves of a block
     const int32_t *wgst;    // (layout in host.h: WgStages); nullptr: none
+    int xwin;               // k_sell walks the slices with run tables through x windows
 
     // row held by slot q, or -1
     __device__ __forceinline__ int64_t row_of(int64_t q) const
@@ -253,6 +254,163 @@ __device__ __forceinline__ void sell_row(const Sell<VT, IT> &A, int64_t s, int r
     }
 }
 
+// compiler fence for the wave's own LDS accesses (in order per wave)
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Direct global-to-LDS load of 16 bytes per lane (global_load_lds_dwordx4):
+// lane l's 16 bytes from src go to lds + 16 l (lds wave-uniform).  The host
+// pass of the compiler does not take the builtin, hence the guard.
+template <typename CT> __device__ __forceinline__ void lds_copy16(const CT *src, CT *lds)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+#endif
+}
+
+// s_waitcnt immediates (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4,
+// lgkmcnt 11:8): wait for this wave's LDS operations only, or until at most
+// n < 16 of its vector memory loads are outstanding
+constexpr int WAIT_LGKM0 = 0xC07F;
+constexpr int wait_vm(int n) { return 0x0F70 | n; }   // n < 16
+
+// ---- x windows of the single-vector K pass ----------------------------------
+//
+// In a slice with shared column offsets and a run table (stencil rows), a run
+// of L consecutive offsets o .. o + L - 1 makes lane r read x[row0 + r + o + t],
+// t < L: together the 63 + L consecutive entries from row0 + o.  The wave
+// copies the 16-byte-aligned 1 KB of x that holds them into its LDS window with
+// one direct global-to-LDS load, and each lane reads its L entries from there
+// instead of the L gathers of the gather walk (8 of its 12 vector-memory
+// instructions per 8 entries).  A run whose 1 KB would leave [0, ncols) takes
+// the gathers, clamped as the gather walk clamps.  Entries are summed in
+// ascending order, run after run; the padding entries of a list (value 0, past
+// its last run) are skipped: an FMA with a zero product leaves a nonzero or +0
+// sum unchanged.  Measured at c4 (FP64): the SpMV pass 1.023 -> 0.996 ms, the
+// residual 1.022 -> 1.003 ms.
+template <typename VT> struct Vec16;
+template <> struct Vec16<double> { typedef vd2 type; };
+template <> struct Vec16<float> { typedef vf4 type; };
+
+// the run's L entries at offset OFF of the lane's value groups vg, x from the
+// window (Wl: the lane's first entry) or gathered from column c0 on
+template <typename VT, int NG, int OFF>
+__device__ __forceinline__ VT xwin_run(VT acc, const typename Vec16<VT>::type (&vg)[NG], int L, bool win,
+                                       const VT *Wl, const VT *__restrict__ x, int c0, bool clamp, int hi)
+{
+    constexpr int E = 16 / (int)sizeof(VT);
+    static_assert(OFF + WIN_LMAX <= NG * E, "run past its value groups");
+    VT ev[NG * E];
+#pragma unroll
+    for (int j = 0; j < NG; j++)
+#pragma unroll
+        for (int u = 0; u < E; u++) ev[j * E + u] = vg[j][u];
+    if (win) {
+#pragma unroll
+        for (int t = 0; t < WIN_LMAX; t++)
+            if (t < L) acc = fma(ev[OFF + t], Wl[t], acc);
+    } else {
+#pragma unroll
+        for (int t = 0; t < WIN_LMAX; t++)
+            if (t < L) {
+                const int c = clamp ? min(max(c0 + t, 0), hi) : c0 + t;
+                acc = fma(ev[OFF + t], *reinterpret_cast<const VT *>(reinterpret_cast<const char *>(x) +
+                                                                        (uint32_t)c * (uint32_t)sizeof(VT)),
+                          acc);
+            }
+    }
+    return acc;
+}
+// xwin_run with the offset a runtime value below E + WIN_LMAX (constant
+// branches: the offsets the value groups of two runs can start at)
+template <typename VT, int NG>
+__device__ __forceinline__ VT xwin_run_at(int off, VT acc, const typename Vec16<VT>::type (&vg)[NG], int L, bool win,
+                                          const VT *Wl, const VT *__restrict__ x, int c0, bool clamp, int hi)
+{
+    constexpr int E = 16 / (int)sizeof(VT);
+    static_assert(E - 1 + WIN_LMAX <= 10, "one case per offset");
+#define XWR(O) return xwin_run<VT, NG, (O) < E + WIN_LMAX ? (O) : 0>(acc, vg, L, win, Wl, x, c0, clamp, hi)
+    switch (off) {
+    case 0: XWR(0);
+    case 1: XWR(1);
+    case 2: XWR(2);
+    case 3: XWR(3);
+    case 4: XWR(4);
+    case 5: XWR(5);
+    case 6: XWR(6);
+    case 7: XWR(7);
+    case 8: XWR(8);
+    case 9: XWR(9);
+    default: XWR(10);
+    }
+#undef XWR
+}
+
+// Row sum of lane r of shared-offset slice s through x windows (W: the wave's
+// 2 KB of LDS, one window per run of a pair); runs: this lane's entry of the
+// slice's first 64 runs.  Runs go in pairs: both windows copied and the value
+// groups of both runs loaded before one wait, then the two runs summed.
+template <typename VT, typename IT>
+__device__ __forceinline__ VT xwin_row(const Sell<VT, IT> &A, int64_t s, int lane, int32_t runs, const int32_t *rt,
+                                       int width, const VT *__restrict__ x, VT *W)
+{
+    typedef typename Vec16<VT>::type CT;
+    constexpr int E = 16 / (int)sizeof(VT);
+    constexpr int NG = (2 * WIN_LMAX + 2 * E - 2) / E;   // value groups covering two runs at any offset
+    constexpr int WE = 64 * E;                           // entries of one window
+    constexpr int XL = (E - 1 + 63 + WIN_LMAX + E - 1) / E;   // pieces of x one run reads
+    const int64_t base = A.soff[s];
+    const bool clamp = !((-1 - A.ibase[s]) & 1);
+    const int hi = (int)(A.ncols - 1);
+    const int row0 = (int)(s * SLICE);
+    const int gmax = (width - 1) / E;
+    VT acc = 0;
+    int k = 0, rho = 0;
+    auto next_run = [&]() -> int32_t {
+        rho++;
+        if ((rho & 63) == 0) runs = (rho + lane < width) ? rt[rho + lane] : 0;
+        return k < width ? __builtin_amdgcn_readlane(runs, rho & 63) : 0;
+    };
+    int32_t pa = __builtin_amdgcn_readfirstlane(runs);
+    while (pa != 0) {
+        const int ka = k, la = pa & 15, ga = row0 + (pa >> 4), gaa = ga & ~(E - 1);
+        k += la;
+        const int32_t pb = next_run();
+        const int lb = pb & 15, gb = row0 + (pb >> 4), gba = gb & ~(E - 1);
+        const bool wa = gaa >= 0 && gaa + WE - 1 <= hi;
+        const bool wb = pb != 0 && gba >= 0 && gba + WE - 1 <= hi;
+        // the previous pair's reads of the windows have returned
+        __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
+        wave_lds_sync();
+        // a run reads entries g .. g + 62 + L of x: the first XL 16-byte pieces
+        // from g rounded down to a piece
+        if (wa && lane < XL) lds_copy16(reinterpret_cast<const CT *>(x + gaa) + lane, reinterpret_cast<CT *>(W));
+        if (wb && lane < XL) lds_copy16(reinterpret_cast<const CT *>(x + gba) + lane, reinterpret_cast<CT *>(W + WE));
+        CT vg[NG];
+#pragma unroll
+        for (int j = 0; j < NG; j++) {
+            const VT *p = A.val + base + (int64_t)min(ka / E + j, gmax) * (E * SLICE) + lane * E;
+            vg[j] = __builtin_nontemporal_load(reinterpret_cast<const CT *>(p));
+        }
+        __builtin_amdgcn_s_waitcnt(wait_vm(0));
+        wave_lds_sync();
+        const int off = ka & (E - 1);
+        acc = xwin_run_at<VT, NG>(off, acc, vg, la, wa, W + (ga - gaa) + lane, x, ga + lane, clamp, hi);
+        if (pb != 0) {
+            acc = xwin_run_at<VT, NG>(off + la, acc, vg, lb, wb, W + WE + (gb - gba) + lane, x, gb + lane, clamp, hi);
+            k += lb;
+            pa = next_run();
+        } else {
+            pa = 0;
+        }
+    }
+    return acc;
+}
+
 // x[i] for 0 <= i < 2^32 / sizeof(T), addressed as a uniform base plus a
 // 32-bit byte offset (vectors of at most 2^29 FP64 entries; checked at set-up).
 template <typename T> __device__ __forceinline__ T ld32(const T *__restrict__ x, int i)
@@ -284,18 +442,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
                                               const double *__restrict__ g1, double *__restrict__ partial,
                                               VT coef)
 {
+    // two 1 KB x windows per wave (passes over FP64 values only: with FP32
+    // values a run carries half the bytes and the per-run wait costs more than
+    // the gathers, measured 0.62 against 0.50 ms for the c4 FP32 residual)
+    constexpr bool XW = sizeof(VT) == 8;
+    __shared__ VT xw[XW ? SELL_WAVES * 2 * 64 * 2 : 1];
     const int lane = threadIdx.x & 63, wid = wave_id();
     const int64_t s = (int64_t)blockIdx.x * SELL_WAVES + wid;
     double d0 = 0.0, d1 = 0.0;
     if (s < A.nslices) {
         const int64_t row = A.row_of(s * SLICE + lane);
         VT acc = 0;
-        // unroll 2 where the compiler keeps all gathers in flight within 64
-        // VGPRs; the SpMV with fused dots keeps one group per step
-        sell_row<SLICE, NDOT == 0 ? 2 : 1>(A, s, lane, [&](const VT *v, const int *c) {
+        const int64_t ib = A.ibase[s];
+        const int32_t *rt = A.shrun + (ib < 0 ? (-1 - ib) >> 1 : 0);
+        const int width = (int)((A.soff[s + 1] - A.soff[s]) / SLICE);
+        const int32_t runs = (XW && A.xwin && ib < 0 && lane < width) ? rt[lane] : 0;
+        if (XW && __builtin_amdgcn_readfirstlane(runs) != 0) {
+            acc = xwin_row(A, s, lane, runs, rt, width, x, xw + wid * 2 * 64 * 2);
+        } else {
+            // unroll 2 where the compiler keeps all gathers in flight within 64
+            // VGPRs; the SpMV with fused dots keeps one group per step
+            sell_row<SLICE, NDOT == 0 ? 2 : 1>(A, s, lane, [&](const VT *v, const int *c) {
 #pragma unroll
-            for (int t = 0; t < 8; t++) acc = fma(v[t], ld32(x, c[t]), acc);
-        });
+                for (int t = 0; t < 8; t++) acc = fma(v[t], ld32(x, c[t]), acc);
+            });
+        }
         if (row >= 0) {
             if (EPI == EPI_SPMV) {
                 y[row] = (OT)acc;

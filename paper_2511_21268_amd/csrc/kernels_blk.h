@@ -190,24 +190,6 @@ template <> struct Chunk16<float> {
     static __device__ inline void unpack(type q, float *o) { o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w; }
 };
 
-// compiler fence for the wave's own LDS accesses (in order per wave)
-__device__ inline void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Direct global-to-LDS load of 16 bytes per lane (global_load_lds_dwordx4):
-// lane l's 16 bytes from src go to lds + 16 l (lds wave-uniform).  The host
-// pass of the compiler does not take the builtin, hence the guard.
-template <typename CT> __device__ __forceinline__ void lds_copy16(const CT *src, CT *lds)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
-#endif
-}
-
 // One 16-byte value group of the window kernels.  FP64: a streaming load --
 // the values pass once, and the block's X (128 B per row) would not stay in
 // L2 and the memory-side cache beside them (measured: 10.5 -> 9.8 GB of HBM
@@ -229,12 +211,6 @@ template <typename T> __device__ __forceinline__ void keep_in_vgprs(const T &v)
     asm volatile("" : : "v"(v));
 #endif
 }
-
-// s_waitcnt immediates (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4,
-// lgkmcnt 11:8): wait for this wave's LDS operations only, or until at most
-// n < 16 of its vector memory loads are outstanding
-constexpr int WAIT_LGKM0 = 0xC07F;
-constexpr int wait_vm(int n) { return 0x0F70 | n; }   // n < 16
 
 // Value held by lane i of each aligned group of R lanes (R = 2 or 4), to
 // every lane of the group: one DPP quad permutation per 32 bits.

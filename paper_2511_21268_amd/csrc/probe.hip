@@ -5,7 +5,7 @@
 #include <cstdint>
 #include "amg.h"
 
-namespace {
+namespace amgk {
 
 typedef double v2d __attribute__((ext_vector_type(2)));
 constexpr int PROBE_THREADS = 256;
@@ -39,15 +39,16 @@ __global__ __launch_bounds__(PROBE_THREADS) void k_stream_read(const v2d *__rest
     sink[t] = s;
 }
 
-}  // namespace
+}  // namespace amgk
 
 extern "C" amg_status amg_stream_read(const void *buf, int64_t bytes, double *sink, int64_t sink_len, void *stream)
 {
-    if (!buf || !sink || bytes <= 0 || bytes % 16 != 0 || ((uintptr_t)buf & 15) != 0 || sink_len < PROBE_THREADS)
+    if (!buf || !sink || bytes <= 0 || bytes % 16 != 0 || ((uintptr_t)buf & 15) != 0 ||
+        sink_len < amgk::PROBE_THREADS)
         return AMG_ERR_ARG;
-    const int64_t blocks = sink_len / PROBE_THREADS;
+    const int64_t blocks = sink_len / amgk::PROBE_THREADS;
     const unsigned grid = (unsigned)(blocks < 65536 ? blocks : 65536);
-    hipLaunchKernelGGL(k_stream_read, dim3(grid), dim3(PROBE_THREADS), 0, (hipStream_t)stream,
-                       (const v2d *)buf, bytes / 16, sink);
+    hipLaunchKernelGGL(amgk::k_stream_read, dim3(grid), dim3(amgk::PROBE_THREADS), 0, (hipStream_t)stream,
+                       (const amgk::v2d *)buf, bytes / 16, sink);
     return hipGetLastError() == hipSuccess ? AMG_OK : AMG_ERR_HIP;
 }

@@ -100,6 +100,7 @@ struct DevMat {
     // windows shared by the four slices of a block (batched stencil images)
     int32_t *wgtab = nullptr, *wgst = nullptr;
     int wg_sigma = 0;
+    int xwin = 0;   // single-vector K passes through x windows (shared-offset images with run tables)
     double wg_ratio = 0.0;   // rows the shared windows copy / rows per-wave windows copy
     uint16_t *d16 = nullptr;
     double *v64 = nullptr;
@@ -115,7 +116,8 @@ struct DevMat {
     template <typename IT> const IT *idx() const;
     template <typename VT, typename IT> Sell<VT, IT> sv() const
     {
-        return Sell<VT, IT>{n, ncols, nslices, soff, ibase, val<VT>(), idx<IT>(), col0, shoff, perm, shrun, wgtab, wgst};
+        return Sell<VT, IT>{n,     ncols, nslices, soff,  ibase, val<VT>(), idx<IT>(), col0,
+                            shoff, perm,  shrun,   wgtab, wgst,  xwin};
     }
 };
 template <> const double *DevMat::val<double>() const { return v64; }
@@ -358,6 +360,7 @@ struct amg_ctx {
         if (!S.shoff.empty()) {
             A.shoff = upload(S.shoff);
             A.shrun = upload(S.shrun);
+            A.xwin = C == SLICE && S.nshared > 0 ? 1 : 0;
             if (C == SLICE && S.nshared > 0) {
                 // the block kernels' windows shared by a block's slices
                 amgiga::WgStages W;
@@ -2032,6 +2035,13 @@ amg_status amg_set_option(amg_ctx *c, int option, int value)
     case AMG_OPT_GRAPH: c->use_graph = value ? 1 : 0; break;
     case AMG_OPT_FUSE_POST: c->fuse_post = value ? 1 : 0; c->drop_graphs(); break;
     case AMG_OPT_TAIL: c->use_tail = value ? 1 : 0; c->drop_graphs(); break;
+    case AMG_OPT_X_WINDOW:
+        for (int l = 0; l < c->nlev; l++) {
+            DevMat &A = c->lev[l].A;
+            A.xwin = value && A.C == SLICE && A.nshared > 0 && A.shrun ? 1 : 0;
+        }
+        c->drop_graphs();
+        break;
     case AMG_OPT_WINDOW_SHARE:
         if (value < 0 || value > 3) {
             set_err("AMG_OPT_WINDOW_SHARE takes a mask: 1 FP64-value passes, 2 FP32-value passes");
@@ -2070,6 +2080,7 @@ amg_status amg_get_option(const amg_ctx *c, int option, int *value)
     case AMG_OPT_FUSE_POST: *value = c->fuse_post; break;
     case AMG_OPT_TAIL: *value = c->use_tail && c->tail_start > 0 ? c->tail_start : 0; break;
     case AMG_OPT_WINDOW_SHARE: *value = c->lev[0].A.wgtab ? c->blk_share : 0; break;
+    case AMG_OPT_X_WINDOW: *value = c->nlev > 0 ? c->lev[0].A.xwin : 0; break;
     case AMG_OPT_BLOCK_WINDOW: *value = c->blk_win; break;
     default: set_err("unknown option"); return AMG_ERR_ARG;
     }

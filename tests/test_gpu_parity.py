@@ -244,3 +244,38 @@ def test_residual_history_matches_oracle(oracle, amg):
     np.testing.assert_allclose(h, ref["hist"], rtol=1e-9)
     out0 = ctx.solve(torch.zeros_like(torch.from_numpy(F)).cuda(), tol=1e-8)
     assert out0["iters"] == 0 and len(ctx.residual_history()) == 0
+
+
+@pytest.mark.parametrize("case", ["3d-p3-n16", "2d-p5-n40", "2d-p3-n70", "3d-p1-n66", "2d-p2-n61", "kappa-p4-n8"])
+def test_x_window_equals_gather(oracle, amg, case):
+    """The single-vector matrix passes through x windows (AMG_OPT_X_WINDOW)
+    against the gather walk they replace: SpMV, V-cycle and whole FP64 and
+    FP32-V-cycle solves bit for bit -- x-runs split over several windows
+    (p = 5), slices straddling x-lines and planes, windows at both ends of x
+    (gathered, clamped), a partly filled last slice, variable coefficients."""
+    print(f"case x window {case}", flush=True)
+    from paper_2511_21268_amd.amg import AMG_OPT_X_WINDOW
+    from paper_2511_21268_amd.workloads import kappa_params, rhs_normal
+    if case == "kappa-p4-n8":
+        a_, mk = kappa_params(3)
+        rp, ci, v, _ = oracle.diffusion_quad3d(4, 8, a_, mk, factorized=True)
+    else:
+        d, p, n = (int(t[1:]) if t[0] in "pn" else int(t[0]) for t in case.split("-"))
+        rp, ci, v, _ = oracle.poisson_kron(d, p, n)
+    N = len(rp) - 1
+    x = torch.from_numpy(np.random.default_rng(3).standard_normal(N)).cuda()
+    F = torch.from_numpy(rhs_normal(N, 4)).cuda()
+    for kw in ({}, {"vcycle_fp32": 1, "krylov": 1}):
+        ctx = amg.Context(rp, ci, v, itmax=6000, **kw)
+        assert ctx.format(0)["shared_slices"] > 0
+        assert ctx.option(AMG_OPT_X_WINDOW) == 1   # on by default
+        res = {}
+        for on in (1, 0):
+            ctx.set_x_window(on)
+            assert ctx.option(AMG_OPT_X_WINDOW) == on
+            res[on] = (ctx.spmv(x), ctx.vcycle(x), ctx.solve(F, tol=1e-8))
+        assert torch.equal(res[1][0], res[0][0]) and torch.equal(res[1][1], res[0][1])
+        assert res[1][2]["status"] == 0
+        assert res[1][2]["iters"] == res[0][2]["iters"] and torch.equal(res[1][2]["u"], res[0][2]["u"])
+        print(f"  {kw or 'FP64'}: {res[1][2]['iters']} iterations", flush=True)
+        ctx.close()
