@@ -33,9 +33,10 @@ HBM_PEAK_GBS = 8000.0
 # the two files, concatenated), else null.
 TRAFFIC_SOURCE = "profiles/k_sell_c4_fp64_pmc.md"
 MEASURED_TRAFFIC = {
-    # (workload, SHA-256 of kernels.h + solver.hip): bytes per launch, SpMV and
-    # residual launches of one solve
-    ("c4", "27b5a1693429e0c8a348f3d6e679a8653fe964ef6814545ec579719519a99786"): 6653032544,
+    # (workload, SHA-256 of kernels.h + solver.hip, x windows on): bytes per
+    # launch, SpMV and residual launches of one solve
+    ("c4", "9c40f6d0073b9ed475e3afc8f6f5e9f1c5137286a905a09e4dc79c308bb8d2ef", 1): 6629786832,
+    ("c4", "9c40f6d0073b9ed475e3afc8f6f5e9f1c5137286a905a09e4dc79c308bb8d2ef", 0): 5936292790,
 }
 
 
@@ -155,6 +156,9 @@ def main():
                     help="replay each iteration's launches from HIP graphs in the timed steps (the per-launch "
                          "events that profiling records cannot be replayed, so the roofline then comes from one "
                          "further, eager, profiled solve after the timed steps)")
+    ap.add_argument("--x-window", choices=["auto", "0", "1"], default="auto",
+                    help="single-vector FP64 K passes through x windows (1) or gathers (0); auto: the set-up's "
+                         "autotuner decides")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--one-core-iters", type=int, default=4,
                     help="iterations of the one-core oracle sample (scaled to the full count)")
@@ -223,6 +227,9 @@ def main():
     if args.learned:
         kw["smoother"] = 1
     ctx = amg.Context(rp, ci, v, **kw)
+    if args.x_window != "auto":
+        ctx.set_x_window(int(args.x_window))
+    xwin = ctx.option(amgmod.AMG_OPT_X_WINDOW)
     if args.mode in ("learned", "learned32") or args.learned:
         from paper_2511_21268_amd import learned
         accepted, coefs = learned.apply_learned(ctx)
@@ -306,7 +313,7 @@ def main():
         kname = "k_sell_cheb + k_sell (level-0 Chebyshev / SpMV / residual passes)"
     else:
         kname = "k_sell (level-0 SpMV / residual / smoother pass)"
-    traffic = MEASURED_TRAFFIC.get((args.workload, kernel_source_sha())) if args.mode == "fp64" else None
+    traffic = MEASURED_TRAFFIC.get((args.workload, kernel_source_sha(), xwin)) if args.mode == "fp64" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kname, "launches": dl, "avg_launch_ms": round(kernel_ms, 4),
@@ -358,6 +365,7 @@ def main():
                       "opc": round(ctx.opc(), 4), "setup_s": round(setup_s, 2),
                       "setup_on_device": bool(args.setup_device),
                       "spmv_gbs": round(achieved, 1),
+                      "x_window": xwin,
                       "block_variant": list(ctx.batched_variant()) if nrhs > 1 else None,
                       "block_window": ({"rows_per_lane": ctx.option(amgmod.AMG_OPT_BLOCK_WINDOW),
                                         "shared_mask": ctx.option(amgmod.AMG_OPT_WINDOW_SHARE)}

@@ -317,12 +317,14 @@ const char *amg_last_error(void);
  *   the block copies once for all four waves and which run of which wave each
  *   serves, in each wave's run order.  amg_get_option returns the mask, 0 for
  *   an image without such lists.  Bitwise the same results.
- * AMG_OPT_X_WINDOW (default on): the single-vector matrix passes over FP64
+ * AMG_OPT_X_WINDOW (autotuned by amg_setup): the single-vector matrix passes over FP64
  *   values (SpMV, residual, smoother sweep) walk the slices of stencil images
  *   that have run tables through x windows: per run of consecutive offsets, the
  *   1 KB of x the slice's 64 rows read is copied once into LDS and every lane
  *   reads its entries there, instead of one gather per entry; runs whose 1 KB
- *   would leave x take the gathers.  Bitwise the same results.
+ *   would leave x take the gathers.  amg_setup times both walks on the level-0
+ *   residual and keeps the faster (the gathers gain more from a faster memory;
+ *   the two differ by a few percent either way).  Bitwise the same results.
  * amg_get_option returns the current value of an option. */
 typedef enum {
     AMG_OPT_GRAPH = 1,

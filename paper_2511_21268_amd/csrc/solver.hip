@@ -402,6 +402,36 @@ struct amg_ctx {
         (void)hipEventDestroy(e1);
         return best;
     }
+    // x windows or the gather walk for the single-vector FP64 K passes,
+    // whichever runs faster on this GPU: three residual passes each (measured
+    // at c4: x windows 0.999 against 1.025 ms on one box, 0.996 against
+    // ~0.97 ms on others -- the gather walk gains more from a faster memory)
+    void tune_xwin()
+    {
+        DevMat &A = lev[0].A;
+        if (!A.xwin || !A.v64) return;
+        for (double *v : {p, r})
+            hipLaunchKernelGGL((k_fill<double>), dim3(vgrid(n)), dim3(256), 0, stream, n, 1.0, v);
+        HIPCHK(hipGetLastError());
+        const int prof_saved = prof;
+        prof = 0;
+        auto passes = [&] {
+            for (int i = 0; i < 3; i++)
+                sell<double, double, double, EPI_RESID, 0>(0, p, r, lev[0].invd<double>(), q, nullptr, nullptr);
+        };
+        // warm-up (clocks), then the two walks alternately, the best of each
+        for (int i = 0; i < 4; i++) passes();
+        float t[2] = {1e30f, 1e30f};
+        for (int rep = 0; rep < 2; rep++)
+            for (int on : {1, 0}) {
+                A.xwin = on;
+                const float ms = time_passes(passes);
+                tune_log.push_back({std::string("x windows ") + (on ? "on" : "off"), ms});
+                t[on] = std::min(t[on], ms);
+            }
+        A.xwin = t[1] <= t[0] ? 1 : 0;
+        prof = prof_saved;
+    }
     // The level-0 passes of one batched iteration: FP64 outer SpMV and two
     // passes in the V-cycle precision.
     template <typename VT> void level0_passes()
@@ -1493,6 +1523,7 @@ static amg_status build_device(amg_ctx *c, const CsrView &K0)
     HIPCHK(hipHostMalloc((void **)&c->hsc, S_NSLOTS * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipEventCreateWithFlags(&c->ev_iter, hipEventDisableTiming));
     c->choose_tail();
+    c->tune_xwin();
     if (c->prm.nrhs > 1) c->tune_blocks(K0);
     HIPCHK(hipStreamSynchronize(c->stream));
     return AMG_OK;
