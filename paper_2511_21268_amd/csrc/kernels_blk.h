@@ -1178,16 +1178,12 @@ __global__ __launch_bounds__(FIN_THREADS) void k_bfinalize(const double *__restr
 #pragma unroll
         for (int j = 0; j < NB; j++) { lds[wid * NB + j] = s0[j]; lds[(NW + wid) * NB + j] = s1[j]; }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-#pragma unroll
-    for (int j = 0; j < NB; j++) {
+    // thread j: column j, its waves summed in order (the columns are independent)
+    if (threadIdx.x >= NB) return;
+    {
+        const int j = threadIdx.x;
         double a = 0.0, b = 0.0;
         for (int w = 0; w < NW; w++) { a += lds[w * NB + j]; b += lds[(NW + w) * NB + j]; }
-        s0[j] = a;
-        s1[j] = b;
-    }
-    for (int j = 0; j < NB; j++) {
-        const double a = s0[j], b = s1[j];
         double *F = sc + B_FLAG * NB + j, *D = sc + B_DONE * NB + j;
         switch (op) {
         case BF_FF:
